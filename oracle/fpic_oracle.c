@@ -1,0 +1,442 @@
+/*
+ * fpic_oracle.c -- plain CPU FP64 reference of the particle-in-cell neutrino
+ * flavor method of Richers, Willcox, Ford & Myers, "Particle-in-cell
+ * Simulation of the Neutrino Fast Flavor Instability" (arXiv:2101.02745).
+ *
+ * TEST INFRASTRUCTURE.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  It shares no code,
+ * header or table with the HIP library: it reads the same input *arrays*
+ * and nothing else.
+ *
+ * It is written to be checked by eye against the paper, not to be fast:
+ *   - every particle's density matrices are unpacked into full 3x3 complex
+ *     matrices (Sec. II.B stores only the upper triangle);
+ *   - deposition follows eq. pic_deposition literally: four moment fields
+ *     n, f, nbar, fbar, one particle after another, in particle order;
+ *   - interpolation follows eq. pic_interpolation with the same weights;
+ *   - the Hamiltonians follow eq. potentials and the antineutrino
+ *     conventions of Sec. II.A (Hbar_vac = H_vac^*, Hbar_nunu = -H_nunu^*);
+ *     the matter term is zero (comoving frame with no background leptons);
+ *   - the right-hand side is eq. eom, d rho/dt = -i [H, rho], with both
+ *     products H rho and rho H formed as full matrix products;
+ *   - time integration is the classical fourth-order Runge-Kutta method
+ *     (Sec. II.C), all particles together.
+ *
+ * Units: hbar = c = 1 and sqrt(2) G_F = 1 (densities in units of the
+ * reference density, so the self-interaction strength mu is 1).
+ *
+ * Particle positions.  A particle starts at the centre of its cell and its
+ * direction never changes (eq. eom: dx/dt = Omega), so its position at time
+ * t is x0 + Omega t.  Runge-Kutta integrates a constant velocity exactly, so
+ * the oracle uses that closed form at every stage time.  Along each axis the
+ * displacement measured in cells is u = (Omega_a t) / dx_a; the particle
+ * lies between the centres of cells (c_a + floor(u)) and (c_a + floor(u) + 1)
+ * (periodic), at fraction phi = u - floor(u) of the way.  The linear
+ * ("cloud in cell", first-order) shape function then gives weight 1 - phi to
+ * the first and phi to the second (Sec. II.B.1 shape functions; order 1).
+ * Along an axis with a single cell the particle always lies in cell 0.
+ * Stage times are t = n dt + c_s dt with c_s in {0, 1/2, 1/2, 1}, each
+ * product and sum rounded once (this file is compiled with
+ * -ffp-contract=off).
+ *
+ * State layout: state[18][ndir][ncell], see the input-generator module; the
+ * particle with direction d starting in cell c is (d, c); cells are numbered
+ * x fastest.
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef double complex cplx;
+
+typedef struct {
+    int64_t ncell[3];   /* cells along x, y, z */
+    double dx[3];       /* cell widths */
+    int64_t ndir;       /* directions (particles per cell) */
+    const double *dirs; /* [ndir][3] unit vectors Omega */
+    const double *N;    /* [ndir] neutrinos per particle */
+    const double *Nbar; /* [ndir] antineutrinos per particle */
+    const double *Hvac; /* [3][3] complex, row-major (re, im) pairs */
+    double dt;
+} oracle_problem;
+
+/* ------------------------------------------------------------------ */
+/* small helpers                                                        */
+/* ------------------------------------------------------------------ */
+static int64_t ncell_total(const oracle_problem *P)
+{
+    return P->ncell[0] * P->ncell[1] * P->ncell[2];
+}
+
+static int64_t pmod(int64_t a, int64_t n)
+{
+    int64_t r = a % n;
+    return r < 0 ? r + n : r;
+}
+
+/* Unpack the 9 stored reals (diagonal, then Re/Im of the e-mu, e-tau and
+ * mu-tau entries) of a Hermitian matrix; consecutive reals are `stride`
+ * doubles apart. */
+static void unpack(const double *s, int64_t stride, cplx m[3][3])
+{
+    m[0][0] = s[0 * stride];
+    m[1][1] = s[1 * stride];
+    m[2][2] = s[2 * stride];
+    m[0][1] = s[3 * stride] + I * s[4 * stride];
+    m[0][2] = s[5 * stride] + I * s[6 * stride];
+    m[1][2] = s[7 * stride] + I * s[8 * stride];
+    m[1][0] = conj(m[0][1]);
+    m[2][0] = conj(m[0][2]);
+    m[2][1] = conj(m[1][2]);
+}
+
+/* Store the diagonal (real part) and the upper triangle of m. */
+static void pack(cplx m[3][3], double *s, int64_t stride)
+{
+    s[0 * stride] = creal(m[0][0]);
+    s[1 * stride] = creal(m[1][1]);
+    s[2 * stride] = creal(m[2][2]);
+    s[3 * stride] = creal(m[0][1]);
+    s[4 * stride] = cimag(m[0][1]);
+    s[5 * stride] = creal(m[0][2]);
+    s[6 * stride] = cimag(m[0][2]);
+    s[7 * stride] = creal(m[1][2]);
+    s[8 * stride] = cimag(m[1][2]);
+}
+
+static void matmul(cplx a[3][3], cplx b[3][3], cplx out[3][3])
+{
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+            cplx s = 0;
+            for (int k = 0; k < 3; k++)
+                s += a[i][k] * b[k][j];
+            out[i][j] = s;
+        }
+}
+
+/* -i [H, rho] = -i (H rho - rho H) */
+static void commutator_rhs(cplx H[3][3], cplx rho[3][3], cplx out[3][3])
+{
+    cplx Hr[3][3], rH[3][3];
+    matmul(H, rho, Hr);
+    matmul(rho, H, rH);
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++)
+            out[i][j] = -I * (Hr[i][j] - rH[i][j]);
+}
+
+static void load_hvac(const oracle_problem *P, cplx H[3][3])
+{
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++)
+            H[i][j] = P->Hvac[2 * (3 * i + j)] + I * P->Hvac[2 * (3 * i + j) + 1];
+}
+
+/* ------------------------------------------------------------------ */
+/* shape function                                                       */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int n;
+    int64_t cell[8];
+    double w[8];
+} stencil;
+
+/* Cells touched by particle (d, c) at time t and their weights w_pj. */
+static void cic_stencil(const oracle_problem *P, int64_t d, int64_t c, double t,
+                        stencil *S)
+{
+    const int64_t nx = P->ncell[0], ny = P->ncell[1];
+    int64_t home[3] = {c % nx, (c / nx) % ny, c / (nx * ny)};
+    int64_t lo[3];
+    double wlo[3], whi[3];
+    int two[3];
+    for (int a = 0; a < 3; a++) {
+        if (P->ncell[a] == 1) {
+            lo[a] = 0;
+            wlo[a] = 1.0;
+            whi[a] = 0.0;
+            two[a] = 0;
+            continue;
+        }
+        double u = (P->dirs[3 * d + a] * t) / P->dx[a];
+        double fl = floor(u);
+        double phi = u - fl;
+        lo[a] = pmod(home[a] + (int64_t)fl, P->ncell[a]);
+        wlo[a] = 1.0 - phi;
+        whi[a] = phi;
+        two[a] = 1;
+    }
+    S->n = 0;
+    for (int bz = 0; bz <= two[2]; bz++)
+        for (int by = 0; by <= two[1]; by++)
+            for (int bx = 0; bx <= two[0]; bx++) {
+                int64_t ix = (lo[0] + bx) % P->ncell[0];
+                int64_t iy = (lo[1] + by) % P->ncell[1];
+                int64_t iz = (lo[2] + bz) % P->ncell[2];
+                double w = (bx ? whi[0] : wlo[0]) * (by ? whi[1] : wlo[1]);
+                w = w * (bz ? whi[2] : wlo[2]);
+                S->cell[S->n] = (iz * ny + iy) * nx + ix;
+                S->w[S->n] = w;
+                S->n++;
+            }
+}
+
+/* ------------------------------------------------------------------ */
+/* deposition (eq. pic_deposition)                                      */
+/* ------------------------------------------------------------------ */
+/* Moment fields, per cell: n[3][3], f[axis][3][3], nbar, fbar. */
+typedef struct {
+    cplx n[3][3];
+    cplx f[3][3][3];
+    cplx nb[3][3];
+    cplx fb[3][3][3];
+} moments;
+
+static void deposit(const oracle_problem *P, const double *state, double t,
+                    moments *grid)
+{
+    const int64_t nc = ncell_total(P), nd = P->ndir, np = nc * nd;
+    const double dV = P->dx[0] * P->dx[1] * P->dx[2];
+    memset(grid, 0, sizeof(moments) * (size_t)nc);
+    for (int64_t d = 0; d < nd; d++) {
+        const double *v = P->dirs + 3 * d;
+        for (int64_t c = 0; c < nc; c++) {
+            const int64_t p = d * nc + c;
+            cplx rho[3][3], rhob[3][3];
+            unpack(state + p, np, rho);
+            unpack(state + 9 * np + p, np, rhob);
+            stencil S;
+            cic_stencil(P, d, c, t, &S);
+            for (int s = 0; s < S.n; s++) {
+                moments *g = grid + S.cell[s];
+                const double wN = S.w[s] * P->N[d];
+                const double wNb = S.w[s] * P->Nbar[d];
+                for (int i = 0; i < 3; i++)
+                    for (int j = 0; j < 3; j++) {
+                        g->n[i][j] += wN * rho[i][j];
+                        g->nb[i][j] += wNb * rhob[i][j];
+                        for (int a = 0; a < 3; a++) {
+                            g->f[a][i][j] += wN * rho[i][j] * v[a];
+                            g->fb[a][i][j] += wNb * rhob[i][j] * v[a];
+                        }
+                    }
+            }
+        }
+    }
+    for (int64_t c = 0; c < nc; c++) {
+        moments *g = grid + c;
+        for (int i = 0; i < 3; i++)
+            for (int j = 0; j < 3; j++) {
+                g->n[i][j] /= dV;
+                g->nb[i][j] /= dV;
+                for (int a = 0; a < 3; a++) {
+                    g->f[a][i][j] /= dV;
+                    g->fb[a][i][j] /= dV;
+                }
+            }
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* interpolation, Hamiltonians, right-hand side                         */
+/* ------------------------------------------------------------------ */
+static void interpolate(const moments *grid, const stencil *S, moments *out)
+{
+    memset(out, 0, sizeof(moments));
+    for (int s = 0; s < S->n; s++) {
+        const moments *g = grid + S->cell[s];
+        const double w = S->w[s];
+        for (int i = 0; i < 3; i++)
+            for (int j = 0; j < 3; j++) {
+                out->n[i][j] += w * g->n[i][j];
+                out->nb[i][j] += w * g->nb[i][j];
+                for (int a = 0; a < 3; a++) {
+                    out->f[a][i][j] += w * g->f[a][i][j];
+                    out->fb[a][i][j] += w * g->fb[a][i][j];
+                }
+            }
+    }
+}
+
+/* Right-hand side of eq. eom for every particle at time t. */
+static void rhs(const oracle_problem *P, const double *state, double t,
+                moments *grid, double *out)
+{
+    const int64_t nc = ncell_total(P), nd = P->ndir, np = nc * nd;
+    cplx Hv[3][3];
+    load_hvac(P, Hv);
+    deposit(P, state, t, grid);
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
+    for (int64_t p = 0; p < np; p++) {
+        const int64_t d = p / nc, c = p % nc;
+        const double *v = P->dirs + 3 * d;
+        stencil S;
+        cic_stencil(P, d, c, t, &S);
+        moments m;
+        interpolate(grid, &S, &m);
+        cplx Hnn[3][3], H[3][3], Hb[3][3];
+        for (int i = 0; i < 3; i++)
+            for (int j = 0; j < 3; j++) {
+                cplx h = m.n[i][j] - conj(m.nb[i][j]);
+                for (int a = 0; a < 3; a++)
+                    h -= v[a] * (m.f[a][i][j] - conj(m.fb[a][i][j]));
+                Hnn[i][j] = h;
+            }
+        for (int i = 0; i < 3; i++)
+            for (int j = 0; j < 3; j++) {
+                H[i][j] = Hv[i][j] + Hnn[i][j];
+                Hb[i][j] = conj(Hv[i][j]) - conj(Hnn[i][j]);
+            }
+        cplx rho[3][3], rhob[3][3], k[3][3], kb[3][3];
+        unpack(state + p, np, rho);
+        unpack(state + 9 * np + p, np, rhob);
+        commutator_rhs(H, rho, k);
+        commutator_rhs(Hb, rhob, kb);
+        pack(k, out + p, np);
+        pack(kb, out + 9 * np + p, np);
+    }
+}
+
+static double stage_time(int64_t n, double dt, double c)
+{
+    double tn = (double)n * dt;
+    return tn + c * dt;
+}
+
+/* ------------------------------------------------------------------ */
+/* exported entry points                                               */
+/* ------------------------------------------------------------------ */
+int oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0)
+        omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
+
+/* One evaluation of the right-hand side at time t; out has the state's
+ * shape. */
+int oracle_rhs(const oracle_problem *P, const double *state, double t, double *out)
+{
+    moments *grid = malloc(sizeof(moments) * (size_t)ncell_total(P));
+    if (!grid)
+        return -1;
+    rhs(P, state, t, grid, out);
+    free(grid);
+    return 0;
+}
+
+/* nsteps classical RK4 steps, in place, starting at step number n0
+ * (time n0 * dt). */
+int oracle_step(const oracle_problem *P, double *state, int64_t n0, int64_t nsteps)
+{
+    const int64_t len = 18 * P->ndir * ncell_total(P);
+    const double dt = P->dt;
+    moments *grid = malloc(sizeof(moments) * (size_t)ncell_total(P));
+    double *k = malloc(sizeof(double) * (size_t)len);
+    double *ks = malloc(sizeof(double) * (size_t)len);
+    double *ys = malloc(sizeof(double) * (size_t)len);
+    if (!grid || !k || !ks || !ys) {
+        free(grid); free(k); free(ks); free(ys);
+        return -1;
+    }
+    for (int64_t n = n0; n < n0 + nsteps; n++) {
+        /* k1 */
+        rhs(P, state, stage_time(n, dt, 0.0), grid, k);
+        for (int64_t i = 0; i < len; i++) {
+            ks[i] = k[i];
+            ys[i] = state[i] + (0.5 * dt) * k[i];
+        }
+        /* k2 */
+        rhs(P, ys, stage_time(n, dt, 0.5), grid, k);
+        for (int64_t i = 0; i < len; i++) {
+            ks[i] = ks[i] + 2.0 * k[i];
+            ys[i] = state[i] + (0.5 * dt) * k[i];
+        }
+        /* k3 */
+        rhs(P, ys, stage_time(n, dt, 0.5), grid, k);
+        for (int64_t i = 0; i < len; i++) {
+            ks[i] = ks[i] + 2.0 * k[i];
+            ys[i] = state[i] + dt * k[i];
+        }
+        /* k4 */
+        rhs(P, ys, stage_time(n, dt, 1.0), grid, k);
+        for (int64_t i = 0; i < len; i++) {
+            ks[i] = ks[i] + k[i];
+            state[i] = state[i] + (dt / 6.0) * ks[i];
+        }
+    }
+    free(grid); free(k); free(ks); free(ys);
+    return 0;
+}
+
+/* The four moment fields at time t, out[72][ncell]: n, f_x, f_y, f_z,
+ * nbar, fbar_x, fbar_y, fbar_z, each as 9 packed reals. */
+int oracle_moments(const oracle_problem *P, const double *state, double t, double *out)
+{
+    const int64_t nc = ncell_total(P);
+    moments *grid = malloc(sizeof(moments) * (size_t)nc);
+    if (!grid)
+        return -1;
+    deposit(P, state, t, grid);
+    for (int64_t c = 0; c < nc; c++) {
+        moments *g = grid + c;
+        pack(g->n, out + 0 * 9 * nc + c, nc);
+        for (int a = 0; a < 3; a++)
+            pack(g->f[a], out + (1 + a) * 9 * nc + c, nc);
+        pack(g->nb, out + 4 * 9 * nc + c, nc);
+        for (int a = 0; a < 3; a++)
+            pack(g->fb[a], out + (5 + a) * 9 * nc + c, nc);
+    }
+    free(grid);
+    return 0;
+}
+
+/* Interpolate an arbitrary cell field G[ncomp][ncell] to every particle
+ * at time t (eq. pic_interpolation applied component-wise):
+ * out[ncomp][ndir][ncell]. */
+int oracle_gather(const oracle_problem *P, const double *G, int64_t ncomp, double t,
+                  double *out)
+{
+    const int64_t nc = ncell_total(P), nd = P->ndir, np = nc * nd;
+    for (int64_t p = 0; p < np; p++) {
+        stencil S;
+        cic_stencil(P, p / nc, p % nc, t, &S);
+        for (int64_t q = 0; q < ncomp; q++) {
+            double s = 0.0;
+            for (int i = 0; i < S.n; i++)
+                s += S.w[i] * G[q * nc + S.cell[i]];
+            out[q * np + p] = s;
+        }
+    }
+    return 0;
+}
+
+/* Sum over particles of N rho and Nbar rhobar: out[2][9] packed reals. */
+int oracle_flavor_totals(const oracle_problem *P, const double *state, double *out)
+{
+    const int64_t nc = ncell_total(P), nd = P->ndir, np = nc * nd;
+    for (int k = 0; k < 18; k++)
+        out[k] = 0.0;
+    for (int64_t d = 0; d < nd; d++)
+        for (int64_t c = 0; c < nc; c++) {
+            const int64_t p = d * nc + c;
+            for (int k = 0; k < 9; k++) {
+                out[k] += P->N[d] * state[k * np + p];
+                out[9 + k] += P->Nbar[d] * state[(9 + k) * np + p];
+            }
+        }
+    return 0;
+}

@@ -1,0 +1,134 @@
+"""ctypes binding of the CPU FP64 reference (test infrastructure only).
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg use
+this module.  It wraps ``fpic_oracle.c``; see that file for what each
+routine computes and which passage of the paper it follows.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+# FPIC_ORACLE_LIB lets the mutation test load a deliberately broken build.
+LIB_PATH = os.environ.get("FPIC_ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
+
+_dp = C.POINTER(C.c_double)
+
+
+class _Problem(C.Structure):
+    _fields_ = [("ncell", C.c_int64 * 3), ("dx", C.c_double * 3),
+                ("ndir", C.c_int64), ("dirs", _dp), ("N", _dp),
+                ("Nbar", _dp), ("Hvac", _dp), ("dt", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from . import build as _b
+            _b.build()
+        _lib = C.CDLL(LIB_PATH)
+        P = C.POINTER(_Problem)
+        for name, args in {
+            "oracle_rhs": [P, _dp, C.c_double, _dp],
+            "oracle_step": [P, _dp, C.c_int64, C.c_int64],
+            "oracle_moments": [P, _dp, C.c_double, _dp],
+            "oracle_gather": [P, _dp, C.c_int64, C.c_double, _dp],
+            "oracle_flavor_totals": [P, _dp, _dp],
+        }.items():
+            fn = getattr(_lib, name)
+            fn.argtypes = args
+            fn.restype = C.c_int
+        _lib.oracle_set_threads.argtypes = [C.c_int]
+        _lib.oracle_set_threads.restype = C.c_int
+    return _lib
+
+
+def set_threads(n: int) -> int:
+    """Set the OpenMP thread count (n <= 0 keeps it); returns the count."""
+    return lib().oracle_set_threads(int(n))
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(_dp)
+
+
+class Problem:
+    """A periodic box with one particle per direction per cell.
+
+    ncell: (nx, ny, nz); dx: cell widths; dirs [ndir][3]; N, Nbar [ndir]
+    (neutrinos per particle); hvac: 3x3 complex; dt: time step.
+    """
+
+    def __init__(self, ncell, dx, dirs, N, Nbar, hvac, dt: float):
+        self.ncell = tuple(int(n) for n in ncell)
+        self.dx = tuple(float(x) for x in dx)
+        self.dirs = np.ascontiguousarray(dirs, dtype=np.float64).reshape(-1, 3)
+        self.ndir = self.dirs.shape[0]
+        self.N = np.ascontiguousarray(N, dtype=np.float64).reshape(self.ndir)
+        self.Nbar = np.ascontiguousarray(Nbar, dtype=np.float64).reshape(self.ndir)
+        H = np.asarray(hvac, dtype=np.complex128).reshape(3, 3)
+        h = np.empty(18)
+        h[0::2] = H.real.ravel()
+        h[1::2] = H.imag.ravel()
+        self.hvac = h
+        self.dt = float(dt)
+        self._s = _Problem((C.c_int64 * 3)(*self.ncell), (C.c_double * 3)(*self.dx),
+                           self.ndir, _ptr(self.dirs), _ptr(self.N),
+                           _ptr(self.Nbar), _ptr(self.hvac), self.dt)
+
+    @classmethod
+    def from_workload(cls, w, hvac=None) -> "Problem":
+        N, Nbar = w.weights()
+        return cls(w.ncell, w.dx, w.dirs(), N, Nbar,
+                   w.hvac() if hvac is None else hvac, w.dt)
+
+    @property
+    def ncell_total(self) -> int:
+        return self.ncell[0] * self.ncell[1] * self.ncell[2]
+
+    def _state(self, state: np.ndarray) -> np.ndarray:
+        s = np.ascontiguousarray(state, dtype=np.float64)
+        if s.size != 18 * self.ndir * self.ncell_total:
+            raise ValueError("state has the wrong size")
+        return s
+
+    def step(self, state: np.ndarray, nsteps: int, n0: int = 0) -> np.ndarray:
+        """Return the state after nsteps RK4 steps from step number n0."""
+        s = self._state(state).copy()
+        if lib().oracle_step(C.byref(self._s), _ptr(s), int(n0), int(nsteps)):
+            raise MemoryError("oracle_step failed")
+        return s.reshape(18, self.ndir, self.ncell_total)
+
+    def rhs(self, state: np.ndarray, t: float) -> np.ndarray:
+        s = self._state(state)
+        out = np.empty_like(s)
+        if lib().oracle_rhs(C.byref(self._s), _ptr(s), float(t), _ptr(out)):
+            raise MemoryError("oracle_rhs failed")
+        return out.reshape(18, self.ndir, self.ncell_total)
+
+    def moments(self, state: np.ndarray, t: float) -> np.ndarray:
+        s = self._state(state)
+        out = np.empty((72, self.ncell_total))
+        if lib().oracle_moments(C.byref(self._s), _ptr(s), float(t), _ptr(out)):
+            raise MemoryError("oracle_moments failed")
+        return out
+
+    def gather(self, G: np.ndarray, t: float) -> np.ndarray:
+        G = np.ascontiguousarray(G, dtype=np.float64).reshape(-1, self.ncell_total)
+        out = np.empty((G.shape[0], self.ndir, self.ncell_total))
+        lib().oracle_gather(C.byref(self._s), _ptr(G), G.shape[0], float(t), _ptr(out))
+        return out
+
+    def flavor_totals(self, state: np.ndarray) -> np.ndarray:
+        s = self._state(state)
+        out = np.empty((2, 9))
+        lib().oracle_flavor_totals(C.byref(self._s), _ptr(s), _ptr(out))
+        return out
