@@ -1,0 +1,149 @@
+#!/usr/bin/env python3
+"""Throughput of the PIC flavor hot path on one MI355X.
+
+One step = one classical RK4 step of the whole box: four times (deposit with
+the cloud-in-cell shape, interpolation, Hamiltonian, commutator, stage
+update).  The workload is the 1D box of 2048 cells and 378 directions
+(774,144 particles), dt = 0.1/mu, seeded synthetic initial state.
+
+Prints one JSON line.  `value` is particle-steps per second over the timed
+region (state resident in HBM, hipGraph-replayed steps).  `roofline` reports
+the dominant kernel against the HBM peak, from its algorithmic bytes per
+launch and its mean launch time measured with HIP events on the library's
+stream; `cpu_baseline` is the CPU FP64 reference timed on a bounded sample
+of the same workload on this host.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "particle-steps/s (deposit+gather+RK4) on 1 GPU vs roofline; adjoint/forward ratio"
+STATE_B = 18 * 8        # bytes of one particle's state
+GRID_B = 36 * 8         # bytes of one cell's combined moments
+# passes over the particle state per stage kernel (read + write), see the design doc
+STAGE_PASSES = {1: 2, 2: 3, 3: 3, 4: 5}
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("fpic_1d.hip", "fpic_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2101_02745_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str, launches_bytes: float):
+    """HBM bytes per launch from committed counter runs, if they were taken on
+    the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    ent = rec.get(workload, {}).get(kernel)
+    if not ent or ent.get("source_hash") != kernel_source_hash():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def cpu_baseline(w, budget_s=20.0):
+    import numpy as np
+    from oracle import Problem, set_threads
+    threads = set_threads(min(16, os.cpu_count() or 1))
+    P = Problem.from_workload(w)
+    s = w.state0()
+    t0 = time.perf_counter()
+    s = P.step(s, 1)
+    t1 = time.perf_counter() - t0
+    n = int(max(1, min(20, budget_s / max(t1, 1e-3))))
+    t0 = time.perf_counter()
+    P.step(s, n, n0=1)
+    dt = time.perf_counter() - t0
+    return {"value": w.nparticles * n / dt, "unit": "particle-steps/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{n} RK4 steps of the full {w.name} box ({w.nparticles} particles) "
+                      f"after one warm-up step, {threads} OpenMP threads"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="1d_2048x378")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
+    ap.add_argument("--tuning", default="", help="JSON launch shape (default: built-in)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU decomposition is a design note, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2101_02745_amd import inputs as I
+    from paper_2101_02745_amd.sim import Sim
+
+    w = I.workload(args.workload)
+    tuning = json.loads(args.tuning) if args.tuning else None
+    sim = Sim.from_workload(w, tuning=tuning)
+    sim.set_state(w.state0())
+    torch.cuda.synchronize()
+    print(f"[bench] {w.name}: {w.nparticles} particles, warmup {args.warmup} steps",
+          file=sys.stderr, flush=True)
+    sim.step(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = 1e3 * wall / args.steps
+    value = w.nparticles * args.steps / wall
+    print(f"[bench] timed {args.steps} steps: {ms_step:.4f} ms/step", file=sys.stderr, flush=True)
+
+    # per-kernel launch times (HIP events on the library's stream)
+    ms = sim.profile(20)
+    stage_ms = {s: ms[2 * (s - 1)] for s in (1, 2, 3, 4)}
+    red_ms = [ms[2 * s - 1] for s in (1, 2, 3, 4)]
+    dom = max(stage_ms, key=lambda s: stage_ms[s])
+    ncell = w.ncell_total
+    alg_bytes = STAGE_PASSES[dom] * STATE_B * w.nparticles + 2 * GRID_B * ncell
+    achieved = alg_bytes / (stage_ms[dom] * 1e-3) / 1e9
+    kname = f"stage{dom}"
+    traffic = measured_traffic(kname, w.name, alg_bytes)
+    step_bytes = sum(STAGE_PASSES.values()) * STATE_B * w.nparticles + 4 * 2 * GRID_B * ncell
+    ok = sim.check(1e-10)
+
+    rec = {
+        "metric": METRIC, "value": value, "unit": "particle-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": w.name, "ncell": list(w.ncell), "ndir": w.ndir,
+                   "particles": w.nparticles, "dt": w.dt, "shape": "cic",
+                   "integrator": "rk4", "launch": sim.tune.as_dict() if sim.tune else "default"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": f"stage1d_kernel<{dom}>",
+                     "alg_bytes_per_launch": alg_bytes, "ms_per_launch": stage_ms[dom]},
+        "step_roofline": {"alg_bytes_per_step": step_bytes,
+                          "achieved_GBs": step_bytes / (ms_step * 1e-3) / 1e9,
+                          "frac": step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                          "stage_ms": [stage_ms[s] for s in (1, 2, 3, 4)],
+                          "reduce_ms": red_ms},
+        "trace_error": ok,
+    }
+    if not args.no_cpu:
+        print("[bench] CPU baseline (oracle)", file=sys.stderr, flush=True)
+        rec["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

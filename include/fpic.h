@@ -1,0 +1,175 @@
+/*
+ * fpic.h -- C ABI of libflavorpic: the hot path of the particle-in-cell
+ * neutrino flavor method of Richers, Willcox, Ford & Myers, "Particle-in-cell
+ * Simulation of the Neutrino Fast Flavor Instability" (arXiv:2101.02745),
+ * as hand-written HIP kernels for AMD Instinct MI355X (gfx950).
+ *
+ * What one step computes (Sec. II.B-II.C):
+ *   for each of the four stages of classical RK4 (Sec. II.C),
+ *     - deposit every particle's density matrices onto the grid with the
+ *       linear (cloud-in-cell) shape function (Sec. II.B.1,
+ *       eq. pic_deposition), combined as n - nbar^* and f - fbar^*;
+ *     - interpolate those moments back to every particle with the same
+ *       weights (Sec. II.B.2, eq. pic_interpolation) and form
+ *       H = H_vac + (n - nbar^*) - Omega.(f - fbar^*) and
+ *       Hbar = H_vac^* - [(n - nbar^*) - Omega.(f - fbar^*)]^*
+ *       (Sec. II.A, eq. potentials; matter term zero);
+ *     - evaluate d rho/dt = -i [H, rho], d rhobar/dt = -i [Hbar, rhobar]
+ *       (eq. eom) and form the next stage state.
+ *
+ * Conventions
+ *   - Units: hbar = c = 1, sqrt(2) G_F = 1.
+ *   - Every function returns FPIC_OK (0) or a negative FPIC_E* code and
+ *     never throws; fpic_last_error() gives the calling thread's last message.
+ *   - "device" pointers are HIP device memory on the context's device;
+ *     "host" pointers are ordinary host memory.  Host arrays are copied
+ *     before the call returns; the caller keeps ownership of everything.
+ *   - Device work is enqueued on the stream given at creation (an
+ *     hipStream_t passed as void*).  Only functions marked SYNC wait for it.
+ *   - The caller owns one device workspace per context (size from
+ *     fpic_workspace_bytes); the library never allocates device memory.
+ *     The workspace must stay allocated until fpic_destroy.
+ *
+ * State layout (device or host, float64): state[18][ndir][ncell].  The 18
+ * reals of a particle are rho_ee, rho_mumu, rho_tautau, Re/Im rho_emu,
+ * Re/Im rho_etau, Re/Im rho_mutau, then the same nine for rhobar (only the
+ * diagonal and the upper triangle are stored, Sec. II.B).  Cells are
+ * numbered x fastest: cell = (z * ny + y) * nx + x.  Particle (d, c) is the
+ * one with direction d that started at the centre of cell c (one particle
+ * per direction per cell, Sec. III.A and App. B); at time t it has moved
+ * Omega_d t.
+ */
+#ifndef FPIC_H
+#define FPIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FPIC_OK 0
+#define FPIC_EINVAL (-1)       /* bad argument or configuration */
+#define FPIC_EHIP (-2)         /* a HIP runtime call failed */
+#define FPIC_ESTATE (-3)       /* call out of order (e.g. step before set_state) */
+#define FPIC_ENUMERIC (-4)     /* NaN/Inf or trace drift found by fpic_check */
+#define FPIC_EUNSUPPORTED (-5) /* valid but not implemented (e.g. dt too large) */
+
+typedef void *fpic_stream; /* hipStream_t */
+
+/* A periodic box with one particle per direction per cell. */
+typedef struct fpic_config {
+    int32_t ncell[3];    /* cells along x, y, z; a 1D box is {1, 1, nz} */
+    double dx[3];        /* cell widths (cell volume dx*dy*dz) */
+    int32_t ndir;        /* directions = particles per cell */
+    const double *dirs;  /* host [ndir][3] unit vectors Omega_d */
+    const double *N;     /* host [ndir] neutrinos per particle */
+    const double *Nbar;  /* host [ndir] antineutrinos per particle */
+    double hvac[18];     /* vacuum Hamiltonian, 3x3 complex Hermitian,
+                            row-major (re, im) pairs, flavor basis */
+    double dt;           /* time step; a stage may move no particle by a
+                            whole cell: dt/2 * max|Omega_a| < dx_a */
+    int32_t shape_order; /* 1 (linear, cloud-in-cell) */
+    int32_t flags;       /* reserved, 0 */
+} fpic_config;
+
+/* Launch shape.  Zero fields take the built-in choice; fpic_autotune
+ * measures candidates on the device and returns the fastest. */
+typedef struct fpic_tuning {
+    int32_t waves;           /* 64-lane waves per workgroup: 1, 2 or 4 */
+    int32_t dirs_per_wave;   /* directions each wave sweeps, >= 1 */
+    int32_t steps_per_graph; /* steps captured in one hipGraph, >= 1 */
+    int32_t reserved;
+} fpic_tuning;
+
+typedef struct fpic_ctx fpic_ctx;
+
+/* Bytes of device workspace fpic_create needs for this configuration. */
+int fpic_workspace_bytes(const fpic_config *cfg, const fpic_tuning *tune, size_t *bytes);
+
+/* Validate cfg, upload its tables into the workspace (device, caller-owned,
+ * >= fpic_workspace_bytes, 256-byte aligned) and record the step graph.
+ * tune may be NULL.  stream: hipStream_t for all later work. */
+int fpic_create(const fpic_config *cfg, const fpic_tuning *tune, void *workspace,
+                size_t workspace_bytes, fpic_stream stream, fpic_ctx **out);
+
+/* Copy a state (device, [18][ndir][ncell]) in, set the step counter to
+ * step0 (time step0*dt) and deposit the first-stage moments. */
+int fpic_set_state(fpic_ctx *ctx, const double *state, int64_t step0);
+
+/* Copy the current state out (device, [18][ndir][ncell]). */
+int fpic_get_state(fpic_ctx *ctx, double *state);
+
+/* Advance nsteps >= 0 classical RK4 steps (Sec. II.C); asynchronous. */
+int fpic_step(fpic_ctx *ctx, int64_t nsteps);
+
+/* Deposit the four moment fields of the current state at the current time
+ * (eq. pic_deposition, kept separate for neutrinos and antineutrinos):
+ * out (device) [72][ncell] = n, f_x, f_y, f_z, nbar, fbar_x, fbar_y,
+ * fbar_z, each as 9 packed reals per cell, per unit volume. */
+int fpic_moments(fpic_ctx *ctx, double *out);
+
+/* SYNC.  sum_p N_p rho_p and sum_p Nbar_p rhobar_p as 2 x 9 packed reals
+ * (host out[18]). */
+int fpic_flavor_totals(fpic_ctx *ctx, double *out);
+
+/* SYNC.  Largest |Tr rho - 1| and |Tr rhobar - 1| over all particles (host
+ * *max_trace_err); returns FPIC_ENUMERIC if any state entry is NaN/Inf or
+ * the trace error exceeds tol. */
+int fpic_check(fpic_ctx *ctx, double tol, double *max_trace_err);
+
+/* SYNC.  Current step number (time = step * dt). */
+int fpic_get_step(fpic_ctx *ctx, int64_t *step);
+
+/* SYNC.  Wait for all work enqueued by this context. */
+int fpic_sync(fpic_ctx *ctx);
+
+/* Free the context's host objects and graphs (not the workspace). */
+void fpic_destroy(fpic_ctx *ctx);
+
+/* SYNC.  Measurement: advance nsteps steps launching each kernel on its own
+ * (outside the graph) with HIP events between launches, and return the mean
+ * milliseconds per launch (host ms[8]) of: stage 1, its reduction, stage 2,
+ * its reduction, stage 3, its reduction, stage 4, its reduction. */
+int fpic_profile(fpic_ctx *ctx, int32_t nsteps, double *ms);
+
+/* Message of the calling thread's last failed call ("" if none). */
+const char *fpic_last_error(void);
+
+/* ---------------------------------------------------------------------
+ * Batches: many independent 1D boxes of uneven size advanced together,
+ * one launch per RK stage over a cost-sorted table of all their tiles,
+ * the whole step captured in one hipGraph.  Each simulation keeps its own
+ * dt, cell width, directions and weights.  Not in the paper: a throughput
+ * device for parameter studies like its Sec. IV.
+ * --------------------------------------------------------------------- */
+typedef struct fpic_batch fpic_batch;
+
+int fpic_batch_workspace_bytes(int32_t nsim, const fpic_config *cfgs,
+                               const fpic_tuning *tune, size_t *bytes);
+int fpic_batch_create(int32_t nsim, const fpic_config *cfgs, const fpic_tuning *tune,
+                      void *workspace, size_t workspace_bytes, fpic_stream stream,
+                      fpic_batch **out);
+/* state (device) [18][ndir_sim][ncell_sim] of simulation sim */
+int fpic_batch_set_state(fpic_batch *b, int32_t sim, const double *state, int64_t step0);
+int fpic_batch_get_state(fpic_batch *b, int32_t sim, double *state);
+int fpic_batch_step(fpic_batch *b, int64_t nsteps);
+/* SYNC.  host out[nsim][18] */
+int fpic_batch_flavor_totals(fpic_batch *b, double *out);
+int fpic_batch_sync(fpic_batch *b);
+void fpic_batch_destroy(fpic_batch *b);
+
+/* ---------------------------------------------------------------------
+ * Autotuning: time candidate launch shapes for cfg on the device (using a
+ * scratch workspace of `bytes`, device) and return the fastest in *best
+ * (host).  ms_per_step (host, may be NULL) receives its time.  SYNC.
+ * --------------------------------------------------------------------- */
+int fpic_autotune(int32_t nsim, const fpic_config *cfgs, void *workspace, size_t bytes,
+                  fpic_stream stream, fpic_tuning *best, double *ms_per_step);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FPIC_H */

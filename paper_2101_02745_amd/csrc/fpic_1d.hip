@@ -1,0 +1,523 @@
+// HIP kernels of the 1D hot path (gfx950, FP64, wave64).
+//
+// One launch per Runge-Kutta stage covers every tile of every simulation of
+// a batch.  A workgroup owns one tile of TILE = 64 consecutive cells and one
+// group of directions; each of its waves sweeps `dpw` directions.  For
+// direction d, lane l handles the particle whose *next-stage* left cell is
+// m = tile*64 + l (positions are implicit, see below).  Per particle the
+// lane
+//   1. forms the stage state y_s from Y and the previous slope,
+//   2. interpolates the staged grid tile (LDS) at the particle's current
+//      position with the linear shape function (eq. pic_interpolation),
+//   3. builds H and Hbar (eq. potentials, antineutrino conventions of
+//      Sec. II.A) and the slopes -i[H, rho], -i[Hbar, rhobar] (eq. eom),
+//   4. writes the slope (or the finished step) and forms the next-stage
+//      state,
+//   5. deposits that state with the next-stage weights (eq. pic_deposition):
+//      its left weight goes to cell m, its right weight to cell m+1, which
+//      lane l+1 picks up with a one-lane shuffle; the last lane's right part
+//      goes to an edge partial.
+// The deposit therefore needs no atomics: each lane accumulates the 36
+// combined moments of its own cell over its directions in registers, the
+// waves of a workgroup are summed in LDS in a fixed order, and a small
+// reduction kernel sums the direction groups (and the edge partials) in a
+// fixed order.  Results are bitwise reproducible run to run.
+//
+// Positions.  Every particle starts at the centre of its cell and moves with
+// constant Omega (eq. eom), so at stage time t its displacement along z in
+// cells is u = (Omega_z t) / dz, the same for every particle of a direction:
+// floor(u) is the integer shift, u - floor(u) the CIC fraction.  Stage times
+// are t = n dt + c_s dt (c_s = 0, 1/2, 1/2, 1), each operation rounded once,
+// exactly as the CPU reference forms them.
+#include "fpic_internal.h"
+
+namespace fpic {
+
+__device__ __forceinline__ double stage_time(int64_t n, double dt, double c)
+{
+#pragma clang fp contract(off)
+    const double tn = (double)n * dt;
+    return tn + c * dt;
+}
+
+struct Shift {
+    int64_t i;
+    double phi;
+};
+
+__device__ __forceinline__ Shift shift_of(double v, double t, double dx)
+{
+#pragma clang fp contract(off)
+    const double u = (v * t) / dx;
+    const double fl = floor(u);
+    Shift s;
+    s.i = (int64_t)fl;
+    s.phi = u - fl;
+    return s;
+}
+
+__device__ __forceinline__ int pmod_i64(int64_t a, int n)
+{
+    int64_t r = a % n;
+    return (int)(r < 0 ? r + n : r);
+}
+
+// k = -i [H, rho] for Hermitian H, rho given as 9 packed reals (diagonal,
+// then Re/Im of the (0,1), (0,2), (1,2) entries).  With C = H rho:
+// k_aa = 2 Im C_aa and k_ab = -i (C_ab - conj(C_ba)) for a < b.
+__device__ __forceinline__ void commutator(const double h[9], const double r[9], double k[9])
+{
+    const double h0 = h[0], h1 = h[1], h2 = h[2];
+    const double ar = h[3], ai = h[4], br = h[5], bi = h[6], cr = h[7], ci = h[8];
+    const double p0 = r[0], p1 = r[1], p2 = r[2];
+    const double xr = r[3], xi = r[4], yr = r[5], yi = r[6], zr = r[7], zi = r[8];
+
+    k[0] = 2.0 * ((ai * xr - ar * xi) + (bi * yr - br * yi));
+    k[1] = 2.0 * ((ar * xi - ai * xr) + (ci * zr - cr * zi));
+    k[2] = 2.0 * ((br * yi - bi * yr) + (cr * zi - ci * zr));
+
+    // C01 = h0 x + a p1 + b z^*,  C10 = a^* p0 + h1 x^* + c y^*
+    const double c01r = h0 * xr + ar * p1 + (br * zr + bi * zi);
+    const double c01i = h0 * xi + ai * p1 + (bi * zr - br * zi);
+    const double c10r = ar * p0 + h1 * xr + (cr * yr + ci * yi);
+    const double c10i = -ai * p0 - h1 * xi + (ci * yr - cr * yi);
+    k[3] = c01i + c10i;
+    k[4] = c10r - c01r;
+
+    // C02 = h0 y + a z + b p2,  C20 = b^* p0 + c^* x^* + h2 y^*
+    const double c02r = h0 * yr + (ar * zr - ai * zi) + br * p2;
+    const double c02i = h0 * yi + (ar * zi + ai * zr) + bi * p2;
+    const double c20r = br * p0 + (cr * xr - ci * xi) + h2 * yr;
+    const double c20i = -bi * p0 - (cr * xi + ci * xr) - h2 * yi;
+    k[5] = c02i + c20i;
+    k[6] = c20r - c02r;
+
+    // C12 = a^* y + h1 z + c p2,  C21 = b^* x + c^* p1 + h2 z^*
+    const double c12r = (ar * yr + ai * yi) + h1 * zr + cr * p2;
+    const double c12i = (ar * yi - ai * yr) + h1 * zi + ci * p2;
+    const double c21r = (br * xr + bi * xi) + cr * p1 + h2 * zr;
+    const double c21i = (br * xi - bi * xr) - ci * p1 - h2 * zi;
+    k[7] = c12i + c21i;
+    k[8] = c21r - c12r;
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(MAX_WAVES * TILE)
+stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ sims, int max_dpw)
+{
+    extern __shared__ double smem[];
+    const WorkItem wi = work[blockIdx.x];
+    // private copy: the kernel's stores cannot alias the descriptor
+    const SimDesc S = sims[wi.sim];
+    const int lane = threadIdx.x & (TILE - 1);
+    const int wave = threadIdx.x / TILE;
+    const int nwaves = blockDim.x / TILE;
+    const int nc = S.ncell;
+    const int64_t np = S.np;
+    const int tile0 = wi.tile * TILE;
+    const int m = tile0 + lane;
+    const bool active = m < nc;
+    const int nact = min(TILE, nc - tile0);
+    const int64_t n = *S.step;
+    const double dt = S.dt, dz = S.dz;
+
+    // stage times of the current (gathered) and next (deposited) positions
+    double t_cur = 0.0, t_nxt;
+    if (MODE == M_S1) {
+        t_cur = stage_time(n, dt, 0.0);
+        t_nxt = stage_time(n, dt, 0.5);
+    } else if (MODE == M_S2) {
+        t_cur = stage_time(n, dt, 0.5);
+        t_nxt = stage_time(n, dt, 0.5);
+    } else if (MODE == M_S3) {
+        t_cur = stage_time(n, dt, 0.5);
+        t_nxt = stage_time(n, dt, 1.0);
+    } else if (MODE == M_S4) {
+        t_cur = stage_time(n, dt, 1.0);
+        t_nxt = stage_time(n + 1, dt, 0.0);
+    } else {
+        t_nxt = stage_time(n, dt, 0.0);
+    }
+
+    double *Gt = smem;                          // [NG][GT_STRIDE]
+    double *eb = smem + NG * GT_STRIDE + wave * max_dpw * 9;
+
+    if (MODE <= M_S4) {
+        // S1 and S3 read G0, S2 and S4 read G1 (ping-pong with the reduce)
+        const double *Gin = (MODE == M_S1 || MODE == M_S3) ? S.G0 : S.G1;
+        for (int idx = threadIdx.x; idx < NG * GT_CELLS; idx += blockDim.x) {
+            const int comp = idx / GT_CELLS;
+            const int k = idx - comp * GT_CELLS;
+            const int cell = pmod_i64((int64_t)tile0 - 1 + k, nc);
+            Gt[comp * GT_STRIDE + k] = Gin[(size_t)comp * nc + cell];
+        }
+        __syncthreads();
+    }
+
+    double hv[9];
+#pragma unroll
+    for (int k = 0; k < 9; k++)
+        hv[k] = S.hvac[k];
+
+    double acc[NG];
+#pragma unroll
+    for (int k = 0; k < NG; k++)
+        acc[k] = 0.0;
+
+    const int dbeg = wi.group * S.dpg + wave * S.dpw;
+    const int dend = min(dbeg + S.dpw, S.ndir);
+
+    for (int d = dbeg; d < dend; ++d) {
+        const double vx = S.vx[d], vy = S.vy[d], vz = S.vz[d];
+        const double wN = S.wN[d], wNb = S.wNb[d];
+        const Shift sn = shift_of(vz, t_nxt, dz);
+        const int r = pmod_i64(sn.i, nc);
+        int c = m - r;
+        if (c < 0)
+            c += nc;
+        const int64_t p = (int64_t)d * nc + c;
+
+        double X[9];
+        if (active) {
+            double Y[18];
+#pragma unroll
+            for (int k = 0; k < 18; k++)
+                Y[k] = S.Y[k * np + p];
+            if (MODE == M_DEPOSIT) {
+#pragma unroll
+                for (int k = 0; k < 9; k++)
+                    X[k] = (k == 4 || k == 6 || k == 8) ? wN * Y[k] + wNb * Y[9 + k]
+                                                        : wN * Y[k] - wNb * Y[9 + k];
+            } else if (MODE == M_MOM_NU) {
+#pragma unroll
+                for (int k = 0; k < 9; k++)
+                    X[k] = wN * Y[k];
+            } else if (MODE == M_MOM_NUBAR) {
+#pragma unroll
+                for (int k = 0; k < 9; k++)
+                    X[k] = wNb * Y[9 + k];
+            } else {
+                // interpolate the staged grid at the current position
+                const Shift sc = shift_of(vz, t_cur, dz);
+                int delta = (int)(sn.i - sc.i);
+                delta = max(-1, min(1, delta));
+                const int kl = lane - delta + 1;  // LDS column of cell m - delta
+                const double phi = sc.phi, omp = 1.0 - phi;
+                double Hnn[9];
+#pragma unroll
+                for (int k = 0; k < 9; k++) {
+                    const double *g = Gt + k * GT_STRIDE + kl;
+                    const double A = omp * g[0] + phi * g[1];
+                    const double Bx = omp * g[9 * GT_STRIDE] + phi * g[9 * GT_STRIDE + 1];
+                    const double By = omp * g[18 * GT_STRIDE] + phi * g[18 * GT_STRIDE + 1];
+                    const double Bz = omp * g[27 * GT_STRIDE] + phi * g[27 * GT_STRIDE + 1];
+                    Hnn[k] = A - (vx * Bx + vy * By + vz * Bz);
+                }
+                // stage state
+                const double *Kp = (MODE == M_S2) ? S.K1 : (MODE == M_S3) ? S.K2 : S.K3;
+                const double a = (MODE == M_S4) ? dt : 0.5 * dt;
+                double y[18];
+#pragma unroll
+                for (int k = 0; k < 18; k++)
+                    y[k] = (MODE == M_S1) ? Y[k] : Y[k] + a * Kp[k * np + p];
+                // Hamiltonians: H = Hvac + Hnn, Hbar = (Hvac - Hnn)^*
+                double H[9], Hb[9], kk[18];
+#pragma unroll
+                for (int k = 0; k < 9; k++) {
+                    H[k] = hv[k] + Hnn[k];
+                    const double hb = hv[k] - Hnn[k];
+                    Hb[k] = (k == 4 || k == 6 || k == 8) ? -hb : hb;
+                }
+                commutator(H, y, kk);
+                commutator(Hb, y + 9, kk + 9);
+                double yn[18];
+                if (MODE == M_S4) {
+                    const double h6 = dt / 6.0;
+#pragma unroll
+                    for (int k = 0; k < 18; k++) {
+                        const double s1 = S.K1[k * np + p] + 2.0 * S.K2[k * np + p];
+                        const double s2 = s1 + 2.0 * S.K3[k * np + p];
+                        yn[k] = Y[k] + h6 * (s2 + kk[k]);
+                        S.Y[k * np + p] = yn[k];
+                    }
+                } else {
+                    double *Ko = (MODE == M_S1) ? S.K1 : (MODE == M_S2) ? S.K2 : S.K3;
+                    const double an = (MODE == M_S3) ? dt : 0.5 * dt;
+#pragma unroll
+                    for (int k = 0; k < 18; k++) {
+                        Ko[k * np + p] = kk[k];
+                        yn[k] = Y[k] + an * kk[k];
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < 9; k++)
+                    X[k] = (k == 4 || k == 6 || k == 8) ? wN * yn[k] + wNb * yn[9 + k]
+                                                        : wN * yn[k] - wNb * yn[9 + k];
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < 9; k++)
+                X[k] = 0.0;
+        }
+
+        // deposit with the next-stage weights: cell m gets (1 - phi') of its
+        // own particle and phi' of the particle one lane to the left
+        const double ph = sn.phi, omph = 1.0 - ph;
+#pragma unroll
+        for (int k = 0; k < 9; k++) {
+            double xl = __shfl_up(X[k], 1, TILE);
+            xl = (lane == 0) ? 0.0 : xl;
+            const double xc = omph * X[k] + ph * xl;
+            acc[k] += xc;
+            acc[9 + k] += vx * xc;
+            acc[18 + k] += vy * xc;
+            acc[27 + k] += vz * xc;
+        }
+        if (lane == nact - 1) {
+#pragma unroll
+            for (int k = 0; k < 9; k++)
+                eb[(d - dbeg) * 9 + k] = ph * X[k];
+        }
+    }
+
+    // ---- workgroup reduction (fixed order over waves) -----------------
+    __syncthreads();  // the grid tile is no longer needed: reuse it
+    double *redb = smem;  // [NG][TILE]
+    for (int w = 0; w < nwaves; ++w) {
+        if (wave == w) {
+#pragma unroll
+            for (int k = 0; k < NG; k++)
+                redb[k * TILE + lane] = (w == 0) ? acc[k] : redb[k * TILE + lane] + acc[k];
+        }
+        __syncthreads();
+    }
+    // edge partial of each wave: lanes 0..35 sum their component over the
+    // wave's directions
+    double *esum = smem + NG * TILE;  // [nwaves][NG], inside the old tile area
+    if (lane < NG) {
+        const int comp = lane % 9, grp = lane / 9;
+        double s = 0.0;
+        for (int d = dbeg; d < dend; ++d) {
+            const double coef = (grp == 0) ? 1.0 : (grp == 1) ? S.vx[d] : (grp == 2) ? S.vy[d] : S.vz[d];
+            s += coef * eb[(d - dbeg) * 9 + comp];
+        }
+        esum[wave * NG + lane] = s;
+    }
+    __syncthreads();
+
+    const int ntc = S.ntile * TILE;
+    double *part = S.part + (size_t)wi.group * NG * ntc;
+    for (int idx = threadIdx.x; idx < NG * TILE; idx += blockDim.x) {
+        const int k = idx / TILE, l = idx - k * TILE;
+        part[(size_t)k * ntc + tile0 + l] = redb[idx];
+    }
+    if (threadIdx.x < NG) {
+        double s = 0.0;
+        for (int w = 0; w < nwaves; ++w)
+            s += esum[w * NG + threadIdx.x];
+        S.edge[((size_t)wi.group * NG + threadIdx.x) * S.ntile + wi.tile] = s;
+    }
+}
+
+// Sum the direction-group partials of one tile in a fixed order and close
+// the periodic box: cell tile*64 also receives the right-edge partial of
+// the previous tile (cell 0 that of the last tile).
+__global__ void __launch_bounds__(256)
+reduce1d_kernel(const RedItem *__restrict__ items, const SimDesc *__restrict__ sims, int which,
+                double *override_out, int tick)
+{
+    const RedItem it = items[blockIdx.x];
+    const SimDesc &S = sims[it.sim];
+    const int nc = S.ncell, ntile = S.ntile, ntc = ntile * TILE;
+    const int tile0 = it.tile * TILE;
+    const int nact = min(TILE, nc - tile0);
+    double *out = (which == 0) ? S.G0 : (which == 1) ? S.G1 : override_out;
+    const int tprev = (it.tile + ntile - 1) % ntile;
+    for (int idx = threadIdx.x; idx < NG * TILE; idx += blockDim.x) {
+        const int k = idx / TILE, l = idx - k * TILE;
+        if (l >= nact)
+            continue;
+        double s = 0.0;
+        for (int g = 0; g < S.ngroup; ++g)
+            s += S.part[((size_t)g * NG + k) * ntc + tile0 + l];
+        if (l == 0)
+            for (int g = 0; g < S.ngroup; ++g)
+                s += S.edge[((size_t)g * NG + k) * ntile + tprev];
+        out[(size_t)k * nc + tile0 + l] = s;
+    }
+    if (tick && it.tile == 0 && threadIdx.x == 0)
+        *S.step += 1;
+}
+
+__global__ void set_step_kernel(const SimDesc *sims, int lo, int hi, int64_t value)
+{
+    const int i = lo + (int)threadIdx.x;
+    if (i < hi)
+        *sims[i].step = value;
+}
+
+// Deterministic two-level sums for diagnostics: block b sums particles
+// b, b + nblk*256, ... per thread, then a fixed LDS tree.
+__global__ void __launch_bounds__(256)
+totals_kernel(const SimDesc *sims, int sim, double *partial)
+{
+    const SimDesc &S = sims[sim];
+    __shared__ double sh[256];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int k = 0; k < 18; ++k) {
+        double s = 0.0;
+        for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < S.np; p += stride) {
+            const int d = (int)(p / S.ncell);
+            const double w = (k < 9) ? S.Nw[d] : S.Nbw[d];
+            s += w * S.Y[k * S.np + p];
+        }
+        sh[threadIdx.x] = s;
+        __syncthreads();
+        for (int h = 128; h > 0; h >>= 1) {
+            if ((int)threadIdx.x < h)
+                sh[threadIdx.x] += sh[threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0)
+            partial[(size_t)blockIdx.x * 18 + k] = sh[0];
+        __syncthreads();
+    }
+}
+
+__global__ void sum_blocks_kernel(const double *partial, int nblk, int width, double *out)
+{
+    const int k = threadIdx.x;
+    if (k >= width)
+        return;
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b)
+        s += partial[(size_t)b * width + k];
+    out[k] = s;
+}
+
+// max |Tr rho - 1|, max |Tr rhobar - 1|, count of non-finite entries
+__global__ void __launch_bounds__(256)
+check_kernel(const SimDesc *sims, int sim, double *partial)
+{
+    const SimDesc &S = sims[sim];
+    __shared__ double sh[3][256];
+    double e0 = 0.0, e1 = 0.0, bad = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < S.np; p += stride) {
+        double v[18];
+        for (int k = 0; k < 18; ++k) {
+            v[k] = S.Y[k * S.np + p];
+            if (!isfinite(v[k]))
+                bad += 1.0;
+        }
+        e0 = fmax(e0, fabs(v[0] + v[1] + v[2] - 1.0));
+        e1 = fmax(e1, fabs(v[9] + v[10] + v[11] - 1.0));
+    }
+    sh[0][threadIdx.x] = e0;
+    sh[1][threadIdx.x] = e1;
+    sh[2][threadIdx.x] = bad;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            sh[0][threadIdx.x] = fmax(sh[0][threadIdx.x], sh[0][threadIdx.x + h]);
+            sh[1][threadIdx.x] = fmax(sh[1][threadIdx.x], sh[1][threadIdx.x + h]);
+            sh[2][threadIdx.x] += sh[2][threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[blockIdx.x * 3 + 0] = sh[0][0];
+        partial[blockIdx.x * 3 + 1] = sh[1][0];
+        partial[blockIdx.x * 3 + 2] = sh[2][0];
+    }
+}
+
+__global__ void check_final_kernel(const double *partial, int nblk, double *out)
+{
+    if (threadIdx.x != 0)
+        return;
+    double e0 = 0.0, e1 = 0.0, bad = 0.0;
+    for (int b = 0; b < nblk; ++b) {
+        e0 = fmax(e0, partial[b * 3 + 0]);
+        e1 = fmax(e1, partial[b * 3 + 1]);
+        bad += partial[b * 3 + 2];
+    }
+    out[0] = e0;
+    out[1] = e1;
+    out[2] = bad;
+}
+
+// Electron-flavor state rho = rhobar = diag(1, 0, 0) (autotuning input).
+__global__ void fill_state_kernel(const SimDesc *sims, int sim)
+{
+    const SimDesc &S = sims[sim];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < S.np; p += stride)
+        for (int k = 0; k < 18; ++k)
+            S.Y[k * S.np + p] = (k == 0 || k == 9) ? 1.0 : 0.0;
+}
+
+size_t stage1d_smem_bytes(int waves, int max_dpw)
+{
+    size_t tile = (size_t)NG * GT_STRIDE;
+    size_t red = (size_t)NG * TILE + (size_t)waves * NG;
+    size_t base = tile > red ? tile : red;
+    return (base + (size_t)waves * max_dpw * 9) * sizeof(double);
+}
+
+hipError_t launch_stage1d(int mode, const WorkItem *work, int nwork, const SimDesc *sims,
+                          int waves, int max_dpw, hipStream_t s)
+{
+    const dim3 grid(nwork), block(waves * TILE);
+    const size_t smem = stage1d_smem_bytes(waves, max_dpw);
+    switch (mode) {
+    case M_S1: stage1d_kernel<M_S1><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
+    case M_S2: stage1d_kernel<M_S2><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
+    case M_S3: stage1d_kernel<M_S3><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
+    case M_S4: stage1d_kernel<M_S4><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
+    case M_DEPOSIT: stage1d_kernel<M_DEPOSIT><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
+    case M_MOM_NU: stage1d_kernel<M_MOM_NU><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
+    case M_MOM_NUBAR: stage1d_kernel<M_MOM_NUBAR><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce1d(const RedItem *items, int nitems, const SimDesc *sims, int which,
+                           double *override_out, int tick, hipStream_t s)
+{
+    reduce1d_kernel<<<dim3(nitems), dim3(256), 0, s>>>(items, sims, which, override_out, tick);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_step(const SimDesc *sims, int lo, int hi, int64_t value, hipStream_t s)
+{
+    const int n = hi - lo;
+    set_step_kernel<<<1, n < 1 ? 1 : n, 0, s>>>(sims, lo, hi, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_totals(const SimDesc *sims, int sim, int nblk, double *out18, hipStream_t s)
+{
+    // partials live after the 18 outputs in the same scratch area
+    double *partial = out18 + 18;
+    totals_kernel<<<nblk, 256, 0, s>>>(sims, sim, partial);
+    sum_blocks_kernel<<<1, 64, 0, s>>>(partial, nblk, 18, out18);
+    return hipGetLastError();
+}
+
+hipError_t launch_check(const SimDesc *sims, int sim, int nblk, double *out3, hipStream_t s)
+{
+    double *partial = out3 + 3;
+    check_kernel<<<nblk, 256, 0, s>>>(sims, sim, partial);
+    check_final_kernel<<<1, 64, 0, s>>>(partial, nblk, out3);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_state(const SimDesc *sims, int sim, hipStream_t s)
+{
+    fill_state_kernel<<<1024, 256, 0, s>>>(sims, sim);
+    return hipGetLastError();
+}
+
+}  // namespace fpic

@@ -1,0 +1,84 @@
+// Internal declarations shared by the HIP kernels and the host runtime of
+// libflavorpic.  Not part of the public ABI (see include/fpic.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+namespace fpic {
+
+// Cells per tile = lanes per wave: lane l of every wave of a workgroup owns
+// cell tile*TILE + l, so one wave's loads of one direction are contiguous.
+constexpr int TILE = 64;
+// Combined moments per cell: A = n - nbar^* (9 packed reals), then
+// B_x, B_y, B_z = f_i - fbar_i^* (9 each).
+constexpr int NG = 36;
+// Staged grid tile: cells tile*TILE-1 .. tile*TILE+65 (67 cells, padded).
+constexpr int GT_CELLS = 67;
+constexpr int GT_STRIDE = 68;
+constexpr int MAX_WAVES = 4;
+
+enum Mode : int {
+    M_S1 = 1,       // RK stage 1: k1 = F(Y), deposit Y + dt/2 k1
+    M_S2 = 2,       // stage 2: k2 = F(Y + dt/2 k1), deposit Y + dt/2 k2
+    M_S3 = 3,       // stage 3: k3 = F(Y + dt/2 k2), deposit Y + dt k3
+    M_S4 = 4,       // stage 4: k4 = F(Y + dt k3), Y += dt/6 (k1+2k2+2k3+k4),
+                    //          deposit the new Y (first stage of next step)
+    M_DEPOSIT = 5,  // deposit Y at the current step time
+    M_MOM_NU = 6,   // deposit N rho alone (moments n, f)
+    M_MOM_NUBAR = 7 // deposit Nbar rhobar alone (moments nbar, fbar)
+};
+
+// One 1D simulation as the kernels see it.  All pointers are device
+// pointers into the caller's workspace.
+struct SimDesc {
+    int32_t ncell;   // cells along z
+    int32_t ndir;    // directions
+    int32_t ntile;   // ceil(ncell / TILE)
+    int32_t ngroup;  // direction groups = workgroups per tile
+    int32_t dpw;     // directions per wave
+    int32_t dpg;     // directions per group = waves * dpw
+    int64_t np;      // particles = ndir * ncell
+    double dt;       // time step
+    double dz;       // cell width
+    double hvac[9];  // vacuum Hamiltonian, packed (diag, Re/Im upper)
+    const double *vx, *vy, *vz;  // [ndir] direction components
+    const double *wN, *wNb;      // [ndir] N / dV, Nbar / dV
+    const double *Nw, *Nbw;      // [ndir] N, Nbar
+    double *Y;                   // [18][ndir][ncell] state
+    double *K1, *K2, *K3;        // [18][ndir][ncell] stage slopes
+    double *G0, *G1;             // [36][ncell] deposited moments (ping-pong)
+    double *part;                // [ngroup][36][ntile*TILE] per-group partials
+    double *edge;                // [ngroup][36][ntile] right-edge partials
+    double *red;                 // [nred][18] scratch for reductions
+    int64_t *step;               // current step number
+};
+
+struct WorkItem {
+    int32_t sim, tile, group, pad;
+};
+
+struct RedItem {
+    int32_t sim, tile;
+};
+
+// Launchers (fpic_1d.hip).
+hipError_t launch_stage1d(int mode, const WorkItem *work, int nwork, const SimDesc *sims,
+                          int waves, int max_dpw, hipStream_t s);
+hipError_t launch_reduce1d(const RedItem *items, int nitems, const SimDesc *sims, int which,
+                           double *override_out, int tick, hipStream_t s);
+hipError_t launch_set_step(const SimDesc *sims, int sim_lo, int sim_hi, int64_t value,
+                           hipStream_t s);
+hipError_t launch_totals(const SimDesc *sims, int sim, int nblk, double *out18, hipStream_t s);
+hipError_t launch_check(const SimDesc *sims, int sim, int nblk, double *out2, hipStream_t s);
+hipError_t launch_fill_state(const SimDesc *sims, int sim, hipStream_t s);
+
+size_t stage1d_smem_bytes(int waves, int max_dpw);
+
+// Record msg as the calling thread's last error and return code.
+int fail(int code, const std::string &msg);
+
+}  // namespace fpic

@@ -1,0 +1,789 @@
+// Host runtime and C ABI of libflavorpic (see include/fpic.h).
+//
+// A context is a batch of one simulation: every 1D entry point runs the same
+// segmented kernels over a table of (simulation, tile, direction group)
+// work items.  The runtime carves the caller's workspace, uploads the small
+// per-simulation tables, builds the work tables (cost-sorted for the step,
+// contiguous per simulation for per-simulation calls), and captures one and
+// K RK4 steps into hipGraphs on a private stream; fpic_step replays them on
+// the caller's stream.  Kernels read the step number from device memory, so
+// the captured graphs stay valid as time advances.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "fpic.h"
+#include "fpic_internal.h"
+#include "fpic_3d.h"
+
+using namespace fpic;
+
+namespace {
+thread_local std::string g_err;
+}  // namespace
+
+int fpic::fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+namespace {
+
+#define HIPCHECK(x)                                                                     \
+    do {                                                                                \
+        hipError_t e_ = (x);                                                            \
+        if (e_ != hipSuccess)                                                           \
+            return fail(FPIC_EHIP, std::string(#x) + ": " + hipGetErrorString(e_));    \
+    } while (0)
+
+size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Carver {
+    size_t off = 0;
+    size_t take(size_t bytes)
+    {
+        off = align_up(off);
+        size_t o = off;
+        off += bytes;
+        return o;
+    }
+};
+
+constexpr int kRedBlocks = 256;  // blocks of the diagnostic reductions
+
+// Sizes and offsets of one simulation inside the workspace.
+struct SimPlan {
+    int ncell = 0, ndir = 0, ntile = 0, ngroup = 0, dpw = 0;
+    int64_t np = 0;
+    size_t o_tab = 0, o_Y = 0, o_K1 = 0, o_K2 = 0, o_K3 = 0, o_G0 = 0, o_G1 = 0;
+    size_t o_part = 0, o_edge = 0, o_step = 0;
+};
+
+struct Plan {
+    int nsim = 0, waves = 0, max_dpw = 0, spg = 0;
+    std::vector<SimPlan> sims;
+    size_t o_desc = 0, o_work = 0, o_red = 0, o_scratch = 0, total = 0;
+    int nwork = 0, nred = 0;
+};
+
+int validate_1d(const fpic_config &c, int idx)
+{
+    char buf[256];
+    auto bad = [&](const char *what) {
+        std::snprintf(buf, sizeof buf, "config %d: %s", idx, what);
+        return fail(FPIC_EINVAL, buf);
+    };
+    if (c.ncell[0] < 1 || c.ncell[1] < 1 || c.ncell[2] < 1)
+        return bad("cell counts must be >= 1");
+    if (c.ndir < 1)
+        return bad("ndir must be >= 1");
+    if (!c.dirs || !c.N || !c.Nbar)
+        return bad("dirs, N and Nbar must be non-null host arrays");
+    if (c.shape_order != 1)
+        return fail(FPIC_EUNSUPPORTED, "only shape_order 1 (cloud in cell) is implemented");
+    for (int a = 0; a < 3; ++a)
+        if (!(c.dx[a] > 0.0) || !std::isfinite(c.dx[a]))
+            return bad("cell widths must be positive and finite");
+    if (!(c.dt > 0.0) || !std::isfinite(c.dt))
+        return bad("dt must be positive and finite");
+    if ((int64_t)c.ncell[0] * c.ncell[1] * c.ncell[2] > (int64_t)1 << 30)
+        return bad("too many cells");
+    double hmax = 0.0;
+    for (int i = 0; i < 18; ++i) {
+        if (!std::isfinite(c.hvac[i]))
+            return bad("hvac has a non-finite entry");
+        hmax = std::max(hmax, std::fabs(c.hvac[i]));
+    }
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            const double re = c.hvac[2 * (3 * i + j)], im = c.hvac[2 * (3 * i + j) + 1];
+            const double rt = c.hvac[2 * (3 * j + i)], it = c.hvac[2 * (3 * j + i) + 1];
+            if (std::fabs(re - rt) + std::fabs(im + it) > 1e-12 * (1.0 + hmax))
+                return bad("hvac is not Hermitian");
+        }
+    double vmax[3] = {0, 0, 0};
+    for (int d = 0; d < c.ndir; ++d) {
+        const double *v = c.dirs + 3 * d;
+        const double n2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+        if (!std::isfinite(n2) || std::fabs(n2 - 1.0) > 1e-9)
+            return bad("directions must be unit vectors");
+        if (!std::isfinite(c.N[d]) || !std::isfinite(c.Nbar[d]))
+            return bad("weights must be finite");
+        for (int a = 0; a < 3; ++a)
+            vmax[a] = std::max(vmax[a], std::fabs(v[a]));
+    }
+    for (int a = 0; a < 3; ++a)
+        if (c.ncell[a] > 1 && 0.5 * c.dt * vmax[a] / c.dx[a] >= 1.0 - 1e-9)
+            return fail(FPIC_EUNSUPPORTED,
+                        "dt too large: a particle may cross a whole cell within one "
+                        "Runge-Kutta stage (need dt/2 * max|Omega| < dx)");
+    return FPIC_OK;
+}
+
+bool is_1d(const fpic_config &c) { return c.ncell[0] == 1 && c.ncell[1] == 1; }
+
+int make_plan(int nsim, const fpic_config *cfgs, const fpic_tuning *tune, Plan &P)
+{
+    if (nsim < 1 || !cfgs)
+        return fail(FPIC_EINVAL, "need at least one configuration");
+    for (int i = 0; i < nsim; ++i) {
+        int rc = validate_1d(cfgs[i], i);
+        if (rc)
+            return rc;
+        if (!is_1d(cfgs[i]))
+            return fail(FPIC_EINVAL, "batches hold 1D boxes only (ncell = {1, 1, nz})");
+    }
+    P = Plan();
+    P.nsim = nsim;
+    P.waves = (tune && tune->waves) ? tune->waves : 4;
+    if (P.waves != 1 && P.waves != 2 && P.waves != 4)
+        return fail(FPIC_EINVAL, "waves must be 1, 2 or 4");
+    P.spg = (tune && tune->steps_per_graph) ? tune->steps_per_graph : 8;
+    if (P.spg < 1 || P.spg > 256)
+        return fail(FPIC_EINVAL, "steps_per_graph must be in 1..256");
+    int64_t wavedirs = 0;
+    for (int i = 0; i < nsim; ++i)
+        wavedirs += (int64_t)((cfgs[i].ncell[2] + TILE - 1) / TILE) * cfgs[i].ndir;
+    int dpw = (tune && tune->dirs_per_wave) ? tune->dirs_per_wave : 0;
+    if (dpw < 0 || dpw > 256)
+        return fail(FPIC_EINVAL, "dirs_per_wave must be in 0..256");
+    if (!dpw) {
+        // aim at about 1024 workgroups in total
+        const int64_t target = 1024LL * P.waves;
+        dpw = (int)std::max<int64_t>(1, std::min<int64_t>(64, (wavedirs + target - 1) / target));
+    }
+    Carver cv;
+    P.sims.resize(nsim);
+    for (int i = 0; i < nsim; ++i) {
+        SimPlan &s = P.sims[i];
+        s.ncell = cfgs[i].ncell[2];
+        s.ndir = cfgs[i].ndir;
+        s.np = (int64_t)s.ncell * s.ndir;
+        s.ntile = (s.ncell + TILE - 1) / TILE;
+        s.dpw = std::min(dpw, s.ndir);
+        const int dpg = s.dpw * P.waves;
+        s.ngroup = (s.ndir + dpg - 1) / dpg;
+        P.max_dpw = std::max(P.max_dpw, s.dpw);
+        const size_t st = sizeof(double) * 18 * (size_t)s.np;
+        s.o_tab = cv.take(sizeof(double) * 7 * s.ndir);
+        s.o_Y = cv.take(st);
+        s.o_K1 = cv.take(st);
+        s.o_K2 = cv.take(st);
+        s.o_K3 = cv.take(st);
+        s.o_G0 = cv.take(sizeof(double) * NG * s.ncell);
+        s.o_G1 = cv.take(sizeof(double) * NG * s.ncell);
+        s.o_part = cv.take(sizeof(double) * (size_t)s.ngroup * NG * s.ntile * TILE);
+        s.o_edge = cv.take(sizeof(double) * (size_t)s.ngroup * NG * s.ntile);
+        s.o_step = cv.take(sizeof(int64_t));
+        P.nwork += s.ntile * s.ngroup;
+        P.nred += s.ntile;
+    }
+    P.o_desc = cv.take(sizeof(SimDesc) * nsim);
+    // global (cost-sorted) table followed by the per-simulation tables
+    P.o_work = cv.take(sizeof(WorkItem) * 2 * (size_t)P.nwork);
+    P.o_red = cv.take(sizeof(RedItem) * (size_t)P.nred);
+    P.o_scratch = cv.take(sizeof(double) * (3 + 18 + 18 * kRedBlocks + 3 * kRedBlocks));
+    P.total = align_up(cv.off);
+    return FPIC_OK;
+}
+
+}  // namespace
+
+struct fpic_batch {
+    Plan plan;
+    hipStream_t stream = nullptr;  // caller's
+    hipStream_t cap = nullptr;     // private capture stream
+    char *ws = nullptr;
+    SimDesc *ddesc = nullptr;
+    WorkItem *dwork = nullptr;     // [nwork] sorted, then [nwork] per-sim
+    RedItem *dred = nullptr;
+    double *dscratch = nullptr;
+    double *hbuf = nullptr;        // pinned host staging
+    std::vector<SimDesc> hdesc;
+    std::vector<int> swork_off, sred_off;
+    std::vector<bool> state_set;
+    hipGraphExec_t g1 = nullptr, gK = nullptr;
+};
+
+struct fpic_ctx {
+    fpic_batch *b = nullptr;       // 1D
+    fpic3d::Ctx3D *c3 = nullptr;   // 3D
+};
+
+namespace {
+
+int capture_steps(fpic_batch *b, int nsteps, hipGraphExec_t *exec)
+{
+    const Plan &P = b->plan;
+    HIPCHECK(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+    hipError_t err = hipSuccess;
+    for (int s = 0; s < nsteps && err == hipSuccess; ++s)
+        for (int st = M_S1; st <= M_S4 && err == hipSuccess; ++st) {
+            err = launch_stage1d(st, b->dwork, P.nwork, b->ddesc, P.waves, P.max_dpw, b->cap);
+            if (err == hipSuccess)
+                err = launch_reduce1d(b->dred, P.nred, b->ddesc,
+                                      (st == M_S1 || st == M_S3) ? 1 : 0, nullptr,
+                                      st == M_S4 ? 1 : 0, b->cap);
+        }
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(b->cap, &graph);
+    if (err != hipSuccess) {
+        if (graph)
+            (void)hipGraphDestroy(graph);
+        return fail(FPIC_EHIP, std::string("kernel launch during capture: ") + hipGetErrorString(err));
+    }
+    HIPCHECK(e2);
+    hipError_t e3 = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    HIPCHECK(e3);
+    return FPIC_OK;
+}
+
+int batch_build(int nsim, const fpic_config *cfgs, const fpic_tuning *tune, void *workspace,
+                size_t bytes, fpic_stream stream, fpic_batch **out)
+{
+    if (!out)
+        return fail(FPIC_EINVAL, "out is null");
+    *out = nullptr;
+    Plan P;
+    int rc = make_plan(nsim, cfgs, tune, P);
+    if (rc)
+        return rc;
+    if (!workspace || bytes < P.total)
+        return fail(FPIC_EINVAL, "workspace missing or smaller than fpic_workspace_bytes");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256)
+        return fail(FPIC_EINVAL, "workspace must be 256-byte aligned");
+
+    fpic_batch *b = new fpic_batch();
+    b->plan = P;
+    b->stream = static_cast<hipStream_t>(stream);
+    b->ws = static_cast<char *>(workspace);
+    b->ddesc = reinterpret_cast<SimDesc *>(b->ws + P.o_desc);
+    b->dwork = reinterpret_cast<WorkItem *>(b->ws + P.o_work);
+    b->dred = reinterpret_cast<RedItem *>(b->ws + P.o_red);
+    b->dscratch = reinterpret_cast<double *>(b->ws + P.o_scratch);
+    b->state_set.assign(nsim, false);
+
+    auto cleanup = [&](int code) {
+        fpic_batch_destroy(b);
+        return code;
+    };
+
+    // tables and descriptors
+    std::vector<double> tab;
+    b->hdesc.resize(nsim);
+    std::vector<WorkItem> work, persim;
+    std::vector<std::pair<int, WorkItem>> costed;
+    std::vector<RedItem> red;
+    for (int i = 0; i < nsim; ++i) {
+        const fpic_config &c = cfgs[i];
+        const SimPlan &s = P.sims[i];
+        const double dV = c.dx[0] * c.dx[1] * c.dx[2];
+        tab.assign(7 * (size_t)s.ndir, 0.0);
+        for (int d = 0; d < s.ndir; ++d) {
+            tab[0 * s.ndir + d] = c.dirs[3 * d + 0];
+            tab[1 * s.ndir + d] = c.dirs[3 * d + 1];
+            tab[2 * s.ndir + d] = c.dirs[3 * d + 2];
+            tab[3 * s.ndir + d] = c.N[d] / dV;
+            tab[4 * s.ndir + d] = c.Nbar[d] / dV;
+            tab[5 * s.ndir + d] = c.N[d];
+            tab[6 * s.ndir + d] = c.Nbar[d];
+        }
+        hipError_t e = hipMemcpy(b->ws + s.o_tab, tab.data(), sizeof(double) * tab.size(),
+                                 hipMemcpyHostToDevice);
+        if (e != hipSuccess)
+            return cleanup(fail(FPIC_EHIP, std::string("upload tables: ") + hipGetErrorString(e)));
+        SimDesc &D = b->hdesc[i];
+        std::memset(&D, 0, sizeof D);
+        D.ncell = s.ncell;
+        D.ndir = s.ndir;
+        D.ntile = s.ntile;
+        D.ngroup = s.ngroup;
+        D.dpw = s.dpw;
+        D.dpg = s.dpw * P.waves;
+        D.np = s.np;
+        D.dt = c.dt;
+        D.dz = c.dx[2];
+        // packed upper triangle of hvac
+        const double *h = c.hvac;
+        const double hv[9] = {h[0], h[8], h[16], h[2], h[3], h[4], h[5], h[10], h[11]};
+        for (int k = 0; k < 9; ++k)
+            D.hvac[k] = hv[k];
+        const double *tb = reinterpret_cast<const double *>(b->ws + s.o_tab);
+        D.vx = tb;
+        D.vy = tb + s.ndir;
+        D.vz = tb + 2 * s.ndir;
+        D.wN = tb + 3 * s.ndir;
+        D.wNb = tb + 4 * s.ndir;
+        D.Nw = tb + 5 * s.ndir;
+        D.Nbw = tb + 6 * s.ndir;
+        D.Y = reinterpret_cast<double *>(b->ws + s.o_Y);
+        D.K1 = reinterpret_cast<double *>(b->ws + s.o_K1);
+        D.K2 = reinterpret_cast<double *>(b->ws + s.o_K2);
+        D.K3 = reinterpret_cast<double *>(b->ws + s.o_K3);
+        D.G0 = reinterpret_cast<double *>(b->ws + s.o_G0);
+        D.G1 = reinterpret_cast<double *>(b->ws + s.o_G1);
+        D.part = reinterpret_cast<double *>(b->ws + s.o_part);
+        D.edge = reinterpret_cast<double *>(b->ws + s.o_edge);
+        D.red = b->dscratch;
+        D.step = reinterpret_cast<int64_t *>(b->ws + s.o_step);
+
+        b->swork_off.push_back((int)persim.size());
+        b->sred_off.push_back((int)red.size());
+        const int dpg = D.dpg;
+        for (int t = 0; t < s.ntile; ++t) {
+            for (int g = 0; g < s.ngroup; ++g) {
+                WorkItem w{i, t, g, 0};
+                const int nd = std::min(dpg, s.ndir - g * dpg);
+                persim.push_back(w);
+                costed.push_back({nd, w});
+            }
+            red.push_back(RedItem{i, t});
+        }
+    }
+    // longest work first so the tail of the launch holds the short items
+    std::stable_sort(costed.begin(), costed.end(),
+                     [](const std::pair<int, WorkItem> &a, const std::pair<int, WorkItem> &b2) {
+                         return a.first > b2.first;
+                     });
+    for (auto &cw : costed)
+        work.push_back(cw.second);
+    work.insert(work.end(), persim.begin(), persim.end());
+
+    hipError_t e = hipMemcpy(b->ddesc, b->hdesc.data(), sizeof(SimDesc) * nsim, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(b->dwork, work.data(), sizeof(WorkItem) * work.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(b->dred, red.data(), sizeof(RedItem) * red.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipHostMalloc(reinterpret_cast<void **>(&b->hbuf), sizeof(double) * 64, hipHostMallocDefault);
+    if (e == hipSuccess)
+        e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+    if (e != hipSuccess)
+        return cleanup(fail(FPIC_EHIP, std::string("create: ") + hipGetErrorString(e)));
+    for (int i = 0; i < nsim; ++i)
+        b->swork_off[i] += P.nwork;
+
+    rc = capture_steps(b, 1, &b->g1);
+    if (!rc && P.spg > 1)
+        rc = capture_steps(b, P.spg, &b->gK);
+    if (rc)
+        return cleanup(rc);
+    *out = b;
+    return FPIC_OK;
+}
+
+int sim_work(fpic_batch *b, int sim, int *off, int *n, int *roff, int *rn)
+{
+    const SimPlan &s = b->plan.sims[sim];
+    *off = b->swork_off[sim];
+    *n = s.ntile * s.ngroup;
+    *roff = b->sred_off[sim];
+    *rn = s.ntile;
+    return 0;
+}
+
+int batch_set_state(fpic_batch *b, int sim, const double *state, int64_t step0)
+{
+    if (!b || sim < 0 || sim >= b->plan.nsim || !state)
+        return fail(FPIC_EINVAL, "set_state: bad batch, simulation index or state pointer");
+    const SimPlan &s = b->plan.sims[sim];
+    const SimDesc &D = b->hdesc[sim];
+    HIPCHECK(hipMemcpyAsync(D.Y, state, sizeof(double) * 18 * s.np, hipMemcpyDeviceToDevice, b->stream));
+    HIPCHECK(launch_set_step(b->ddesc, sim, sim + 1, step0, b->stream));
+    int off, n, roff, rn;
+    sim_work(b, sim, &off, &n, &roff, &rn);
+    HIPCHECK(launch_stage1d(M_DEPOSIT, b->dwork + off, n, b->ddesc, b->plan.waves, b->plan.max_dpw,
+                            b->stream));
+    HIPCHECK(launch_reduce1d(b->dred + roff, rn, b->ddesc, 0, nullptr, 0, b->stream));
+    b->state_set[sim] = true;
+    return FPIC_OK;
+}
+
+int batch_step(fpic_batch *b, int64_t nsteps)
+{
+    if (!b || nsteps < 0)
+        return fail(FPIC_EINVAL, "step: bad batch or negative step count");
+    for (bool ok : b->state_set)
+        if (!ok)
+            return fail(FPIC_ESTATE, "step before set_state");
+    const int K = b->plan.spg;
+    int64_t left = nsteps;
+    while (K > 1 && left >= K) {
+        HIPCHECK(hipGraphLaunch(b->gK, b->stream));
+        left -= K;
+    }
+    while (left > 0) {
+        HIPCHECK(hipGraphLaunch(b->g1, b->stream));
+        --left;
+    }
+    return FPIC_OK;
+}
+
+int batch_totals(fpic_batch *b, int sim, double *out18)
+{
+    const SimPlan &s = b->plan.sims[sim];
+    const int nblk = (int)std::max<int64_t>(1, std::min<int64_t>(kRedBlocks, (s.np + 255) / 256));
+    HIPCHECK(launch_totals(b->ddesc, sim, nblk, b->dscratch, b->stream));
+    HIPCHECK(hipMemcpyAsync(b->hbuf, b->dscratch, sizeof(double) * 18, hipMemcpyDeviceToHost, b->stream));
+    HIPCHECK(hipStreamSynchronize(b->stream));
+    std::memcpy(out18, b->hbuf, sizeof(double) * 18);
+    return FPIC_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ batch ABI
+extern "C" {
+
+const char *fpic_last_error(void) { return g_err.c_str(); }
+
+int fpic_batch_workspace_bytes(int32_t nsim, const fpic_config *cfgs, const fpic_tuning *tune,
+                               size_t *bytes)
+{
+    if (!bytes)
+        return fail(FPIC_EINVAL, "bytes is null");
+    Plan P;
+    int rc = make_plan(nsim, cfgs, tune, P);
+    if (rc)
+        return rc;
+    *bytes = P.total;
+    return FPIC_OK;
+}
+
+int fpic_batch_create(int32_t nsim, const fpic_config *cfgs, const fpic_tuning *tune, void *workspace,
+                      size_t workspace_bytes, fpic_stream stream, fpic_batch **out)
+{
+    return batch_build(nsim, cfgs, tune, workspace, workspace_bytes, stream, out);
+}
+
+int fpic_batch_set_state(fpic_batch *b, int32_t sim, const double *state, int64_t step0)
+{
+    return batch_set_state(b, sim, state, step0);
+}
+
+int fpic_batch_get_state(fpic_batch *b, int32_t sim, double *state)
+{
+    if (!b || sim < 0 || sim >= b->plan.nsim || !state)
+        return fail(FPIC_EINVAL, "get_state: bad batch, simulation index or state pointer");
+    const SimDesc &D = b->hdesc[sim];
+    HIPCHECK(hipMemcpyAsync(state, D.Y, sizeof(double) * 18 * D.np, hipMemcpyDeviceToDevice, b->stream));
+    return FPIC_OK;
+}
+
+int fpic_batch_step(fpic_batch *b, int64_t nsteps) { return batch_step(b, nsteps); }
+
+int fpic_batch_flavor_totals(fpic_batch *b, double *out)
+{
+    if (!b || !out)
+        return fail(FPIC_EINVAL, "flavor_totals: null argument");
+    for (int i = 0; i < b->plan.nsim; ++i) {
+        int rc = batch_totals(b, i, out + 18 * (size_t)i);
+        if (rc)
+            return rc;
+    }
+    return FPIC_OK;
+}
+
+int fpic_batch_sync(fpic_batch *b)
+{
+    if (!b)
+        return fail(FPIC_EINVAL, "null batch");
+    HIPCHECK(hipStreamSynchronize(b->stream));
+    return FPIC_OK;
+}
+
+void fpic_batch_destroy(fpic_batch *b)
+{
+    if (!b)
+        return;
+    if (b->stream)
+        (void)hipStreamSynchronize(b->stream);
+    if (b->g1)
+        (void)hipGraphExecDestroy(b->g1);
+    if (b->gK)
+        (void)hipGraphExecDestroy(b->gK);
+    if (b->cap)
+        (void)hipStreamDestroy(b->cap);
+    if (b->hbuf)
+        (void)hipHostFree(b->hbuf);
+    delete b;
+}
+
+// ------------------------------------------------------------ single-box ABI
+int fpic_workspace_bytes(const fpic_config *cfg, const fpic_tuning *tune, size_t *bytes)
+{
+    if (!cfg || !bytes)
+        return fail(FPIC_EINVAL, "null argument");
+    if (!is_1d(*cfg))
+        return fpic3d::workspace_bytes(*cfg, tune, bytes);
+    return fpic_batch_workspace_bytes(1, cfg, tune, bytes);
+}
+
+int fpic_create(const fpic_config *cfg, const fpic_tuning *tune, void *workspace, size_t bytes,
+                fpic_stream stream, fpic_ctx **out)
+{
+    if (!cfg || !out)
+        return fail(FPIC_EINVAL, "null argument");
+    *out = nullptr;
+    fpic_ctx *c = new fpic_ctx();
+    int rc;
+    if (is_1d(*cfg))
+        rc = batch_build(1, cfg, tune, workspace, bytes, stream, &c->b);
+    else
+        rc = fpic3d::create(*cfg, tune, workspace, bytes, stream, &c->c3);
+    if (rc) {
+        delete c;
+        return rc;
+    }
+    *out = c;
+    return FPIC_OK;
+}
+
+int fpic_set_state(fpic_ctx *c, const double *state, int64_t step0)
+{
+    if (!c)
+        return fail(FPIC_EINVAL, "null context");
+    if (c->c3)
+        return fpic3d::set_state(c->c3, state, step0);
+    return batch_set_state(c->b, 0, state, step0);
+}
+
+int fpic_get_state(fpic_ctx *c, double *state)
+{
+    if (!c)
+        return fail(FPIC_EINVAL, "null context");
+    if (c->c3)
+        return fpic3d::get_state(c->c3, state);
+    return fpic_batch_get_state(c->b, 0, state);
+}
+
+int fpic_step(fpic_ctx *c, int64_t nsteps)
+{
+    if (!c)
+        return fail(FPIC_EINVAL, "null context");
+    if (c->c3)
+        return fpic3d::step(c->c3, nsteps);
+    return batch_step(c->b, nsteps);
+}
+
+int fpic_moments(fpic_ctx *c, double *out)
+{
+    if (!c || !out)
+        return fail(FPIC_EINVAL, "null argument");
+    if (c->c3)
+        return fpic3d::moments(c->c3, out);
+    fpic_batch *b = c->b;
+    if (!b->state_set[0])
+        return fail(FPIC_ESTATE, "moments before set_state");
+    int off, n, roff, rn;
+    sim_work(b, 0, &off, &n, &roff, &rn);
+    const int nc = b->plan.sims[0].ncell;
+    HIPCHECK(launch_stage1d(M_MOM_NU, b->dwork + off, n, b->ddesc, b->plan.waves, b->plan.max_dpw, b->stream));
+    HIPCHECK(launch_reduce1d(b->dred + roff, rn, b->ddesc, 2, out, 0, b->stream));
+    HIPCHECK(launch_stage1d(M_MOM_NUBAR, b->dwork + off, n, b->ddesc, b->plan.waves, b->plan.max_dpw, b->stream));
+    HIPCHECK(launch_reduce1d(b->dred + roff, rn, b->ddesc, 2, out + (size_t)NG * nc, 0, b->stream));
+    return FPIC_OK;
+}
+
+int fpic_flavor_totals(fpic_ctx *c, double *out)
+{
+    if (!c || !out)
+        return fail(FPIC_EINVAL, "null argument");
+    if (c->c3)
+        return fpic3d::flavor_totals(c->c3, out);
+    if (!c->b->state_set[0])
+        return fail(FPIC_ESTATE, "flavor_totals before set_state");
+    return batch_totals(c->b, 0, out);
+}
+
+int fpic_check(fpic_ctx *c, double tol, double *max_trace_err)
+{
+    if (!c)
+        return fail(FPIC_EINVAL, "null context");
+    double r[3];
+    if (c->c3) {
+        int rc = fpic3d::check(c->c3, r);
+        if (rc)
+            return rc;
+    } else {
+        fpic_batch *b = c->b;
+        if (!b->state_set[0])
+            return fail(FPIC_ESTATE, "check before set_state");
+        const SimPlan &s = b->plan.sims[0];
+        const int nblk = (int)std::max<int64_t>(1, std::min<int64_t>(kRedBlocks, (s.np + 255) / 256));
+        HIPCHECK(launch_check(b->ddesc, 0, nblk, b->dscratch, b->stream));
+        HIPCHECK(hipMemcpyAsync(b->hbuf, b->dscratch, sizeof(double) * 3, hipMemcpyDeviceToHost, b->stream));
+        HIPCHECK(hipStreamSynchronize(b->stream));
+        std::memcpy(r, b->hbuf, sizeof r);
+    }
+    const double e = std::max(r[0], r[1]);
+    if (max_trace_err)
+        *max_trace_err = e;
+    if (r[2] > 0.0)
+        return fail(FPIC_ENUMERIC, "state holds NaN or Inf entries");
+    if (!(e <= tol))
+        return fail(FPIC_ENUMERIC, "trace drift exceeds the tolerance");
+    return FPIC_OK;
+}
+
+int fpic_get_step(fpic_ctx *c, int64_t *step)
+{
+    if (!c || !step)
+        return fail(FPIC_EINVAL, "null argument");
+    if (c->c3)
+        return fpic3d::get_step(c->c3, step);
+    fpic_batch *b = c->b;
+    HIPCHECK(hipMemcpyAsync(b->hbuf, b->hdesc[0].step, sizeof(int64_t), hipMemcpyDeviceToHost, b->stream));
+    HIPCHECK(hipStreamSynchronize(b->stream));
+    std::memcpy(step, b->hbuf, sizeof(int64_t));
+    return FPIC_OK;
+}
+
+int fpic_sync(fpic_ctx *c)
+{
+    if (!c)
+        return fail(FPIC_EINVAL, "null context");
+    if (c->c3)
+        return fpic3d::sync(c->c3);
+    return fpic_batch_sync(c->b);
+}
+
+void fpic_destroy(fpic_ctx *c)
+{
+    if (!c)
+        return;
+    if (c->b)
+        fpic_batch_destroy(c->b);
+    if (c->c3)
+        fpic3d::destroy(c->c3);
+    delete c;
+}
+
+// ------------------------------------------------------------ measurement
+int fpic_profile(fpic_ctx *c, int32_t nsteps, double *ms)
+{
+    if (!c || !ms || nsteps < 1)
+        return fail(FPIC_EINVAL, "profile: bad argument");
+    if (c->c3)
+        return fpic3d::profile(c->c3, nsteps, ms);
+    fpic_batch *b = c->b;
+    if (!b->state_set[0])
+        return fail(FPIC_ESTATE, "profile before set_state");
+    const Plan &P = b->plan;
+    hipEvent_t ev[9];
+    for (auto &e : ev)
+        HIPCHECK(hipEventCreate(&e));
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int rc = FPIC_OK;
+    for (int n = 0; n < nsteps && !rc; ++n) {
+        hipError_t err = hipEventRecord(ev[0], b->stream);
+        for (int st = M_S1; st <= M_S4 && err == hipSuccess; ++st) {
+            err = launch_stage1d(st, b->dwork, P.nwork, b->ddesc, P.waves, P.max_dpw, b->stream);
+            if (err == hipSuccess)
+                err = hipEventRecord(ev[2 * st - 1], b->stream);
+            if (err == hipSuccess)
+                err = launch_reduce1d(b->dred, P.nred, b->ddesc, (st == M_S1 || st == M_S3) ? 1 : 0,
+                                      nullptr, st == M_S4 ? 1 : 0, b->stream);
+            if (err == hipSuccess)
+                err = hipEventRecord(ev[2 * st], b->stream);
+        }
+        if (err == hipSuccess)
+            err = hipEventSynchronize(ev[8]);
+        for (int k = 0; k < 8 && err == hipSuccess; ++k) {
+            float t = 0.f;
+            err = hipEventElapsedTime(&t, ev[k], ev[k + 1]);
+            acc[k] += t;
+        }
+        if (err != hipSuccess)
+            rc = fail(FPIC_EHIP, std::string("profile: ") + hipGetErrorString(err));
+    }
+    for (auto &e : ev)
+        (void)hipEventDestroy(e);
+    for (int k = 0; k < 8; ++k)
+        ms[k] = acc[k] / nsteps;
+    return rc;
+}
+
+// ------------------------------------------------------------- autotuning
+int fpic_autotune(int32_t nsim, const fpic_config *cfgs, void *workspace, size_t bytes,
+                  fpic_stream stream, fpic_tuning *best, double *ms_per_step)
+{
+    if (!best)
+        return fail(FPIC_EINVAL, "best is null");
+    if (nsim == 1 && cfgs && !is_1d(cfgs[0]))
+        return fpic3d::autotune(cfgs[0], workspace, bytes, stream, best, ms_per_step);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double best_ms = 1e300;
+    fpic_tuning bt{};
+    int tried = 0;
+    for (int waves : {1, 2, 4})
+        for (int dpw : {1, 2, 3, 4, 6, 8, 12, 16, 24, 32}) {
+            fpic_tuning t{waves, dpw, 8, 0};
+            Plan P;
+            if (make_plan(nsim, cfgs, &t, P))
+                return fail(FPIC_EINVAL, g_err);
+            if (P.total > bytes)
+                continue;
+            // skip shapes whose partial sums would dwarf the grid
+            bool too_many = false;
+            for (auto &sp : P.sims)
+                if (sp.ngroup > 96)
+                    too_many = true;
+            if (too_many)
+                continue;
+            fpic_batch *b = nullptr;
+            int rc = batch_build(nsim, cfgs, &t, workspace, bytes, stream, &b);
+            if (rc)
+                return rc;
+            for (int i = 0; i < nsim; ++i) {
+                hipError_t e = launch_fill_state(b->ddesc, i, s);
+                if (e != hipSuccess) {
+                    fpic_batch_destroy(b);
+                    return fail(FPIC_EHIP, hipGetErrorString(e));
+                }
+                int off, n, roff, rn;
+                sim_work(b, i, &off, &n, &roff, &rn);
+                (void)launch_stage1d(M_DEPOSIT, b->dwork + off, n, b->ddesc, P.waves, P.max_dpw, s);
+                (void)launch_reduce1d(b->dred + roff, rn, b->ddesc, 0, nullptr, 0, s);
+                b->state_set[i] = true;
+            }
+            hipEvent_t e0, e1;
+            (void)hipEventCreate(&e0);
+            (void)hipEventCreate(&e1);
+            int rc2 = batch_step(b, 8);
+            (void)hipEventRecord(e0, s);
+            const int nrep = 16;
+            if (!rc2)
+                rc2 = batch_step(b, nrep);
+            (void)hipEventRecord(e1, s);
+            hipError_t es = hipEventSynchronize(e1);
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            fpic_batch_destroy(b);
+            if (rc2)
+                return rc2;
+            if (es != hipSuccess)
+                return fail(FPIC_EHIP, hipGetErrorString(es));
+            ++tried;
+            const double per = ms / nrep;
+            if (per < best_ms) {
+                best_ms = per;
+                bt = t;
+            }
+        }
+    if (!tried)
+        return fail(FPIC_EINVAL, "workspace too small for every candidate shape");
+    *best = bt;
+    if (ms_per_step)
+        *ms_per_step = best_ms;
+    return FPIC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,218 @@
+"""Python front end of libflavorpic: Sim (one box) and Batch (many 1D
+boxes).  Torch provides the device workspace and the stream; every step of
+the method runs in the HIP library."""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import HostConfig, check
+
+
+def _stream_ptr(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _dev_ptr(t: torch.Tensor, n: int, device) -> int:
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError("expected a contiguous float64 CUDA tensor")
+    if t.numel() != n:
+        raise ValueError(f"expected {n} elements, got {t.numel()}")
+    if t.device != torch.device(device):
+        raise ValueError("tensor is on another device")
+    return t.data_ptr()
+
+
+class Sim:
+    """One periodic box (1D: ncell = (1, 1, nz); 3D otherwise)."""
+
+    def __init__(self, cfg: HostConfig, tuning: Optional[dict] = None,
+                 device: str = "cuda:0"):
+        lib = _lib.load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("libflavorpic needs a HIP device")
+        self.device = torch.device(device)
+        self.cfg = cfg
+        self.tune = _lib.tuning(tuning)
+        tp = C.byref(self.tune) if self.tune is not None else None
+        nbytes = C.c_size_t()
+        check(lib.fpic_workspace_bytes(C.byref(cfg.c), tp, C.byref(nbytes)))
+        self.nbytes = nbytes.value
+        self.ws = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
+        ctx = C.c_void_p()
+        with torch.cuda.device(self.device):
+            check(lib.fpic_create(C.byref(cfg.c), tp, self.ws.data_ptr(), self.nbytes,
+                                  _stream_ptr(self.device), C.byref(ctx)))
+        self.ctx = ctx
+
+    @classmethod
+    def from_workload(cls, w, hvac=None, tuning=None, device="cuda:0"):
+        return cls(HostConfig.from_workload(w, hvac), tuning, device)
+
+    @property
+    def shape(self):
+        return (18, self.cfg.ndir, self.cfg.ncell_total)
+
+    @property
+    def nparticles(self) -> int:
+        return self.cfg.ndir * self.cfg.ncell_total
+
+    def set_state(self, state, step0: int = 0):
+        if isinstance(state, np.ndarray):
+            state = torch.from_numpy(np.ascontiguousarray(state, dtype=np.float64)).to(self.device)
+        n = int(np.prod(self.shape))
+        check(_lib.load().fpic_set_state(self.ctx, _dev_ptr(state, n, self.device), int(step0)))
+        self._keep = state   # stream-ordered copy: keep the source alive
+
+    def get_state(self) -> torch.Tensor:
+        out = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        check(_lib.load().fpic_get_state(self.ctx, out.data_ptr()))
+        return out
+
+    def step(self, nsteps: int = 1):
+        check(_lib.load().fpic_step(self.ctx, int(nsteps)))
+
+    def moments(self) -> torch.Tensor:
+        out = torch.empty((72, self.cfg.ncell_total), dtype=torch.float64, device=self.device)
+        check(_lib.load().fpic_moments(self.ctx, out.data_ptr()))
+        return out
+
+    def flavor_totals(self) -> np.ndarray:
+        out = np.empty(18)
+        check(_lib.load().fpic_flavor_totals(self.ctx, out.ctypes.data_as(_lib._dp)))
+        return out.reshape(2, 9)
+
+    def check(self, tol: float = 1e-10) -> float:
+        e = C.c_double()
+        check(_lib.load().fpic_check(self.ctx, float(tol), C.byref(e)))
+        return e.value
+
+    def step_index(self) -> int:
+        s = C.c_int64()
+        check(_lib.load().fpic_get_step(self.ctx, C.byref(s)))
+        return s.value
+
+    def sync(self):
+        check(_lib.load().fpic_sync(self.ctx))
+
+    def profile(self, nsteps: int = 10) -> np.ndarray:
+        """Mean ms per launch of [stage1, reduce1, ..., stage4, reduce4],
+        measured with HIP events on the context's stream (advances the
+        state by nsteps)."""
+        out = np.empty(8)
+        check(_lib.load().fpic_profile(self.ctx, int(nsteps), out.ctypes.data_as(_lib._dp)))
+        return out
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            _lib.load().fpic_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many independent 1D boxes advanced together (one launch per stage)."""
+
+    def __init__(self, cfgs: Sequence[HostConfig], tuning: Optional[dict] = None,
+                 device: str = "cuda:0"):
+        lib = _lib.load()
+        self.device = torch.device(device)
+        self.cfgs = list(cfgs)
+        arr = (_lib.Config * len(self.cfgs))(*[c.c for c in self.cfgs])
+        self._arr = arr
+        self.tune = _lib.tuning(tuning)
+        tp = C.byref(self.tune) if self.tune is not None else None
+        nbytes = C.c_size_t()
+        check(lib.fpic_batch_workspace_bytes(len(self.cfgs), arr, tp, C.byref(nbytes)))
+        self.nbytes = nbytes.value
+        self.ws = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
+        b = C.c_void_p()
+        with torch.cuda.device(self.device):
+            check(lib.fpic_batch_create(len(self.cfgs), arr, tp, self.ws.data_ptr(), self.nbytes,
+                                        _stream_ptr(self.device), C.byref(b)))
+        self.b = b
+        self._keep = []
+
+    @property
+    def nsim(self):
+        return len(self.cfgs)
+
+    def shape(self, i):
+        return (18, self.cfgs[i].ndir, self.cfgs[i].ncell_total)
+
+    @property
+    def nparticles(self) -> int:
+        return sum(c.ndir * c.ncell_total for c in self.cfgs)
+
+    def set_state(self, i: int, state, step0: int = 0):
+        if isinstance(state, np.ndarray):
+            state = torch.from_numpy(np.ascontiguousarray(state, dtype=np.float64)).to(self.device)
+        n = int(np.prod(self.shape(i)))
+        check(_lib.load().fpic_batch_set_state(self.b, int(i), _dev_ptr(state, n, self.device),
+                                               int(step0)))
+        self._keep.append(state)
+
+    def get_state(self, i: int) -> torch.Tensor:
+        out = torch.empty(self.shape(i), dtype=torch.float64, device=self.device)
+        check(_lib.load().fpic_batch_get_state(self.b, int(i), out.data_ptr()))
+        return out
+
+    def step(self, nsteps: int = 1):
+        check(_lib.load().fpic_batch_step(self.b, int(nsteps)))
+        self._keep = []
+
+    def flavor_totals(self) -> np.ndarray:
+        out = np.empty(18 * self.nsim)
+        check(_lib.load().fpic_batch_flavor_totals(self.b, out.ctypes.data_as(_lib._dp)))
+        return out.reshape(self.nsim, 2, 9)
+
+    def sync(self):
+        check(_lib.load().fpic_batch_sync(self.b))
+
+    def close(self):
+        if getattr(self, "b", None):
+            _lib.load().fpic_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune(cfgs: Sequence[HostConfig], device: str = "cuda:0", workspace_bytes=None):
+    """Time candidate launch shapes on the device; returns (tuning dict,
+    ms per step)."""
+    lib = _lib.load()
+    dev = torch.device(device)
+    cfgs = list(cfgs)
+    arr = (_lib.Config * len(cfgs))(*[c.c for c in cfgs])
+    if workspace_bytes is None:
+        # the smallest shape (1 wave, 1 direction) needs the most partials
+        t = _lib.Tuning()
+        t.waves, t.dirs_per_wave, t.steps_per_graph = 1, 1, 8
+        nb = C.c_size_t()
+        if len(cfgs) == 1 and cfgs[0].ncell[0] * cfgs[0].ncell[1] > 1:
+            check(lib.fpic_workspace_bytes(C.byref(cfgs[0].c), None, C.byref(nb)))
+            workspace_bytes = nb.value * 2
+        else:
+            check(lib.fpic_batch_workspace_bytes(len(cfgs), arr, C.byref(t), C.byref(nb)))
+            workspace_bytes = nb.value
+    ws = torch.empty(int(workspace_bytes), dtype=torch.uint8, device=dev)
+    best = _lib.Tuning()
+    ms = C.c_double()
+    with torch.cuda.device(dev):
+        check(lib.fpic_autotune(len(cfgs), arr, ws.data_ptr(), int(workspace_bytes),
+                                _stream_ptr(dev), C.byref(best), C.byref(ms)))
+    torch.cuda.synchronize(dev)
+    return best.as_dict(), ms.value

@@ -1,0 +1,115 @@
+"""CPU-side checks of the C ABI: the library loads, exports every symbol the
+header declares, and validates configurations on the host (these calls do
+not touch a device)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2101_02745_amd import _lib, inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fpic.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fpic_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libflavorpic.so not built")
+    return _lib.load()
+
+
+def test_header_declares_the_abi():
+    names = declared_functions()
+    for must in ("fpic_create", "fpic_set_state", "fpic_step", "fpic_moments",
+                 "fpic_flavor_totals", "fpic_batch_step", "fpic_autotune"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    # and the binding covers the same set
+    assert set(_lib.EXPORTS) == set(declared_functions())
+
+
+def cfg_of(**kw):
+    w = I.workload("1d_32x26")
+    hc = _lib.HostConfig.from_workload(w)
+    for k, v in kw.items():
+        if k == "dt":
+            hc.c.dt = v
+        elif k == "shape_order":
+            hc.c.shape_order = v
+        elif k == "hvac":
+            hc.c.hvac[:] = v
+        elif k == "dirs":
+            hc.dirs[:] = v
+        elif k == "ncell":
+            hc.c.ncell[:] = v
+    return hc
+
+
+def ws_bytes(lib, hc, tune=None):
+    n = C.c_size_t()
+    t = _lib.tuning(tune)
+    rc = lib.fpic_workspace_bytes(C.byref(hc.c), C.byref(t) if t else None, C.byref(n))
+    return rc, n.value
+
+
+def test_workspace_size_is_consistent(lib):
+    hc = cfg_of()
+    rc, n = ws_bytes(lib, hc)
+    assert rc == 0
+    P = 26 * 32
+    assert n >= 4 * 18 * 8 * P          # state + three slopes
+    assert n < 64 * 18 * 8 * P + (1 << 20)
+    rc2, n2 = ws_bytes(lib, hc, {"waves": 1, "dirs_per_wave": 1})
+    assert rc2 == 0 and n2 > n          # more direction groups, more partials
+
+
+@pytest.mark.parametrize("kw,code", [
+    ({"dt": 5.0}, _lib.FPIC_EUNSUPPORTED),       # crosses a cell per stage
+    ({"dt": -0.1}, _lib.FPIC_EINVAL),
+    ({"dt": float("nan")}, _lib.FPIC_EINVAL),
+    ({"shape_order": 2}, _lib.FPIC_EUNSUPPORTED),
+    ({"hvac": [0.0, 1.0] + [0.0] * 16}, _lib.FPIC_EINVAL),   # not Hermitian
+    ({"dirs": 2.0}, _lib.FPIC_EINVAL),           # not unit vectors
+    ({"ncell": [1, 1, 0]}, _lib.FPIC_EINVAL),
+])
+def test_bad_configs_rejected(lib, kw, code):
+    hc = cfg_of(**kw)
+    rc, _ = ws_bytes(lib, hc)
+    assert rc == code
+    assert len(lib.fpic_last_error()) > 0
+
+
+def test_bad_tuning_rejected(lib):
+    hc = cfg_of()
+    rc, _ = ws_bytes(lib, hc, {"waves": 3})
+    assert rc == _lib.FPIC_EINVAL
+    rc, _ = ws_bytes(lib, hc, {"steps_per_graph": 1000})
+    assert rc == _lib.FPIC_EINVAL
+
+
+def test_batch_rejects_3d(lib):
+    hc = cfg_of(ncell=[2, 2, 2])
+    arr = (_lib.Config * 1)(hc.c)
+    n = C.c_size_t()
+    assert lib.fpic_batch_workspace_bytes(1, arr, None, C.byref(n)) == _lib.FPIC_EINVAL
+
+
+def test_null_arguments(lib):
+    n = C.c_size_t()
+    assert lib.fpic_workspace_bytes(None, None, C.byref(n)) == _lib.FPIC_EINVAL
+    assert lib.fpic_step(None, 1) == _lib.FPIC_EINVAL
+    assert lib.fpic_sync(None) == _lib.FPIC_EINVAL
+    lib.fpic_destroy(None)          # no-op

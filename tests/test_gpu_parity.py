@@ -1,0 +1,237 @@
+"""Parity of the HIP path with the CPU FP64 reference on identical seeded
+inputs (the library is called through its C ABI via the ctypes binding).
+
+Error metric: normwise per field class, e = max|x_gpu - x_ref| / max|x_ref|,
+separately for the diagonal and the off-diagonal (complex magnitude) parts of
+rho and rhobar; entries that are exactly zero in the reference must be
+exactly zero.  The deposit is fixed-order (no atomics), so the bar is 1e-12
+up to the horizon where the reference's own sensitivity to a one-ulp change
+stays below it.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import Problem
+from paper_2101_02745_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    return torch
+
+
+def field_errors(got, ref):
+    got = np.asarray(got).reshape(18, -1)
+    ref = np.asarray(ref).reshape(18, -1)
+    zero = ref == 0.0
+    assert np.all(got[zero] == 0.0), "entries exactly zero in the reference are not zero"
+    out = {}
+    for name, b in (("rho", 0), ("rhobar", 9)):
+        dr, dg = ref[b:b + 3], got[b:b + 3]
+        out[name + "_diag"] = np.abs(dg - dr).max() / max(np.abs(dr).max(), 1e-300)
+        off_r = np.stack([ref[b + 3] + 1j * ref[b + 4], ref[b + 5] + 1j * ref[b + 6],
+                          ref[b + 7] + 1j * ref[b + 8]])
+        off_g = np.stack([got[b + 3] + 1j * got[b + 4], got[b + 5] + 1j * got[b + 6],
+                          got[b + 7] + 1j * got[b + 8]])
+        scale = np.abs(off_r).max()
+        out[name + "_off"] = (np.abs(off_g - off_r).max() / scale) if scale > 0 else np.abs(off_g).max()
+    return out
+
+
+def assert_parity(got, ref, tol=TOL, what=""):
+    e = field_errors(got, ref)
+    worst = max(e.values())
+    assert worst <= tol, f"{what}: {e}"
+    return worst
+
+
+def make(w, hvac=None, tuning=None):
+    from paper_2101_02745_amd.sim import Sim
+    return Sim.from_workload(w, hvac=hvac, tuning=tuning), Problem.from_workload(w, hvac=hvac)
+
+
+def run_pair(w, nsteps, hvac=None, tuning=None, step0=0):
+    sim, P = make(w, hvac, tuning)
+    s0 = w.state0()
+    sim.set_state(s0, step0)
+    sim.step(nsteps)
+    got = sim.get_state().cpu().numpy()
+    ref = P.step(s0, nsteps, n0=step0)
+    return sim, P, got, ref
+
+
+def test_one_step_1d_32x26(torch_dev):
+    w = I.workload("1d_32x26")
+    _, _, got, ref = run_pair(w, 1)
+    assert_parity(got, ref, what="one step")
+
+
+def test_full_run_1d_32x26(torch_dev):
+    """All 200 steps of the 32-cell, 26-direction box: the reference's own
+    one-ulp sensitivity stays below 1e-13 over this horizon."""
+    w = I.workload("1d_32x26")
+    sim, P = make(w)
+    s0 = w.state0()
+    sim.set_state(s0)
+    ref = s0
+    for k in range(4):
+        sim.step(50)
+        ref = P.step(ref, 50, n0=50 * k)
+        assert_parity(sim.get_state().cpu().numpy(), ref, what=f"after {50 * (k + 1)} steps")
+    assert sim.step_index() == 200
+
+
+@pytest.mark.parametrize("ncell,ndir", [(1, 26), (2, 6), (63, 26), (64, 26), (65, 26),
+                                        (130, 8), (200, 378), (333, 128)])
+def test_ragged_shapes(torch_dev, ncell, ndir):
+    w = I.Workload(name="r", ncell=(1, 1, ncell), length=(1.0, 1.0, 0.2 * ncell),
+                   ndir=ndir, dt=0.1, steps=0, f=0.2, fbar=-0.3, nbar_over_n=0.9,
+                   seed=7, alpha=1e-3)
+    _, _, got, ref = run_pair(w, 6)
+    assert_parity(got, ref, what=f"{ncell}x{ndir}")
+
+
+@pytest.mark.parametrize("tuning", [{"waves": 1, "dirs_per_wave": 1},
+                                    {"waves": 2, "dirs_per_wave": 3},
+                                    {"waves": 4, "dirs_per_wave": 5, "steps_per_graph": 3}])
+def test_launch_shapes(torch_dev, tuning):
+    w = I.scaled(I.workload("1d_2048x378"), ncell=(1, 1, 150), ndir=92)
+    _, _, got, ref = run_pair(w, 7, tuning=tuning)
+    assert_parity(got, ref, what=str(tuning))
+
+
+def test_time_origin(torch_dev):
+    """set_state(step0) puts particles where they are at t = step0 * dt."""
+    w = I.scaled(I.workload("1d_512x128"), ncell=(1, 1, 80), ndir=26)
+    _, _, got, ref = run_pair(w, 5, step0=12345)
+    assert_parity(got, ref, what="step0")
+
+
+def test_moments_totals_check(torch_dev):
+    w = I.Workload(name="m", ncell=(1, 1, 70), length=(1.0, 1.0, 14.0), ndir=26,
+                   dt=0.1, steps=0, f=0.2, fbar=-0.3, nbar_over_n=0.9, seed=3,
+                   alpha=1e-2)
+    sim, P, got, ref = run_pair(w, 9)
+    mom = sim.moments().cpu().numpy()
+    mref = P.moments(ref, 9 * w.dt)
+    assert np.abs(mom - mref).max() <= TOL * np.abs(mref).max()
+    tot = sim.flavor_totals()
+    tref = P.flavor_totals(ref)
+    assert np.abs(tot - tref).max() <= TOL * np.abs(tref).max()
+    err = sim.check(1e-12)
+    assert err < 1e-13
+    assert sim.step_index() == 9
+
+
+def test_check_flags_nan(torch_dev):
+    from paper_2101_02745_amd._lib import FpicError, FPIC_ENUMERIC
+    import torch
+    w = I.Workload(name="n", ncell=(1, 1, 10), length=(1.0, 1.0, 2.0), ndir=6,
+                   dt=0.1, steps=0)
+    sim, _ = make(w)
+    s0 = torch.from_numpy(w.state0()).cuda()
+    s0[3, 2, 4] = float("nan")
+    sim.set_state(s0)
+    with pytest.raises(FpicError) as ei:
+        sim.check(1e-10)
+    assert ei.value.code == FPIC_ENUMERIC
+
+
+def test_deterministic_and_graph_chunking(torch_dev):
+    w = I.scaled(I.workload("1d_2048x378"), ncell=(1, 1, 256), ndir=92)
+    outs = []
+    for chunks in ([13], [8, 5], [1] * 13, [13]):
+        sim, _ = make(w)
+        sim.set_state(w.state0())
+        for c in chunks:
+            sim.step(c)
+        outs.append(sim.get_state().cpu().numpy())
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
+def test_lepton_number_conserved_on_gpu(torch_dev):
+    w = I.Workload(name="l", ncell=(1, 1, 64), length=(1.0, 1.0, 16.0), ndir=26,
+                   dt=0.1, steps=0, f=1 / 3, fbar=-1 / 3, nbar_over_n=0.8, seed=4,
+                   alpha=1e-4, vacuum=False)
+    sim, P = make(w)
+    s0 = w.state0()
+    sim.set_state(s0)
+    t0 = sim.flavor_totals()
+    sim.step(300)
+    t1 = sim.flavor_totals()
+    L0 = t0[0] - t0[1] * np.array([1, 1, 1, 1, -1, 1, -1, 1, -1])
+    L1 = t1[0] - t1[1] * np.array([1, 1, 1, 1, -1, 1, -1, 1, -1])
+    scale = np.abs(P.N).sum() * w.ncell_total
+    assert np.abs(t1[0, 1] - t0[0, 1]) > 1e-2 * scale / w.ncell_total   # flavor moved
+    assert np.abs(L1 - L0).max() < 1e-13 * scale
+
+
+def test_two_beam_growth_on_gpu(torch_dev):
+    """Inhomogeneous two-beam instability (App. A.4) on the HIP path: growth
+    rate 2 mu within the paper's 4.3e-3."""
+    from paper_2101_02745_amd.sim import Sim
+    from paper_2101_02745_amd._lib import HostConfig
+    mu, k, n, dt = 1.0, 2.0, 64, 0.01
+    L = 2 * math.pi / k
+    dz = L / n
+    hc = HostConfig((1, 1, n), (1.0, 1.0, dz), [[0, 0, 1.0], [0, 0, -1.0]],
+                    [mu * dz, 0.0], [0.0, mu * dz], np.zeros((3, 3)), dt)
+    sim = Sim(hc)
+    z0 = (np.arange(n) + 0.5) * dz
+    st = np.zeros((18, 2, n))
+    st[3] = st[12] = 1e-9 * np.sin(k * z0)
+    st[1], st[10] = st[3] ** 2, st[12] ** 2
+    st[0], st[9] = 1 - st[1], 1 - st[10]
+    sim.set_state(st)
+    amps = []
+    for nsteps in (200, 400):
+        sim.step(nsteps)
+        s = sim.get_state().cpu().numpy()
+        t = sim.step_index() * dt
+        S = s[3, 0] + 1j * s[4, 0]
+        amps.append(abs(np.sum(S * np.exp(-1j * k * (z0 + t)))) / n)
+    rate = math.log(amps[1] / amps[0]) / (400 * dt)
+    assert abs(rate - 2 * mu) / (2 * mu) < 4.3e-3, rate
+
+
+def test_full_size_1d_2048x378(torch_dev):
+    """The benchmark's workload at full size (774,144 particles) in the
+    benchmark's launch shape: every output of two steps against the
+    reference."""
+    w = I.workload("1d_2048x378")
+    _, _, got, ref = run_pair(w, 2)
+    assert_parity(got, ref, what="2048x378")
+
+
+def test_batch_matches_single_runs(torch_dev):
+    from paper_2101_02745_amd.sim import Batch, Sim
+    from paper_2101_02745_amd._lib import HostConfig
+    ws = I.batch_workloads(nsim=5, steps=0)
+    ws = [I.scaled(w, ncell=(1, 1, 64 + 37 * i), ndir=w.ndir if w.ndir < 378 else 92)
+          for i, w in enumerate(ws)]
+    tune = {"waves": 2, "dirs_per_wave": 4, "steps_per_graph": 4}
+    b = Batch([HostConfig.from_workload(w) for w in ws], tuning=tune)
+    for i, w in enumerate(ws):
+        b.set_state(i, w.state0())
+    b.step(10)
+    tots = b.flavor_totals()
+    for i, w in enumerate(ws):
+        got = b.get_state(i).cpu().numpy()
+        single = Sim.from_workload(w, tuning=tune)
+        single.set_state(w.state0())
+        single.step(10)
+        assert np.array_equal(got, single.get_state().cpu().numpy())
+        ref = Problem.from_workload(w).step(w.state0(), 10)
+        assert_parity(got, ref, what=f"batch sim {i}")
+        tref = Problem.from_workload(w).flavor_totals(ref)
+        assert np.abs(tots[i] - tref).max() <= TOL * np.abs(tref).max()
