@@ -78,8 +78,23 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="1d_2048x378")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
-    ap.add_argument("--tuning", default="", help="JSON launch shape (default: built-in)")
+    ap.add_argument("--tuning", default="",
+                    help="JSON launch shape; default: autotune on the device first")
+    ap.add_argument("--probe", default="", choices=["", "copy", "kernels"],
+                    help="counter-collection modes: 'copy' runs a plain 1 GiB device copy "
+                         "(the reference for HBM byte counters); 'kernels' runs 5 steps "
+                         "with every kernel launched on its own, then exits")
     args = ap.parse_args()
+    if args.probe == "copy":
+        import torch
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")   # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"probe": "copy", "bytes_read": src.numel() * 8,
+                          "bytes_written": dst.numel() * 8, "launches": 5}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the multi-GPU decomposition is a design note, not built)", file=sys.stderr)
@@ -91,10 +106,23 @@ def main():
     from paper_2101_02745_amd.sim import Sim
 
     w = I.workload(args.workload)
-    tuning = json.loads(args.tuning) if args.tuning else None
+    tune_ms = None
+    if args.tuning:
+        tuning = json.loads(args.tuning)
+    else:
+        from paper_2101_02745_amd._lib import HostConfig
+        from paper_2101_02745_amd.sim import autotune
+        tuning, tune_ms = autotune([HostConfig.from_workload(w)])
+        print(f"[bench] autotuned launch shape {tuning} ({tune_ms:.4f} ms/step)",
+              file=sys.stderr, flush=True)
     sim = Sim.from_workload(w, tuning=tuning)
     sim.set_state(w.state0())
     torch.cuda.synchronize()
+    if args.probe == "kernels":
+        ms = sim.profile(5)
+        print(json.dumps({"probe": "kernels", "workload": w.name, "ms": list(ms),
+                          "tuning": sim.tune.as_dict() if sim.tune else None}), flush=True)
+        return
     print(f"[bench] {w.name}: {w.nparticles} particles, warmup {args.warmup} steps",
           file=sys.stderr, flush=True)
     sim.step(args.warmup)
@@ -127,7 +155,8 @@ def main():
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": w.name, "ncell": list(w.ncell), "ndir": w.ndir,
                    "particles": w.nparticles, "dt": w.dt, "shape": "cic",
-                   "integrator": "rk4", "launch": sim.tune.as_dict() if sim.tune else "default"},
+                   "integrator": "rk4", "launch": sim.tune.as_dict() if sim.tune else "default",
+                   "launch_source": "explicit" if args.tuning else "autotuned"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": f"stage1d_kernel<{dom}>",

@@ -56,6 +56,15 @@ __device__ __forceinline__ Shift shift_of(double v, double t, double dx)
     return s;
 }
 
+// Value of the lane one below (lane 0 receives 0): DPP wave_shr:1 on the two
+// 32-bit halves, no LDS traffic.
+__device__ __forceinline__ double lane_below(double x)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), 0x138, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), 0x138, 0xf, 0xf, true);
+    return __hiloint2double(hi, lo);
+}
+
 __device__ __forceinline__ int pmod_i64(int64_t a, int n)
 {
     int64_t r = a % n;
@@ -101,6 +110,25 @@ __device__ __forceinline__ void commutator(const double h[9], const double r[9],
     k[8] = c21r - c12r;
 }
 
+// Global-memory accesses through explicit address-space-1 pointers (the
+// descriptor's pointers are generic, which would otherwise give flat loads).
+typedef __attribute__((address_space(1))) double gdouble;
+__device__ __forceinline__ double gld(const double *p) { return *(const gdouble *)p; }
+__device__ __forceinline__ void gst(double *p, double v) { *(gdouble *)p = v; }
+
+// r = i mod n for an integer-valued double i (|i| < 2^52), without 64-bit
+// integer division.
+__device__ __forceinline__ int pmod_dbl(double i, int n)
+{
+    const double nd = (double)n;
+    double r = i - nd * floor(i / nd);
+    if (r < 0.0)
+        r += nd;
+    if (r >= nd)
+        r -= nd;
+    return (int)r;
+}
+
 template <int MODE>
 __global__ void __launch_bounds__(MAX_WAVES * TILE)
 stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ sims, int max_dpw)
@@ -110,7 +138,7 @@ stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ si
     // private copy: the kernel's stores cannot alias the descriptor
     const SimDesc S = sims[wi.sim];
     const int lane = threadIdx.x & (TILE - 1);
-    const int wave = threadIdx.x / TILE;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / TILE);
     const int nwaves = blockDim.x / TILE;
     const int nc = S.ncell;
     const int64_t np = S.np;
@@ -139,20 +167,40 @@ stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ si
         t_nxt = stage_time(n, dt, 0.0);
     }
 
-    double *Gt = smem;                          // [NG][GT_STRIDE]
-    double *eb = smem + NG * GT_STRIDE + wave * max_dpw * 9;
+    // LDS: [grid tile | reduction] [edge buffers] [per-direction shifts]
+    const int gslot = max(NG * GT_STRIDE, NG * TILE + nwaves * NG);
+    double *Gt = smem;                                   // [NG][GT_STRIDE]
+    double *eb = smem + gslot + wave * max_dpw * 9;      // [dpw][9] of this wave
+    double *tphi = smem + gslot + nwaves * max_dpw * 9;  // [dpg][2]: phi_cur, phi_nxt
+    int *tint = (int *)(tphi + 2 * nwaves * max_dpw);    // [dpg][2]: r, delta
 
+    const int dgrp0 = wi.group * S.dpg;
+    // shifts of the workgroup's directions, one thread per direction
+    for (int j = threadIdx.x; j < S.dpg; j += blockDim.x) {
+        const int d = dgrp0 + j;
+        if (d < S.ndir) {
+            const double vz = S.vz[d];
+            const Shift sn = shift_of(vz, t_nxt, dz);
+            const Shift sc = shift_of(vz, t_cur, dz);
+            tphi[2 * j + 0] = sc.phi;
+            tphi[2 * j + 1] = sn.phi;
+            tint[2 * j + 0] = pmod_dbl((double)sn.i, nc);
+            tint[2 * j + 1] = max(-1, min(1, (int)(sn.i - sc.i)));
+        }
+    }
     if (MODE <= M_S4) {
         // S1 and S3 read G0, S2 and S4 read G1 (ping-pong with the reduce)
         const double *Gin = (MODE == M_S1 || MODE == M_S3) ? S.G0 : S.G1;
         for (int idx = threadIdx.x; idx < NG * GT_CELLS; idx += blockDim.x) {
             const int comp = idx / GT_CELLS;
             const int k = idx - comp * GT_CELLS;
-            const int cell = pmod_i64((int64_t)tile0 - 1 + k, nc);
-            Gt[comp * GT_STRIDE + k] = Gin[(size_t)comp * nc + cell];
+            int cell = tile0 - 1 + k;
+            cell = (cell < 0) ? cell + nc : cell;
+            cell = (nc < GT_CELLS) ? cell % nc : (cell >= nc ? cell - nc : cell);
+            Gt[comp * GT_STRIDE + k] = gld(Gin + (size_t)comp * nc + cell);
         }
-        __syncthreads();
     }
+    __syncthreads();
 
     double hv[9];
 #pragma unroll
@@ -164,14 +212,15 @@ stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ si
     for (int k = 0; k < NG; k++)
         acc[k] = 0.0;
 
-    const int dbeg = wi.group * S.dpg + wave * S.dpw;
+    const int dbeg = dgrp0 + wave * S.dpw;
     const int dend = min(dbeg + S.dpw, S.ndir);
 
     for (int d = dbeg; d < dend; ++d) {
+        const int j = d - dgrp0;
         const double vx = S.vx[d], vy = S.vy[d], vz = S.vz[d];
         const double wN = S.wN[d], wNb = S.wNb[d];
-        const Shift sn = shift_of(vz, t_nxt, dz);
-        const int r = pmod_i64(sn.i, nc);
+        const double ph = tphi[2 * j + 1];
+        const int r = tint[2 * j + 0];
         int c = m - r;
         if (c < 0)
             c += nc;
@@ -182,7 +231,7 @@ stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ si
             double Y[18];
 #pragma unroll
             for (int k = 0; k < 18; k++)
-                Y[k] = S.Y[k * np + p];
+                Y[k] = gld(S.Y + k * np + p);
             if (MODE == M_DEPOSIT) {
 #pragma unroll
                 for (int k = 0; k < 9; k++)
@@ -198,11 +247,8 @@ stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ si
                     X[k] = wNb * Y[9 + k];
             } else {
                 // interpolate the staged grid at the current position
-                const Shift sc = shift_of(vz, t_cur, dz);
-                int delta = (int)(sn.i - sc.i);
-                delta = max(-1, min(1, delta));
-                const int kl = lane - delta + 1;  // LDS column of cell m - delta
-                const double phi = sc.phi, omp = 1.0 - phi;
+                const int kl = lane - tint[2 * j + 1] + 1;  // LDS column of cell m - delta
+                const double phi = tphi[2 * j + 0], omp = 1.0 - phi;
                 double Hnn[9];
 #pragma unroll
                 for (int k = 0; k < 9; k++) {
@@ -213,13 +259,32 @@ stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ si
                     const double Bz = omp * g[27 * GT_STRIDE] + phi * g[27 * GT_STRIDE + 1];
                     Hnn[k] = A - (vx * Bx + vy * By + vz * Bz);
                 }
-                // stage state
-                const double *Kp = (MODE == M_S2) ? S.K1 : (MODE == M_S3) ? S.K2 : S.K3;
-                const double a = (MODE == M_S4) ? dt : 0.5 * dt;
-                double y[18];
+                // stage state y, and the base the next state is built on:
+                // Y for stages 1-3, Y + dt/6 (k1 + 2 k2 + 2 k3) for stage 4
+                // (the slopes are consumed before the commutators)
+                double y[18], base[18];
+                if (MODE == M_S1) {
 #pragma unroll
-                for (int k = 0; k < 18; k++)
-                    y[k] = (MODE == M_S1) ? Y[k] : Y[k] + a * Kp[k * np + p];
+                    for (int k = 0; k < 18; k++)
+                        y[k] = base[k] = Y[k];
+                } else if (MODE == M_S4) {
+                    const double h6 = dt / 6.0;
+#pragma unroll
+                    for (int k = 0; k < 18; k++) {
+                        const double k3 = gld(S.K3 + k * np + p);
+                        y[k] = Y[k] + dt * k3;
+                        const double ks = (gld(S.K1 + k * np + p) + 2.0 * gld(S.K2 + k * np + p)) + 2.0 * k3;
+                        base[k] = Y[k] + h6 * ks;
+                    }
+                } else {
+                    const double *Kp = (MODE == M_S2) ? S.K1 : S.K2;
+                    const double a = 0.5 * dt;
+#pragma unroll
+                    for (int k = 0; k < 18; k++) {
+                        y[k] = Y[k] + a * gld(Kp + k * np + p);
+                        base[k] = Y[k];
+                    }
+                }
                 // Hamiltonians: H = Hvac + Hnn, Hbar = (Hvac - Hnn)^*
                 double H[9], Hb[9], kk[18];
 #pragma unroll
@@ -235,18 +300,16 @@ stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ si
                     const double h6 = dt / 6.0;
 #pragma unroll
                     for (int k = 0; k < 18; k++) {
-                        const double s1 = S.K1[k * np + p] + 2.0 * S.K2[k * np + p];
-                        const double s2 = s1 + 2.0 * S.K3[k * np + p];
-                        yn[k] = Y[k] + h6 * (s2 + kk[k]);
-                        S.Y[k * np + p] = yn[k];
+                        yn[k] = base[k] + h6 * kk[k];
+                        gst(S.Y + k * np + p, yn[k]);
                     }
                 } else {
                     double *Ko = (MODE == M_S1) ? S.K1 : (MODE == M_S2) ? S.K2 : S.K3;
                     const double an = (MODE == M_S3) ? dt : 0.5 * dt;
 #pragma unroll
                     for (int k = 0; k < 18; k++) {
-                        Ko[k * np + p] = kk[k];
-                        yn[k] = Y[k] + an * kk[k];
+                        gst(Ko + k * np + p, kk[k]);
+                        yn[k] = base[k] + an * kk[k];
                     }
                 }
 #pragma unroll
@@ -262,10 +325,10 @@ stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ si
 
         // deposit with the next-stage weights: cell m gets (1 - phi') of its
         // own particle and phi' of the particle one lane to the left
-        const double ph = sn.phi, omph = 1.0 - ph;
+        const double omph = 1.0 - ph;
 #pragma unroll
         for (int k = 0; k < 9; k++) {
-            double xl = __shfl_up(X[k], 1, TILE);
+            double xl = lane_below(X[k]);
             xl = (lane == 0) ? 0.0 : xl;
             const double xc = omph * X[k] + ph * xl;
             acc[k] += xc;
@@ -293,7 +356,7 @@ stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ si
     }
     // edge partial of each wave: lanes 0..35 sum their component over the
     // wave's directions
-    double *esum = smem + NG * TILE;  // [nwaves][NG], inside the old tile area
+    double *esum = smem + NG * TILE;  // [nwaves][NG]
     if (lane < NG) {
         const int comp = lane % 9, grp = lane / 9;
         double s = 0.0;
@@ -309,19 +372,20 @@ stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ si
     double *part = S.part + (size_t)wi.group * NG * ntc;
     for (int idx = threadIdx.x; idx < NG * TILE; idx += blockDim.x) {
         const int k = idx / TILE, l = idx - k * TILE;
-        part[(size_t)k * ntc + tile0 + l] = redb[idx];
+        gst(part + (size_t)k * ntc + tile0 + l, redb[idx]);
     }
     if (threadIdx.x < NG) {
         double s = 0.0;
         for (int w = 0; w < nwaves; ++w)
             s += esum[w * NG + threadIdx.x];
-        S.edge[((size_t)wi.group * NG + threadIdx.x) * S.ntile + wi.tile] = s;
+        gst(S.edge + ((size_t)wi.group * NG + threadIdx.x) * S.ntile + wi.tile, s);
     }
 }
 
 // Sum the direction-group partials of one tile in a fixed order and close
 // the periodic box: cell tile*64 also receives the right-edge partial of
-// the previous tile (cell 0 that of the last tile).
+// the previous tile (cell 0 that of the last tile).  Block (item, q) handles
+// components 4q .. 4q+3 of the item's 64 cells, one thread per value.
 __global__ void __launch_bounds__(256)
 reduce1d_kernel(const RedItem *__restrict__ items, const SimDesc *__restrict__ sims, int which,
                 double *override_out, int tick)
@@ -332,20 +396,23 @@ reduce1d_kernel(const RedItem *__restrict__ items, const SimDesc *__restrict__ s
     const int tile0 = it.tile * TILE;
     const int nact = min(TILE, nc - tile0);
     double *out = (which == 0) ? S.G0 : (which == 1) ? S.G1 : override_out;
-    const int tprev = (it.tile + ntile - 1) % ntile;
-    for (int idx = threadIdx.x; idx < NG * TILE; idx += blockDim.x) {
-        const int k = idx / TILE, l = idx - k * TILE;
-        if (l >= nact)
-            continue;
+    const int k = blockIdx.y * 4 + (threadIdx.x >> 6);
+    const int l = threadIdx.x & (TILE - 1);
+    if (l < nact) {
+        const int ng = S.ngroup;
+        const double *pp = S.part + (size_t)k * ntc + tile0 + l;
+        const size_t gstride = (size_t)NG * ntc;
         double s = 0.0;
-        for (int g = 0; g < S.ngroup; ++g)
-            s += S.part[((size_t)g * NG + k) * ntc + tile0 + l];
-        if (l == 0)
-            for (int g = 0; g < S.ngroup; ++g)
+        for (int g = 0; g < ng; ++g)
+            s += pp[g * gstride];
+        if (l == 0) {
+            const int tprev = (it.tile + ntile - 1) % ntile;
+            for (int g = 0; g < ng; ++g)
                 s += S.edge[((size_t)g * NG + k) * ntile + tprev];
+        }
         out[(size_t)k * nc + tile0 + l] = s;
     }
-    if (tick && it.tile == 0 && threadIdx.x == 0)
+    if (tick && it.tile == 0 && blockIdx.y == 0 && threadIdx.x == 0)
         *S.step += 1;
 }
 
@@ -461,8 +528,10 @@ size_t stage1d_smem_bytes(int waves, int max_dpw)
 {
     size_t tile = (size_t)NG * GT_STRIDE;
     size_t red = (size_t)NG * TILE + (size_t)waves * NG;
-    size_t base = tile > red ? tile : red;
-    return (base + (size_t)waves * max_dpw * 9) * sizeof(double);
+    size_t gslot = tile > red ? tile : red;
+    const size_t dpg = (size_t)waves * max_dpw;
+    // grid slot, edge buffers, phi table, (r, delta) table
+    return (gslot + dpg * 9 + dpg * 2) * sizeof(double) + dpg * 2 * sizeof(int);
 }
 
 hipError_t launch_stage1d(int mode, const WorkItem *work, int nwork, const SimDesc *sims,
@@ -486,7 +555,7 @@ hipError_t launch_stage1d(int mode, const WorkItem *work, int nwork, const SimDe
 hipError_t launch_reduce1d(const RedItem *items, int nitems, const SimDesc *sims, int which,
                            double *override_out, int tick, hipStream_t s)
 {
-    reduce1d_kernel<<<dim3(nitems), dim3(256), 0, s>>>(items, sims, which, override_out, tick);
+    reduce1d_kernel<<<dim3(nitems, NG / 4), dim3(256), 0, s>>>(items, sims, which, override_out, tick);
     return hipGetLastError();
 }
 

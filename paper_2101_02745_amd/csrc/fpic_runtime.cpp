@@ -243,6 +243,33 @@ int capture_steps(fpic_batch *b, int nsteps, hipGraphExec_t *exec)
     return FPIC_OK;
 }
 
+// The dispatcher hands workgroup b to XCD b % 8, and each XCD has its own
+// L2.  Place item i of the preferred sequence at launch slot b such that
+// every XCD receives one contiguous run of the sequence.
+constexpr int kXcds = 8;
+void xcd_order(const std::vector<WorkItem> &seq, std::vector<WorkItem> &out)
+{
+    const size_t n = seq.size();
+    out.assign(n, WorkItem{0, 0, 0, 0});
+    const size_t per = n / kXcds, extra = n % kXcds;
+    // XCD x takes items [start_x, start_x + count_x) of seq
+    std::vector<size_t> start(kXcds), count(kXcds);
+    size_t at = 0;
+    for (int x = 0; x < kXcds; ++x) {
+        count[x] = per + ((size_t)x < extra ? 1 : 0);
+        start[x] = at;
+        at += count[x];
+    }
+    std::vector<size_t> used(kXcds, 0);
+    for (size_t b = 0; b < n; ++b) {
+        int x = (int)(b % kXcds);
+        // slots beyond an XCD's share go to the next XCD with items left
+        for (int tries = 0; tries < kXcds && used[x] >= count[x]; ++tries)
+            x = (x + 1) % kXcds;
+        out[b] = seq[start[x] + used[x]++];
+    }
+}
+
 int batch_build(int nsim, const fpic_config *cfgs, const fpic_tuning *tune, void *workspace,
                 size_t bytes, fpic_stream stream, fpic_batch **out)
 {
@@ -345,14 +372,40 @@ int batch_build(int nsim, const fpic_config *cfgs, const fpic_tuning *tune, void
             red.push_back(RedItem{i, t});
         }
     }
-    // longest work first so the tail of the launch holds the short items
+    // Longest work first so the tail of the launch holds the short items;
+    // among equals, direction group outer and tile inner, so neighbouring
+    // tiles of one group (which share cache lines at their edges) are
+    // consecutive.
     std::stable_sort(costed.begin(), costed.end(),
                      [](const std::pair<int, WorkItem> &a, const std::pair<int, WorkItem> &b2) {
-                         return a.first > b2.first;
+                         if (a.first != b2.first)
+                             return a.first > b2.first;
+                         if (a.second.sim != b2.second.sim)
+                             return a.second.sim < b2.second.sim;
+                         if (a.second.group != b2.second.group)
+                             return a.second.group < b2.second.group;
+                         return a.second.tile < b2.second.tile;
                      });
-    for (auto &cw : costed)
-        work.push_back(cw.second);
-    work.insert(work.end(), persim.begin(), persim.end());
+    {
+        std::vector<WorkItem> seq;
+        for (auto &cw : costed)
+            seq.push_back(cw.second);
+        xcd_order(seq, work);
+    }
+    {
+        std::vector<WorkItem> tmp;
+        for (int i = 0; i < nsim; ++i) {
+            // per-simulation tables get the same treatment, simulation by
+            // simulation (each is launched on its own)
+            const SimPlan &s = P.sims[i];
+            std::vector<WorkItem> one;
+            for (int g = 0; g < s.ngroup; ++g)
+                for (int t = 0; t < s.ntile; ++t)
+                    one.push_back(WorkItem{i, t, g, 0});
+            xcd_order(one, tmp);
+            work.insert(work.end(), tmp.begin(), tmp.end());
+        }
+    }
 
     hipError_t e = hipMemcpy(b->ddesc, b->hdesc.data(), sizeof(SimDesc) * nsim, hipMemcpyHostToDevice);
     if (e == hipSuccess)
