@@ -264,6 +264,28 @@ static void interpolate(const moments *grid, const stencil *S, moments *out)
     }
 }
 
+/* Hamiltonians of a particle with direction v from its interpolated
+ * moments (eq. potentials, matter term zero):
+ *   H_nunu = (n - nbar^*) - v.(f - fbar^*),  H = H_vac + H_nunu,
+ *   Hbar = H_vac^* - H_nunu^*  (antineutrino conventions of Sec. II.A). */
+static void hamiltonians(const moments *m, const double *v, cplx Hv[3][3], cplx H[3][3],
+                         cplx Hb[3][3])
+{
+    cplx Hnn[3][3];
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+            cplx h = m->n[i][j] - conj(m->nb[i][j]);
+            for (int a = 0; a < 3; a++)
+                h -= v[a] * (m->f[a][i][j] - conj(m->fb[a][i][j]));
+            Hnn[i][j] = h;
+        }
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+            H[i][j] = Hv[i][j] + Hnn[i][j];
+            Hb[i][j] = conj(Hv[i][j]) - conj(Hnn[i][j]);
+        }
+}
+
 /* Right-hand side of eq. eom for every particle at time t. */
 static void rhs(const oracle_problem *P, const double *state, double t,
                 moments *grid, double *out)
@@ -282,19 +304,8 @@ static void rhs(const oracle_problem *P, const double *state, double t,
         cic_stencil(P, d, c, t, &S);
         moments m;
         interpolate(grid, &S, &m);
-        cplx Hnn[3][3], H[3][3], Hb[3][3];
-        for (int i = 0; i < 3; i++)
-            for (int j = 0; j < 3; j++) {
-                cplx h = m.n[i][j] - conj(m.nb[i][j]);
-                for (int a = 0; a < 3; a++)
-                    h -= v[a] * (m.f[a][i][j] - conj(m.fb[a][i][j]));
-                Hnn[i][j] = h;
-            }
-        for (int i = 0; i < 3; i++)
-            for (int j = 0; j < 3; j++) {
-                H[i][j] = Hv[i][j] + Hnn[i][j];
-                Hb[i][j] = conj(Hv[i][j]) - conj(Hnn[i][j]);
-            }
+        cplx H[3][3], Hb[3][3];
+        hamiltonians(&m, v, Hv, H, Hb);
         cplx rho[3][3], rhob[3][3], k[3][3], kb[3][3];
         unpack(state + p, np, rho);
         unpack(state + 9 * np + p, np, rhob);
@@ -438,5 +449,221 @@ int oracle_flavor_totals(const oracle_problem *P, const double *state, double *o
                 out[9 + k] += P->Nbar[d] * state[(9 + k) * np + p];
             }
         }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* reverse mode (reference adjoint)                                     */
+/* ------------------------------------------------------------------ */
+/* The discrete adjoint of the steps above, derived independently of any
+ * other implementation: every operation's transpose is written out with
+ * full complex matrices.  A real-valued loss L depends on a Hermitian
+ * matrix M through its packed reals m; a matrix cotangent X means
+ * dL = Re Tr(X^dagger dM).  Conversions:
+ *   packed gradient of X:  (Re X_aa, Re X_ab + Re X_ba, Im X_ab - Im X_ba)
+ *   matrix form of a packed cotangent g (used for the slopes):
+ *                          X_aa = g_aa, X_ab = (g_re + i g_im) / 2,
+ *                          X_ba = conj(X_ab). */
+static void packed_to_cotangent(const double *g, int64_t stride, cplx X[3][3])
+{
+    X[0][0] = g[0 * stride];
+    X[1][1] = g[1 * stride];
+    X[2][2] = g[2 * stride];
+    X[0][1] = 0.5 * (g[3 * stride] + I * g[4 * stride]);
+    X[0][2] = 0.5 * (g[5 * stride] + I * g[6 * stride]);
+    X[1][2] = 0.5 * (g[7 * stride] + I * g[8 * stride]);
+    X[1][0] = conj(X[0][1]);
+    X[2][0] = conj(X[0][2]);
+    X[2][1] = conj(X[1][2]);
+}
+
+static void cotangent_to_packed_add(cplx X[3][3], double *g, int64_t stride)
+{
+    g[0 * stride] += creal(X[0][0]);
+    g[1 * stride] += creal(X[1][1]);
+    g[2 * stride] += creal(X[2][2]);
+    g[3 * stride] += creal(X[0][1]) + creal(X[1][0]);
+    g[4 * stride] += cimag(X[0][1]) - cimag(X[1][0]);
+    g[5 * stride] += creal(X[0][2]) + creal(X[2][0]);
+    g[6 * stride] += cimag(X[0][2]) - cimag(X[2][0]);
+    g[7 * stride] += creal(X[1][2]) + creal(X[2][1]);
+    g[8 * stride] += cimag(X[1][2]) - cimag(X[2][1]);
+}
+
+/* VJP of the right-hand side at (t, y): given g = dL/dk (state-shaped),
+ * add dL/dy into gy and dL/dN, dL/dNbar into gN, gNb. */
+static void rhs_vjp(const oracle_problem *P, const double *y, double t, const double *g,
+                    moments *grid, moments *cot, double *gy, double *gN, double *gNb)
+{
+    const int64_t nc = ncell_total(P), nd = P->ndir, np = nc * nd;
+    const double dV = P->dx[0] * P->dx[1] * P->dx[2];
+    cplx Hv[3][3];
+    load_hvac(P, Hv);
+    deposit(P, y, t, grid);
+    memset(cot, 0, sizeof(moments) * (size_t)nc);
+    /* commutators, Hamiltonians and the transpose of the interpolation */
+    for (int64_t p = 0; p < np; p++) {
+        const int64_t d = p / nc, c = p % nc;
+        const double *v = P->dirs + 3 * d;
+        stencil S;
+        cic_stencil(P, d, c, t, &S);
+        moments m;
+        interpolate(grid, &S, &m);
+        cplx H[3][3], Hb[3][3];
+        hamiltonians(&m, v, Hv, H, Hb);
+        cplx rho[3][3], rhob[3][3], Gc[3][3], Gb[3][3];
+        unpack(y + p, np, rho);
+        unpack(y + 9 * np + p, np, rhob);
+        packed_to_cotangent(g + p, np, Gc);
+        packed_to_cotangent(g + 9 * np + p, np, Gb);
+        /* k = -i[H, rho]:  cot(rho) = -i[G, H],  cot(H) = -i[rho, G] */
+        cplx Xr[3][3], Xh[3][3], Xrb[3][3], Xhb[3][3];
+        commutator_rhs(Gc, H, Xr);
+        commutator_rhs(rho, Gc, Xh);
+        commutator_rhs(Gb, Hb, Xrb);
+        commutator_rhs(rhob, Gb, Xhb);
+        cotangent_to_packed_add(Xr, gy + p, np);
+        cotangent_to_packed_add(Xrb, gy + 9 * np + p, np);
+        /* H = Hv + Hnn, Hbar = Hv^* - Hnn^*: cot(Hnn) = Xh - conj(Xhb) */
+        cplx Xn[3][3];
+        for (int i = 0; i < 3; i++)
+            for (int j = 0; j < 3; j++)
+                Xn[i][j] = Xh[i][j] - conj(Xhb[i][j]);
+        /* Hnn = n - nb^* - sum_a v_a (f_a - fb_a^*), then the interpolation
+         * transposed onto the cells */
+        for (int s = 0; s < S.n; s++) {
+            moments *q = cot + S.cell[s];
+            const double w = S.w[s];
+            for (int i = 0; i < 3; i++)
+                for (int j = 0; j < 3; j++) {
+                    q->n[i][j] += w * Xn[i][j];
+                    q->nb[i][j] -= w * conj(Xn[i][j]);
+                    for (int a = 0; a < 3; a++) {
+                        q->f[a][i][j] -= w * v[a] * Xn[i][j];
+                        q->fb[a][i][j] += w * v[a] * conj(Xn[i][j]);
+                    }
+                }
+        }
+    }
+    /* transpose of the deposition: n_j = sum_q w N rho_q / dV etc. */
+    for (int64_t p = 0; p < np; p++) {
+        const int64_t d = p / nc, c = p % nc;
+        const double *v = P->dirs + 3 * d;
+        stencil S;
+        cic_stencil(P, d, c, t, &S);
+        cplx Z[3][3], Zb[3][3];
+        for (int i = 0; i < 3; i++)
+            for (int j = 0; j < 3; j++) {
+                Z[i][j] = 0;
+                Zb[i][j] = 0;
+            }
+        for (int s = 0; s < S.n; s++) {
+            const moments *q = cot + S.cell[s];
+            const double w = S.w[s];
+            for (int i = 0; i < 3; i++)
+                for (int j = 0; j < 3; j++) {
+                    cplx zn = q->n[i][j], zb = q->nb[i][j];
+                    for (int a = 0; a < 3; a++) {
+                        zn += v[a] * q->f[a][i][j];
+                        zb += v[a] * q->fb[a][i][j];
+                    }
+                    Z[i][j] += w * zn / dV;
+                    Zb[i][j] += w * zb / dV;
+                }
+        }
+        cplx rho[3][3], rhob[3][3], XN[3][3], XNb[3][3];
+        unpack(y + p, np, rho);
+        unpack(y + 9 * np + p, np, rhob);
+        double dn = 0.0, dnb = 0.0;
+        for (int i = 0; i < 3; i++)
+            for (int j = 0; j < 3; j++) {
+                XN[i][j] = P->N[d] * Z[i][j];
+                XNb[i][j] = P->Nbar[d] * Zb[i][j];
+                dn += creal(conj(Z[i][j]) * rho[i][j]);
+                dnb += creal(conj(Zb[i][j]) * rhob[i][j]);
+            }
+        cotangent_to_packed_add(XN, gy + p, np);
+        cotangent_to_packed_add(XNb, gy + 9 * np + p, np);
+        gN[d] += dn;
+        gNb[d] += dnb;
+    }
+}
+
+/* Reverse mode of nsteps RK4 steps from step n0 starting at state0: given
+ * lam = dL/d(final state), return dL/d(state0) in lam (in place) and add
+ * dL/dN, dL/dNbar into gN, gNb.  All intermediate states are kept in
+ * memory (small problems only). */
+int oracle_adjoint(const oracle_problem *P, const double *state0, int64_t n0, int64_t nsteps,
+                   double *lam, double *gN, double *gNb)
+{
+    const int64_t nc = ncell_total(P), len = 18 * P->ndir * nc;
+    const double dt = P->dt;
+    double *traj = malloc(sizeof(double) * (size_t)len * (size_t)(nsteps + 1));
+    moments *grid = malloc(sizeof(moments) * (size_t)nc);
+    moments *cot = malloc(sizeof(moments) * (size_t)nc);
+    double *k = malloc(sizeof(double) * (size_t)len * 3);
+    double *ys = malloc(sizeof(double) * (size_t)len * 4);
+    double *gs = malloc(sizeof(double) * (size_t)len);
+    double *ls = malloc(sizeof(double) * (size_t)len);
+    double *lsum = malloc(sizeof(double) * (size_t)len);
+    if (!traj || !grid || !cot || !k || !ys || !gs || !ls || !lsum) {
+        free(traj); free(grid); free(cot); free(k); free(ys); free(gs); free(ls); free(lsum);
+        return -1;
+    }
+    memcpy(traj, state0, sizeof(double) * (size_t)len);
+    for (int64_t s = 0; s < nsteps; s++) {
+        memcpy(traj + (s + 1) * len, traj + s * len, sizeof(double) * (size_t)len);
+        oracle_step(P, traj + (s + 1) * len, n0 + s, 1);
+    }
+    for (int64_t s = nsteps - 1; s >= 0; s--) {
+        const int64_t n = n0 + s;
+        const double *Y = traj + s * len;
+        double *k1 = k, *k2 = k + len, *k3 = k + 2 * len;
+        double *y1 = ys, *y2 = ys + len, *y3 = ys + 2 * len, *y4 = ys + 3 * len;
+        /* recompute the stage states */
+        memcpy(y1, Y, sizeof(double) * (size_t)len);
+        rhs(P, y1, stage_time(n, dt, 0.0), grid, k1);
+        for (int64_t i = 0; i < len; i++)
+            y2[i] = Y[i] + (0.5 * dt) * k1[i];
+        rhs(P, y2, stage_time(n, dt, 0.5), grid, k2);
+        for (int64_t i = 0; i < len; i++)
+            y3[i] = Y[i] + (0.5 * dt) * k2[i];
+        rhs(P, y3, stage_time(n, dt, 0.5), grid, k3);
+        for (int64_t i = 0; i < len; i++)
+            y4[i] = Y[i] + dt * k3[i];
+        /* Y' = Y + dt/6 (k1 + 2 k2 + 2 k3 + k4): walk the stages backwards;
+         * gs = dL/dk_s, ls = dL/dy_s, lsum = dL/dY */
+        memcpy(lsum, lam, sizeof(double) * (size_t)len);
+        /* stage 4 */
+        for (int64_t i = 0; i < len; i++) {
+            gs[i] = (dt / 6.0) * lam[i];
+            ls[i] = 0.0;
+        }
+        rhs_vjp(P, y4, stage_time(n, dt, 1.0), gs, grid, cot, ls, gN, gNb);
+        for (int64_t i = 0; i < len; i++) {
+            lsum[i] += ls[i];
+            gs[i] = (dt / 3.0) * lam[i] + dt * ls[i];
+            ls[i] = 0.0;
+        }
+        /* stage 3 */
+        rhs_vjp(P, y3, stage_time(n, dt, 0.5), gs, grid, cot, ls, gN, gNb);
+        for (int64_t i = 0; i < len; i++) {
+            lsum[i] += ls[i];
+            gs[i] = (dt / 3.0) * lam[i] + (0.5 * dt) * ls[i];
+            ls[i] = 0.0;
+        }
+        /* stage 2 */
+        rhs_vjp(P, y2, stage_time(n, dt, 0.5), gs, grid, cot, ls, gN, gNb);
+        for (int64_t i = 0; i < len; i++) {
+            lsum[i] += ls[i];
+            gs[i] = (dt / 6.0) * lam[i] + (0.5 * dt) * ls[i];
+            ls[i] = 0.0;
+        }
+        /* stage 1 */
+        rhs_vjp(P, y1, stage_time(n, dt, 0.0), gs, grid, cot, ls, gN, gNb);
+        for (int64_t i = 0; i < len; i++)
+            lam[i] = lsum[i] + ls[i];
+    }
+    free(traj); free(grid); free(cot); free(k); free(ys); free(gs); free(ls); free(lsum);
     return 0;
 }

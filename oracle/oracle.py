@@ -42,6 +42,7 @@ def lib():
             "oracle_moments": [P, _dp, C.c_double, _dp],
             "oracle_gather": [P, _dp, C.c_int64, C.c_double, _dp],
             "oracle_flavor_totals": [P, _dp, _dp],
+            "oracle_adjoint": [P, _dp, C.c_int64, C.c_int64, _dp, _dp, _dp],
         }.items():
             fn = getattr(_lib, name)
             fn.argtypes = args
@@ -126,6 +127,19 @@ class Problem:
         out = np.empty((G.shape[0], self.ndir, self.ncell_total))
         lib().oracle_gather(C.byref(self._s), _ptr(G), G.shape[0], float(t), _ptr(out))
         return out
+
+    def adjoint(self, state0: np.ndarray, nsteps: int, dL_dfinal: np.ndarray, n0: int = 0):
+        """Reference reverse mode: returns (dL/dstate0, dL/dN, dL/dNbar) for a
+        loss whose gradient with respect to the state after nsteps steps is
+        dL_dfinal."""
+        s = self._state(state0)
+        lam = self._state(dL_dfinal).copy()
+        gN = np.zeros(self.ndir)
+        gNb = np.zeros(self.ndir)
+        if lib().oracle_adjoint(C.byref(self._s), _ptr(s), int(n0), int(nsteps), _ptr(lam),
+                                _ptr(gN), _ptr(gNb)):
+            raise MemoryError("oracle_adjoint failed")
+        return lam.reshape(18, self.ndir, self.ncell_total), gN, gNb
 
     def flavor_totals(self, state: np.ndarray) -> np.ndarray:
         s = self._state(state)

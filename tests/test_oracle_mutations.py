@@ -21,12 +21,12 @@ MUTANTS = {
                                      "Hb[i][j] = Hv[i][j] - conj(Hnn[i][j]);"),
     "antinu_selfint_sign": ("Hb[i][j] = conj(Hv[i][j]) - conj(Hnn[i][j]);",
                             "Hb[i][j] = conj(Hv[i][j]) + conj(Hnn[i][j]);"),
-    "flux_term_sign": ("h -= v[a] * (m.f[a][i][j] - conj(m.fb[a][i][j]));",
-                       "h += v[a] * (m.f[a][i][j] - conj(m.fb[a][i][j]));"),
-    "flux_term_dropped": ("h -= v[a] * (m.f[a][i][j] - conj(m.fb[a][i][j]));",
+    "flux_term_sign": ("h -= v[a] * (m->f[a][i][j] - conj(m->fb[a][i][j]));",
+                       "h += v[a] * (m->f[a][i][j] - conj(m->fb[a][i][j]));"),
+    "flux_term_dropped": ("h -= v[a] * (m->f[a][i][j] - conj(m->fb[a][i][j]));",
                           "(void)a;"),
-    "nbar_not_conjugated": ("cplx h = m.n[i][j] - conj(m.nb[i][j]);",
-                            "cplx h = m.n[i][j] - m.nb[i][j];"),
+    "nbar_not_conjugated": ("cplx h = m->n[i][j] - conj(m->nb[i][j]);",
+                            "cplx h = m->n[i][j] - m->nb[i][j];"),
     "matmul_transposed": ("s += a[i][k] * b[k][j];", "s += a[k][i] * b[k][j];"),
     "cic_weights_swapped": ("wlo[a] = 1.0 - phi;\n        whi[a] = phi;",
                             "wlo[a] = phi;\n        whi[a] = 1.0 - phi;"),
@@ -41,6 +41,15 @@ MUTANTS = {
     "volume_not_divided": ("g->n[i][j] /= dV;", "g->n[i][j] /= 1.0;"),
     "gather_weight_dropped": ("out->n[i][j] += w * g->n[i][j];",
                               "out->n[i][j] += g->n[i][j];"),
+    # reverse mode
+    "adjoint_rho_cotangent_sign": ("commutator_rhs(Gc, H, Xr);", "commutator_rhs(H, Gc, Xr);"),
+    "adjoint_hbar_not_conjugated": ("Xn[i][j] = Xh[i][j] - conj(Xhb[i][j]);",
+                                    "Xn[i][j] = Xh[i][j] - Xhb[i][j];"),
+    "adjoint_flux_transpose_sign": ("q->f[a][i][j] -= w * v[a] * Xn[i][j];",
+                                    "q->f[a][i][j] += w * v[a] * Xn[i][j];"),
+    "adjoint_volume_dropped": ("Z[i][j] += w * zn / dV;", "Z[i][j] += w * zn;"),
+    "adjoint_stage_coefficient": ("gs[i] = (dt / 3.0) * lam[i] + (0.5 * dt) * ls[i];",
+                                  "gs[i] = (dt / 6.0) * lam[i] + (0.5 * dt) * ls[i];"),
 }
 
 
@@ -59,7 +68,8 @@ def test_pins_catch_mutant(name, tmp_path):
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q",
                         "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle_pins.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_invariants.py")],
+                        os.path.join(ROOT, "tests", "test_oracle_invariants.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_adjoint.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True,
                        timeout=600)
     assert r.returncode != 0, f"no pin caught mutant {name}:\n{r.stdout[-2000:]}"
