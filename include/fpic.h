@@ -161,6 +161,38 @@ int fpic_batch_sync(fpic_batch *b);
 void fpic_batch_destroy(fpic_batch *b);
 
 /* ---------------------------------------------------------------------
+ * Reverse mode (1D boxes).  A hand-written discrete adjoint of the RK4
+ * steps above (deposit, interpolation, Hamiltonians, commutators, stage
+ * updates), with checkpointing: the forward pass stores the state every
+ * ckpt_every steps; the backward pass recomputes each segment (storing its
+ * stage slopes and moment grids) and sweeps it in reverse.  Not in the
+ * paper: it gives d(loss)/d(initial state) and d(loss)/d(weights N, Nbar),
+ * from which the caller forms gradients with respect to the densities,
+ * fluxes and perturbation seeds of the initial condition.
+ * --------------------------------------------------------------------- */
+typedef struct fpic_adjoint_cfg {
+    int64_t nsteps;     /* steps of the forward pass, >= 1 */
+    int32_t ckpt_every; /* steps between stored states, >= 1 */
+    int32_t reserved;
+} fpic_adjoint_cfg;
+
+/* Bytes of extra device workspace the adjoint needs for ctx and acfg. */
+int fpic_adjoint_workspace_bytes(fpic_ctx *ctx, const fpic_adjoint_cfg *acfg, size_t *bytes);
+
+/* Run acfg->nsteps steps from the context's current state (as fpic_step),
+ * storing checkpoints in the adjoint workspace (device, caller-owned,
+ * 256-byte aligned, kept until the backward pass). */
+int fpic_adjoint_forward(fpic_ctx *ctx, const fpic_adjoint_cfg *acfg, void *workspace,
+                         size_t workspace_bytes);
+
+/* SYNC.  Given dL/d(final state) (device [18][ndir][ncell]), write
+ * dL/d(state at the start of fpic_adjoint_forward) (device, same shape),
+ * and dL/dN, dL/dNbar per direction (host [ndir] each).  The context keeps
+ * its final state and step number. */
+int fpic_adjoint_backward(fpic_ctx *ctx, const double *dL_dfinal, double *dL_dstart,
+                          double *dL_dN, double *dL_dNbar);
+
+/* ---------------------------------------------------------------------
  * Autotuning: time candidate launch shapes for cfg on the device (using a
  * scratch workspace of `bytes`, device) and return the fastest in *best
  * (host).  ms_per_step (host, may be NULL) receives its time.  SYNC.

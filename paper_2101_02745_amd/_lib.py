@@ -48,6 +48,10 @@ class Tuning(C.Structure):
                 "steps_per_graph": self.steps_per_graph}
 
 
+class AdjointCfg(C.Structure):
+    _fields_ = [("nsteps", C.c_int64), ("ckpt_every", C.c_int32), ("reserved", C.c_int32)]
+
+
 EXPORTS = {
     # name: (restype, argtypes)
     "fpic_workspace_bytes": (C.c_int, [C.POINTER(Config), C.POINTER(Tuning), C.POINTER(C.c_size_t)]),
@@ -76,6 +80,10 @@ EXPORTS = {
     "fpic_batch_destroy": (None, [C.c_void_p]),
     "fpic_autotune": (C.c_int, [C.c_int32, C.POINTER(Config), C.c_void_p, C.c_size_t, C.c_void_p,
                                 C.POINTER(Tuning), _dp]),
+    "fpic_adjoint_workspace_bytes": (C.c_int, [C.c_void_p, C.POINTER(AdjointCfg),
+                                               C.POINTER(C.c_size_t)]),
+    "fpic_adjoint_forward": (C.c_int, [C.c_void_p, C.POINTER(AdjointCfg), C.c_void_p, C.c_size_t]),
+    "fpic_adjoint_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, _dp, _dp]),
 }
 
 _lib = None

@@ -189,8 +189,7 @@ stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ si
         }
     }
     if (MODE <= M_S4) {
-        // S1 and S3 read G0, S2 and S4 read G1 (ping-pong with the reduce)
-        const double *Gin = (MODE == M_S1 || MODE == M_S3) ? S.G0 : S.G1;
+        const double *Gin = S.G[MODE - 1];
         for (int idx = threadIdx.x; idx < NG * GT_CELLS; idx += blockDim.x) {
             const int comp = idx / GT_CELLS;
             const int k = idx - comp * GT_CELLS;
@@ -301,7 +300,7 @@ stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ si
 #pragma unroll
                     for (int k = 0; k < 18; k++) {
                         yn[k] = base[k] + h6 * kk[k];
-                        gst(S.Y + k * np + p, yn[k]);
+                        gst(S.Yout + k * np + p, yn[k]);
                     }
                 } else {
                     double *Ko = (MODE == M_S1) ? S.K1 : (MODE == M_S2) ? S.K2 : S.K3;
@@ -382,6 +381,263 @@ stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ si
     }
 }
 
+// ---------------------------------------------------------------------------
+// Reverse mode of one Runge-Kutta stage (hand-written adjoint).
+//
+// For stage s with slope k_s = F(t_s, y_s), given g_s = dL/dk_s, the stage
+// adjoint dL/dy_s = F_y^T g_s and the weight gradients F_w^T g_s are
+//   per particle:   G = g with halved off-diagonals (packed cotangent ->
+//                   Hermitian matrix), direct part D = -i[G, H] (off-
+//                   diagonals doubled back), dH = -i[rho, G];
+//                   the same with (Hbar, rhobar); the source
+//                   S = dH - conj-sign * dHbar (cotangent of H_nunu),
+//   deposit:        Gamma_A = sum_p w S_p, Gamma_B = -sum_p w Omega_p S_p
+//                   (the transpose of the interpolation, same weights),
+//   gather:         dX = Gamma_A + Omega . Gamma_B (the transpose of the
+//                   deposition), dL/drho = D + (N/dV) dX,
+//                   dL/drhobar = Dbar - conj-sign (Nbar/dV) dX,
+//                   dL/d(N/dV) += rho . dX, dL/d(Nbar/dV) -= rhobar . dX.
+// Phase 0 forms g_s from the step's lambda and the previous stage's lambda,
+// writes D and deposits S; phase 1 gathers Gamma, writes the stage lambda
+// and accumulates the step's lambda and the weight gradients.  Both phases
+// place particles at t_s (the same weights as the forward pass).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        v += __shfl_xor(v, off, TILE);
+    return v;
+}
+
+template <int PHASE, int STAGE>
+__global__ void __launch_bounds__(MAX_WAVES * TILE)
+adj1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ sims, int max_dpw)
+{
+    extern __shared__ double smem[];
+    const WorkItem wi = work[blockIdx.x];
+    const SimDesc S = sims[wi.sim];
+    const int lane = threadIdx.x & (TILE - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / TILE);
+    const int nwaves = blockDim.x / TILE;
+    const int nc = S.ncell;
+    const int64_t np = S.np;
+    const int tile0 = wi.tile * TILE;
+    const int m = tile0 + lane;
+    const bool active = m < nc;
+    const int nact = min(TILE, nc - tile0);
+    const int64_t n = *S.step;
+    const double dt = S.dt, dz = S.dz;
+    const double cs = (STAGE == 1) ? 0.0 : (STAGE == 4) ? 1.0 : 0.5;
+    const double ts = stage_time(n, dt, cs);
+
+    const int gslot = max(NG * GT_STRIDE, NG * TILE + nwaves * NG);
+    double *Gt = smem;
+    double *eb = smem + gslot + wave * max_dpw * 9;
+    double *tphi = smem + gslot + nwaves * max_dpw * 9;
+    int *tint = (int *)(tphi + 2 * nwaves * max_dpw);
+
+    const int dgrp0 = wi.group * S.dpg;
+    for (int j = threadIdx.x; j < S.dpg; j += blockDim.x) {
+        const int d = dgrp0 + j;
+        if (d < S.ndir) {
+            const Shift sh = shift_of(S.vz[d], ts, dz);
+            tphi[2 * j + 0] = sh.phi;
+            tint[2 * j + 0] = pmod_dbl((double)sh.i, nc);
+        }
+    }
+    {
+        const double *Gin = (PHASE == 0) ? S.G[STAGE - 1] : S.GA;
+        for (int idx = threadIdx.x; idx < NG * GT_CELLS; idx += blockDim.x) {
+            const int comp = idx / GT_CELLS;
+            const int k = idx - comp * GT_CELLS;
+            int cell = tile0 - 1 + k;
+            cell = (cell < 0) ? cell + nc : cell;
+            cell = (nc < GT_CELLS) ? cell % nc : (cell >= nc ? cell - nc : cell);
+            Gt[comp * GT_STRIDE + k] = gld(Gin + (size_t)comp * nc + cell);
+        }
+    }
+    __syncthreads();
+
+    double hv[9];
+#pragma unroll
+    for (int k = 0; k < 9; k++)
+        hv[k] = S.hvac[k];
+    double acc[NG];
+#pragma unroll
+    for (int k = 0; k < NG; k++)
+        acc[k] = 0.0;
+
+    const double *lam_in = S.lam[(n + 1) & 1];
+    double *lam_out = S.lam[n & 1];
+    const double *Kp = (STAGE == 2) ? S.K1 : (STAGE == 3) ? S.K2 : S.K3;
+    const double a = (STAGE == 4) ? dt : 0.5 * dt;
+
+    const int dbeg = dgrp0 + wave * S.dpw;
+    const int dend = min(dbeg + S.dpw, S.ndir);
+    for (int d = dbeg; d < dend; ++d) {
+        const int j = d - dgrp0;
+        const double vx = S.vx[d], vy = S.vy[d], vz = S.vz[d];
+        const double wN = S.wN[d], wNb = S.wNb[d];
+        const double ph = tphi[2 * j + 0], omph = 1.0 - ph;
+        int c = m - tint[2 * j + 0];
+        if (c < 0)
+            c += nc;
+        const int64_t p = (int64_t)d * nc + c;
+
+        // interpolate the staged grid (moments in phase 0, adjoint sources
+        // in phase 1): q = A - Omega.B or A + Omega.B
+        const double bsg = (PHASE == 0) ? -1.0 : 1.0;
+        double q[9];
+#pragma unroll
+        for (int k = 0; k < 9; k++) {
+            const double *g = Gt + k * GT_STRIDE + lane + 1;
+            const double A = omph * g[0] + ph * g[1];
+            const double Bx = omph * g[9 * GT_STRIDE] + ph * g[9 * GT_STRIDE + 1];
+            const double By = omph * g[18 * GT_STRIDE] + ph * g[18 * GT_STRIDE + 1];
+            const double Bz = omph * g[27 * GT_STRIDE] + ph * g[27 * GT_STRIDE + 1];
+            q[k] = A + bsg * (vx * Bx + vy * By + vz * Bz);
+        }
+
+        double X[9];
+        double sN = 0.0, sNb = 0.0;
+        if (active) {
+            double y[18];
+#pragma unroll
+            for (int k = 0; k < 18; k++) {
+                const double Yk = gld(S.Y + k * np + p);
+                y[k] = (STAGE == 1) ? Yk : Yk + a * gld(Kp + k * np + p);
+            }
+            if (PHASE == 0) {
+                // g_s from the step's lambda and the later stage's lambda
+                const double c1 = (STAGE == 1 || STAGE == 4) ? dt / 6.0 : dt / 3.0;
+                const double c2 = (STAGE == 3) ? dt : 0.5 * dt;
+                double G[18];
+#pragma unroll
+                for (int k = 0; k < 18; k++) {
+                    double gk = c1 * gld(lam_in + k * np + p);
+                    if (STAGE < 4)
+                        gk += c2 * gld(S.lcur + k * np + p);
+                    const int kk = k % 9;
+                    G[k] = (kk >= 3) ? 0.5 * gk : gk;
+                }
+                double H[9], Hb[9];
+#pragma unroll
+                for (int k = 0; k < 9; k++) {
+                    H[k] = hv[k] + q[k];
+                    const double hb = hv[k] - q[k];
+                    Hb[k] = (k == 4 || k == 6 || k == 8) ? -hb : hb;
+                }
+                double Dn[9], Db[9], dH[9], dHb[9];
+                commutator(G, H, Dn);
+                commutator(y, G, dH);
+                commutator(G + 9, Hb, Db);
+                commutator(y + 9, G + 9, dHb);
+#pragma unroll
+                for (int k = 0; k < 9; k++) {
+                    const double f = (k >= 3) ? 2.0 : 1.0;
+                    gst(S.dres + k * np + p, f * Dn[k]);
+                    gst(S.dres + (9 + k) * np + p, f * Db[k]);
+                    const double sgn = (k == 4 || k == 6 || k == 8) ? -1.0 : 1.0;
+                    X[k] = f * (dH[k] - sgn * dHb[k]);
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < 9; k++) {
+                    const double sgn = (k == 4 || k == 6 || k == 8) ? -1.0 : 1.0;
+                    const double ln = gld(S.dres + k * np + p) + wN * q[k];
+                    const double lb = gld(S.dres + (9 + k) * np + p) - sgn * wNb * q[k];
+                    gst(S.lcur + k * np + p, ln);
+                    gst(S.lcur + (9 + k) * np + p, lb);
+                    const double base_n = (STAGE == 4) ? gld(lam_in + k * np + p) : gld(lam_out + k * np + p);
+                    const double base_b = (STAGE == 4) ? gld(lam_in + (9 + k) * np + p)
+                                                       : gld(lam_out + (9 + k) * np + p);
+                    gst(lam_out + k * np + p, base_n + ln);
+                    gst(lam_out + (9 + k) * np + p, base_b + lb);
+                    sN += y[k] * q[k];
+                    sNb -= sgn * y[9 + k] * q[k];
+                }
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < 9; k++)
+                X[k] = 0.0;
+        }
+
+        if (PHASE == 0) {
+            // deposit the sources: cell m gets (1 - phi) of its own
+            // particle and phi of the particle one lane to the left
+#pragma unroll
+            for (int k = 0; k < 9; k++) {
+                double xl = lane_below(X[k]);
+                xl = (lane == 0) ? 0.0 : xl;
+                const double xc = omph * X[k] + ph * xl;
+                acc[k] += xc;
+                acc[9 + k] -= vx * xc;
+                acc[18 + k] -= vy * xc;
+                acc[27 + k] -= vz * xc;
+            }
+            if (lane == nact - 1) {
+#pragma unroll
+                for (int k = 0; k < 9; k++)
+                    eb[(d - dbeg) * 9 + k] = ph * X[k];
+            }
+        } else {
+            sN = wave_sum(sN);
+            sNb = wave_sum(sNb);
+            if (lane == 0) {
+                const size_t at = (size_t)d * S.ntile + wi.tile;
+                gst(S.dwN + at, gld(S.dwN + at) + sN);
+                gst(S.dwNb + at, gld(S.dwNb + at) + sNb);
+            }
+        }
+    }
+    if (PHASE == 1)
+        return;
+
+    // ---- workgroup reduction of the deposited sources (as in the stages)
+    __syncthreads();
+    double *redb = smem;
+    for (int w = 0; w < nwaves; ++w) {
+        if (wave == w) {
+#pragma unroll
+            for (int k = 0; k < NG; k++)
+                redb[k * TILE + lane] = (w == 0) ? acc[k] : redb[k * TILE + lane] + acc[k];
+        }
+        __syncthreads();
+    }
+    double *esum = smem + NG * TILE;
+    if (lane < NG) {
+        const int comp = lane % 9, grp = lane / 9;
+        double sacc = 0.0;
+        for (int d = dbeg; d < dend; ++d) {
+            const double coef = (grp == 0) ? 1.0 : (grp == 1) ? -S.vx[d] : (grp == 2) ? -S.vy[d] : -S.vz[d];
+            sacc += coef * eb[(d - dbeg) * 9 + comp];
+        }
+        esum[wave * NG + lane] = sacc;
+    }
+    __syncthreads();
+    const int ntc = S.ntile * TILE;
+    double *part = S.part + (size_t)wi.group * NG * ntc;
+    for (int idx = threadIdx.x; idx < NG * TILE; idx += blockDim.x) {
+        const int k = idx / TILE, l = idx - k * TILE;
+        gst(part + (size_t)k * ntc + tile0 + l, redb[idx]);
+    }
+    if (threadIdx.x < NG) {
+        double sacc = 0.0;
+        for (int w = 0; w < nwaves; ++w)
+            sacc += esum[w * NG + threadIdx.x];
+        gst(S.edge + ((size_t)wi.group * NG + threadIdx.x) * S.ntile + wi.tile, sacc);
+    }
+}
+
+__global__ void fill_kernel(double *p, size_t n, double v)
+{
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        p[i] = v;
+}
+
 // Sum the direction-group partials of one tile in a fixed order and close
 // the periodic box: cell tile*64 also receives the right-edge partial of
 // the previous tile (cell 0 that of the last tile).  Block (item, q) handles
@@ -395,7 +651,7 @@ reduce1d_kernel(const RedItem *__restrict__ items, const SimDesc *__restrict__ s
     const int nc = S.ncell, ntile = S.ntile, ntc = ntile * TILE;
     const int tile0 = it.tile * TILE;
     const int nact = min(TILE, nc - tile0);
-    double *out = (which == 0) ? S.G0 : (which == 1) ? S.G1 : override_out;
+    double *out = (which <= 4) ? S.G[which] : (which == RED_GA) ? S.GA : override_out;
     const int k = blockIdx.y * 4 + (threadIdx.x >> 6);
     const int l = threadIdx.x & (TILE - 1);
     if (l < nact) {
@@ -413,7 +669,25 @@ reduce1d_kernel(const RedItem *__restrict__ items, const SimDesc *__restrict__ s
         out[(size_t)k * nc + tile0 + l] = s;
     }
     if (tick && it.tile == 0 && blockIdx.y == 0 && threadIdx.x == 0)
-        *S.step += 1;
+        *S.step += tick;
+}
+
+__global__ void tick_kernel(const SimDesc *sims, int64_t delta)
+{
+    if (threadIdx.x == 0)
+        *sims[0].step += delta;
+}
+
+// dst[d] = scale * sum_t src[d * ntile + t], fixed order over tiles
+__global__ void tile_sum_kernel(const double *src, int ndir, int ntile, double scale, double *dst)
+{
+    const int d = blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= ndir)
+        return;
+    double s = 0.0;
+    for (int t = 0; t < ntile; ++t)
+        s += src[(size_t)d * ntile + t];
+    dst[d] = scale * s;
 }
 
 __global__ void set_step_kernel(const SimDesc *sims, int lo, int hi, int64_t value)
@@ -556,6 +830,45 @@ hipError_t launch_reduce1d(const RedItem *items, int nitems, const SimDesc *sims
                            double *override_out, int tick, hipStream_t s)
 {
     reduce1d_kernel<<<dim3(nitems, NG / 4), dim3(256), 0, s>>>(items, sims, which, override_out, tick);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj1d(int phase, int stage, const WorkItem *work, int nwork, const SimDesc *sims,
+                        int waves, int max_dpw, hipStream_t s)
+{
+    const dim3 grid(nwork), block(waves * TILE);
+    const size_t smem = stage1d_smem_bytes(waves, max_dpw);
+    const int key = phase * 10 + stage;
+    switch (key) {
+    case 1: adj1d_kernel<0, 1><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
+    case 2: adj1d_kernel<0, 2><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
+    case 3: adj1d_kernel<0, 3><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
+    case 4: adj1d_kernel<0, 4><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
+    case 11: adj1d_kernel<1, 1><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
+    case 12: adj1d_kernel<1, 2><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
+    case 13: adj1d_kernel<1, 3><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
+    case 14: adj1d_kernel<1, 4><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_tick(const SimDesc *sims, int64_t delta, hipStream_t s)
+{
+    tick_kernel<<<1, 64, 0, s>>>(sims, delta);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_sum(const double *src, int ndir, int ntile, double scale, double *dst,
+                           hipStream_t s)
+{
+    tile_sum_kernel<<<(ndir + 255) / 256, 256, 0, s>>>(src, ndir, ntile, scale, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(double *p, size_t n, double v, hipStream_t s)
+{
+    fill_kernel<<<512, 256, 0, s>>>(p, n, v);
     return hipGetLastError();
 }
 

@@ -32,6 +32,10 @@ enum Mode : int {
     M_MOM_NUBAR = 7 // deposit Nbar rhobar alone (moments nbar, fbar)
 };
 
+// reduction targets: 0..4 -> G[which], RED_GA -> GA, RED_OUT -> explicit
+constexpr int RED_GA = 5;
+constexpr int RED_OUT = 6;
+
 // One 1D simulation as the kernels see it.  All pointers are device
 // pointers into the caller's workspace.
 struct SimDesc {
@@ -49,12 +53,22 @@ struct SimDesc {
     const double *wN, *wNb;      // [ndir] N / dV, Nbar / dV
     const double *Nw, *Nbw;      // [ndir] N, Nbar
     double *Y;                   // [18][ndir][ncell] state
+    double *Yout;                // where stage 4 writes the new state (normally Y)
     double *K1, *K2, *K3;        // [18][ndir][ncell] stage slopes
-    double *G0, *G1;             // [36][ncell] deposited moments (ping-pong)
+    // [36][ncell] deposited moments: stage s reads G[s-1]; the reduction
+    // after stage s writes G[s] (G[4] is the next step's G[0]).  A single
+    // box ping-pongs two buffers: {g0, g1, g0, g1, g0}.
+    double *G[5];
     double *part;                // [ngroup][36][ntile*TILE] per-group partials
     double *edge;                // [ngroup][36][ntile] right-edge partials
     double *red;                 // [nred][18] scratch for reductions
     int64_t *step;               // current step number
+    // adjoint (reverse-mode) buffers, null outside the adjoint
+    double *GA;                  // [36][ncell] deposited adjoint sources
+    double *lam[2];              // [18][ndir][ncell] lambda of step n lives in lam[n & 1]
+    double *lcur;                // [18][ndir][ncell] lambda of the latest stage state
+    double *dres;                // [18][ndir][ncell] direct part of a stage adjoint
+    double *dwN, *dwNb;          // [ndir][ntile] gradients w.r.t. N/dV, Nbar/dV
 };
 
 struct WorkItem {
@@ -70,6 +84,14 @@ hipError_t launch_stage1d(int mode, const WorkItem *work, int nwork, const SimDe
                           int waves, int max_dpw, hipStream_t s);
 hipError_t launch_reduce1d(const RedItem *items, int nitems, const SimDesc *sims, int which,
                            double *override_out, int tick, hipStream_t s);
+// adjoint stage kernels: phase 0 = sources and their deposit, phase 1 =
+// gather of the deposited sources and the stage lambda
+hipError_t launch_adj1d(int phase, int stage, const WorkItem *work, int nwork, const SimDesc *sims,
+                        int waves, int max_dpw, hipStream_t s);
+hipError_t launch_fill(double *p, size_t n, double v, hipStream_t s);
+hipError_t launch_tick(const SimDesc *sims, int64_t delta, hipStream_t s);
+hipError_t launch_tile_sum(const double *src, int ndir, int ntile, double scale, double *dst,
+                           hipStream_t s);
 hipError_t launch_set_step(const SimDesc *sims, int sim_lo, int sim_hi, int64_t value,
                            hipStream_t s);
 hipError_t launch_totals(const SimDesc *sims, int sim, int nblk, double *out18, hipStream_t s);

@@ -207,6 +207,17 @@ struct fpic_batch {
     std::vector<int> swork_off, sred_off;
     std::vector<bool> state_set;
     hipGraphExec_t g1 = nullptr, gK = nullptr;
+    double cell_volume = 1.0;      // of simulation 0
+    // reverse mode (single 1D box)
+    struct Adj {
+        bool forward_done = false;
+        int64_t n_start = 0, nsteps = 0;
+        int L = 0, nseg = 0;
+        char *ws = nullptr;
+        size_t o_ckpt = 0, o_segY = 0, o_segK = 0, o_segG = 0, o_lam = 0, o_lcur = 0,
+               o_dres = 0, o_GA = 0, o_dw = 0, o_descF = 0, o_descR = 0, o_out = 0, total = 0;
+        std::vector<std::pair<int, hipGraphExec_t>> recompute, reverse;  // by length
+    } adj;
 };
 
 struct fpic_ctx {
@@ -225,8 +236,7 @@ int capture_steps(fpic_batch *b, int nsteps, hipGraphExec_t *exec)
         for (int st = M_S1; st <= M_S4 && err == hipSuccess; ++st) {
             err = launch_stage1d(st, b->dwork, P.nwork, b->ddesc, P.waves, P.max_dpw, b->cap);
             if (err == hipSuccess)
-                err = launch_reduce1d(b->dred, P.nred, b->ddesc,
-                                      (st == M_S1 || st == M_S3) ? 1 : 0, nullptr,
+                err = launch_reduce1d(b->dred, P.nred, b->ddesc, st, nullptr,
                                       st == M_S4 ? 1 : 0, b->cap);
         }
     hipGraph_t graph = nullptr;
@@ -294,6 +304,7 @@ int batch_build(int nsim, const fpic_config *cfgs, const fpic_tuning *tune, void
     b->dred = reinterpret_cast<RedItem *>(b->ws + P.o_red);
     b->dscratch = reinterpret_cast<double *>(b->ws + P.o_scratch);
     b->state_set.assign(nsim, false);
+    b->cell_volume = cfgs[0].dx[0] * cfgs[0].dx[1] * cfgs[0].dx[2];
 
     auto cleanup = [&](int code) {
         fpic_batch_destroy(b);
@@ -349,11 +360,17 @@ int batch_build(int nsim, const fpic_config *cfgs, const fpic_tuning *tune, void
         D.Nw = tb + 5 * s.ndir;
         D.Nbw = tb + 6 * s.ndir;
         D.Y = reinterpret_cast<double *>(b->ws + s.o_Y);
+        D.Yout = D.Y;
         D.K1 = reinterpret_cast<double *>(b->ws + s.o_K1);
         D.K2 = reinterpret_cast<double *>(b->ws + s.o_K2);
         D.K3 = reinterpret_cast<double *>(b->ws + s.o_K3);
-        D.G0 = reinterpret_cast<double *>(b->ws + s.o_G0);
-        D.G1 = reinterpret_cast<double *>(b->ws + s.o_G1);
+        double *g0 = reinterpret_cast<double *>(b->ws + s.o_G0);
+        double *g1 = reinterpret_cast<double *>(b->ws + s.o_G1);
+        D.G[0] = g0;
+        D.G[1] = g1;
+        D.G[2] = g0;
+        D.G[3] = g1;
+        D.G[4] = g0;
         D.part = reinterpret_cast<double *>(b->ws + s.o_part);
         D.edge = reinterpret_cast<double *>(b->ws + s.o_edge);
         D.red = b->dscratch;
@@ -556,6 +573,10 @@ void fpic_batch_destroy(fpic_batch *b)
         return;
     if (b->stream)
         (void)hipStreamSynchronize(b->stream);
+    for (auto &g : b->adj.recompute)
+        (void)hipGraphExecDestroy(g.second);
+    for (auto &g : b->adj.reverse)
+        (void)hipGraphExecDestroy(g.second);
     if (b->g1)
         (void)hipGraphExecDestroy(b->g1);
     if (b->gK)
@@ -637,9 +658,9 @@ int fpic_moments(fpic_ctx *c, double *out)
     sim_work(b, 0, &off, &n, &roff, &rn);
     const int nc = b->plan.sims[0].ncell;
     HIPCHECK(launch_stage1d(M_MOM_NU, b->dwork + off, n, b->ddesc, b->plan.waves, b->plan.max_dpw, b->stream));
-    HIPCHECK(launch_reduce1d(b->dred + roff, rn, b->ddesc, 2, out, 0, b->stream));
+    HIPCHECK(launch_reduce1d(b->dred + roff, rn, b->ddesc, RED_OUT, out, 0, b->stream));
     HIPCHECK(launch_stage1d(M_MOM_NUBAR, b->dwork + off, n, b->ddesc, b->plan.waves, b->plan.max_dpw, b->stream));
-    HIPCHECK(launch_reduce1d(b->dred + roff, rn, b->ddesc, 2, out + (size_t)NG * nc, 0, b->stream));
+    HIPCHECK(launch_reduce1d(b->dred + roff, rn, b->ddesc, RED_OUT, out + (size_t)NG * nc, 0, b->stream));
     return FPIC_OK;
 }
 
@@ -740,8 +761,8 @@ int fpic_profile(fpic_ctx *c, int32_t nsteps, double *ms)
             if (err == hipSuccess)
                 err = hipEventRecord(ev[2 * st - 1], b->stream);
             if (err == hipSuccess)
-                err = launch_reduce1d(b->dred, P.nred, b->ddesc, (st == M_S1 || st == M_S3) ? 1 : 0,
-                                      nullptr, st == M_S4 ? 1 : 0, b->stream);
+                err = launch_reduce1d(b->dred, P.nred, b->ddesc, st, nullptr,
+                                      st == M_S4 ? 1 : 0, b->stream);
             if (err == hipSuccess)
                 err = hipEventRecord(ev[2 * st], b->stream);
         }
@@ -762,6 +783,286 @@ int fpic_profile(fpic_ctx *c, int32_t nsteps, double *ms)
     return rc;
 }
 
+
+}  // extern "C"
+
+// ------------------------------------------------------------ reverse mode
+namespace {
+
+void adj_layout(const fpic_batch *b, int64_t nsteps, int L, fpic_batch::Adj &A)
+{
+    const SimPlan &s = b->plan.sims[0];
+    const size_t st = sizeof(double) * 18 * (size_t)s.np;
+    const size_t gr = sizeof(double) * NG * (size_t)s.ncell;
+    A.L = L;
+    A.nseg = (int)((nsteps + L - 1) / L);
+    Carver cv;
+    A.o_ckpt = cv.take(st * A.nseg);
+    A.o_segY = cv.take(st * (L + 1));
+    A.o_segK = cv.take(st * 3 * (size_t)L);
+    A.o_segG = cv.take(gr * 4 * (size_t)(L + 1));
+    A.o_lam = cv.take(2 * st);
+    A.o_lcur = cv.take(st);
+    A.o_dres = cv.take(st);
+    A.o_GA = cv.take(gr);
+    A.o_dw = cv.take(sizeof(double) * 2 * (size_t)s.ndir * s.ntile);
+    A.o_descF = cv.take(sizeof(SimDesc) * L);
+    A.o_descR = cv.take(sizeof(SimDesc) * L);
+    A.o_out = cv.take(sizeof(double) * 2 * (size_t)s.ndir);
+    A.total = align_up(cv.off);
+}
+
+int adj_check_cfg(fpic_ctx *c, const fpic_adjoint_cfg *a)
+{
+    if (!c || !a)
+        return fail(FPIC_EINVAL, "adjoint: null argument");
+    if (c->c3 || !c->b || c->b->plan.nsim != 1)
+        return fail(FPIC_EUNSUPPORTED, "the adjoint covers single 1D boxes");
+    if (a->nsteps < 1 || a->ckpt_every < 1)
+        return fail(FPIC_EINVAL, "adjoint: nsteps and ckpt_every must be >= 1");
+    return FPIC_OK;
+}
+
+// capture `fn` (which launches on stream s) into an executable graph
+template <class F>
+int capture(hipStream_t s, F fn, hipGraphExec_t *exec)
+{
+    HIPCHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    hipError_t err = fn();
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(s, &graph);
+    if (err != hipSuccess) {
+        if (graph)
+            (void)hipGraphDestroy(graph);
+        return fail(FPIC_EHIP, std::string("launch during capture: ") + hipGetErrorString(err));
+    }
+    HIPCHECK(e2);
+    hipError_t e3 = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    HIPCHECK(e3);
+    return FPIC_OK;
+}
+
+int adj_graph(fpic_batch *b, bool reverse, int len, hipGraphExec_t *out)
+{
+    auto &cache = reverse ? b->adj.reverse : b->adj.recompute;
+    for (auto &g : cache)
+        if (g.first == len) {
+            *out = g.second;
+            return FPIC_OK;
+        }
+    const Plan &P = b->plan;
+    const SimDesc *F = reinterpret_cast<const SimDesc *>(b->adj.ws + b->adj.o_descF);
+    const SimDesc *R = reinterpret_cast<const SimDesc *>(b->adj.ws + b->adj.o_descR);
+    hipGraphExec_t g = nullptr;
+    int rc;
+    if (!reverse) {
+        rc = capture(b->cap, [&]() -> hipError_t {
+            for (int j = 0; j < len; ++j)
+                for (int st = M_S1; st <= M_S4; ++st) {
+                    hipError_t e = launch_stage1d(st, b->dwork, P.nwork, F + j, P.waves, P.max_dpw, b->cap);
+                    if (e == hipSuccess)
+                        e = launch_reduce1d(b->dred, P.nred, F + j, st, nullptr, st == M_S4 ? 1 : 0, b->cap);
+                    if (e != hipSuccess)
+                        return e;
+                }
+            return hipSuccess;
+        }, &g);
+    } else {
+        rc = capture(b->cap, [&]() -> hipError_t {
+            for (int j = len - 1; j >= 0; --j) {
+                for (int st = 4; st >= 1; --st) {
+                    hipError_t e = launch_adj1d(0, st, b->dwork, P.nwork, R + j, P.waves, P.max_dpw, b->cap);
+                    if (e == hipSuccess)
+                        e = launch_reduce1d(b->dred, P.nred, R + j, RED_GA, nullptr, 0, b->cap);
+                    if (e == hipSuccess)
+                        e = launch_adj1d(1, st, b->dwork, P.nwork, R + j, P.waves, P.max_dpw, b->cap);
+                    if (e != hipSuccess)
+                        return e;
+                }
+                hipError_t e = launch_tick(R + j, -1, b->cap);
+                if (e != hipSuccess)
+                    return e;
+            }
+            return hipSuccess;
+        }, &g);
+    }
+    if (rc)
+        return rc;
+    cache.push_back({len, g});
+    *out = g;
+    return FPIC_OK;
+}
+
+int read_step(fpic_batch *b, int64_t *step)
+{
+    HIPCHECK(hipMemcpyAsync(b->hbuf, b->hdesc[0].step, sizeof(int64_t), hipMemcpyDeviceToHost, b->stream));
+    HIPCHECK(hipStreamSynchronize(b->stream));
+    std::memcpy(step, b->hbuf, sizeof(int64_t));
+    return FPIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fpic_adjoint_workspace_bytes(fpic_ctx *c, const fpic_adjoint_cfg *a, size_t *bytes)
+{
+    int rc = adj_check_cfg(c, a);
+    if (rc)
+        return rc;
+    if (!bytes)
+        return fail(FPIC_EINVAL, "bytes is null");
+    fpic_batch::Adj A;
+    adj_layout(c->b, a->nsteps, (int)std::min<int64_t>(a->ckpt_every, a->nsteps), A);
+    *bytes = A.total;
+    return FPIC_OK;
+}
+
+int fpic_adjoint_forward(fpic_ctx *c, const fpic_adjoint_cfg *a, void *ws, size_t bytes)
+{
+    int rc = adj_check_cfg(c, a);
+    if (rc)
+        return rc;
+    fpic_batch *b = c->b;
+    if (!b->state_set[0])
+        return fail(FPIC_ESTATE, "adjoint forward before set_state");
+    const int L = (int)std::min<int64_t>(a->ckpt_every, a->nsteps);
+    fpic_batch::Adj A;
+    adj_layout(b, a->nsteps, L, A);
+    if (!ws || bytes < A.total || reinterpret_cast<uintptr_t>(ws) % 256)
+        return fail(FPIC_EINVAL, "adjoint workspace missing, too small or misaligned");
+    // graphs of an earlier layout point at old descriptors: drop them
+    for (auto &g : b->adj.recompute)
+        (void)hipGraphExecDestroy(g.second);
+    for (auto &g : b->adj.reverse)
+        (void)hipGraphExecDestroy(g.second);
+    A.ws = static_cast<char *>(ws);
+    b->adj = A;
+    rc = read_step(b, &b->adj.n_start);
+    if (rc)
+        return rc;
+    b->adj.nsteps = a->nsteps;
+
+    // per-step descriptors of a segment
+    const SimPlan &sp = b->plan.sims[0];
+    const size_t st = 18 * (size_t)sp.np, gr = NG * (size_t)sp.ncell;
+    double *segY = reinterpret_cast<double *>(A.ws + A.o_segY);
+    double *segK = reinterpret_cast<double *>(A.ws + A.o_segK);
+    double *segG = reinterpret_cast<double *>(A.ws + A.o_segG);
+    double *lam = reinterpret_cast<double *>(A.ws + A.o_lam);
+    double *dw = reinterpret_cast<double *>(A.ws + A.o_dw);
+    std::vector<SimDesc> F(L), R(L);
+    for (int j = 0; j < L; ++j) {
+        SimDesc D = b->hdesc[0];
+        D.Y = segY + st * j;
+        D.Yout = segY + st * (j + 1);
+        D.K1 = segK + st * (3 * (size_t)j + 0);
+        D.K2 = segK + st * (3 * (size_t)j + 1);
+        D.K3 = segK + st * (3 * (size_t)j + 2);
+        for (int q = 0; q < 4; ++q)
+            D.G[q] = segG + gr * (4 * (size_t)j + q);
+        D.G[4] = segG + gr * (4 * (size_t)(j + 1));
+        D.GA = reinterpret_cast<double *>(A.ws + A.o_GA);
+        D.lam[0] = lam;
+        D.lam[1] = lam + st;
+        D.lcur = reinterpret_cast<double *>(A.ws + A.o_lcur);
+        D.dres = reinterpret_cast<double *>(A.ws + A.o_dres);
+        D.dwN = dw;
+        D.dwNb = dw + (size_t)sp.ndir * sp.ntile;
+        F[j] = D;
+        R[j] = D;
+    }
+    HIPCHECK(hipMemcpyAsync(A.ws + A.o_descF, F.data(), sizeof(SimDesc) * L, hipMemcpyHostToDevice, b->stream));
+    HIPCHECK(hipMemcpyAsync(A.ws + A.o_descR, R.data(), sizeof(SimDesc) * L, hipMemcpyHostToDevice, b->stream));
+    HIPCHECK(hipStreamSynchronize(b->stream));
+
+    // forward with checkpoints
+    double *ckpt = reinterpret_cast<double *>(A.ws + A.o_ckpt);
+    int64_t left = a->nsteps;
+    for (int seg = 0; seg < A.nseg; ++seg) {
+        HIPCHECK(hipMemcpyAsync(ckpt + st * seg, b->hdesc[0].Y, sizeof(double) * st,
+                                hipMemcpyDeviceToDevice, b->stream));
+        const int64_t n = std::min<int64_t>(L, left);
+        rc = batch_step(b, n);
+        if (rc)
+            return rc;
+        left -= n;
+    }
+    b->adj.forward_done = true;
+    return FPIC_OK;
+}
+
+int fpic_adjoint_backward(fpic_ctx *c, const double *dLdy_end, double *dLdy0, double *dLdN,
+                          double *dLdNbar)
+{
+    if (!c || !c->b || c->c3)
+        return fail(FPIC_EINVAL, "adjoint backward: bad context");
+    fpic_batch *b = c->b;
+    fpic_batch::Adj &A = b->adj;
+    if (!A.forward_done)
+        return fail(FPIC_ESTATE, "adjoint backward before fpic_adjoint_forward");
+    if (!dLdy_end || !dLdy0 || !dLdN || !dLdNbar)
+        return fail(FPIC_EINVAL, "adjoint backward: null argument");
+    const SimPlan &sp = b->plan.sims[0];
+    const Plan &P = b->plan;
+    const size_t st = 18 * (size_t)sp.np;
+    double *ckpt = reinterpret_cast<double *>(A.ws + A.o_ckpt);
+    double *segY = reinterpret_cast<double *>(A.ws + A.o_segY);
+    double *lam = reinterpret_cast<double *>(A.ws + A.o_lam);
+    double *dw = reinterpret_cast<double *>(A.ws + A.o_dw);
+    double *outw = reinterpret_cast<double *>(A.ws + A.o_out);
+    const SimDesc *F = reinterpret_cast<const SimDesc *>(A.ws + A.o_descF);
+    const int64_t n_end = A.n_start + A.nsteps;
+    hipStream_t s = b->stream;
+
+    HIPCHECK(hipMemcpyAsync(lam + st * (size_t)(n_end & 1), dLdy_end, sizeof(double) * st,
+                            hipMemcpyDeviceToDevice, s));
+    HIPCHECK(launch_fill(dw, 2 * (size_t)sp.ndir * sp.ntile, 0.0, s));
+    int off, n, roff, rn;
+    sim_work(b, 0, &off, &n, &roff, &rn);
+    for (int seg = A.nseg - 1; seg >= 0; --seg) {
+        const int64_t n0 = A.n_start + (int64_t)seg * A.L;
+        const int len = (int)std::min<int64_t>(A.L, n_end - n0);
+        // restore the checkpoint and recompute the segment, keeping its
+        // states, slopes and moment grids
+        HIPCHECK(hipMemcpyAsync(segY, ckpt + st * seg, sizeof(double) * st, hipMemcpyDeviceToDevice, s));
+        HIPCHECK(launch_set_step(F, 0, 1, n0, s));
+        HIPCHECK(launch_stage1d(M_DEPOSIT, b->dwork + off, n, F, P.waves, P.max_dpw, s));
+        HIPCHECK(launch_reduce1d(b->dred + roff, rn, F, 0, nullptr, 0, s));
+        hipGraphExec_t g = nullptr;
+        int rc = adj_graph(b, false, len, &g);
+        if (rc)
+            return rc;
+        HIPCHECK(hipGraphLaunch(g, s));
+        // sweep the segment backwards
+        HIPCHECK(launch_set_step(F, 0, 1, n0 + len - 1, s));
+        rc = adj_graph(b, true, len, &g);
+        if (rc)
+            return rc;
+        HIPCHECK(hipGraphLaunch(g, s));
+    }
+    HIPCHECK(hipMemcpyAsync(dLdy0, lam + st * (size_t)(A.n_start & 1), sizeof(double) * st,
+                            hipMemcpyDeviceToDevice, s));
+    // the kernels accumulate dL/d(N/dV); dL/dN = dL/d(N/dV) / dV
+    HIPCHECK(launch_tile_sum(dw, sp.ndir, sp.ntile, 1.0, outw, s));
+    HIPCHECK(launch_tile_sum(dw + (size_t)sp.ndir * sp.ntile, sp.ndir, sp.ntile, 1.0, outw + sp.ndir, s));
+    std::vector<double> h(2 * (size_t)sp.ndir);
+    HIPCHECK(hipMemcpyAsync(h.data(), outw, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
+    // restore the step counter of the context (its state was never touched)
+    HIPCHECK(launch_set_step(b->ddesc, 0, 1, n_end, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    const double inv_dV = 1.0 / b->cell_volume;
+    for (int d = 0; d < sp.ndir; ++d) {
+        dLdN[d] = h[d] * inv_dV;
+        dLdNbar[d] = h[sp.ndir + d] * inv_dV;
+    }
+    return FPIC_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
 // ------------------------------------------------------------- autotuning
 int fpic_autotune(int32_t nsim, const fpic_config *cfgs, void *workspace, size_t bytes,
                   fpic_stream stream, fpic_tuning *best, double *ms_per_step)

@@ -107,6 +107,30 @@ class Sim:
         check(_lib.load().fpic_profile(self.ctx, int(nsteps), out.ctypes.data_as(_lib._dp)))
         return out
 
+    def adjoint_forward(self, nsteps: int, ckpt_every: int = 50):
+        """Advance nsteps steps, storing checkpoints for adjoint_backward."""
+        lib = _lib.load()
+        a = _lib.AdjointCfg(int(nsteps), int(ckpt_every), 0)
+        nb = C.c_size_t()
+        check(lib.fpic_adjoint_workspace_bytes(self.ctx, C.byref(a), C.byref(nb)))
+        if getattr(self, "adj_ws", None) is None or self.adj_ws.numel() < nb.value:
+            self.adj_ws = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        check(lib.fpic_adjoint_forward(self.ctx, C.byref(a), self.adj_ws.data_ptr(),
+                                       self.adj_ws.numel()))
+
+    def adjoint_backward(self, dL_dfinal):
+        """Returns (dL/d(start state) [device tensor], dL/dN, dL/dNbar)."""
+        if isinstance(dL_dfinal, np.ndarray):
+            dL_dfinal = torch.from_numpy(np.ascontiguousarray(dL_dfinal)).to(self.device)
+        n = int(np.prod(self.shape))
+        g0 = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        gN = np.zeros(self.cfg.ndir)
+        gNb = np.zeros(self.cfg.ndir)
+        check(_lib.load().fpic_adjoint_backward(self.ctx, _dev_ptr(dL_dfinal, n, self.device),
+                                                g0.data_ptr(), gN.ctypes.data_as(_lib._dp),
+                                                gNb.ctypes.data_as(_lib._dp)))
+        return g0, gN, gNb
+
     def close(self):
         if getattr(self, "ctx", None):
             _lib.load().fpic_destroy(self.ctx)
