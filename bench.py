@@ -71,6 +71,86 @@ def cpu_baseline(w, budget_s=20.0):
                       f"after one warm-up step, {threads} OpenMP threads"}
 
 
+def measure_adjoint(steps=2000, ckpt=50):
+    """Reverse mode on the 512 x 128 gradient workload: time of the plain
+    forward pass, of the checkpointed forward pass and of the backward pass
+    (recompute + reverse sweep), all for the same number of steps."""
+    import numpy as np
+    import torch
+    from paper_2101_02745_amd import inputs as I
+    from paper_2101_02745_amd.sim import Sim
+    w = I.workload("1d_512x128")
+    sim = Sim.from_workload(w)
+    s0 = torch.from_numpy(w.state0()).cuda()
+    N, Nb = w.weights()
+    lam = np.zeros((18, w.ndir, w.ncell_total))
+    lam[1] = lam[2] = (N / (N.sum() * w.ncell_total))[:, None]
+    lam[10] = lam[11] = (Nb / (Nb.sum() * w.ncell_total))[:, None]
+    lam = torch.from_numpy(lam).cuda()
+    sim.set_state(s0)
+    sim.step(20)                       # warm-up
+    sim.set_state(s0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    fwd = time.perf_counter() - t0
+    sim.set_state(s0)
+    sim.adjoint_forward(10, 5)         # warm-up of the reverse path
+    sim.adjoint_backward(lam)
+    sim.set_state(s0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.adjoint_forward(steps, ckpt)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sim.adjoint_backward(lam)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    return {"workload": w.name, "particles": w.nparticles, "steps": steps, "ckpt_every": ckpt,
+            "forward_s": fwd, "checkpointed_forward_s": t1 - t0, "backward_s": t2 - t1,
+            "backward_over_forward": (t2 - t1) / fwd,
+            "total_over_forward": (t2 - t0) / fwd}
+
+
+def measure_batch(steps=100, nsim=64):
+    """64 uneven 1D boxes: one batched launch per stage vs the same boxes
+    run one after another through the single-box path (each with its own
+    captured graph)."""
+    import torch
+    from paper_2101_02745_amd import inputs as I
+    from paper_2101_02745_amd._lib import HostConfig
+    from paper_2101_02745_amd.sim import Batch, Sim
+    ws = I.batch_workloads(nsim=nsim, steps=steps)
+    P = sum(w.nparticles for w in ws)
+    b = Batch([HostConfig.from_workload(w) for w in ws])
+    for i, w in enumerate(ws):
+        b.set_state(i, w.state0())
+    b.step(5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    del b
+    sims = []
+    for w in ws:
+        sm = Sim.from_workload(w)
+        sm.set_state(w.state0())
+        sm.step(5)
+        sims.append(sm)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for sm in sims:
+        sm.step(steps)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    neg = sum(1 for w in ws if min(w.weights()[0].min(), w.weights()[1].min()) < 0)
+    return {"nsim": nsim, "particles": P, "steps": steps,
+            "batched_psteps_per_s": P * steps / tb, "sequential_psteps_per_s": P * steps / ts,
+            "ratio": ts / tb, "sims_with_negative_weights": neg}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,6 +158,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="1d_2048x378")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the adjoint and batch measurements")
     ap.add_argument("--tuning", default="",
                     help="JSON launch shape; default: autotune on the device first")
     ap.add_argument("--probe", default="", choices=["", "copy", "kernels"],
@@ -168,6 +250,13 @@ def main():
                           "reduce_ms": red_ms},
         "trace_error": ok,
     }
+    if not args.no_extra:
+        print("[bench] adjoint/forward on 1d_512x128", file=sys.stderr, flush=True)
+        rec["adjoint"] = measure_adjoint()
+        print(f"[bench] adjoint: {rec['adjoint']}", file=sys.stderr, flush=True)
+        print("[bench] batched vs sequential (64 uneven 1D boxes)", file=sys.stderr, flush=True)
+        rec["batch"] = measure_batch()
+        print(f"[bench] batch: {rec['batch']}", file=sys.stderr, flush=True)
     if not args.no_cpu:
         print("[bench] CPU baseline (oracle)", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline(w)
