@@ -79,8 +79,11 @@ def measure_adjoint(steps=2000, ckpt=50):
     import torch
     from paper_2101_02745_amd import inputs as I
     from paper_2101_02745_amd.sim import Sim
+    from paper_2101_02745_amd._lib import HostConfig
+    from paper_2101_02745_amd.sim import autotune
     w = I.workload("1d_512x128")
-    sim = Sim.from_workload(w)
+    tune, _ = autotune([HostConfig.from_workload(w)])
+    sim = Sim.from_workload(w, tuning=tune)
     s0 = torch.from_numpy(w.state0()).cuda()
     N, Nb = w.weights()
     lam = np.zeros((18, w.ndir, w.ncell_total))
@@ -108,9 +111,46 @@ def measure_adjoint(steps=2000, ckpt=50):
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     return {"workload": w.name, "particles": w.nparticles, "steps": steps, "ckpt_every": ckpt,
+            "launch": tune,
             "forward_s": fwd, "checkpointed_forward_s": t1 - t0, "backward_s": t2 - t1,
             "backward_over_forward": (t2 - t1) / fwd,
             "total_over_forward": (t2 - t0) / fwd}
+
+
+def measure_3d(steps=20):
+    """The 64^3 x 92 box (24,117,248 particles): particle kernels (state
+    passes as in 1D plus a 72-byte deposit source per particle) and the
+    cell-centric deposit kernels (reading the sources)."""
+    import torch
+    from paper_2101_02745_amd import inputs as I
+    from paper_2101_02745_amd._lib import HostConfig
+    from paper_2101_02745_amd.sim import Sim, autotune
+    w = I.workload("3d_64x92")
+    tune, _ = autotune([HostConfig.from_workload(w)])
+    sim = Sim.from_workload(w, tuning=tune)
+    sim.set_state(w.state0())
+    sim.step(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = sim.profile(3)
+    P = w.nparticles
+    part_ms = [ms[0], ms[2], ms[4], ms[6]]
+    dep_ms = [ms[1], ms[3], ms[5], ms[7]]
+    part_bytes = [STAGE_PASSES[s] * STATE_B * P + 72 * P for s in (1, 2, 3, 4)]
+    dep_bytes = 72 * P + GRID_B * w.ncell_total
+    step_bytes = sum(part_bytes) + 4 * dep_bytes
+    ms_step = 1e3 * wall / steps
+    return {"workload": w.name, "particles": P, "steps": steps, "launch": tune,
+            "value": P * steps / wall, "unit": "particle-steps/s", "ms_per_step": ms_step,
+            "particle_kernel_ms": part_ms, "deposit_kernel_ms": dep_ms,
+            "particle_kernel_GBs": [b / (t * 1e-3) / 1e9 for b, t in zip(part_bytes, part_ms)],
+            "deposit_kernel_GBs": [dep_bytes / (t * 1e-3) / 1e9 for t in dep_ms],
+            "alg_bytes_per_step": step_bytes,
+            "step_frac_of_hbm_peak": step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "step_frac_of_fused_floor": 1872 * P / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
 
 def measure_batch(steps=100, nsim=64):
@@ -121,9 +161,12 @@ def measure_batch(steps=100, nsim=64):
     from paper_2101_02745_amd import inputs as I
     from paper_2101_02745_amd._lib import HostConfig
     from paper_2101_02745_amd.sim import Batch, Sim
+    from paper_2101_02745_amd.sim import autotune
     ws = I.batch_workloads(nsim=nsim, steps=steps)
     P = sum(w.nparticles for w in ws)
-    b = Batch([HostConfig.from_workload(w) for w in ws])
+    cfgs = [HostConfig.from_workload(w) for w in ws]
+    tune, _ = autotune(cfgs)
+    b = Batch(cfgs, tuning=tune)
     for i, w in enumerate(ws):
         b.set_state(i, w.state0())
     b.step(5)
@@ -146,7 +189,7 @@ def measure_batch(steps=100, nsim=64):
     torch.cuda.synchronize()
     ts = time.perf_counter() - t0
     neg = sum(1 for w in ws if min(w.weights()[0].min(), w.weights()[1].min()) < 0)
-    return {"nsim": nsim, "particles": P, "steps": steps,
+    return {"nsim": nsim, "particles": P, "steps": steps, "batch_launch": tune,
             "batched_psteps_per_s": P * steps / tb, "sequential_psteps_per_s": P * steps / ts,
             "ratio": ts / tb, "sims_with_negative_weights": neg}
 
@@ -162,7 +205,7 @@ def main():
                     help="skip the adjoint and batch measurements")
     ap.add_argument("--tuning", default="",
                     help="JSON launch shape; default: autotune on the device first")
-    ap.add_argument("--probe", default="", choices=["", "copy", "kernels"],
+    ap.add_argument("--probe", default="", choices=["", "copy", "kernels", "adjoint"],
                     help="counter-collection modes: 'copy' runs a plain 1 GiB device copy "
                          "(the reference for HBM byte counters); 'kernels' runs 5 steps "
                          "with every kernel launched on its own, then exits")
@@ -176,6 +219,10 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"probe": "copy", "bytes_read": src.numel() * 8,
                           "bytes_written": dst.numel() * 8, "launches": 5}), flush=True)
+        return
+    if args.probe == "adjoint":
+        r = measure_adjoint(steps=200, ckpt=50)
+        print(json.dumps({"probe": "adjoint", **r}), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -254,6 +301,9 @@ def main():
         print("[bench] adjoint/forward on 1d_512x128", file=sys.stderr, flush=True)
         rec["adjoint"] = measure_adjoint()
         print(f"[bench] adjoint: {rec['adjoint']}", file=sys.stderr, flush=True)
+        print("[bench] 3D box 64^3 x 92", file=sys.stderr, flush=True)
+        rec["box3d"] = measure_3d()
+        print(f"[bench] 3d: {rec['box3d']}", file=sys.stderr, flush=True)
         print("[bench] batched vs sequential (64 uneven 1D boxes)", file=sys.stderr, flush=True)
         rec["batch"] = measure_batch()
         print(f"[bench] batch: {rec['batch']}", file=sys.stderr, flush=True)

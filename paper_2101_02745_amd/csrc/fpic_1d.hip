@@ -658,13 +658,36 @@ reduce1d_kernel(const RedItem *__restrict__ items, const SimDesc *__restrict__ s
         const int ng = S.ngroup;
         const double *pp = S.part + (size_t)k * ntc + tile0 + l;
         const size_t gstride = (size_t)NG * ntc;
+        // loads in flight together, sums in group order
         double s = 0.0;
-        for (int g = 0; g < ng; ++g)
-            s += pp[g * gstride];
+        int g = 0;
+        for (; g + 8 <= ng; g += 8) {
+            double v[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                v[q] = gld(pp + (size_t)(g + q) * gstride);
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                s += v[q];
+        }
+        for (; g < ng; ++g)
+            s += gld(pp + (size_t)g * gstride);
         if (l == 0) {
             const int tprev = (it.tile + ntile - 1) % ntile;
-            for (int g = 0; g < ng; ++g)
-                s += S.edge[((size_t)g * NG + k) * ntile + tprev];
+            const double *ep = S.edge + (size_t)k * ntile + tprev;
+            const size_t estride = (size_t)NG * ntile;
+            int g2 = 0;
+            for (; g2 + 8 <= ng; g2 += 8) {
+                double v[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    v[q] = gld(ep + (size_t)(g2 + q) * estride);
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    s += v[q];
+            }
+            for (; g2 < ng; ++g2)
+                s += gld(ep + (size_t)g2 * estride);
         }
         out[(size_t)k * nc + tile0 + l] = s;
     }
