@@ -214,6 +214,23 @@ class Batch:
             pass
 
 
+def domain_averages(moments: torch.Tensor) -> dict:
+    """Domain averages of the magnitudes of the moment entries (Sec. III.B):
+    <|n_ab|> and <|f^(x)_ab|> for neutrinos and antineutrinos, from the
+    [72][ncell] output of Sim.moments().  Keys: 'n', 'fx', 'nbar', 'fxbar',
+    each a 3x3 array of averages (diagonal and upper triangle filled)."""
+    m = moments.double()
+    out = {}
+    for name, base in (("n", 0), ("fx", 9), ("nbar", 36), ("fxbar", 45)):
+        a = np.zeros((3, 3))
+        for i in range(3):
+            a[i, i] = m[base + i].abs().mean().item()
+        for (i, j), k in (((0, 1), 3), ((0, 2), 5), ((1, 2), 7)):
+            a[i, j] = torch.hypot(m[base + k], m[base + k + 1]).mean().item()
+        out[name] = a
+    return out
+
+
 def autotune(cfgs: Sequence[HostConfig], device: str = "cuda:0", workspace_bytes=None):
     """Time candidate launch shapes on the device; returns (tuning dict,
     ms per step)."""

@@ -130,6 +130,14 @@ def test_moments_totals_check(torch_dev):
     err = sim.check(1e-12)
     assert err < 1e-13
     assert sim.step_index() == 9
+    # domain averages of the moment magnitudes (Sec. III.B diagnostic)
+    import torch
+    from paper_2101_02745_amd.sim import domain_averages
+    avg = domain_averages(torch.from_numpy(mom))
+    ref_avg = domain_averages(torch.from_numpy(mref))
+    for key in avg:
+        assert np.allclose(avg[key], ref_avg[key], rtol=1e-10, atol=1e-15)
+    assert avg["n"][0, 1] == pytest.approx(np.hypot(mref[3], mref[4]).mean(), rel=1e-10)
 
 
 def test_check_flags_nan(torch_dev):

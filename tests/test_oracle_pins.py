@@ -282,8 +282,12 @@ def test_p6_deposit_gather_bruteforce(ncell, dx):
         expect += [(Xb * v[:, a]) @ W / dV for a in range(3)]
         expect = np.concatenate(expect)
         assert np.abs(mom - expect).max() < 1e-12 * np.abs(expect).max()
-        # conservation: sum_j dV n_j = sum_p N_p rho_p
+        # conservation: sum_j dV n_j = sum_p N_p rho_p, also for the
+        # flavor totals
         assert np.allclose(mom[:9].sum(1) * dV, Xn.sum(1), rtol=0, atol=1e-13)
+        tot = P.flavor_totals(st)
+        assert np.allclose(tot[0], mom[:9].sum(1) * dV, rtol=0, atol=1e-13)
+        assert np.allclose(tot[1], mom[36:45].sum(1) * dV, rtol=0, atol=1e-13)
         G = rng.normal(size=(5, nc))
         g = P.gather(G, t)
         assert np.abs(g.reshape(5, -1) - G @ W.T).max() < 1e-13
