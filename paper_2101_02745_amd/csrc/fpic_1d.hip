@@ -410,7 +410,17 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-template <int PHASE, int STAGE>
+// One launch covers the second half of stage SB's adjoint (DO_B: gather the
+// deposited sources, stage lambda, step lambda and weight gradients) and the
+// first half of stage SA = SB - 1 (DO_A: g_SA from the step lambda and the
+// stage lambda just formed, direct part, sources and their deposit), for the
+// same particle in the same lane.  Lanes are anchored at the deposit time
+// t_SA (at t_SB when only DO_B); the sources of stage SB are gathered at
+// t_SB, which lies at most one cell away (offset delta), as in the forward
+// stage kernels.
+__device__ __forceinline__ double stage_c(int s) { return s == 1 ? 0.0 : (s == 4 ? 1.0 : 0.5); }
+
+template <bool DO_B, bool DO_A, int SB, int SA>
 __global__ void __launch_bounds__(MAX_WAVES * TILE)
 adj1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ sims, int max_dpw)
 {
@@ -428,34 +438,47 @@ adj1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ sims
     const int nact = min(TILE, nc - tile0);
     const int64_t n = *S.step;
     const double dt = S.dt, dz = S.dz;
-    const double cs = (STAGE == 1) ? 0.0 : (STAGE == 4) ? 1.0 : 0.5;
-    const double ts = stage_time(n, dt, cs);
+    const double tA = DO_A ? stage_time(n, dt, stage_c(SA)) : 0.0;
+    const double tB = DO_B ? stage_time(n, dt, stage_c(SB)) : 0.0;
+    const double tanc = DO_A ? tA : tB;
 
+    // LDS: [Gamma tile | reduction] [stage-SA grid tile] [edge buffers]
+    //      [phi_anchor, phi_B per direction] [r, delta per direction]
     const int gslot = max(NG * GT_STRIDE, NG * TILE + nwaves * NG);
-    double *Gt = smem;
-    double *eb = smem + gslot + wave * max_dpw * 9;
-    double *tphi = smem + gslot + nwaves * max_dpw * 9;
+    double *GtB = smem;
+    double *GtA = smem + gslot;
+    double *eb = smem + 2 * gslot + wave * max_dpw * 9;
+    double *tphi = smem + 2 * gslot + nwaves * max_dpw * 9;
     int *tint = (int *)(tphi + 2 * nwaves * max_dpw);
 
     const int dgrp0 = wi.group * S.dpg;
     for (int j = threadIdx.x; j < S.dpg; j += blockDim.x) {
         const int d = dgrp0 + j;
         if (d < S.ndir) {
-            const Shift sh = shift_of(S.vz[d], ts, dz);
-            tphi[2 * j + 0] = sh.phi;
-            tint[2 * j + 0] = pmod_dbl((double)sh.i, nc);
+            const Shift sa = shift_of(S.vz[d], tanc, dz);
+            tphi[2 * j + 0] = sa.phi;
+            tint[2 * j + 0] = pmod_dbl((double)sa.i, nc);
+            if (DO_A && DO_B) {
+                const Shift sb = shift_of(S.vz[d], tB, dz);
+                tphi[2 * j + 1] = sb.phi;
+                tint[2 * j + 1] = max(-1, min(1, (int)(sa.i - sb.i)));
+            } else {
+                tphi[2 * j + 1] = sa.phi;
+                tint[2 * j + 1] = 0;
+            }
         }
     }
-    {
-        const double *Gin = (PHASE == 0) ? S.G[STAGE - 1] : S.GA;
-        for (int idx = threadIdx.x; idx < NG * GT_CELLS; idx += blockDim.x) {
-            const int comp = idx / GT_CELLS;
-            const int k = idx - comp * GT_CELLS;
-            int cell = tile0 - 1 + k;
-            cell = (cell < 0) ? cell + nc : cell;
-            cell = (nc < GT_CELLS) ? cell % nc : (cell >= nc ? cell - nc : cell);
-            Gt[comp * GT_STRIDE + k] = gld(Gin + (size_t)comp * nc + cell);
-        }
+    for (int idx = threadIdx.x; idx < NG * GT_CELLS; idx += blockDim.x) {
+        const int comp = idx / GT_CELLS;
+        const int k = idx - comp * GT_CELLS;
+        int cell = tile0 - 1 + k;
+        cell = (cell < 0) ? cell + nc : cell;
+        cell = (nc < GT_CELLS) ? cell % nc : (cell >= nc ? cell - nc : cell);
+        const size_t at = (size_t)comp * nc + cell;
+        if (DO_B)
+            GtB[comp * GT_STRIDE + k] = gld(S.GA + at);
+        if (DO_A)
+            GtA[comp * GT_STRIDE + k] = gld(S.G[SA - 1] + at);
     }
     __syncthreads();
 
@@ -470,8 +493,10 @@ adj1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ sims
 
     const double *lam_in = S.lam[(n + 1) & 1];
     double *lam_out = S.lam[n & 1];
-    const double *Kp = (STAGE == 2) ? S.K1 : (STAGE == 3) ? S.K2 : S.K3;
-    const double a = (STAGE == 4) ? dt : 0.5 * dt;
+    const double *KB = (SB == 2) ? S.K1 : (SB == 3) ? S.K2 : S.K3;
+    const double aB = (SB == 4) ? dt : 0.5 * dt;
+    const double *KA = (SA == 2) ? S.K1 : (SA == 3) ? S.K2 : S.K3;
+    const double aA = (SA == 4) ? dt : 0.5 * dt;
 
     const int dbeg = dgrp0 + wave * S.dpw;
     const int dend = min(dbeg + S.dpw, S.ndir);
@@ -479,110 +504,54 @@ adj1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ sims
         const int j = d - dgrp0;
         const double vx = S.vx[d], vy = S.vy[d], vz = S.vz[d];
         const double wN = S.wN[d], wNb = S.wNb[d];
-        const double ph = tphi[2 * j + 0], omph = 1.0 - ph;
+        const double phA = tphi[2 * j + 0], omA = 1.0 - phA;
         int c = m - tint[2 * j + 0];
         if (c < 0)
             c += nc;
         const int64_t p = (int64_t)d * nc + c;
 
-        // interpolate the staged grid (moments in phase 0, adjoint sources
-        // in phase 1): q = A - Omega.B or A + Omega.B
-        const double bsg = (PHASE == 0) ? -1.0 : 1.0;
-        double q[9];
+        double Yv[18];
 #pragma unroll
-        for (int k = 0; k < 9; k++) {
-            const double *g = Gt + k * GT_STRIDE + lane + 1;
-            const double A = omph * g[0] + ph * g[1];
-            const double Bx = omph * g[9 * GT_STRIDE] + ph * g[9 * GT_STRIDE + 1];
-            const double By = omph * g[18 * GT_STRIDE] + ph * g[18 * GT_STRIDE + 1];
-            const double Bz = omph * g[27 * GT_STRIDE] + ph * g[27 * GT_STRIDE + 1];
-            q[k] = A + bsg * (vx * Bx + vy * By + vz * Bz);
-        }
+        for (int k = 0; k < 18; k++)
+            Yv[k] = active ? gld(S.Y + k * np + p) : 0.0;
 
-        double X[9];
+        double lam_s[18];
         double sN = 0.0, sNb = 0.0;
-        if (active) {
-            double y[18];
+        if (DO_B) {
+            // gather the deposited sources at t_SB: dX = Gamma_A + Omega.Gamma_B
+            const int kl = lane - tint[2 * j + 1] + 1;
+            const double phB = tphi[2 * j + 1], omB = 1.0 - phB;
+            double dX[9];
 #pragma unroll
-            for (int k = 0; k < 18; k++) {
-                const double Yk = gld(S.Y + k * np + p);
-                y[k] = (STAGE == 1) ? Yk : Yk + a * gld(Kp + k * np + p);
+            for (int k = 0; k < 9; k++) {
+                const double *g = GtB + k * GT_STRIDE + kl;
+                const double A = omB * g[0] + phB * g[1];
+                const double Bx = omB * g[9 * GT_STRIDE] + phB * g[9 * GT_STRIDE + 1];
+                const double By = omB * g[18 * GT_STRIDE] + phB * g[18 * GT_STRIDE + 1];
+                const double Bz = omB * g[27 * GT_STRIDE] + phB * g[27 * GT_STRIDE + 1];
+                dX[k] = A + (vx * Bx + vy * By + vz * Bz);
             }
-            if (PHASE == 0) {
-                // g_s from the step's lambda and the later stage's lambda
-                const double c1 = (STAGE == 1 || STAGE == 4) ? dt / 6.0 : dt / 3.0;
-                const double c2 = (STAGE == 3) ? dt : 0.5 * dt;
-                double G[18];
-#pragma unroll
-                for (int k = 0; k < 18; k++) {
-                    double gk = c1 * gld(lam_in + k * np + p);
-                    if (STAGE < 4)
-                        gk += c2 * gld(S.lcur + k * np + p);
-                    const int kk = k % 9;
-                    G[k] = (kk >= 3) ? 0.5 * gk : gk;
-                }
-                double H[9], Hb[9];
+            if (active) {
 #pragma unroll
                 for (int k = 0; k < 9; k++) {
-                    H[k] = hv[k] + q[k];
-                    const double hb = hv[k] - q[k];
-                    Hb[k] = (k == 4 || k == 6 || k == 8) ? -hb : hb;
-                }
-                double Dn[9], Db[9], dH[9], dHb[9];
-                commutator(G, H, Dn);
-                commutator(y, G, dH);
-                commutator(G + 9, Hb, Db);
-                commutator(y + 9, G + 9, dHb);
-#pragma unroll
-                for (int k = 0; k < 9; k++) {
-                    const double f = (k >= 3) ? 2.0 : 1.0;
-                    gst(S.dres + k * np + p, f * Dn[k]);
-                    gst(S.dres + (9 + k) * np + p, f * Db[k]);
                     const double sgn = (k == 4 || k == 6 || k == 8) ? -1.0 : 1.0;
-                    X[k] = f * (dH[k] - sgn * dHb[k]);
+                    const double yb = (SB == 1) ? Yv[k] : Yv[k] + aB * gld(KB + k * np + p);
+                    const double ybb = (SB == 1) ? Yv[9 + k] : Yv[9 + k] + aB * gld(KB + (9 + k) * np + p);
+                    lam_s[k] = gld(S.dres + k * np + p) + wN * dX[k];
+                    lam_s[9 + k] = gld(S.dres + (9 + k) * np + p) - sgn * wNb * dX[k];
+                    const double base_n = (SB == 4) ? gld(lam_in + k * np + p) : gld(lam_out + k * np + p);
+                    const double base_b = (SB == 4) ? gld(lam_in + (9 + k) * np + p)
+                                                    : gld(lam_out + (9 + k) * np + p);
+                    gst(lam_out + k * np + p, base_n + lam_s[k]);
+                    gst(lam_out + (9 + k) * np + p, base_b + lam_s[9 + k]);
+                    sN += yb * dX[k];
+                    sNb -= sgn * ybb * dX[k];
                 }
             } else {
 #pragma unroll
-                for (int k = 0; k < 9; k++) {
-                    const double sgn = (k == 4 || k == 6 || k == 8) ? -1.0 : 1.0;
-                    const double ln = gld(S.dres + k * np + p) + wN * q[k];
-                    const double lb = gld(S.dres + (9 + k) * np + p) - sgn * wNb * q[k];
-                    gst(S.lcur + k * np + p, ln);
-                    gst(S.lcur + (9 + k) * np + p, lb);
-                    const double base_n = (STAGE == 4) ? gld(lam_in + k * np + p) : gld(lam_out + k * np + p);
-                    const double base_b = (STAGE == 4) ? gld(lam_in + (9 + k) * np + p)
-                                                       : gld(lam_out + (9 + k) * np + p);
-                    gst(lam_out + k * np + p, base_n + ln);
-                    gst(lam_out + (9 + k) * np + p, base_b + lb);
-                    sN += y[k] * q[k];
-                    sNb -= sgn * y[9 + k] * q[k];
-                }
+                for (int k = 0; k < 18; k++)
+                    lam_s[k] = 0.0;
             }
-        } else {
-#pragma unroll
-            for (int k = 0; k < 9; k++)
-                X[k] = 0.0;
-        }
-
-        if (PHASE == 0) {
-            // deposit the sources: cell m gets (1 - phi) of its own
-            // particle and phi of the particle one lane to the left
-#pragma unroll
-            for (int k = 0; k < 9; k++) {
-                double xl = lane_below(X[k]);
-                xl = (lane == 0) ? 0.0 : xl;
-                const double xc = omph * X[k] + ph * xl;
-                acc[k] += xc;
-                acc[9 + k] -= vx * xc;
-                acc[18 + k] -= vy * xc;
-                acc[27 + k] -= vz * xc;
-            }
-            if (lane == nact - 1) {
-#pragma unroll
-                for (int k = 0; k < 9; k++)
-                    eb[(d - dbeg) * 9 + k] = ph * X[k];
-            }
-        } else {
             sN = wave_sum(sN);
             sNb = wave_sum(sNb);
             if (lane == 0) {
@@ -591,8 +560,75 @@ adj1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ sims
                 gst(S.dwNb + at, gld(S.dwNb + at) + sNb);
             }
         }
+
+        if (DO_A) {
+            double X[9];
+            // interpolate the stage-SA grid at t_SA (the anchor time)
+            double Hnn[9];
+#pragma unroll
+            for (int k = 0; k < 9; k++) {
+                const double *g = GtA + k * GT_STRIDE + lane + 1;
+                const double A = omA * g[0] + phA * g[1];
+                const double Bx = omA * g[9 * GT_STRIDE] + phA * g[9 * GT_STRIDE + 1];
+                const double By = omA * g[18 * GT_STRIDE] + phA * g[18 * GT_STRIDE + 1];
+                const double Bz = omA * g[27 * GT_STRIDE] + phA * g[27 * GT_STRIDE + 1];
+                Hnn[k] = A - (vx * Bx + vy * By + vz * Bz);
+            }
+            if (active) {
+                const double c1 = (SA == 1 || SA == 4) ? dt / 6.0 : dt / 3.0;
+                const double c2 = (SA == 3) ? dt : 0.5 * dt;
+                // neutrinos, then antineutrinos
+#pragma unroll
+                for (int part = 0; part < 2; part++) {
+                    const int o = 9 * part;
+                    double G[9], y[9], H[9];
+#pragma unroll
+                    for (int k = 0; k < 9; k++) {
+                        double gk = c1 * gld(lam_in + (o + k) * np + p);
+                        if (DO_B)
+                            gk += c2 * lam_s[o + k];
+                        G[k] = (k >= 3) ? 0.5 * gk : gk;
+                        y[k] = (SA == 1) ? Yv[o + k] : Yv[o + k] + aA * gld(KA + (o + k) * np + p);
+                        const double hk = part == 0 ? hv[k] + Hnn[k] : hv[k] - Hnn[k];
+                        H[k] = (part == 1 && (k == 4 || k == 6 || k == 8)) ? -hk : hk;
+                    }
+                    double Dk[9], dH[9];
+                    commutator(G, H, Dk);
+                    commutator(y, G, dH);
+#pragma unroll
+                    for (int k = 0; k < 9; k++) {
+                        const double f = (k >= 3) ? 2.0 : 1.0;
+                        gst(S.dres + (o + k) * np + p, f * Dk[k]);
+                        const double sgn = (k == 4 || k == 6 || k == 8) ? -1.0 : 1.0;
+                        // source: dH for neutrinos minus conj-sign * dHbar
+                        X[k] = (part == 0) ? f * dH[k] : X[k] - sgn * f * dH[k];
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < 9; k++)
+                    X[k] = 0.0;
+            }
+            // deposit the sources at t_SA: cell m gets (1 - phi) of its own
+            // particle and phi of the particle one lane to the left
+#pragma unroll
+            for (int k = 0; k < 9; k++) {
+                double xl = lane_below(X[k]);
+                xl = (lane == 0) ? 0.0 : xl;
+                const double xc = omA * X[k] + phA * xl;
+                acc[k] += xc;
+                acc[9 + k] -= vx * xc;
+                acc[18 + k] -= vy * xc;
+                acc[27 + k] -= vz * xc;
+            }
+            if (lane == nact - 1) {
+#pragma unroll
+                for (int k = 0; k < 9; k++)
+                    eb[(d - dbeg) * 9 + k] = phA * X[k];
+            }
+        }
     }
-    if (PHASE == 1)
+    if (!DO_A)
         return;
 
     // ---- workgroup reduction of the deposited sources (as in the stages)
@@ -856,21 +892,28 @@ hipError_t launch_reduce1d(const RedItem *items, int nitems, const SimDesc *sims
     return hipGetLastError();
 }
 
-hipError_t launch_adj1d(int phase, int stage, const WorkItem *work, int nwork, const SimDesc *sims,
-                        int waves, int max_dpw, hipStream_t s)
+size_t adj1d_smem_bytes(int waves, int max_dpw)
+{
+    size_t tile = (size_t)NG * GT_STRIDE;
+    size_t red = (size_t)NG * TILE + (size_t)waves * NG;
+    size_t gslot = tile > red ? tile : red;
+    const size_t dpg = (size_t)waves * max_dpw;
+    return (2 * gslot + dpg * 9 + dpg * 2) * sizeof(double) + dpg * 2 * sizeof(int);
+}
+
+// kind 4: stage 4 sources; 3, 2, 1: gather of stage kind+1 fused with the
+// sources of stage kind; 0: gather of stage 1
+hipError_t launch_adj1d(int kind, const WorkItem *work, int nwork, const SimDesc *sims, int waves,
+                        int max_dpw, hipStream_t s)
 {
     const dim3 grid(nwork), block(waves * TILE);
-    const size_t smem = stage1d_smem_bytes(waves, max_dpw);
-    const int key = phase * 10 + stage;
-    switch (key) {
-    case 1: adj1d_kernel<0, 1><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
-    case 2: adj1d_kernel<0, 2><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
-    case 3: adj1d_kernel<0, 3><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
-    case 4: adj1d_kernel<0, 4><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
-    case 11: adj1d_kernel<1, 1><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
-    case 12: adj1d_kernel<1, 2><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
-    case 13: adj1d_kernel<1, 3><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
-    case 14: adj1d_kernel<1, 4><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
+    const size_t smem = adj1d_smem_bytes(waves, max_dpw);
+    switch (kind) {
+    case 4: adj1d_kernel<false, true, 5, 4><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
+    case 3: adj1d_kernel<true, true, 4, 3><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
+    case 2: adj1d_kernel<true, true, 3, 2><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
+    case 1: adj1d_kernel<true, true, 2, 1><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
+    case 0: adj1d_kernel<true, false, 1, 0><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

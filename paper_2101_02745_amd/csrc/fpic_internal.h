@@ -84,10 +84,12 @@ hipError_t launch_stage1d(int mode, const WorkItem *work, int nwork, const SimDe
                           int waves, int max_dpw, hipStream_t s);
 hipError_t launch_reduce1d(const RedItem *items, int nitems, const SimDesc *sims, int which,
                            double *override_out, int tick, hipStream_t s);
-// adjoint stage kernels: phase 0 = sources and their deposit, phase 1 =
-// gather of the deposited sources and the stage lambda
-hipError_t launch_adj1d(int phase, int stage, const WorkItem *work, int nwork, const SimDesc *sims,
-                        int waves, int max_dpw, hipStream_t s);
+// adjoint kernels: kind 4 = sources of stage 4 and their deposit; kind 3, 2,
+// 1 = gather of the sources of stage kind+1 (stage lambda, step lambda,
+// weight gradients) fused with the sources of stage kind; kind 0 = gather of
+// the sources of stage 1
+hipError_t launch_adj1d(int kind, const WorkItem *work, int nwork, const SimDesc *sims, int waves,
+                        int max_dpw, hipStream_t s);
 hipError_t launch_fill(double *p, size_t n, double v, hipStream_t s);
 hipError_t launch_tick(const SimDesc *sims, int64_t delta, hipStream_t s);
 hipError_t launch_tile_sum(const double *src, int ndir, int ntile, double scale, double *dst,

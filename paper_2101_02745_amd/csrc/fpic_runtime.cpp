@@ -871,12 +871,13 @@ int adj_graph(fpic_batch *b, bool reverse, int len, hipGraphExec_t *out)
     } else {
         rc = capture(b->cap, [&]() -> hipError_t {
             for (int j = len - 1; j >= 0; --j) {
-                for (int st = 4; st >= 1; --st) {
-                    hipError_t e = launch_adj1d(0, st, b->dwork, P.nwork, R + j, P.waves, P.max_dpw, b->cap);
-                    if (e == hipSuccess)
+                // sources of stage 4, then (gather of stage s+1 with the
+                // sources of stage s) for s = 3, 2, 1, then the gather of
+                // stage 1; each source deposit is closed by a reduction
+                for (int kind = 4; kind >= 0; --kind) {
+                    hipError_t e = launch_adj1d(kind, b->dwork, P.nwork, R + j, P.waves, P.max_dpw, b->cap);
+                    if (e == hipSuccess && kind > 0)
                         e = launch_reduce1d(b->dred, P.nred, R + j, RED_GA, nullptr, 0, b->cap);
-                    if (e == hipSuccess)
-                        e = launch_adj1d(1, st, b->dwork, P.nwork, R + j, P.waves, P.max_dpw, b->cap);
                     if (e != hipSuccess)
                         return e;
                 }
