@@ -1,19 +1,20 @@
 // 3D periodic boxes: two kernels per Runge-Kutta stage.
 //
-// particle kernel (one wave = one x-row of cells and one direction at a time,
-// lane = x): forms the stage state, interpolates the 36 combined moments at
-// the particle's current position with the trilinear cloud-in-cell weights
-// (y and z first, from the four neighbouring rows, then x from the lane one
-// to the right), builds H and Hbar, the commutator slopes and the next stage
-// state, and writes that state's deposit source X = (N/dV) rho - (Nbar/dV)
-// rhobar^* (9 reals per particle).
+// particle kernel (a workgroup = one x-row of current cells and a group of
+// directions, lane = x): forms the stage state, interpolates the 36 combined
+// moments at the particle's current position with the trilinear
+// cloud-in-cell weights (y and z first, from the four neighbouring grid rows
+// staged in LDS, then x from the lane one to the right), builds H and Hbar,
+// the commutator slopes and the next stage state, and writes that state's
+// deposit source X = (N/dV) rho - (Nbar/dV) rhobar^* (9 reals per particle).
 //
-// deposit kernel (one wave = one x-row of cells, all directions in a fixed
-// order): every cell pulls X from the eight particles whose next-stage
-// positions straddle it (four rows in y and z, then the lane one to the left
-// in x) with the same weights, and accumulates the 36 combined moments in
-// registers.  Each cell is written once: no atomics, no partial sums, bitwise
-// reproducible.
+// deposit kernel (one wave = one x-row of destination cells, all directions
+// in a fixed order; a workgroup holds a small patch of neighbouring rows):
+// every cell pulls X from the eight particles whose next-stage positions
+// straddle it (four rows in y and z, then the lane one to the left in x)
+// with the same weights, and accumulates the 36 combined moments in
+// registers.  Each cell is written once: no atomics, no partial sums,
+// bitwise reproducible.
 //
 // Positions are implicit as in 1D: particle (d, c) is at cell c shifted by
 // floor(Omega_a t / dx_a) along each axis with fraction Omega_a t / dx_a minus
@@ -116,20 +117,34 @@ __device__ __forceinline__ void commutator(const double h[9], const double r[9],
     k[8] = c21r - c12r;
 }
 
-// MODE 1..4: Runge-Kutta stages; 5: deposit sources of the current state
+// MODE 1..4: Runge-Kutta stages; 5: deposit sources of the current state.
+//
+// A workgroup owns one row (y, z) of *current* lower cells and a group of
+// directions (waves x dpw); for direction d, lane x takes the particle whose
+// lower cell at the stage time is (x, y, z), i.e. the one stored at cell
+// (x, y, z) minus the direction's integer shift.  Every particle of the
+// workgroup then interpolates from the same four grid rows (y or y + 1,
+// z or z + 1), which are staged in LDS once per workgroup; the particle data
+// of each direction is one contiguous row, rotated in x.  MODE 5 has no
+// interpolation and takes the particles in storage order.
+constexpr int MAX_WAVES3 = 8;
+
 template <int MODE>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(MAX_WAVES3 * W)
 particle3d_kernel(const Desc3 *__restrict__ dp, int dpw, int nitems)
 {
+    __shared__ double Gt[MODE == 5 ? 1 : 4 * NG * W];  // [row q = 2 cz + cy][comp][x]
     const Desc3 S = *dp;
     const int lane = threadIdx.x & (W - 1);
-    const int item = blockIdx.x * (blockDim.x / W) + __builtin_amdgcn_readfirstlane(threadIdx.x / W);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / W);
+    const int nwaves = blockDim.x / W;
+    const int item = blockIdx.x;
     if (item >= nitems)
-        return;
+        return;  // whole workgroup: uniform
     const int nx = S.n[0], ny = S.n[1], nz = S.n[2];
     const int nrows = ny * nz;
     const int row = item % nrows, grp = item / nrows;
-    const int y = row % ny, z = row / ny;
+    const int y0 = row % ny, z0 = row / ny;
     const bool active = lane < nx;
     const int64_t n = *S.step;
     const double dt = S.dt;
@@ -142,13 +157,39 @@ particle3d_kernel(const Desc3 *__restrict__ dp, int dpw, int nitems)
         t_cur = stage_time(n, dt, 0.0);
     const double *Gin = S.G[(MODE - 1) & 1];
     const double *Kp = (MODE == 2) ? S.K1 : (MODE == 3) ? S.K2 : S.K3;
-    const int64_t c = (int64_t)row * nx + (active ? lane : 0);
-    const int dbeg = grp * dpw, dend = min(dbeg + dpw, S.ndir);
+    const int dbeg = (grp * nwaves + wave) * dpw, dend = min(dbeg + dpw, S.ndir);
     const int right = (lane + 1) % (nx < 1 ? 1 : nx);
+
+    if (MODE != 5) {
+        for (int idx = threadIdx.x; idx < 4 * NG * nx; idx += blockDim.x) {
+            const int x = idx % nx, t = idx / nx;
+            const int comp = t % NG, q = t / NG;
+            int yy = y0 + (q & 1), zz = z0 + (q >> 1);
+            yy = (yy >= ny) ? yy - ny : yy;
+            zz = (zz >= nz) ? zz - nz : zz;
+            Gt[(q * NG + comp) * W + x] = gld(Gin + (int64_t)comp * S.ncell + ((int64_t)zz * ny + yy) * nx + x);
+        }
+        __syncthreads();
+    }
 
     for (int d = dbeg; d < dend; ++d) {
         const double vx = S.v[0][d], vy = S.v[1][d], vz = S.v[2][d];
         const double wN = S.wN[d], wNb = S.wNb[d];
+        int rx = 0, ry = 0, rz = 0;
+        double fx = 0.0, fy = 0.0, fz = 0.0;
+        int64_t c;
+        if (MODE == 5) {
+            c = (int64_t)row * nx + (active ? lane : 0);
+        } else {
+            axis_shift(vx, t_cur, S.dx[0], nx, &rx, &fx);
+            axis_shift(vy, t_cur, S.dx[1], ny, &ry, &fy);
+            axis_shift(vz, t_cur, S.dx[2], nz, &rz, &fz);
+            int cx = lane - rx, cy = y0 - ry, cz = z0 - rz;
+            cx = (cx < 0) ? cx + nx : cx;
+            cy = (cy < 0) ? cy + ny : cy;
+            cz = (cz < 0) ? cz + nz : cz;
+            c = ((int64_t)cz * ny + cy) * nx + (active ? cx : 0);
+        }
         const int64_t p = (int64_t)d * S.ncell + c;
         double Y[18];
 #pragma unroll
@@ -160,32 +201,15 @@ particle3d_kernel(const Desc3 *__restrict__ dp, int dpw, int nitems)
             for (int k = 0; k < 18; k++)
                 yn[k] = Y[k];
         } else {
-            int rx, ry, rz;
-            double fx, fy, fz;
-            axis_shift(vx, t_cur, S.dx[0], nx, &rx, &fx);
-            axis_shift(vy, t_cur, S.dx[1], ny, &ry, &fy);
-            axis_shift(vz, t_cur, S.dx[2], nz, &rz, &fz);
-            // y/z interpolation at x' = x + shift from the four rows, then x
-            // with the lane to the right (periodic in x); one group of 9
-            // components (A, B_x, B_y, B_z) at a time:
-            // Hnn = A - (vx B_x + vy B_y + vz B_z)
-            int xs = lane + rx;
-            xs = (xs >= nx) ? xs - nx : xs;
-            xs = active ? xs : 0;
-            int64_t rowoff[4];
+            // y/z interpolation from the four staged rows, then x with the
+            // lane to the right (periodic in x); one group of 9 components
+            // (A, B_x, B_y, B_z) at a time: Hnn = A - (vx B_x + vy B_y + vz B_z)
             double wyz[4];
 #pragma unroll
             for (int cz = 0; cz < 2; cz++)
 #pragma unroll
-                for (int cy = 0; cy < 2; cy++) {
-                    int yy = y + ry + cy, zz = z + rz + cz;
-                    yy = (yy >= ny) ? yy - ny : yy;
-                    yy = (yy >= ny) ? yy - ny : yy;
-                    zz = (zz >= nz) ? zz - nz : zz;
-                    zz = (zz >= nz) ? zz - nz : zz;
-                    rowoff[2 * cz + cy] = ((int64_t)zz * ny + yy) * nx + xs;
+                for (int cy = 0; cy < 2; cy++)
                     wyz[2 * cz + cy] = (cy ? fy : 1.0 - fy) * (cz ? fz : 1.0 - fz);
-                }
             double Hnn[9];
 #pragma unroll
             for (int k = 0; k < 9; k++)
@@ -195,11 +219,11 @@ particle3d_kernel(const Desc3 *__restrict__ dp, int dpw, int nitems)
                 const double coef = (grp4 == 0) ? 1.0 : (grp4 == 1) ? -vx : (grp4 == 2) ? -vy : -vz;
 #pragma unroll
                 for (int k = 0; k < 9; k++) {
-                    const double *g = Gin + (int64_t)(9 * grp4 + k) * S.ncell;
+                    const double *g = Gt + (9 * grp4 + k) * W + lane;
                     double r = 0.0;
 #pragma unroll
                     for (int q = 0; q < 4; q++)
-                        r += wyz[q] * gld(g + rowoff[q]);
+                        r += wyz[q] * (active ? g[q * NG * W] : 0.0);
                     const double nb = lane_get(r, right);
                     const double val = (1.0 - fx) * r + fx * nb;
                     Hnn[k] += coef * val;
@@ -269,16 +293,82 @@ particle3d_kernel(const Desc3 *__restrict__ dp, int dpw, int nitems)
 
 // Deposit of the sources at the positions of time t = (n + cnext) dt
 // (cnext_num / 2 steps after step n's start; 2 means the next step).
-__global__ void __launch_bounds__(256)
+// Each wave owns one x-row of destination cells and sweeps every direction
+// in ascending order; per direction it interpolates the sources of the four
+// rows in y and z (pull_dir), then in x with the lane to the left
+// (accumulate).
+struct Pull {
+    double X[9];       // sources interpolated in y and z at the lane's x
+    double fx, vx, vy, vz;
+};
+
+__device__ __forceinline__ void pull_dir(const Desc3 &S, int d, double t, int y, int z, int lane,
+                                         bool active, Pull &o)
+{
+    const int nx = S.n[0], ny = S.n[1], nz = S.n[2];
+    o.vx = S.v[0][d];
+    o.vy = S.v[1][d];
+    o.vz = S.v[2][d];
+    int rx, ry, rz;
+    double fy, fz;
+    axis_shift(o.vx, t, S.dx[0], nx, &rx, &o.fx);
+    axis_shift(o.vy, t, S.dx[1], ny, &ry, &fy);
+    axis_shift(o.vz, t, S.dx[2], nz, &rz, &fz);
+    int xs = lane - rx;
+    xs = (xs < 0) ? xs + nx : xs;
+    xs = active ? xs : 0;
+#pragma unroll
+    for (int k = 0; k < 9; k++)
+        o.X[k] = 0.0;
+#pragma unroll
+    for (int cz = 0; cz < 2; cz++)
+#pragma unroll
+        for (int cy = 0; cy < 2; cy++) {
+            int yy = y - ry - cy, zz = z - rz - cz;
+            yy = (yy < 0) ? yy + ny : yy;
+            yy = (yy < 0) ? yy + ny : yy;
+            zz = (zz < 0) ? zz + nz : zz;
+            zz = (zz < 0) ? zz + nz : zz;
+            const double w = (cy ? fy : 1.0 - fy) * (cz ? fz : 1.0 - fz);
+            const double *xp = S.X + (int64_t)d * S.ncell + ((int64_t)zz * ny + yy) * nx + xs;
+#pragma unroll
+            for (int k = 0; k < 9; k++)
+                o.X[k] += w * (active ? gld(xp + (int64_t)k * S.np) : 0.0);
+        }
+}
+
+__device__ __forceinline__ void accumulate(const Pull &o, int left, double acc[NG])
+{
+#pragma unroll
+    for (int k = 0; k < 9; k++) {
+        const double xl = lane_get(o.X[k], left);
+        const double xc = (1.0 - o.fx) * o.X[k] + o.fx * xl;
+        acc[k] += xc;
+        acc[9 + k] += o.vx * xc;
+        acc[18 + k] += o.vy * xc;
+        acc[27 + k] += o.vz * xc;
+    }
+}
+
+// A deposit workgroup covers a patch of DEP_PY x DEP_PZ destination rows,
+// one wave per row; its waves sweep the directions in the same order, so
+// the source rows they share (a patch of (DEP_PY + 1) x (DEP_PZ + 1) rows
+// per direction) are mostly read from memory once.
+constexpr int DEP_PY = 2, DEP_PZ = 2;
+constexpr int DEP_WAVES = DEP_PY * DEP_PZ;
+
+__global__ void __launch_bounds__(DEP_WAVES * W)
 deposit3d_kernel(const Desc3 *__restrict__ dp, int half_steps, int out_buf)
 {
     const Desc3 S = *dp;
     const int lane = threadIdx.x & (W - 1);
-    const int row = blockIdx.x * (blockDim.x / W) + __builtin_amdgcn_readfirstlane(threadIdx.x / W);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / W);
     const int nx = S.n[0], ny = S.n[1], nz = S.n[2];
-    if (row >= ny * nz)
-        return;
-    const int y = row % ny, z = row / ny;
+    const int npy = (ny + DEP_PY - 1) / DEP_PY;
+    const int y = (blockIdx.x % npy) * DEP_PY + wave % DEP_PY;
+    const int z = (blockIdx.x / npy) * DEP_PZ + wave / DEP_PY;
+    if (y >= ny || z >= nz)
+        return;  // no workgroup barrier in this kernel
     const bool active = lane < nx;
     const int64_t n0 = *S.step;
     // half_steps: 0 -> t_n, 1 -> t_n + dt/2, 2 -> t_n + dt (stage 4 of step
@@ -294,51 +384,22 @@ deposit3d_kernel(const Desc3 *__restrict__ dp, int half_steps, int out_buf)
     for (int q = 0; q < NG; q++)
         acc[q] = 0.0;
     for (int d = 0; d < S.ndir; ++d) {
-        const double vx = S.v[0][d], vy = S.v[1][d], vz = S.v[2][d];
-        int rx, ry, rz;
-        double fx, fy, fz;
-        axis_shift(vx, t, S.dx[0], nx, &rx, &fx);
-        axis_shift(vy, t, S.dx[1], ny, &ry, &fy);
-        axis_shift(vz, t, S.dx[2], nz, &rz, &fz);
-        int xs = lane - rx;
-        xs = (xs < 0) ? xs + nx : xs;
-        xs = active ? xs : 0;
-        double Xyz[9];
-#pragma unroll
-        for (int k = 0; k < 9; k++)
-            Xyz[k] = 0.0;
-#pragma unroll
-        for (int cz = 0; cz < 2; cz++)
-#pragma unroll
-            for (int cy = 0; cy < 2; cy++) {
-                int yy = y - ry - cy, zz = z - rz - cz;
-                yy = (yy < 0) ? yy + ny : yy;
-                yy = (yy < 0) ? yy + ny : yy;
-                zz = (zz < 0) ? zz + nz : zz;
-                zz = (zz < 0) ? zz + nz : zz;
-                const double w = (cy ? fy : 1.0 - fy) * (cz ? fz : 1.0 - fz);
-                const double *xp = S.X + (int64_t)d * S.ncell + ((int64_t)zz * ny + yy) * nx + xs;
-#pragma unroll
-                for (int k = 0; k < 9; k++)
-                    Xyz[k] += w * (active ? gld(xp + (int64_t)k * S.np) : 0.0);
-            }
-#pragma unroll
-        for (int k = 0; k < 9; k++) {
-            const double xl = lane_get(Xyz[k], left);
-            const double xc = (1.0 - fx) * Xyz[k] + fx * xl;
-            acc[k] += xc;
-            acc[9 + k] += vx * xc;
-            acc[18 + k] += vy * xc;
-            acc[27 + k] += vz * xc;
-        }
+        Pull a;
+        pull_dir(S, d, t, y, z, lane, active, a);
+        accumulate(a, left, acc);
     }
     if (active) {
-        double *G = S.G[out_buf];
-        const int64_t cell = (int64_t)row * nx + lane;
+        double *G = out_buf ? S.G[1] : S.G[0];  // (no dynamic index into the descriptor)
+        const int64_t cell = ((int64_t)z * ny + y) * nx + lane;
 #pragma unroll
         for (int q = 0; q < NG; q++)
             gst(G + (int64_t)q * S.ncell + cell, acc[q]);
     }
+}
+
+static unsigned deposit_blocks(const Desc3 &h)
+{
+    return (unsigned)(((h.n[1] + DEP_PY - 1) / DEP_PY) * ((h.n[2] + DEP_PZ - 1) / DEP_PZ));
 }
 
 // moments of neutrinos (which = 0) or antineutrinos (1) at the current step
@@ -453,7 +514,7 @@ struct Ctx3D {
     Desc3 *d = nullptr;
     char *ws = nullptr;
     hipStream_t stream = nullptr, cap = nullptr;
-    int dpw = 0, ngroup = 0, spg = 8, nitems = 0;
+    int waves = 8, dpw = 0, ngroup = 0, spg = 8, nitems = 0;
     double *scratch = nullptr, *hbuf = nullptr;
     hipGraphExec_t g1 = nullptr, gK = nullptr;
     bool state_set = false;
@@ -463,7 +524,7 @@ static size_t al(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
     size_t tab, Y, K1, K2, K3, X, G0, G1, step, desc, scratch, total;
-    int dpw, ngroup, spg;
+    int waves, dpw, ngroup, spg;
 };
 
 static int validate(const fpic_config &c)
@@ -523,14 +584,21 @@ static int layout(const fpic_config &c, const fpic_tuning *t, Layout &L)
     const int64_t nc = (int64_t)c.ncell[0] * c.ncell[1] * c.ncell[2];
     const int64_t np = nc * c.ndir;
     const int64_t nrows = (int64_t)c.ncell[1] * c.ncell[2];
+    L.waves = (t && t->waves) ? t->waves : 8;
+    if (L.waves != 1 && L.waves != 2 && L.waves != 4 && L.waves != MAX_WAVES3)
+        return fail(FPIC_EINVAL, "waves must be 1, 2, 4 or 8 for 3D boxes");
     L.dpw = (t && t->dirs_per_wave) ? t->dirs_per_wave : 0;
     if (L.dpw < 0 || L.dpw > 4096)
         return fail(FPIC_EINVAL, "dirs_per_wave out of range");
     if (!L.dpw) {
-        // about 16k waves in total
-        L.dpw = (int)std::max<int64_t>(1, std::min<int64_t>(c.ndir, (nrows * c.ndir + 16383) / 16384));
+        // one direction group per row when there are enough rows to fill
+        // the chip (about 2048 workgroups), more groups otherwise
+        const int64_t groups = std::max<int64_t>(1, (2048 + nrows - 1) / nrows);
+        const int64_t dpg = std::max<int64_t>(L.waves, (c.ndir + groups - 1) / groups);
+        L.dpw = (int)((dpg + L.waves - 1) / L.waves);
     }
-    L.ngroup = (c.ndir + L.dpw - 1) / L.dpw;
+    const int dpg = L.waves * L.dpw;
+    L.ngroup = (c.ndir + dpg - 1) / dpg;
     L.spg = (t && t->steps_per_graph) ? t->steps_per_graph : 8;
     if (L.spg < 1 || L.spg > 256)
         return fail(FPIC_EINVAL, "steps_per_graph must be in 1..256");
@@ -569,16 +637,15 @@ int workspace_bytes(const fpic_config &cfg, const fpic_tuning *tune, size_t *byt
 
 static hipError_t launch_step(Ctx3D *c, hipStream_t s)
 {
-    const int nrows = c->h.n[1] * c->h.n[2];
-    const dim3 pgrid((c->nitems + 3) / 4), dgrid((nrows + 3) / 4), blk(256);
+    const dim3 pgrid(c->nitems), pblk(c->waves * W), dgrid(deposit_blocks(c->h)), blk(DEP_WAVES * W);
     // stage s reads G[(s-1)&1]; its deposit writes G[s&1]
-    particle3d_kernel<1><<<pgrid, blk, 0, s>>>(c->d, c->dpw, c->nitems);
+    particle3d_kernel<1><<<pgrid, pblk, 0, s>>>(c->d, c->dpw, c->nitems);
     deposit3d_kernel<<<dgrid, blk, 0, s>>>(c->d, 1, 1);
-    particle3d_kernel<2><<<pgrid, blk, 0, s>>>(c->d, c->dpw, c->nitems);
+    particle3d_kernel<2><<<pgrid, pblk, 0, s>>>(c->d, c->dpw, c->nitems);
     deposit3d_kernel<<<dgrid, blk, 0, s>>>(c->d, 1, 0);
-    particle3d_kernel<3><<<pgrid, blk, 0, s>>>(c->d, c->dpw, c->nitems);
+    particle3d_kernel<3><<<pgrid, pblk, 0, s>>>(c->d, c->dpw, c->nitems);
     deposit3d_kernel<<<dgrid, blk, 0, s>>>(c->d, 2, 1);
-    particle3d_kernel<4><<<pgrid, blk, 0, s>>>(c->d, c->dpw, c->nitems);
+    particle3d_kernel<4><<<pgrid, pblk, 0, s>>>(c->d, c->dpw, c->nitems);
     deposit3d_kernel<<<dgrid, blk, 0, s>>>(c->d, 3, 0);
     tick3d<<<1, 64, 0, s>>>(c->d);
     return hipGetLastError();
@@ -616,6 +683,7 @@ int create(const fpic_config &cfg, const fpic_tuning *tune, void *ws, size_t byt
     Ctx3D *c = new Ctx3D();
     c->ws = static_cast<char *>(ws);
     c->stream = static_cast<hipStream_t>(stream);
+    c->waves = L.waves;
     c->dpw = L.dpw;
     c->ngroup = L.ngroup;
     c->spg = L.spg;
@@ -691,8 +759,8 @@ int set_state(Ctx3D *c, const double *state, int64_t step0)
     HIPCHECK(hipMemcpyAsync(c->h.Y, state, sizeof(double) * 18 * c->h.np, hipMemcpyDeviceToDevice, c->stream));
     set_step3d<<<1, 64, 0, c->stream>>>(c->d, step0);
     HIPCHECK(hipGetLastError());
-    const dim3 pgrid((c->nitems + 3) / 4), dgrid((c->h.n[1] * c->h.n[2] + 3) / 4), blk(256);
-    particle3d_kernel<5><<<pgrid, blk, 0, c->stream>>>(c->d, c->dpw, c->nitems);
+    const dim3 pgrid(c->nitems), pblk(c->waves * W), dgrid(deposit_blocks(c->h)), blk(DEP_WAVES * W);
+    particle3d_kernel<5><<<pgrid, pblk, 0, c->stream>>>(c->d, c->dpw, c->nitems);
     deposit3d_kernel<<<dgrid, blk, 0, c->stream>>>(c->d, 0, 0);
     HIPCHECK(hipGetLastError());
     c->state_set = true;
@@ -732,7 +800,7 @@ int moments(Ctx3D *c, double *out)
     // the deposit kernel writes G[out_buf]; point a copy of the descriptor
     // at the caller's buffer
     Desc3 D = c->h;
-    const dim3 dgrid((c->h.n[1] * c->h.n[2] + 3) / 4), blk(256);
+    const dim3 dgrid(deposit_blocks(c->h)), blk(DEP_WAVES * W);
     for (int which = 0; which < 2; ++which) {
         D.G[0] = out + (size_t)which * NG * c->h.ncell;
         HIPCHECK(hipMemcpyAsync(c->scratch, &D, sizeof D, hipMemcpyHostToDevice, c->stream));
@@ -794,8 +862,7 @@ int profile(Ctx3D *c, int nsteps, double *ms)
 {
     if (!c->state_set)
         return fail(FPIC_ESTATE, "profile before set_state");
-    const int nrows = c->h.n[1] * c->h.n[2];
-    const dim3 pgrid((c->nitems + 3) / 4), dgrid((nrows + 3) / 4), blk(256);
+    const dim3 pgrid(c->nitems), pblk(c->waves * W), dgrid(deposit_blocks(c->h)), blk(DEP_WAVES * W);
     hipEvent_t ev[9];
     for (auto &e : ev)
         HIPCHECK(hipEventCreate(&e));
@@ -804,19 +871,19 @@ int profile(Ctx3D *c, int nsteps, double *ms)
     int rc = FPIC_OK;
     for (int n = 0; n < nsteps && !rc; ++n) {
         (void)hipEventRecord(ev[0], s);
-        particle3d_kernel<1><<<pgrid, blk, 0, s>>>(c->d, c->dpw, c->nitems);
+        particle3d_kernel<1><<<pgrid, pblk, 0, s>>>(c->d, c->dpw, c->nitems);
         (void)hipEventRecord(ev[1], s);
         deposit3d_kernel<<<dgrid, blk, 0, s>>>(c->d, 1, 1);
         (void)hipEventRecord(ev[2], s);
-        particle3d_kernel<2><<<pgrid, blk, 0, s>>>(c->d, c->dpw, c->nitems);
+        particle3d_kernel<2><<<pgrid, pblk, 0, s>>>(c->d, c->dpw, c->nitems);
         (void)hipEventRecord(ev[3], s);
         deposit3d_kernel<<<dgrid, blk, 0, s>>>(c->d, 1, 0);
         (void)hipEventRecord(ev[4], s);
-        particle3d_kernel<3><<<pgrid, blk, 0, s>>>(c->d, c->dpw, c->nitems);
+        particle3d_kernel<3><<<pgrid, pblk, 0, s>>>(c->d, c->dpw, c->nitems);
         (void)hipEventRecord(ev[5], s);
         deposit3d_kernel<<<dgrid, blk, 0, s>>>(c->d, 2, 1);
         (void)hipEventRecord(ev[6], s);
-        particle3d_kernel<4><<<pgrid, blk, 0, s>>>(c->d, c->dpw, c->nitems);
+        particle3d_kernel<4><<<pgrid, pblk, 0, s>>>(c->d, c->dpw, c->nitems);
         (void)hipEventRecord(ev[7], s);
         deposit3d_kernel<<<dgrid, blk, 0, s>>>(c->d, 3, 0);
         tick3d<<<1, 64, 0, s>>>(c->d);
@@ -863,10 +930,15 @@ int autotune(const fpic_config &cfg, void *ws, size_t bytes, fpic_stream stream,
     double best_ms = 1e300;
     fpic_tuning bt{};
     int tried = 0;
-    for (int dpw : {1, 2, 4, 8, 16, 23, 46, 92}) {
-        if (dpw > cfg.ndir)
-            continue;
-        fpic_tuning t{0, dpw, 4, 0};
+    std::vector<std::pair<int, int>> cands;  // (waves, dirs per wave)
+    for (int waves : {2, 4, 8})
+        for (int groups : {1, 2, 4}) {
+            const int dpw = (cfg.ndir + waves * groups - 1) / (waves * groups);
+            if (dpw >= 1 && (groups == 1 || dpw > 1))
+                cands.emplace_back(waves, dpw);
+        }
+    for (auto [waves, dpw] : cands) {
+        fpic_tuning t{waves, dpw, 4, 0};
         Ctx3D *c = nullptr;
         int rc = create(cfg, &t, ws, bytes, stream, &c);
         if (rc)

@@ -25,34 +25,39 @@ def box(ncell, ndir, dx=0.5, dt=0.1, **kw):
                       seed=kw.pop("seed", 3), alpha=kw.pop("alpha", 1e-2))
 
 
-@pytest.mark.parametrize("ncell,ndir,tuning", [
-    ((8, 6, 5), 26, None),
-    ((64, 3, 4), 92, None),
-    ((13, 7, 3), 26, {"dirs_per_wave": 5}),
-    ((16, 1, 8), 26, None),     # one-cell axis in y
-    ((1, 12, 10), 6, None),     # one-cell axis in x
-    ((5, 4, 1), 92, {"dirs_per_wave": 92}),
+@pytest.mark.parametrize("ncell,ndir,tuning,step0", [
+    ((8, 6, 5), 26, None, 2),
+    ((64, 3, 4), 92, None, 2),
+    ((13, 7, 3), 26, {"dirs_per_wave": 5}, 2),
+    ((16, 1, 8), 26, None, 2),     # one-cell axis in y
+    ((1, 12, 10), 6, None, 2),     # one-cell axis in x
+    ((5, 4, 1), 92, {"dirs_per_wave": 92}, 2),
+    # late times: every direction's shift has wrapped the box several times;
+    # the launch shapes split the directions into several groups
+    ((8, 6, 5), 26, {"waves": 1, "dirs_per_wave": 3}, 57),
+    ((13, 7, 3), 26, {"waves": 2, "dirs_per_wave": 2}, 1000),
+    ((64, 3, 4), 92, {"waves": 4, "dirs_per_wave": 7}, 333),
 ])
-def test_3d_parity(torch_dev, ncell, ndir, tuning):
+def test_3d_parity(torch_dev, ncell, ndir, tuning, step0):
     from paper_2101_02745_amd.sim import Sim
     w = box(ncell, ndir)
     s0 = w.state0()
     sim = Sim.from_workload(w, tuning=tuning)
-    sim.set_state(s0, step0=2)
+    sim.set_state(s0, step0=step0)
     sim.step(4)
     got = sim.get_state().cpu().numpy()
     P = Problem.from_workload(w)
-    ref = P.step(s0, 4, n0=2)
+    ref = P.step(s0, 4, n0=step0)
     assert_parity(got, ref, what=str(ncell))
     mom = sim.moments().cpu().numpy()
-    mref = P.moments(ref, 6 * w.dt)
+    mref = P.moments(ref, (step0 + 4) * w.dt)
     assert np.abs(mom - mref).max() <= 1e-12 * np.abs(mref).max()
     tot = sim.flavor_totals()
     assert np.abs(tot - P.flavor_totals(ref)).max() <= 1e-12 * np.abs(tot).max()
     assert sim.check(1e-12) < 1e-13
     # determinism
     sim2 = Sim.from_workload(w, tuning=tuning)
-    sim2.set_state(s0, step0=2)
+    sim2.set_state(s0, step0=step0)
     sim2.step(4)
     assert np.array_equal(sim2.get_state().cpu().numpy(), got)
 
