@@ -27,7 +27,8 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "particle-steps/s (deposit+gather+RK4) on 1 GPU vs roofline; adjoint/forward ratio"
 STATE_B = 18 * 8        # bytes of one particle's state
 GRID_B = 36 * 8         # bytes of one cell's combined moments
-# passes over the particle state per stage kernel (read + write), see the design doc
+# passes over the particle state per stage kernel (reads + writes) in the
+# stage-synchronous Runge-Kutta schedule: 2 + 3 + 3 + 5 = 13 per step
 STAGE_PASSES = {1: 2, 2: 3, 3: 3, 4: 5}
 
 
@@ -71,7 +72,7 @@ def cpu_baseline(w, budget_s=20.0):
                       f"after one warm-up step, {threads} OpenMP threads"}
 
 
-def measure_adjoint(steps=2000, ckpt=50):
+def measure_adjoint(steps=2000, ckpt=50, tune=None):
     """Reverse mode on the 512 x 128 gradient workload: time of the plain
     forward pass, of the checkpointed forward pass and of the backward pass
     (recompute + reverse sweep), all for the same number of steps."""
@@ -82,7 +83,8 @@ def measure_adjoint(steps=2000, ckpt=50):
     from paper_2101_02745_amd._lib import HostConfig
     from paper_2101_02745_amd.sim import autotune
     w = I.workload("1d_512x128")
-    tune, _ = autotune([HostConfig.from_workload(w)])
+    if tune is None:
+        tune, _ = autotune([HostConfig.from_workload(w)])
     sim = Sim.from_workload(w, tuning=tune)
     s0 = torch.from_numpy(w.state0()).cuda()
     N, Nb = w.weights()
@@ -221,7 +223,7 @@ def main():
                           "bytes_written": dst.numel() * 8, "launches": 5}), flush=True)
         return
     if args.probe == "adjoint":
-        r = measure_adjoint(steps=200, ckpt=50)
+        r = measure_adjoint(steps=200, ckpt=50, tune=json.loads(args.tuning) if args.tuning else None)
         print(json.dumps({"probe": "adjoint", **r}), flush=True)
         return
     if args.gpus != 1:
