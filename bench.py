@@ -26,10 +26,14 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = "particle-steps/s (deposit+gather+RK4) on 1 GPU vs roofline; adjoint/forward ratio"
 STATE_B = 18 * 8        # bytes of one particle's state
+SLOPE_B = 16 * 8        # bytes of one stored Runge-Kutta slope (traceless: 8 + 8 reals)
 GRID_B = 36 * 8         # bytes of one cell's combined moments
-# passes over the particle state per stage kernel (reads + writes) in the
-# stage-synchronous Runge-Kutta schedule: 2 + 3 + 3 + 5 = 13 per step
-STAGE_PASSES = {1: 2, 2: 3, 3: 3, 4: 5}
+# particle bytes per stage kernel in the stage-synchronous Runge-Kutta
+# schedule: stage 1 reads Y, writes k1; stages 2, 3 read Y and the previous
+# slope, write their slope; stage 4 reads Y, k1, k2, k3 and writes Y
+STAGE_BYTES = {1: STATE_B + SLOPE_B, 2: STATE_B + 2 * SLOPE_B, 3: STATE_B + 2 * SLOPE_B,
+               4: 2 * STATE_B + 3 * SLOPE_B}
+STEP_BYTES = sum(STAGE_BYTES.values())   # 1744 B per particle-step
 
 
 def kernel_source_hash():
@@ -141,7 +145,7 @@ def measure_3d(steps=20):
     P = w.nparticles
     part_ms = [ms[0], ms[2], ms[4], ms[6]]
     dep_ms = [ms[1], ms[3], ms[5], ms[7]]
-    part_bytes = [STAGE_PASSES[s] * STATE_B * P + 72 * P for s in (1, 2, 3, 4)]
+    part_bytes = [STAGE_BYTES[s] * P + 72 * P for s in (1, 2, 3, 4)]
     dep_bytes = 72 * P + GRID_B * w.ncell_total
     step_bytes = sum(part_bytes) + 4 * dep_bytes
     ms_step = 1e3 * wall / steps
@@ -152,7 +156,7 @@ def measure_3d(steps=20):
             "deposit_kernel_GBs": [dep_bytes / (t * 1e-3) / 1e9 for t in dep_ms],
             "alg_bytes_per_step": step_bytes,
             "step_frac_of_hbm_peak": step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
-            "step_frac_of_fused_floor": 1872 * P / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS}
+            "step_frac_of_fused_floor": STEP_BYTES * P / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
 
 def measure_batch(steps=100, nsim=64):
@@ -272,11 +276,11 @@ def main():
     red_ms = [ms[2 * s - 1] for s in (1, 2, 3, 4)]
     dom = max(stage_ms, key=lambda s: stage_ms[s])
     ncell = w.ncell_total
-    alg_bytes = STAGE_PASSES[dom] * STATE_B * w.nparticles + 2 * GRID_B * ncell
+    alg_bytes = STAGE_BYTES[dom] * w.nparticles + 2 * GRID_B * ncell
     achieved = alg_bytes / (stage_ms[dom] * 1e-3) / 1e9
     kname = f"stage{dom}"
     traffic = measured_traffic(kname, w.name, alg_bytes)
-    step_bytes = sum(STAGE_PASSES.values()) * STATE_B * w.nparticles + 4 * 2 * GRID_B * ncell
+    step_bytes = STEP_BYTES * w.nparticles + 4 * 2 * GRID_B * ncell
     ok = sim.check(1e-10)
 
     rec = {

@@ -73,7 +73,9 @@ __device__ __forceinline__ int pmod_i64(int64_t a, int n)
 
 // k = -i [H, rho] for Hermitian H, rho given as 9 packed reals (diagonal,
 // then Re/Im of the (0,1), (0,2), (1,2) entries).  With C = H rho:
-// k_aa = 2 Im C_aa and k_ab = -i (C_ab - conj(C_ba)) for a < b.
+// k_aa = 2 Im C_aa and k_ab = -i (C_ab - conj(C_ba)) for a < b.  The trace
+// of a commutator vanishes: k_00 is formed as -(k_11 + k_22), which is what
+// lets a stored slope drop it (NK).
 __device__ __forceinline__ void commutator(const double h[9], const double r[9], double k[9])
 {
     const double h0 = h[0], h1 = h[1], h2 = h[2];
@@ -81,9 +83,9 @@ __device__ __forceinline__ void commutator(const double h[9], const double r[9],
     const double p0 = r[0], p1 = r[1], p2 = r[2];
     const double xr = r[3], xi = r[4], yr = r[5], yi = r[6], zr = r[7], zi = r[8];
 
-    k[0] = 2.0 * ((ai * xr - ar * xi) + (bi * yr - br * yi));
     k[1] = 2.0 * ((ar * xi - ai * xr) + (ci * zr - cr * zi));
     k[2] = 2.0 * ((br * yi - bi * yr) + (cr * zi - ci * zr));
+    k[0] = -(k[1] + k[2]);
 
     // C01 = h0 x + a p1 + b z^*,  C10 = a^* p0 + h1 x^* + c y^*
     const double c01r = h0 * xr + ar * p1 + (br * zr + bi * zi);
@@ -115,6 +117,29 @@ __device__ __forceinline__ void commutator(const double h[9], const double r[9],
 typedef __attribute__((address_space(1))) double gdouble;
 __device__ __forceinline__ double gld(const double *p) { return *(const gdouble *)p; }
 __device__ __forceinline__ void gst(double *p, double v) { *(gdouble *)p = v; }
+
+// Slopes in memory: NK reals per particle, component c of the packed 18 at
+// slot c - 1 (c = 1..8) or c - 2 (c = 10..17); components 0 and 9 are the
+// negated sums of the next two.
+__device__ __forceinline__ int kslot(int c) { return c < 9 ? c - 1 : c - 2; }
+
+__device__ __forceinline__ void load_slope(const double *K, int64_t np, int64_t p, double k[18])
+{
+#pragma unroll
+    for (int c = 1; c < 18; c++)
+        if (c != 9)
+            k[c] = gld(K + kslot(c) * np + p);
+    k[0] = -(k[1] + k[2]);
+    k[9] = -(k[10] + k[11]);
+}
+
+__device__ __forceinline__ void store_slope(double *K, int64_t np, int64_t p, const double k[18])
+{
+#pragma unroll
+    for (int c = 1; c < 18; c++)
+        if (c != 9)
+            gst(K + kslot(c) * np + p, k[c]);
+}
 
 // r = i mod n for an integer-valued double i (|i| < 2^52), without 64-bit
 // integer division.
@@ -268,19 +293,23 @@ stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ si
                         y[k] = base[k] = Y[k];
                 } else if (MODE == M_S4) {
                     const double h6 = dt / 6.0;
+                    double k1[18], k2[18], k3[18];
+                    load_slope(S.K1, np, p, k1);
+                    load_slope(S.K2, np, p, k2);
+                    load_slope(S.K3, np, p, k3);
 #pragma unroll
                     for (int k = 0; k < 18; k++) {
-                        const double k3 = gld(S.K3 + k * np + p);
-                        y[k] = Y[k] + dt * k3;
-                        const double ks = (gld(S.K1 + k * np + p) + 2.0 * gld(S.K2 + k * np + p)) + 2.0 * k3;
+                        y[k] = Y[k] + dt * k3[k];
+                        const double ks = (k1[k] + 2.0 * k2[k]) + 2.0 * k3[k];
                         base[k] = Y[k] + h6 * ks;
                     }
                 } else {
-                    const double *Kp = (MODE == M_S2) ? S.K1 : S.K2;
                     const double a = 0.5 * dt;
+                    double kp[18];
+                    load_slope((MODE == M_S2) ? S.K1 : S.K2, np, p, kp);
 #pragma unroll
                     for (int k = 0; k < 18; k++) {
-                        y[k] = Y[k] + a * gld(Kp + k * np + p);
+                        y[k] = Y[k] + a * kp[k];
                         base[k] = Y[k];
                     }
                 }
@@ -305,11 +334,10 @@ stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ si
                 } else {
                     double *Ko = (MODE == M_S1) ? S.K1 : (MODE == M_S2) ? S.K2 : S.K3;
                     const double an = (MODE == M_S3) ? dt : 0.5 * dt;
+                    store_slope(Ko, np, p, kk);
 #pragma unroll
-                    for (int k = 0; k < 18; k++) {
-                        gst(Ko + k * np + p, kk[k]);
+                    for (int k = 0; k < 18; k++)
                         yn[k] = base[k] + an * kk[k];
-                    }
                 }
 #pragma unroll
                 for (int k = 0; k < 9; k++)
@@ -491,8 +519,10 @@ adj1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ sims
     for (int k = 0; k < NG; k++)
         acc[k] = 0.0;
 
-    const double *lam_in = S.lam[(n + 1) & 1];
-    double *lam_out = S.lam[n & 1];
+    // (selects, not a run-time index into the descriptor copy, which would
+    // put the whole copy in scratch memory)
+    const double *lam_in = (n & 1) ? S.lam[0] : S.lam[1];
+    double *lam_out = (n & 1) ? S.lam[1] : S.lam[0];
     const double *KB = (SB == 2) ? S.K1 : (SB == 3) ? S.K2 : S.K3;
     const double aB = (SB == 4) ? dt : 0.5 * dt;
     const double *KA = (SA == 2) ? S.K1 : (SA == 3) ? S.K2 : S.K3;
@@ -532,11 +562,24 @@ adj1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ sims
                 dX[k] = A + (vx * Bx + vy * By + vz * Bz);
             }
             if (active) {
+                double kb1 = 0.0, kb2 = 0.0, kb10 = 0.0, kb11 = 0.0;
+                if (SB != 1) {
+                    kb1 = gld(KB + kslot(1) * np + p);
+                    kb2 = gld(KB + kslot(2) * np + p);
+                    kb10 = gld(KB + kslot(10) * np + p);
+                    kb11 = gld(KB + kslot(11) * np + p);
+                }
 #pragma unroll
                 for (int k = 0; k < 9; k++) {
                     const double sgn = (k == 4 || k == 6 || k == 8) ? -1.0 : 1.0;
-                    const double yb = (SB == 1) ? Yv[k] : Yv[k] + aB * gld(KB + k * np + p);
-                    const double ybb = (SB == 1) ? Yv[9 + k] : Yv[9 + k] + aB * gld(KB + (9 + k) * np + p);
+                    double kbn = 0.0, kbb = 0.0;
+                    if (SB != 1) {
+                        kbn = (k == 0) ? -(kb1 + kb2) : (k == 1) ? kb1 : (k == 2) ? kb2 : gld(KB + kslot(k) * np + p);
+                        kbb = (k == 0) ? -(kb10 + kb11) : (k == 1) ? kb10 : (k == 2) ? kb11
+                                                                         : gld(KB + kslot(9 + k) * np + p);
+                    }
+                    const double yb = (SB == 1) ? Yv[k] : Yv[k] + aB * kbn;
+                    const double ybb = (SB == 1) ? Yv[9 + k] : Yv[9 + k] + aB * kbb;
                     lam_s[k] = gld(S.dres + k * np + p) + wN * dX[k];
                     lam_s[9 + k] = gld(S.dres + (9 + k) * np + p) - sgn * wNb * dX[k];
                     const double base_n = (SB == 4) ? gld(lam_in + k * np + p) : gld(lam_out + k * np + p);
@@ -582,13 +625,22 @@ adj1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ sims
                 for (int part = 0; part < 2; part++) {
                     const int o = 9 * part;
                     double G[9], y[9], H[9];
+                    double ka1 = 0.0, ka2 = 0.0;
+                    if (SA != 1) {
+                        ka1 = gld(KA + kslot(o + 1) * np + p);
+                        ka2 = gld(KA + kslot(o + 2) * np + p);
+                    }
 #pragma unroll
                     for (int k = 0; k < 9; k++) {
                         double gk = c1 * gld(lam_in + (o + k) * np + p);
                         if (DO_B)
                             gk += c2 * lam_s[o + k];
                         G[k] = (k >= 3) ? 0.5 * gk : gk;
-                        y[k] = (SA == 1) ? Yv[o + k] : Yv[o + k] + aA * gld(KA + (o + k) * np + p);
+                        double ka = 0.0;
+                        if (SA != 1)
+                            ka = (k == 0) ? -(ka1 + ka2) : (k == 1) ? ka1 : (k == 2) ? ka2
+                                                                     : gld(KA + kslot(o + k) * np + p);
+                        y[k] = (SA == 1) ? Yv[o + k] : Yv[o + k] + aA * ka;
                         const double hk = part == 0 ? hv[k] + Hnn[k] : hv[k] - Hnn[k];
                         H[k] = (part == 1 && (k == 4 || k == 6 || k == 8)) ? -hk : hk;
                     }

@@ -83,6 +83,20 @@ __device__ __forceinline__ void axis_shift(double v, double t, double dx, int n,
     *r = (int)q;
 }
 
+// Slopes in memory: fpic::NK reals per particle (components 0 and 9 are
+// the negated sums of the next two and are not stored).
+__device__ __forceinline__ int kslot(int c) { return c < 9 ? c - 1 : c - 2; }
+
+__device__ __forceinline__ void load_slope(const double *K, int64_t np, int64_t p, bool active, double k[18])
+{
+#pragma unroll
+    for (int c = 1; c < 18; c++)
+        if (c != 9)
+            k[c] = active ? gld(K + kslot(c) * np + p) : 0.0;
+    k[0] = -(k[1] + k[2]);
+    k[9] = -(k[10] + k[11]);
+}
+
 __device__ __forceinline__ double lane_get(double v, int src)
 {
     return __shfl(v, src, W);
@@ -94,9 +108,9 @@ __device__ __forceinline__ void commutator(const double h[9], const double r[9],
     const double ar = h[3], ai = h[4], br = h[5], bi = h[6], cr = h[7], ci = h[8];
     const double p0 = r[0], p1 = r[1], p2 = r[2];
     const double xr = r[3], xi = r[4], yr = r[5], yi = r[6], zr = r[7], zi = r[8];
-    k[0] = 2.0 * ((ai * xr - ar * xi) + (bi * yr - br * yi));
     k[1] = 2.0 * ((ar * xi - ai * xr) + (ci * zr - cr * zi));
     k[2] = 2.0 * ((br * yi - bi * yr) + (cr * zi - ci * zr));
+    k[0] = -(k[1] + k[2]);  // traceless: slopes are stored without k_00
     const double c01r = h0 * xr + ar * p1 + (br * zr + bi * zi);
     const double c01i = h0 * xi + ai * p1 + (bi * zr - br * zi);
     const double c10r = ar * p0 + h1 * xr + (cr * yr + ci * yi);
@@ -237,18 +251,22 @@ particle3d_kernel(const Desc3 *__restrict__ dp, int dpw, int nitems)
                     yv[k] = base[k] = Y[k];
             } else if (MODE == 4) {
                 const double h6 = dt / 6.0;
+                double k1[18], k2[18], k3[18];
+                load_slope(S.K1, S.np, p, active, k1);
+                load_slope(S.K2, S.np, p, active, k2);
+                load_slope(S.K3, S.np, p, active, k3);
 #pragma unroll
                 for (int k = 0; k < 18; k++) {
-                    const double k3 = active ? gld(S.K3 + k * S.np + p) : 0.0;
-                    yv[k] = Y[k] + dt * k3;
-                    const double ks = active ? (gld(S.K1 + k * S.np + p) + 2.0 * gld(S.K2 + k * S.np + p)) + 2.0 * k3
-                                             : 0.0;
+                    yv[k] = Y[k] + dt * k3[k];
+                    const double ks = (k1[k] + 2.0 * k2[k]) + 2.0 * k3[k];
                     base[k] = Y[k] + h6 * ks;
                 }
             } else {
+                double kp[18];
+                load_slope(Kp, S.np, p, active, kp);
 #pragma unroll
                 for (int k = 0; k < 18; k++) {
-                    yv[k] = Y[k] + a * (active ? gld(Kp + k * S.np + p) : 0.0);
+                    yv[k] = Y[k] + a * kp[k];
                     base[k] = Y[k];
                 }
             }
@@ -274,8 +292,8 @@ particle3d_kernel(const Desc3 *__restrict__ dp, int dpw, int nitems)
                 const double an = (MODE == 3) ? dt : 0.5 * dt;
 #pragma unroll
                 for (int k = 0; k < 18; k++) {
-                    if (active)
-                        gst(Ko + k * S.np + p, kk[k]);
+                    if (active && k != 0 && k != 9)
+                        gst(Ko + kslot(k) * S.np + p, kk[k]);
                     yn[k] = base[k] + an * kk[k];
                 }
             }
@@ -610,11 +628,12 @@ static int layout(const fpic_config &c, const fpic_tuning *t, Layout &L)
         return o;
     };
     const size_t st = sizeof(double) * 18 * (size_t)np;
+    const size_t sk = sizeof(double) * fpic::NK * (size_t)np;
     L.tab = take(sizeof(double) * 7 * c.ndir);
     L.Y = take(st);
-    L.K1 = take(st);
-    L.K2 = take(st);
-    L.K3 = take(st);
+    L.K1 = take(sk);
+    L.K2 = take(sk);
+    L.K3 = take(sk);
     L.X = take(sizeof(double) * 9 * (size_t)np);
     L.G0 = take(sizeof(double) * NG * (size_t)nc);
     L.G1 = take(sizeof(double) * NG * (size_t)nc);

@@ -20,6 +20,11 @@ constexpr int NG = 36;
 constexpr int GT_CELLS = 67;
 constexpr int GT_STRIDE = 68;
 constexpr int MAX_WAVES = 4;
+// Reals stored per Runge-Kutta slope.  A slope k = -i[H, rho] is traceless
+// (the trace of a commutator vanishes), so its first diagonal entry is kept
+// as -(k_11 + k_22) and only the other 8 + 8 reals of k and kbar are stored:
+// slot q < 8 holds packed component q + 1, slot q >= 8 component q + 2.
+constexpr int NK = 16;
 
 enum Mode : int {
     M_S1 = 1,       // RK stage 1: k1 = F(Y), deposit Y + dt/2 k1

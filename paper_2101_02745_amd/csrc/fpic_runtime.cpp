@@ -169,11 +169,12 @@ int make_plan(int nsim, const fpic_config *cfgs, const fpic_tuning *tune, Plan &
         s.ngroup = (s.ndir + dpg - 1) / dpg;
         P.max_dpw = std::max(P.max_dpw, s.dpw);
         const size_t st = sizeof(double) * 18 * (size_t)s.np;
+        const size_t sk = sizeof(double) * NK * (size_t)s.np;
         s.o_tab = cv.take(sizeof(double) * 7 * s.ndir);
         s.o_Y = cv.take(st);
-        s.o_K1 = cv.take(st);
-        s.o_K2 = cv.take(st);
-        s.o_K3 = cv.take(st);
+        s.o_K1 = cv.take(sk);
+        s.o_K2 = cv.take(sk);
+        s.o_K3 = cv.take(sk);
         s.o_G0 = cv.take(sizeof(double) * NG * s.ncell);
         s.o_G1 = cv.take(sizeof(double) * NG * s.ncell);
         s.o_part = cv.take(sizeof(double) * (size_t)s.ngroup * NG * s.ntile * TILE);
@@ -799,7 +800,7 @@ void adj_layout(const fpic_batch *b, int64_t nsteps, int L, fpic_batch::Adj &A)
     Carver cv;
     A.o_ckpt = cv.take(st * A.nseg);
     A.o_segY = cv.take(st * (L + 1));
-    A.o_segK = cv.take(st * 3 * (size_t)L);
+    A.o_segK = cv.take(sizeof(double) * NK * (size_t)s.np * 3 * (size_t)L);
     A.o_segG = cv.take(gr * 4 * (size_t)(L + 1));
     A.o_lam = cv.take(2 * st);
     A.o_lcur = cv.take(st);
@@ -947,7 +948,7 @@ int fpic_adjoint_forward(fpic_ctx *c, const fpic_adjoint_cfg *a, void *ws, size_
 
     // per-step descriptors of a segment
     const SimPlan &sp = b->plan.sims[0];
-    const size_t st = 18 * (size_t)sp.np, gr = NG * (size_t)sp.ncell;
+    const size_t st = 18 * (size_t)sp.np, sk = NK * (size_t)sp.np, gr = NG * (size_t)sp.ncell;
     double *segY = reinterpret_cast<double *>(A.ws + A.o_segY);
     double *segK = reinterpret_cast<double *>(A.ws + A.o_segK);
     double *segG = reinterpret_cast<double *>(A.ws + A.o_segG);
@@ -958,9 +959,9 @@ int fpic_adjoint_forward(fpic_ctx *c, const fpic_adjoint_cfg *a, void *ws, size_
         SimDesc D = b->hdesc[0];
         D.Y = segY + st * j;
         D.Yout = segY + st * (j + 1);
-        D.K1 = segK + st * (3 * (size_t)j + 0);
-        D.K2 = segK + st * (3 * (size_t)j + 1);
-        D.K3 = segK + st * (3 * (size_t)j + 2);
+        D.K1 = segK + sk * (3 * (size_t)j + 0);
+        D.K2 = segK + sk * (3 * (size_t)j + 1);
+        D.K3 = segK + sk * (3 * (size_t)j + 2);
         for (int q = 0; q < 4; ++q)
             D.G[q] = segG + gr * (4 * (size_t)j + q);
         D.G[4] = segG + gr * (4 * (size_t)(j + 1));
