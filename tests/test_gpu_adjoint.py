@@ -110,3 +110,35 @@ def test_autograd_against_finite_differences(torch_dev):
     fd = (L(base, seeds.detach() + h * v) - L(base, seeds.detach() - h * v)) / (2 * h)
     ad = float(np.sum(gs * v.cpu().numpy()))
     assert abs(fd - ad) <= 1e-4 * max(abs(ad), 1e-12), (fd, ad)
+
+
+def test_autograd_full_gradient_workload(torch_dev):
+    """The gradient workload at full size: 512 x 128 (65,536 particles), all
+    2000 steps with a checkpoint every 50, at the stable companion point
+    (no crossing in the electron-lepton-number distribution, so the
+    evolution is not chaotic and finite differences are meaningful):
+    d(L_nu + L_nubar)/d(nbar/n, f, fbar) from the adjoint against central
+    differences of the HIP forward pass, h = 1e-6 relative."""
+    import torch
+    from paper_2101_02745_amd.autograd import evolve
+    w = I.workload("1d_512x128_stable")
+    nsteps, ckpt = w.steps, 50
+    assert nsteps == 2000
+    params = torch.tensor([w.nbar_over_n, w.f, w.fbar], dtype=torch.float64, requires_grad=True)
+    seeds = torch.from_numpy(w.alpha * I.seed_draws(w.ndir, w.ncell_total, w.seed)).cuda()
+    Lnu, Lnb = evolve(params, seeds, w, nsteps, ckpt)
+    (Lnu + Lnb).backward()
+    gp = params.grad.numpy().copy()
+
+    def L(p):
+        a, b = evolve(torch.tensor(p, dtype=torch.float64), seeds, w, nsteps, ckpt)
+        return float(a + b)
+
+    base = params.detach().numpy()
+    for i in range(3):
+        h = 1e-6 * max(1.0, abs(base[i]))
+        pp, pm = base.copy(), base.copy()
+        pp[i] += h
+        pm[i] -= h
+        fd = (L(pp) - L(pm)) / (2 * h)
+        assert abs(fd - gp[i]) <= 1e-6 * max(abs(fd), 1e-6), (i, fd, gp[i])
