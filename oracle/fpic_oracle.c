@@ -15,8 +15,10 @@
  *     n, f, nbar, fbar, one particle after another, in particle order;
  *   - interpolation follows eq. pic_interpolation with the same weights;
  *   - the Hamiltonians follow eq. potentials and the antineutrino
- *     conventions of Sec. II.A (Hbar_vac = H_vac^*, Hbar_nunu = -H_nunu^*);
- *     the matter term is zero (comoving frame with no background leptons);
+ *     conventions of Sec. II.A (Hbar_vac = H_vac^*, Hbar_mat = -H_mat^*,
+ *     Hbar_nunu = -H_nunu^*); the matter term is the diagonal potential
+ *     V_a = sqrt(2) G_F (n_a - nbar_a) of the background charged leptons in
+ *     their rest frame (zero lepton flux), an input;
  *   - the right-hand side is eq. eom, d rho/dt = -i [H, rho], with both
  *     products H rho and rho H formed as full matrix products;
  *   - time integration is the classical fourth-order Runge-Kutta method
@@ -63,6 +65,7 @@ typedef struct {
     const double *Nbar; /* [ndir] antineutrinos per particle */
     const double *Hvac; /* [3][3] complex, row-major (re, im) pairs */
     double dt;
+    const double *Vmat; /* [3] matter potential V_e, V_mu, V_tau, or NULL (none) */
 } oracle_problem;
 
 /* ------------------------------------------------------------------ */
@@ -136,6 +139,12 @@ static void load_hvac(const oracle_problem *P, cplx H[3][3])
     for (int i = 0; i < 3; i++)
         for (int j = 0; j < 3; j++)
             H[i][j] = P->Hvac[2 * (3 * i + j)] + I * P->Hvac[2 * (3 * i + j) + 1];
+}
+
+static void load_vmat(const oracle_problem *P, double V[3])
+{
+    for (int a = 0; a < 3; a++)
+        V[a] = P->Vmat ? P->Vmat[a] : 0.0;
 }
 
 /* ------------------------------------------------------------------ */
@@ -265,11 +274,13 @@ static void interpolate(const moments *grid, const stencil *S, moments *out)
 }
 
 /* Hamiltonians of a particle with direction v from its interpolated
- * moments (eq. potentials, matter term zero):
- *   H_nunu = (n - nbar^*) - v.(f - fbar^*),  H = H_vac + H_nunu,
- *   Hbar = H_vac^* - H_nunu^*  (antineutrino conventions of Sec. II.A). */
-static void hamiltonians(const moments *m, const double *v, cplx Hv[3][3], cplx H[3][3],
-                         cplx Hb[3][3])
+ * moments (eq. potentials):
+ *   H_nunu = (n - nbar^*) - v.(f - fbar^*),  H_mat = diag(V),
+ *   H = H_vac + H_mat + H_nunu,
+ *   Hbar = H_vac^* - H_mat^* - H_nunu^*  (antineutrino conventions of
+ *   Sec. II.A). */
+static void hamiltonians(const moments *m, const double *v, cplx Hv[3][3], const double Vm[3],
+                         cplx H[3][3], cplx Hb[3][3])
 {
     cplx Hnn[3][3];
     for (int i = 0; i < 3; i++)
@@ -284,6 +295,10 @@ static void hamiltonians(const moments *m, const double *v, cplx Hv[3][3], cplx 
             H[i][j] = Hv[i][j] + Hnn[i][j];
             Hb[i][j] = conj(Hv[i][j]) - conj(Hnn[i][j]);
         }
+    for (int a = 0; a < 3; a++) {
+        H[a][a] += Vm[a];
+        Hb[a][a] -= Vm[a];
+    }
 }
 
 /* Right-hand side of eq. eom for every particle at time t. */
@@ -292,7 +307,9 @@ static void rhs(const oracle_problem *P, const double *state, double t,
 {
     const int64_t nc = ncell_total(P), nd = P->ndir, np = nc * nd;
     cplx Hv[3][3];
+    double Vm[3];
     load_hvac(P, Hv);
+    load_vmat(P, Vm);
     deposit(P, state, t, grid);
 #ifdef _OPENMP
 #pragma omp parallel for schedule(static)
@@ -305,7 +322,7 @@ static void rhs(const oracle_problem *P, const double *state, double t,
         moments m;
         interpolate(grid, &S, &m);
         cplx H[3][3], Hb[3][3];
-        hamiltonians(&m, v, Hv, H, Hb);
+        hamiltonians(&m, v, Hv, Vm, H, Hb);
         cplx rho[3][3], rhob[3][3], k[3][3], kb[3][3];
         unpack(state + p, np, rho);
         unpack(state + 9 * np + p, np, rhob);
@@ -498,7 +515,9 @@ static void rhs_vjp(const oracle_problem *P, const double *y, double t, const do
     const int64_t nc = ncell_total(P), nd = P->ndir, np = nc * nd;
     const double dV = P->dx[0] * P->dx[1] * P->dx[2];
     cplx Hv[3][3];
+    double Vm[3];
     load_hvac(P, Hv);
+    load_vmat(P, Vm);
     deposit(P, y, t, grid);
     memset(cot, 0, sizeof(moments) * (size_t)nc);
     /* commutators, Hamiltonians and the transpose of the interpolation */
@@ -510,7 +529,7 @@ static void rhs_vjp(const oracle_problem *P, const double *y, double t, const do
         moments m;
         interpolate(grid, &S, &m);
         cplx H[3][3], Hb[3][3];
-        hamiltonians(&m, v, Hv, H, Hb);
+        hamiltonians(&m, v, Hv, Vm, H, Hb);
         cplx rho[3][3], rhob[3][3], Gc[3][3], Gb[3][3];
         unpack(y + p, np, rho);
         unpack(y + 9 * np + p, np, rhob);
@@ -524,7 +543,7 @@ static void rhs_vjp(const oracle_problem *P, const double *y, double t, const do
         commutator_rhs(rhob, Gb, Xhb);
         cotangent_to_packed_add(Xr, gy + p, np);
         cotangent_to_packed_add(Xrb, gy + 9 * np + p, np);
-        /* H = Hv + Hnn, Hbar = Hv^* - Hnn^*: cot(Hnn) = Xh - conj(Xhb) */
+        /* H = Hv + Hm + Hnn, Hbar = Hv^* - Hm^* - Hnn^*: cot(Hnn) = Xh - conj(Xhb) */
         cplx Xn[3][3];
         for (int i = 0; i < 3; i++)
             for (int j = 0; j < 3; j++)

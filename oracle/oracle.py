@@ -22,7 +22,7 @@ _dp = C.POINTER(C.c_double)
 class _Problem(C.Structure):
     _fields_ = [("ncell", C.c_int64 * 3), ("dx", C.c_double * 3),
                 ("ndir", C.c_int64), ("dirs", _dp), ("N", _dp),
-                ("Nbar", _dp), ("Hvac", _dp), ("dt", C.c_double)]
+                ("Nbar", _dp), ("Hvac", _dp), ("dt", C.c_double), ("Vmat", _dp)]
 
 
 _lib = None
@@ -65,10 +65,12 @@ class Problem:
     """A periodic box with one particle per direction per cell.
 
     ncell: (nx, ny, nz); dx: cell widths; dirs [ndir][3]; N, Nbar [ndir]
-    (neutrinos per particle); hvac: 3x3 complex; dt: time step.
+    (neutrinos per particle); hvac: 3x3 complex; dt: time step; vmat: the
+    matter potentials (V_e, V_mu, V_tau) of the background charged leptons
+    (eq. potentials; zero by default).
     """
 
-    def __init__(self, ncell, dx, dirs, N, Nbar, hvac, dt: float):
+    def __init__(self, ncell, dx, dirs, N, Nbar, hvac, dt: float, vmat=None):
         self.ncell = tuple(int(n) for n in ncell)
         self.dx = tuple(float(x) for x in dx)
         self.dirs = np.ascontiguousarray(dirs, dtype=np.float64).reshape(-1, 3)
@@ -81,15 +83,16 @@ class Problem:
         h[1::2] = H.imag.ravel()
         self.hvac = h
         self.dt = float(dt)
+        self.vmat = np.zeros(3) if vmat is None else np.ascontiguousarray(vmat, dtype=np.float64).reshape(3)
         self._s = _Problem((C.c_int64 * 3)(*self.ncell), (C.c_double * 3)(*self.dx),
                            self.ndir, _ptr(self.dirs), _ptr(self.N),
-                           _ptr(self.Nbar), _ptr(self.hvac), self.dt)
+                           _ptr(self.Nbar), _ptr(self.hvac), self.dt, _ptr(self.vmat))
 
     @classmethod
     def from_workload(cls, w, hvac=None) -> "Problem":
         N, Nbar = w.weights()
         return cls(w.ncell, w.dx, w.dirs(), N, Nbar,
-                   w.hvac() if hvac is None else hvac, w.dt)
+                   w.hvac() if hvac is None else hvac, w.dt, vmat=w.vmat)
 
     @property
     def ncell_total(self) -> int:

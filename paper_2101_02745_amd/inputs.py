@@ -294,6 +294,10 @@ class Workload:
     sim: int = 0
     alpha: float = 1e-6
     vacuum: bool = True
+    # matter potentials (V_e, V_mu, V_tau) of the background charged
+    # leptons; the benchmark workloads have none (comoving frame with no
+    # net lepton density, as the paper's fiducial runs)
+    vmat: tuple = (0.0, 0.0, 0.0)
 
     @property
     def ncell_total(self) -> int:

@@ -83,3 +83,22 @@ def test_p12b_vacuum_adjoint_closed_form():
         want[5], want[6] = 2 * X[0, 2].real, 2 * X[0, 2].imag
         want[7], want[8] = 2 * X[1, 2].real, 2 * X[1, 2].imag
         assert np.abs(g0[part] - want).max() < 1e-9 * np.abs(want).max()
+
+
+def test_p12a_adjoint_with_matter():
+    """The reverse mode with a matter potential (a constant diagonal term,
+    opposite in sign for antineutrinos) against central differences."""
+    rng = np.random.default_rng(23)
+    P0, st = small_problem(rng)
+    V = np.array([0.9, -0.3, 0.2])
+    P = Problem(P0.ncell, P0.dx, P0.dirs, P0.N, P0.Nbar, np.zeros((3, 3)), P0.dt, vmat=V)
+    P.hvac[:] = P0.hvac
+    nsteps = 6
+    c = rng.normal(size=st.shape)
+    g0, _, _ = P.adjoint(st, nsteps, c)
+    h = 1e-6
+    for _ in range(3):
+        v = rng.normal(size=st.shape)
+        fd = (loss(P, st + h * v, nsteps, c) - loss(P, st - h * v, nsteps, c)) / (2 * h)
+        ad = float(np.sum(g0 * v))
+        assert abs(fd - ad) <= 1e-7 * max(1.0, abs(ad)), (fd, ad)

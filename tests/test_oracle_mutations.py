@@ -41,6 +41,8 @@ MUTANTS = {
     "volume_not_divided": ("g->n[i][j] /= dV;", "g->n[i][j] /= 1.0;"),
     "gather_weight_dropped": ("out->n[i][j] += w * g->n[i][j];",
                               "out->n[i][j] += g->n[i][j];"),
+    "matter_sign": ("H[a][a] += Vm[a];", "H[a][a] -= Vm[a];"),
+    "antinu_matter_sign": ("Hb[a][a] -= Vm[a];", "Hb[a][a] += Vm[a];"),
     # reverse mode
     "adjoint_rho_cotangent_sign": ("commutator_rhs(Gc, H, Xr);", "commutator_rhs(H, Gc, Xr);"),
     "adjoint_hbar_not_conjugated": ("Xn[i][j] = Xh[i][j] - conj(Xhb[i][j]);",

@@ -364,3 +364,69 @@ def test_p2_fourth_order_with_advection():
         res[m] = P.step(st, m)
     e = [np.abs(res[m] - res[64]).max() for m in (2, 4, 8)]
     assert e[0] / e[1] > 11 and e[1] / e[2] > 13, e
+
+
+# ------------------------------------------------------------ matter term
+def two_level_probability(H, t):
+    """P(e -> mu) of a two-level Hamiltonian started in e: textbook
+    sin^2(2 theta_m) sin^2(Delta_m t / 2) with Delta_m the level splitting."""
+    dd = H[0, 0].real - H[1, 1].real
+    off = abs(H[0, 1])
+    Dm = math.sqrt(dd * dd + 4 * off * off)
+    return (4 * off * off / (Dm * Dm)) * math.sin(Dm * t / 2) ** 2
+
+
+def test_p1_matter_closed_form():
+    """Constant vacuum plus matter Hamiltonian (eq. potentials with the
+    antineutrino conventions of Sec. II.A: H = H_vac + diag(V),
+    Hbar = H_vac^* - diag(V)) and no self-interaction: both evolve in
+    closed form; the antineutrino's matter sign is checked by contrast."""
+    rng = np.random.default_rng(21)
+    H, dirs, st = vacuum_setup(rng)
+    V = np.array([0.7, -0.2, 0.4])
+    zero = np.zeros(dirs.shape[0])
+    dt, nsteps = 0.005, 400
+    P = Problem((1, 1, 3), (1.0, 1.0, 2.0), dirs, zero, zero, H, dt, vmat=V)
+    out = P.step(st, nsteps)
+    t = nsteps * dt
+    Hn = H + np.diag(V)
+    Hb = H.conj() - np.diag(V)
+    err = max(np.abs(herm_from_packed(out[:9]) - vacuum_exact(Hn, herm_from_packed(st[:9]), t)).max(),
+              np.abs(herm_from_packed(out[9:]) - vacuum_exact(Hb, herm_from_packed(st[9:]), t)).max())
+    assert err < 1e-10, err
+    wrong = vacuum_exact(H.conj() + np.diag(V), herm_from_packed(st[9:]), t)
+    assert np.abs(herm_from_packed(out[9:]) - wrong).max() > 1e-3
+
+
+def test_p1_msw_resonant_antineutrino():
+    """App. A.1: one zone, two flavors, the antineutrino at the MSW
+    resonance converts completely, the neutrino (potential of the opposite
+    sign) only partially; both follow the analytic two-level formula far
+    inside the paper's 3.7e-4."""
+    theta, Delta = 0.15, 1.0
+    c, s = math.cos(theta), math.sin(theta)
+    U = np.array([[c, s, 0], [-s, c, 0], [0, 0, 1]], dtype=complex)
+    H = U @ np.diag([0.0, Delta, 0.0]) @ U.conj().T
+    Ve = -Delta * math.cos(2 * theta)        # antineutrino resonance
+    V = np.array([Ve, 0.0, 0.0])
+    st = np.zeros((18, 1, 1))
+    st[0] = 1.0
+    st[9] = 1.0
+    dt = 0.01
+    P = Problem((1, 1, 1), (1.0, 1.0, 1.0), [[0, 0, 1.0]], [0.0], [0.0], H, dt, vmat=V)
+    Hn = H + np.diag(V)
+    Hb = H.conj() - np.diag(V)
+    assert abs(Hb[0, 0] - Hb[1, 1]) < 1e-15          # resonance
+    s_state, dev = st, 0.0
+    for k in range(1, 41):
+        s_state = P.step(s_state, 50, n0=50 * (k - 1))
+        t = 50 * k * dt
+        dev = max(dev, abs(s_state[10, 0, 0] - two_level_probability(Hb, t)),
+                  abs(s_state[1, 0, 0] - two_level_probability(Hn, t)))
+    assert dev < 1e-9 < GOLDEN["msw"]["paper_max_abs_dev"], dev
+    # full conversion of the antineutrino at the first maximum
+    tmax = math.pi / (2 * abs(Hb[0, 1]))
+    n = round(tmax / dt)
+    out = P.step(st, n)
+    assert out[10, 0, 0] > 1 - 1e-6
+    assert out[1, 0, 0] < 0.5
