@@ -68,6 +68,11 @@ typedef struct fpic_config {
     const double *Nbar;  /* host [ndir] antineutrinos per particle */
     double hvac[18];     /* vacuum Hamiltonian, 3x3 complex Hermitian,
                             row-major (re, im) pairs, flavor basis */
+    double vmat[3];      /* matter potentials V_e, V_mu, V_tau of the
+                            background charged leptons (eq. potentials,
+                            their rest frame): H gains diag(V), Hbar
+                            -diag(V) (Hbar_mat = -H_mat^*, Sec. II.A);
+                            0 = no matter */
     double dt;           /* time step; a stage may move no particle by a
                             whole cell: dt/2 * max|Omega_a| < dx_a */
     int32_t shape_order; /* 1 (linear, cloud-in-cell) */

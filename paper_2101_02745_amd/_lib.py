@@ -35,7 +35,7 @@ class FpicError(RuntimeError):
 class Config(C.Structure):
     _fields_ = [("ncell", C.c_int32 * 3), ("dx", C.c_double * 3),
                 ("ndir", C.c_int32), ("dirs", _dp), ("N", _dp), ("Nbar", _dp),
-                ("hvac", C.c_double * 18), ("dt", C.c_double),
+                ("hvac", C.c_double * 18), ("vmat", C.c_double * 3), ("dt", C.c_double),
                 ("shape_order", C.c_int32), ("flags", C.c_int32)]
 
 
@@ -116,7 +116,7 @@ def check(rc: int):
 class HostConfig:
     """A Config plus the host arrays it points to (kept alive together)."""
 
-    def __init__(self, ncell, dx, dirs, N, Nbar, hvac, dt, shape_order=1):
+    def __init__(self, ncell, dx, dirs, N, Nbar, hvac, dt, shape_order=1, vmat=None):
         self.dirs = np.ascontiguousarray(dirs, dtype=np.float64).reshape(-1, 3)
         nd = self.dirs.shape[0]
         self.N = np.ascontiguousarray(N, dtype=np.float64).reshape(nd)
@@ -134,6 +134,7 @@ class HostConfig:
         self.c.N = self.N.ctypes.data_as(_dp)
         self.c.Nbar = self.Nbar.ctypes.data_as(_dp)
         self.c.hvac[:] = h.tolist()
+        self.c.vmat[:] = [0.0, 0.0, 0.0] if vmat is None else [float(x) for x in vmat]
         self.c.dt = float(dt)
         self.c.shape_order = int(shape_order)
         self.c.flags = 0
@@ -150,7 +151,7 @@ class HostConfig:
     def from_workload(cls, w, hvac=None):
         N, Nbar = w.weights()
         return cls(w.ncell, w.dx, w.dirs(), N, Nbar,
-                   w.hvac() if hvac is None else hvac, w.dt)
+                   w.hvac() if hvac is None else hvac, w.dt, vmat=w.vmat)
 
 
 def tuning(t) -> Tuning:

@@ -226,10 +226,12 @@ stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ si
     }
     __syncthreads();
 
-    double hv[9];
+    double hv[9], hvb[9];
 #pragma unroll
-    for (int k = 0; k < 9; k++)
+    for (int k = 0; k < 9; k++) {
         hv[k] = S.hvac[k];
+        hvb[k] = S.hvacb[k];
+    }
 
     double acc[NG];
 #pragma unroll
@@ -313,12 +315,13 @@ stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ si
                         base[k] = Y[k];
                     }
                 }
-                // Hamiltonians: H = Hvac + Hnn, Hbar = (Hvac - Hnn)^*
+                // Hamiltonians: H = Hvac + Hmat + Hnn,
+                // Hbar = (Hvac - Hmat - Hnn)^*
                 double H[9], Hb[9], kk[18];
 #pragma unroll
                 for (int k = 0; k < 9; k++) {
                     H[k] = hv[k] + Hnn[k];
-                    const double hb = hv[k] - Hnn[k];
+                    const double hb = hvb[k] - Hnn[k];
                     Hb[k] = (k == 4 || k == 6 || k == 8) ? -hb : hb;
                 }
                 commutator(H, y, kk);
@@ -510,10 +513,12 @@ adj1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ sims
     }
     __syncthreads();
 
-    double hv[9];
+    double hv[9], hvb[9];
 #pragma unroll
-    for (int k = 0; k < 9; k++)
+    for (int k = 0; k < 9; k++) {
         hv[k] = S.hvac[k];
+        hvb[k] = S.hvacb[k];
+    }
     double acc[NG];
 #pragma unroll
     for (int k = 0; k < NG; k++)
@@ -641,7 +646,7 @@ adj1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ sims
                             ka = (k == 0) ? -(ka1 + ka2) : (k == 1) ? ka1 : (k == 2) ? ka2
                                                                      : gld(KA + kslot(o + k) * np + p);
                         y[k] = (SA == 1) ? Yv[o + k] : Yv[o + k] + aA * ka;
-                        const double hk = part == 0 ? hv[k] + Hnn[k] : hv[k] - Hnn[k];
+                        const double hk = part == 0 ? hv[k] + Hnn[k] : hvb[k] - Hnn[k];
                         H[k] = (part == 1 && (k == 4 || k == 6 || k == 8)) ? -hk : hk;
                     }
                     double Dk[9], dH[9];

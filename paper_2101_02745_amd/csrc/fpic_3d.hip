@@ -41,7 +41,8 @@ struct Desc3 {
     int32_t ndir;
     int64_t ncell, np;
     double dt, dx[3];
-    double hvac[9];
+    double hvac[9];         // constant part of H (vacuum + matter), packed
+    double hvacb[9];        // of Hbar before conjugation (vacuum - matter)
     const double *v[3];     // [ndir] direction components
     const double *wN, *wNb; // [ndir] N/dV, Nbar/dV
     const double *Nw, *Nbw; // [ndir] N, Nbar
@@ -274,7 +275,7 @@ particle3d_kernel(const Desc3 *__restrict__ dp, int dpw, int nitems)
 #pragma unroll
             for (int k = 0; k < 9; k++) {
                 H[k] = S.hvac[k] + Hnn[k];
-                const double hb = S.hvac[k] - Hnn[k];
+                const double hb = S.hvacb[k] - Hnn[k];
                 Hb[k] = (k == 4 || k == 6 || k == 8) ? -hb : hb;
             }
             commutator(H, yv, kk);
@@ -568,6 +569,9 @@ static int validate(const fpic_config &c)
             return fail(FPIC_EINVAL, "hvac has a non-finite entry");
         hmax = std::max(hmax, std::fabs(c.hvac[i]));
     }
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(c.vmat[a]))
+            return fail(FPIC_EINVAL, "vmat has a non-finite entry");
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) {
             const double re = c.hvac[2 * (3 * i + j)], im = c.hvac[2 * (3 * i + j) + 1];
@@ -730,8 +734,10 @@ int create(const fpic_config &cfg, const fpic_tuning *tune, void *ws, size_t byt
     D.dt = cfg.dt;
     const double *h = cfg.hvac;
     const double hv[9] = {h[0], h[8], h[16], h[2], h[3], h[4], h[5], h[10], h[11]};
-    for (int k = 0; k < 9; ++k)
-        D.hvac[k] = hv[k];
+    for (int k = 0; k < 9; ++k) {
+        D.hvac[k] = hv[k] + (k < 3 ? cfg.vmat[k] : 0.0);
+        D.hvacb[k] = hv[k] - (k < 3 ? cfg.vmat[k] : 0.0);
+    }
     const double *tb = reinterpret_cast<const double *>(c->ws + L.tab);
     for (int a = 0; a < 3; ++a)
         D.v[a] = tb + a * nd;

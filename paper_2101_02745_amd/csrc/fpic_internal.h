@@ -53,7 +53,8 @@ struct SimDesc {
     int64_t np;      // particles = ndir * ncell
     double dt;       // time step
     double dz;       // cell width
-    double hvac[9];  // vacuum Hamiltonian, packed (diag, Re/Im upper)
+    double hvac[9];  // constant part of H: vacuum + matter, packed (diag, Re/Im upper)
+    double hvacb[9]; // constant part of Hbar before conjugation: vacuum - matter
     const double *vx, *vy, *vz;  // [ndir] direction components
     const double *wN, *wNb;      // [ndir] N / dV, Nbar / dV
     const double *Nw, *Nbw;      // [ndir] N, Nbar

@@ -98,6 +98,9 @@ int validate_1d(const fpic_config &c, int idx)
             return bad("hvac has a non-finite entry");
         hmax = std::max(hmax, std::fabs(c.hvac[i]));
     }
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(c.vmat[a]))
+            return bad("vmat has a non-finite entry");
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) {
             const double re = c.hvac[2 * (3 * i + j)], im = c.hvac[2 * (3 * i + j) + 1];
@@ -347,11 +350,15 @@ int batch_build(int nsim, const fpic_config *cfgs, const fpic_tuning *tune, void
         D.np = s.np;
         D.dt = c.dt;
         D.dz = c.dx[2];
-        // packed upper triangle of hvac
+        // packed upper triangle of hvac; the matter potential adds to the
+        // diagonal for neutrinos and subtracts for antineutrinos (before
+        // the conjugation that forms Hbar)
         const double *h = c.hvac;
         const double hv[9] = {h[0], h[8], h[16], h[2], h[3], h[4], h[5], h[10], h[11]};
-        for (int k = 0; k < 9; ++k)
-            D.hvac[k] = hv[k];
+        for (int k = 0; k < 9; ++k) {
+            D.hvac[k] = hv[k] + (k < 3 ? c.vmat[k] : 0.0);
+            D.hvacb[k] = hv[k] - (k < 3 ? c.vmat[k] : 0.0);
+        }
         const double *tb = reinterpret_cast<const double *>(b->ws + s.o_tab);
         D.vx = tb;
         D.vy = tb + s.ndir;

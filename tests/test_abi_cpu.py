@@ -51,6 +51,8 @@ def cfg_of(**kw):
             hc.c.shape_order = v
         elif k == "hvac":
             hc.c.hvac[:] = v
+        elif k == "vmat":
+            hc.c.vmat[:] = v
         elif k == "dirs":
             hc.dirs[:] = v
         elif k == "ncell":
@@ -70,7 +72,7 @@ def test_workspace_size_is_consistent(lib):
     rc, n = ws_bytes(lib, hc)
     assert rc == 0
     P = 26 * 32
-    assert n >= 4 * 18 * 8 * P          # state + three slopes
+    assert n >= (18 + 3 * 16) * 8 * P   # state + three slopes of 16 reals
     assert n < 64 * 18 * 8 * P + (1 << 20)
     rc2, n2 = ws_bytes(lib, hc, {"waves": 1, "dirs_per_wave": 1})
     assert rc2 == 0 and n2 > n          # more direction groups, more partials
@@ -82,6 +84,8 @@ def test_workspace_size_is_consistent(lib):
     ({"dt": float("nan")}, _lib.FPIC_EINVAL),
     ({"shape_order": 2}, _lib.FPIC_EUNSUPPORTED),
     ({"hvac": [0.0, 1.0] + [0.0] * 16}, _lib.FPIC_EINVAL),   # not Hermitian
+    ({"vmat": [0.0, float("inf"), 0.0]}, _lib.FPIC_EINVAL),
+    ({"vmat": [0.0, float("inf"), 0.0], "ncell": [4, 4, 4]}, _lib.FPIC_EINVAL),   # 3D path
     ({"dirs": 2.0}, _lib.FPIC_EINVAL),           # not unit vectors
     ({"ncell": [1, 1, 0]}, _lib.FPIC_EINVAL),
 ])
@@ -90,6 +94,8 @@ def test_bad_configs_rejected(lib, kw, code):
     rc, _ = ws_bytes(lib, hc)
     assert rc == code
     assert len(lib.fpic_last_error()) > 0
+    if "vmat" in kw:
+        assert b"vmat" in lib.fpic_last_error()
 
 
 def test_bad_tuning_rejected(lib):

@@ -114,3 +114,15 @@ def test_3d_full_size_lepton_number(torch_dev):
     assert np.abs(t1 - t0).max() > 1e-7 * scale
     assert np.abs(L1 - L0).max() < 1e-12 * scale
     assert sim.check(1e-12) < 1e-13
+
+
+def test_3d_matter_potential(torch_dev):
+    import dataclasses
+    from paper_2101_02745_amd.sim import Sim
+    w = dataclasses.replace(box((9, 5, 4), 26), vmat=(0.5, 0.0, -0.3))
+    s0 = w.state0()
+    sim = Sim.from_workload(w)
+    sim.set_state(s0, step0=7)
+    sim.step(5)
+    ref = Problem.from_workload(w).step(s0, 5, n0=7)
+    assert_parity(sim.get_state().cpu().numpy(), ref, what="3d matter")

@@ -142,3 +142,23 @@ def test_autograd_full_gradient_workload(torch_dev):
         pm[i] -= h
         fd = (L(pp) - L(pm)) / (2 * h)
         assert abs(fd - gp[i]) <= 1e-6 * max(abs(fd), 1e-6), (i, fd, gp[i])
+
+
+def test_adjoint_with_matter(torch_dev):
+    import dataclasses
+    from paper_2101_02745_amd.sim import Sim
+    w = dataclasses.replace(
+        I.Workload(name="am", ncell=(1, 1, 40), length=(1.0, 1.0, 8.0), ndir=26, dt=0.1,
+                   steps=6, f=0.2, fbar=-0.3, nbar_over_n=0.9, seed=12, alpha=1e-2),
+        vmat=(0.6, -0.2, 0.1))
+    rng = np.random.default_rng(40)
+    c = rng.normal(size=(18, w.ndir, w.ncell_total))
+    s0 = w.state0()
+    g_ref, gN_ref, gNb_ref = Problem.from_workload(w).adjoint(s0, 6, c)
+    sim = Sim.from_workload(w)
+    sim.set_state(s0)
+    sim.adjoint_forward(6, 4)
+    g0, gN, gNb = sim.adjoint_backward(c)
+    assert normwise(g0.cpu().numpy(), g_ref) < 1e-10
+    assert normwise(gN, gN_ref) < 1e-10
+    assert normwise(gNb, gNb_ref) < 1e-10

@@ -277,3 +277,52 @@ def test_full_batch_sampled(torch_dev):
         tr = (s[0] + s[1] + s[2] - 1.0).abs().max().item()
         trb = (s[9] + s[10] + s[11] - 1.0).abs().max().item()
         assert max(tr, trb) < 1e-14, (i, tr, trb)
+
+
+@pytest.mark.parametrize("ncell,ndir,tuning", [(70, 26, None), (150, 92, {"waves": 2, "dirs_per_wave": 3})])
+def test_matter_potential_parity(torch_dev, ncell, ndir, tuning):
+    """A background matter potential (eq. potentials; opposite sign for
+    antineutrinos, Sec. II.A) on top of vacuum and self-interaction."""
+    import dataclasses
+    w = dataclasses.replace(
+        I.Workload(name="mat", ncell=(1, 1, ncell), length=(1.0, 1.0, 0.2 * ncell), ndir=ndir,
+                   dt=0.1, steps=0, f=0.2, fbar=-0.3, nbar_over_n=0.9, seed=9, alpha=1e-2),
+        vmat=(0.8, -0.25, 0.1))
+    _, _, got, ref = run_pair(w, 8, tuning=tuning, step0=5)
+    assert_parity(got, ref, what="matter")
+    # the potential matters: without it the result differs
+    ref0 = Problem.from_workload(dataclasses.replace(w, vmat=(0.0, 0.0, 0.0))).step(w.state0(), 8, n0=5)
+    assert np.abs(ref0 - ref).max() > 1e-6
+
+
+def test_msw_resonant_antineutrino_on_gpu(torch_dev):
+    """App. A.1 on the HIP path: one zone, two flavors, the antineutrino at
+    the MSW resonance; deviation from the analytic two-level formula far
+    inside the paper's 3.7e-4, and full conversion at the first maximum."""
+    from paper_2101_02745_amd.sim import Sim
+    from paper_2101_02745_amd._lib import HostConfig
+    from test_oracle_pins import two_level_probability
+    theta, Delta, dt = 0.15, 1.0, 0.01
+    c, s = math.cos(theta), math.sin(theta)
+    U = np.array([[c, s, 0], [-s, c, 0], [0, 0, 1]], dtype=complex)
+    H = U @ np.diag([0.0, Delta, 0.0]) @ U.conj().T
+    V = (-Delta * math.cos(2 * theta), 0.0, 0.0)
+    hc = HostConfig((1, 1, 1), (1.0, 1.0, 1.0), [[0, 0, 1.0]], [0.0], [0.0], H, dt, vmat=V)
+    sim = Sim(hc)
+    st = np.zeros((18, 1, 1))
+    st[0] = st[9] = 1.0
+    sim.set_state(st)
+    Hn, Hb = H + np.diag(V), H.conj() - np.diag(V)
+    dev = 0.0
+    for k in range(1, 41):
+        sim.step(50)
+        out = sim.get_state().cpu().numpy()
+        t = 50 * k * dt
+        dev = max(dev, abs(out[10, 0, 0] - two_level_probability(Hb, t)),
+                  abs(out[1, 0, 0] - two_level_probability(Hn, t)))
+    assert dev < 1e-9, dev
+    n = round(math.pi / (2 * abs(Hb[0, 1])) / dt)
+    sim.set_state(st)
+    sim.step(n)
+    out = sim.get_state().cpu().numpy()
+    assert out[10, 0, 0] > 1 - 1e-6 and out[1, 0, 0] < 0.5
