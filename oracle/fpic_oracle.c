@@ -35,7 +35,9 @@
  * lies between the centres of cells (c_a + floor(u)) and (c_a + floor(u) + 1)
  * (periodic), at fraction phi = u - floor(u) of the way.  The linear
  * ("cloud in cell", first-order) shape function then gives weight 1 - phi to
- * the first and phi to the second (Sec. II.B.1 shape functions; order 1).
+ * the first and phi to the second (Sec. II.B.1 shape functions; order 1);
+ * the quadratic one (order 2, the paper's production choice) spreads the
+ * particle over the nearest cell centre and its two neighbours.
  * Along an axis with a single cell the particle always lies in cell 0.
  * Stage times are t = n dt + c_s dt with c_s in {0, 1/2, 1/2, 1}, each
  * product and sum rounded once (this file is compiled with
@@ -66,6 +68,7 @@ typedef struct {
     const double *Hvac; /* [3][3] complex, row-major (re, im) pairs */
     double dt;
     const double *Vmat; /* [3] matter potential V_e, V_mu, V_tau, or NULL (none) */
+    int32_t shape_order; /* 1 linear (cloud in cell), 2 quadratic */
 } oracle_problem;
 
 /* ------------------------------------------------------------------ */
@@ -152,44 +155,69 @@ static void load_vmat(const oracle_problem *P, double V[3])
 /* ------------------------------------------------------------------ */
 typedef struct {
     int n;
-    int64_t cell[8];
-    double w[8];
+    int64_t cell[27];
+    double w[27];
 } stencil;
 
-/* Cells touched by particle (d, c) at time t and their weights w_pj. */
-static void cic_stencil(const oracle_problem *P, int64_t d, int64_t c, double t,
-                        stencil *S)
+/* Along one axis with n > 1 cells: the particle lies a fraction phi of the
+ * way from the centre of cell `left` to the next.  Writes the first cell of
+ * the axis stencil and its weights; returns the stencil width. */
+static int linear_axis(int64_t left, double phi, int64_t n, int64_t *first, double w[3])
+{
+    *first = left % n;
+    w[0] = 1.0 - phi;
+    w[1] = phi;
+    return 2;
+}
+
+/* Quadratic (triangular-shaped cloud) weights: with j the nearest cell
+ * centre and xi = x - x_j in [-1/2, 1/2), cells j - 1, j, j + 1 get
+ * (1/2 - xi)^2 / 2, 3/4 - xi^2 and (1/2 + xi)^2 / 2. */
+static int quadratic_axis(int64_t left, double phi, int64_t n, int64_t *first, double w[3])
+{
+    const int up = phi < 0.5 ? 0 : 1;   /* nearest centre: left or left + 1 */
+    const double xi = up ? phi - 1.0 : phi;
+    *first = pmod(left + up - 1, n);
+    w[0] = 0.5 * ((0.5 - xi) * (0.5 - xi));
+    w[1] = 0.75 - xi * xi;
+    w[2] = 0.5 * ((0.5 + xi) * (0.5 + xi));
+    return 3;
+}
+
+/* Cells touched by particle (d, c) at time t and their weights w_pj: the
+ * tensor product of the per-axis weights of the shape function of order
+ * P->shape_order (1 linear, 2 quadratic; Sec. II.B.1). */
+static void shape_stencil(const oracle_problem *P, int64_t d, int64_t c, double t,
+                          stencil *S)
 {
     const int64_t nx = P->ncell[0], ny = P->ncell[1];
     int64_t home[3] = {c % nx, (c / nx) % ny, c / (nx * ny)};
-    int64_t lo[3];
-    double wlo[3], whi[3];
-    int two[3];
+    int64_t first[3];
+    double wa[3][3];
+    int cnt[3];
     for (int a = 0; a < 3; a++) {
         if (P->ncell[a] == 1) {
-            lo[a] = 0;
-            wlo[a] = 1.0;
-            whi[a] = 0.0;
-            two[a] = 0;
+            first[a] = 0;
+            wa[a][0] = 1.0;
+            cnt[a] = 1;
             continue;
         }
         double u = (P->dirs[3 * d + a] * t) / P->dx[a];
         double fl = floor(u);
         double phi = u - fl;
-        lo[a] = pmod(home[a] + (int64_t)fl, P->ncell[a]);
-        wlo[a] = 1.0 - phi;
-        whi[a] = phi;
-        two[a] = 1;
+        int64_t left = pmod(home[a] + (int64_t)fl, P->ncell[a]);
+        cnt[a] = (P->shape_order == 2) ? quadratic_axis(left, phi, P->ncell[a], &first[a], wa[a])
+                                       : linear_axis(left, phi, P->ncell[a], &first[a], wa[a]);
     }
     S->n = 0;
-    for (int bz = 0; bz <= two[2]; bz++)
-        for (int by = 0; by <= two[1]; by++)
-            for (int bx = 0; bx <= two[0]; bx++) {
-                int64_t ix = (lo[0] + bx) % P->ncell[0];
-                int64_t iy = (lo[1] + by) % P->ncell[1];
-                int64_t iz = (lo[2] + bz) % P->ncell[2];
-                double w = (bx ? whi[0] : wlo[0]) * (by ? whi[1] : wlo[1]);
-                w = w * (bz ? whi[2] : wlo[2]);
+    for (int bz = 0; bz < cnt[2]; bz++)
+        for (int by = 0; by < cnt[1]; by++)
+            for (int bx = 0; bx < cnt[0]; bx++) {
+                int64_t ix = (first[0] + bx) % P->ncell[0];
+                int64_t iy = (first[1] + by) % P->ncell[1];
+                int64_t iz = (first[2] + bz) % P->ncell[2];
+                double w = wa[0][bx] * wa[1][by];
+                w = w * wa[2][bz];
                 S->cell[S->n] = (iz * ny + iy) * nx + ix;
                 S->w[S->n] = w;
                 S->n++;
@@ -221,7 +249,7 @@ static void deposit(const oracle_problem *P, const double *state, double t,
             unpack(state + p, np, rho);
             unpack(state + 9 * np + p, np, rhob);
             stencil S;
-            cic_stencil(P, d, c, t, &S);
+            shape_stencil(P, d, c, t, &S);
             for (int s = 0; s < S.n; s++) {
                 moments *g = grid + S.cell[s];
                 const double wN = S.w[s] * P->N[d];
@@ -318,7 +346,7 @@ static void rhs(const oracle_problem *P, const double *state, double t,
         const int64_t d = p / nc, c = p % nc;
         const double *v = P->dirs + 3 * d;
         stencil S;
-        cic_stencil(P, d, c, t, &S);
+        shape_stencil(P, d, c, t, &S);
         moments m;
         interpolate(grid, &S, &m);
         cplx H[3][3], Hb[3][3];
@@ -441,7 +469,7 @@ int oracle_gather(const oracle_problem *P, const double *G, int64_t ncomp, doubl
     const int64_t nc = ncell_total(P), nd = P->ndir, np = nc * nd;
     for (int64_t p = 0; p < np; p++) {
         stencil S;
-        cic_stencil(P, p / nc, p % nc, t, &S);
+        shape_stencil(P, p / nc, p % nc, t, &S);
         for (int64_t q = 0; q < ncomp; q++) {
             double s = 0.0;
             for (int i = 0; i < S.n; i++)
@@ -525,7 +553,7 @@ static void rhs_vjp(const oracle_problem *P, const double *y, double t, const do
         const int64_t d = p / nc, c = p % nc;
         const double *v = P->dirs + 3 * d;
         stencil S;
-        cic_stencil(P, d, c, t, &S);
+        shape_stencil(P, d, c, t, &S);
         moments m;
         interpolate(grid, &S, &m);
         cplx H[3][3], Hb[3][3];
@@ -569,7 +597,7 @@ static void rhs_vjp(const oracle_problem *P, const double *y, double t, const do
         const int64_t d = p / nc, c = p % nc;
         const double *v = P->dirs + 3 * d;
         stencil S;
-        cic_stencil(P, d, c, t, &S);
+        shape_stencil(P, d, c, t, &S);
         cplx Z[3][3], Zb[3][3];
         for (int i = 0; i < 3; i++)
             for (int j = 0; j < 3; j++) {

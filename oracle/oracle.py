@@ -22,7 +22,8 @@ _dp = C.POINTER(C.c_double)
 class _Problem(C.Structure):
     _fields_ = [("ncell", C.c_int64 * 3), ("dx", C.c_double * 3),
                 ("ndir", C.c_int64), ("dirs", _dp), ("N", _dp),
-                ("Nbar", _dp), ("Hvac", _dp), ("dt", C.c_double), ("Vmat", _dp)]
+                ("Nbar", _dp), ("Hvac", _dp), ("dt", C.c_double), ("Vmat", _dp),
+                ("shape_order", C.c_int32)]
 
 
 _lib = None
@@ -67,10 +68,11 @@ class Problem:
     ncell: (nx, ny, nz); dx: cell widths; dirs [ndir][3]; N, Nbar [ndir]
     (neutrinos per particle); hvac: 3x3 complex; dt: time step; vmat: the
     matter potentials (V_e, V_mu, V_tau) of the background charged leptons
-    (eq. potentials; zero by default).
+    (eq. potentials; zero by default); shape_order: 1 linear (cloud in
+    cell), 2 quadratic (Sec. II.B.1).
     """
 
-    def __init__(self, ncell, dx, dirs, N, Nbar, hvac, dt: float, vmat=None):
+    def __init__(self, ncell, dx, dirs, N, Nbar, hvac, dt: float, vmat=None, shape_order=1):
         self.ncell = tuple(int(n) for n in ncell)
         self.dx = tuple(float(x) for x in dx)
         self.dirs = np.ascontiguousarray(dirs, dtype=np.float64).reshape(-1, 3)
@@ -86,13 +88,16 @@ class Problem:
         self.vmat = np.zeros(3) if vmat is None else np.ascontiguousarray(vmat, dtype=np.float64).reshape(3)
         self._s = _Problem((C.c_int64 * 3)(*self.ncell), (C.c_double * 3)(*self.dx),
                            self.ndir, _ptr(self.dirs), _ptr(self.N),
-                           _ptr(self.Nbar), _ptr(self.hvac), self.dt, _ptr(self.vmat))
+                           _ptr(self.Nbar), _ptr(self.hvac), self.dt, _ptr(self.vmat),
+                           int(shape_order))
+        self.shape_order = int(shape_order)
 
     @classmethod
     def from_workload(cls, w, hvac=None) -> "Problem":
         N, Nbar = w.weights()
         return cls(w.ncell, w.dx, w.dirs(), N, Nbar,
-                   w.hvac() if hvac is None else hvac, w.dt, vmat=w.vmat)
+                   w.hvac() if hvac is None else hvac, w.dt, vmat=w.vmat,
+                   shape_order=w.shape_order)
 
     @property
     def ncell_total(self) -> int:

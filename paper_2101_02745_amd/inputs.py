@@ -298,6 +298,8 @@ class Workload:
     # leptons; the benchmark workloads have none (comoving frame with no
     # net lepton density, as the paper's fiducial runs)
     vmat: tuple = (0.0, 0.0, 0.0)
+    # shape function order: 1 linear (cloud in cell), 2 quadratic
+    shape_order: int = 1
 
     @property
     def ncell_total(self) -> int:

@@ -28,10 +28,10 @@ GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
 
 
 def small(ncell=16, ndir=26, hvac=None, f=0.0, fbar=-1.0 / 3, nbar=1.0,
-          dt=0.2, L=32.0, seed=1, alpha=1e-6):
+          dt=0.2, L=32.0, seed=1, alpha=1e-6, order=1):
     w = I.Workload(name="t", ncell=(1, 1, ncell), length=(1.0, 1.0, L),
                    ndir=ndir, dt=dt, steps=0, f=f, fbar=fbar,
-                   nbar_over_n=nbar, seed=seed, alpha=alpha)
+                   nbar_over_n=nbar, seed=seed, alpha=alpha, shape_order=order)
     P = Problem.from_workload(w, hvac=hvac)
     return w, P
 
@@ -53,13 +53,14 @@ def test_p3_trace_conserved():
     assert np.abs(out[1] - st[1]).max() > 1e-3
 
 
-@pytest.mark.parametrize("vac", ["none", "diagonal", "mixing"])
-def test_p8_lepton_number(vac):
+@pytest.mark.parametrize("vac,order", [("none", 1), ("diagonal", 1), ("mixing", 1),
+                                       ("none", 2), ("diagonal", 2)])
+def test_p8_lepton_number(vac, order):
     H = {"none": np.zeros((3, 3)),
          "diagonal": np.diag([0.0, 7.4e-5, 2.4e-3]).astype(complex),
          "mixing": I.vacuum_hamiltonian()}[vac]
     w, P = small(ncell=16, ndir=26, hvac=H, f=0.1, fbar=-0.3, nbar=0.8,
-                 alpha=1e-3)
+                 alpha=1e-3, order=order)
     st = w.state0()
     L0 = lepton_matrix(P, st)
     out = P.step(st, 300)

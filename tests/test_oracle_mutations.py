@@ -28,12 +28,17 @@ MUTANTS = {
     "nbar_not_conjugated": ("cplx h = m->n[i][j] - conj(m->nb[i][j]);",
                             "cplx h = m->n[i][j] - m->nb[i][j];"),
     "matmul_transposed": ("s += a[i][k] * b[k][j];", "s += a[k][i] * b[k][j];"),
-    "cic_weights_swapped": ("wlo[a] = 1.0 - phi;\n        whi[a] = phi;",
-                            "wlo[a] = phi;\n        whi[a] = 1.0 - phi;"),
+    "cic_weights_swapped": ("w[0] = 1.0 - phi;\n    w[1] = phi;",
+                            "w[0] = phi;\n    w[1] = 1.0 - phi;"),
+    "quadratic_nearest_centre": ("const int up = phi < 0.5 ? 0 : 1;",
+                                 "const int up = phi < 0.5 ? 1 : 0;"),
+    "quadratic_centre_weight": ("w[1] = 0.75 - xi * xi;", "w[1] = 0.75 + xi * xi;"),
+    "quadratic_edge_weights_swapped": ("w[0] = 0.5 * ((0.5 - xi) * (0.5 - xi));",
+                                       "w[0] = 0.5 * ((0.5 + xi) * (0.5 + xi));"),
     "flux_wrong_axis": ("g->f[a][i][j] += wN * rho[i][j] * v[a];",
                         "g->f[a][i][j] += wN * rho[i][j] * v[2];"),
-    "advection_backwards": ("lo[a] = pmod(home[a] + (int64_t)fl, P->ncell[a]);",
-                            "lo[a] = pmod(home[a] - (int64_t)fl, P->ncell[a]);"),
+    "advection_backwards": ("int64_t left = pmod(home[a] + (int64_t)fl, P->ncell[a]);",
+                            "int64_t left = pmod(home[a] - (int64_t)fl, P->ncell[a]);"),
     "rk4_k2_weight": ("ks[i] = ks[i] + 2.0 * k[i];\n            ys[i] = state[i] + (0.5 * dt) * k[i];",
                       "ks[i] = ks[i] + k[i];\n            ys[i] = state[i] + (0.5 * dt) * k[i];"),
     "rk4_stage_time": ("rhs(P, ys, stage_time(n, dt, 1.0), grid, k);",

@@ -55,8 +55,9 @@ def random_pure_states(rng, n):
     return out
 
 
-def one_d_problem(ncell, L, dirs, N, Nbar, hvac, dt):
-    return Problem((1, 1, ncell), (1.0, 1.0, L / ncell), dirs, N, Nbar, hvac, dt)
+def one_d_problem(ncell, L, dirs, N, Nbar, hvac, dt, order=1):
+    return Problem((1, 1, ncell), (1.0, 1.0, L / ncell), dirs, N, Nbar, hvac, dt,
+                   shape_order=order)
 
 
 # ---------------------------------------------------------------- P1 / P2
@@ -187,7 +188,7 @@ def test_p4_two_beam_stable_for_negative_delta():
 
 # ---------------------------------------------------------------- P5
 def inhomogeneous_growth(cells_per_wavelength, eps=1e-9, dt=0.01,
-                         t_fit=(2.0, 6.0)):
+                         t_fit=(2.0, 6.0), order=1):
     mu, Delta = 1.0, 0.0
     k = 2 * mu - Delta            # fastest mode (App. A.4)
     L = 2 * math.pi / k
@@ -195,7 +196,7 @@ def inhomogeneous_growth(cells_per_wavelength, eps=1e-9, dt=0.01,
     dz = L / n
     dirs = [[0, 0, 1.0], [0, 0, -1.0]]
     P = one_d_problem(n, L, dirs, [mu * dz, 0.0], [0.0, mu * dz],
-                      np.zeros((3, 3)), dt)
+                      np.zeros((3, 3)), dt, order)
     z0 = (np.arange(n) + 0.5) * dz
     st = np.zeros((18, 2, n))
     st[0] = 1.0
@@ -228,11 +229,31 @@ def test_p5_inhomogeneous_two_beam_growth():
     assert err32 / err64 > 3.0, (err32, err64)
 
 
+def test_p5_inhomogeneous_two_beam_growth_quadratic():
+    """The same instability with the quadratic shape function (the paper's
+    production choice, Sec. II.B.1): within the paper's 4.3e-3 at 64 cells
+    per wavelength, second order in the cell width."""
+    rate64, pred = inhomogeneous_growth(64, order=2)
+    err64 = abs(rate64 - pred) / pred
+    assert err64 < GOLDEN["inhomogeneous_two_beam"]["paper_rel_err"], rate64
+    rate32, _ = inhomogeneous_growth(32, order=2)
+    err32 = abs(rate32 - pred) / pred
+    assert err32 / err64 > 3.0, (err32, err64)
+
+
 # ---------------------------------------------------------------- P6
-def dense_weights(ncell, dx, dirs, t):
+def bspline2(r):
+    """Quadratic B-spline (the triangular-shaped cloud) of a distance r in
+    cells: 3/4 - r^2 for |r| <= 1/2, (3/2 - |r|)^2 / 2 for 1/2 < |r| < 3/2."""
+    r = np.abs(r)
+    return np.where(r <= 0.5, 0.75 - r * r, np.where(r < 1.5, 0.5 * (1.5 - r) ** 2, 0.0))
+
+
+def dense_weights(ncell, dx, dirs, t, order=1):
     """W[p, j] from positions x_p = (c + 1/2) dx + Omega t and cell centres
-    (j + 1/2) dx, with the linear shape max(0, 1 - |distance| / dx) along each
-    axis (minimum-image periodic distance)."""
+    (j + 1/2) dx, with the linear shape max(0, 1 - |distance| / dx) (order
+    1) or the quadratic B-spline (order 2) along each axis, summed over the
+    periodic images."""
     nx, ny, nz = ncell
     nc = nx * ny * nz
     nd = len(dirs)
@@ -250,16 +271,23 @@ def dense_weights(ncell, dx, dirs, t):
                 xp = (cells[c, a] + 0.5) * dx[a] + dirs[d][a] * t
                 xj = (np.arange(n) + 0.5) * dx[a]
                 dist = (xp - xj + 0.5 * L) % L - 0.5 * L
-                w_axes.append(np.maximum(0.0, 1.0 - np.abs(dist) / dx[a]))
+                if order == 1:
+                    w_axes.append(np.maximum(0.0, 1.0 - np.abs(dist) / dx[a]))
+                else:
+                    # every periodic image within reach (boxes of 2 cells)
+                    w_axes.append(sum(bspline2(dist / dx[a] + m * n) for m in (-1, 0, 1)))
             wx, wy, wz = w_axes
             full = wz[:, None, None] * wy[None, :, None] * wx[None, None, :]
             W[d * nc + c] = full.reshape(-1)
     return W
 
 
-@pytest.mark.parametrize("ncell,dx", [((1, 1, 7), (1.0, 1.0, 0.37)),
-                                      ((3, 4, 5), (0.5, 0.7, 0.9))])
-def test_p6_deposit_gather_bruteforce(ncell, dx):
+@pytest.mark.parametrize("ncell,dx,order", [((1, 1, 7), (1.0, 1.0, 0.37), 1),
+                                            ((3, 4, 5), (0.5, 0.7, 0.9), 1),
+                                            ((1, 1, 7), (1.0, 1.0, 0.37), 2),
+                                            ((3, 4, 5), (0.5, 0.7, 0.9), 2),
+                                            ((2, 1, 6), (0.4, 1.0, 0.3), 2)])
+def test_p6_deposit_gather_bruteforce(ncell, dx, order):
     rng = np.random.default_rng(13)
     dirs = I.golden_antipodal_directions(6)
     nd, nc = 6, int(np.prod(ncell))
@@ -267,10 +295,10 @@ def test_p6_deposit_gather_bruteforce(ncell, dx):
     Nb = rng.uniform(0.2, 1.0, nd)
     st = np.concatenate([random_pure_states(rng, nd * nc),
                          random_pure_states(rng, nd * nc)]).reshape(18, nd, nc)
-    P = Problem(ncell, dx, dirs, N, Nb, np.zeros((3, 3)), 0.1)
+    P = Problem(ncell, dx, dirs, N, Nb, np.zeros((3, 3)), 0.1, shape_order=order)
     dV = dx[0] * dx[1] * dx[2]
-    for t in (0.0, 0.73, 3.1):
-        W = dense_weights(ncell, dx, dirs, t)
+    for t in (0.0, 0.73, 3.1, 0.25):
+        W = dense_weights(ncell, dx, dirs, t, order)
         assert np.allclose(W.sum(axis=1), 1.0)       # partition of unity
         mom = P.moments(st, t)
         Xn = (N[:, None] * st[:9].reshape(9, nd, nc)).reshape(9, -1)
