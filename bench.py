@@ -159,6 +159,31 @@ def measure_3d(steps=20):
             "step_frac_of_fused_floor": STEP_BYTES * P / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
 
+def measure_quadratic(tuning, steps=200):
+    """The headline box with the quadratic shape function (Sec. II.B.1, the
+    paper's production choice), in the headline's launch shape."""
+    import dataclasses
+    import torch
+    from paper_2101_02745_amd import inputs as I
+    from paper_2101_02745_amd.sim import Sim
+    w = dataclasses.replace(I.workload("1d_2048x378"), shape_order=2)
+    sim = Sim.from_workload(w, tuning=tuning)
+    sim.set_state(w.state0())
+    sim.step(20)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = sim.profile(5)
+    P = w.nparticles
+    return {"workload": w.name + " (quadratic shape)", "particles": P, "steps": steps,
+            "launch": tuning, "value": P * steps / wall, "unit": "particle-steps/s",
+            "ms_per_step": 1e3 * wall / steps,
+            "stage_ms": [ms[0], ms[2], ms[4], ms[6]], "reduce_ms": [ms[1], ms[3], ms[5], ms[7]],
+            "step_frac_of_hbm_peak": STEP_BYTES * P / (wall / steps) / 1e9 / HBM_PEAK_GBS}
+
+
 def measure_batch(steps=100, nsim=64):
     """64 uneven 1D boxes: one batched launch per stage vs the same boxes
     run one after another through the single-box path (each with its own
@@ -310,6 +335,9 @@ def main():
         print("[bench] 3D box 64^3 x 92", file=sys.stderr, flush=True)
         rec["box3d"] = measure_3d()
         print(f"[bench] 3d: {rec['box3d']}", file=sys.stderr, flush=True)
+        print("[bench] quadratic shape on the same box", file=sys.stderr, flush=True)
+        rec["quadratic"] = measure_quadratic(sim.tune.as_dict() if sim.tune else None)
+        print(f"[bench] quadratic: {rec['quadratic']}", file=sys.stderr, flush=True)
         print("[bench] batched vs sequential (64 uneven 1D boxes)", file=sys.stderr, flush=True)
         rec["batch"] = measure_batch()
         print(f"[bench] batch: {rec['batch']}", file=sys.stderr, flush=True)

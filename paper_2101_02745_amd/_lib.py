@@ -151,7 +151,8 @@ class HostConfig:
     def from_workload(cls, w, hvac=None):
         N, Nbar = w.weights()
         return cls(w.ncell, w.dx, w.dirs(), N, Nbar,
-                   w.hvac() if hvac is None else hvac, w.dt, vmat=w.vmat)
+                   w.hvac() if hvac is None else hvac, w.dt,
+                   shape_order=w.shape_order, vmat=w.vmat)
 
 
 def tuning(t) -> Tuning:

@@ -59,7 +59,8 @@ class FlavorEvolve(torch.autograd.Function):
     def forward(ctx, params, seeds, workload, nsteps, ckpt_every=50, tuning=None):
         w = workload
         dirs, N, Nb, dN_df, dNb_dnbar, dNb_dfbar = _weights(w, params.detach().cpu().numpy())
-        hc = HostConfig(w.ncell, w.dx, dirs, N, Nb, w.hvac(), w.dt, vmat=w.vmat)
+        hc = HostConfig(w.ncell, w.dx, dirs, N, Nb, w.hvac(), w.dt,
+                        shape_order=w.shape_order, vmat=w.vmat)
         sim = Sim(hc, tuning=tuning, device=str(seeds.device))
         st0 = state_from_seeds_t(seeds.detach())
         sim.set_state(st0, 0)

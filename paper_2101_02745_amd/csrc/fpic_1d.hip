@@ -65,6 +65,36 @@ __device__ __forceinline__ double lane_below(double x)
     return __hiloint2double(hi, lo);
 }
 
+// Value of the lane one above (lane 63 receives 0): DPP wave_shl:1.
+__device__ __forceinline__ double lane_above(double x)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), 0x130, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), 0x130, 0xf, 0xf, true);
+    return __hiloint2double(hi, lo);
+}
+
+// Quadratic (triangular-shaped cloud) weights from the fraction phi of the
+// way between the centres of cells L and L + 1: the nearest centre is
+// L + up, xi = x - x_(L+up) in [-1/2, 1/2), and cells L + up - 1, L + up,
+// L + up + 1 get (1/2 - xi)^2 / 2, 3/4 - xi^2, (1/2 + xi)^2 / 2 (each
+// operation rounded once, as the CPU reference forms them).
+struct Quad {
+    int up;
+    double w0, w1, w2;
+};
+
+__device__ __forceinline__ Quad quad_weights(double phi)
+{
+#pragma clang fp contract(off)
+    Quad q;
+    q.up = phi < 0.5 ? 0 : 1;
+    const double xi = q.up ? phi - 1.0 : phi;
+    q.w0 = 0.5 * ((0.5 - xi) * (0.5 - xi));
+    q.w1 = 0.75 - xi * xi;
+    q.w2 = 0.5 * ((0.5 + xi) * (0.5 + xi));
+    return q;
+}
+
 __device__ __forceinline__ int pmod_i64(int64_t a, int n)
 {
     int64_t r = a % n;
@@ -154,10 +184,14 @@ __device__ __forceinline__ int pmod_dbl(double i, int n)
     return (int)r;
 }
 
-template <int MODE>
+// SH: shape-function order, 1 (linear) or 2 (quadratic).  The staged grid
+// tile holds cells tile*64 - SH .. tile*64 + 64 + SH; the quadratic deposit
+// reaches one cell left of the tile and two right of it (edge partials).
+template <int MODE, int SH>
 __global__ void __launch_bounds__(MAX_WAVES * TILE)
 stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ sims, int max_dpw)
 {
+    constexpr int GTC = gt_cells(SH), GTS = gt_stride(SH), NE = n_edges(SH);
     extern __shared__ double smem[];
     const WorkItem wi = work[blockIdx.x];
     // private copy: the kernel's stores cannot alias the descriptor
@@ -193,11 +227,11 @@ stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ si
     }
 
     // LDS: [grid tile | reduction] [edge buffers] [per-direction shifts]
-    const int gslot = max(NG * GT_STRIDE, NG * TILE + nwaves * NG);
-    double *Gt = smem;                                   // [NG][GT_STRIDE]
-    double *eb = smem + gslot + wave * max_dpw * 9;      // [dpw][9] of this wave
-    double *tphi = smem + gslot + nwaves * max_dpw * 9;  // [dpg][2]: phi_cur, phi_nxt
-    int *tint = (int *)(tphi + 2 * nwaves * max_dpw);    // [dpg][2]: r, delta
+    const int gslot = max(NG * GTS, NG * TILE + nwaves * NG * NE);
+    double *Gt = smem;                                        // [NG][GTS]
+    double *eb = smem + gslot + wave * max_dpw * 9 * NE;      // [dpw][NE][9] of this wave
+    double *tphi = smem + gslot + nwaves * max_dpw * 9 * NE;  // [dpg][2]: phi_cur, phi_nxt
+    int *tint = (int *)(tphi + 2 * nwaves * max_dpw);         // [dpg][2]: r, delta
 
     const int dgrp0 = wi.group * S.dpg;
     // shifts of the workgroup's directions, one thread per direction
@@ -215,13 +249,17 @@ stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ si
     }
     if (MODE <= M_S4) {
         const double *Gin = S.G[MODE - 1];
-        for (int idx = threadIdx.x; idx < NG * GT_CELLS; idx += blockDim.x) {
-            const int comp = idx / GT_CELLS;
-            const int k = idx - comp * GT_CELLS;
-            int cell = tile0 - 1 + k;
-            cell = (cell < 0) ? cell + nc : cell;
-            cell = (nc < GT_CELLS) ? cell % nc : (cell >= nc ? cell - nc : cell);
-            Gt[comp * GT_STRIDE + k] = gld(Gin + (size_t)comp * nc + cell);
+        for (int idx = threadIdx.x; idx < NG * GTC; idx += blockDim.x) {
+            const int comp = idx / GTC;
+            const int k = idx - comp * GTC;
+            int cell = tile0 - SH + k;
+            if (nc < GTC) {
+                cell %= nc;
+                cell = (cell < 0) ? cell + nc : cell;
+            } else {
+                cell = (cell < 0) ? cell + nc : (cell >= nc ? cell - nc : cell);
+            }
+            Gt[comp * GTS + k] = gld(Gin + (size_t)comp * nc + cell);
         }
     }
     __syncthreads();
@@ -273,16 +311,28 @@ stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ si
                     X[k] = wNb * Y[9 + k];
             } else {
                 // interpolate the staged grid at the current position
-                const int kl = lane - tint[2 * j + 1] + 1;  // LDS column of cell m - delta
+                const int kl = lane - tint[2 * j + 1] + SH;  // LDS column of cell m - delta
                 const double phi = tphi[2 * j + 0], omp = 1.0 - phi;
                 double Hnn[9];
+                if (SH == 2) {
+                    const Quad q = quad_weights(phi);
+#pragma unroll
+                    for (int k = 0; k < 9; k++) {
+                        const double *g = Gt + k * GTS + kl - 1 + q.up;
+                        const double A = (q.w0 * g[0] + q.w1 * g[1]) + q.w2 * g[2];
+                        const double Bx = (q.w0 * g[9 * GTS] + q.w1 * g[9 * GTS + 1]) + q.w2 * g[9 * GTS + 2];
+                        const double By = (q.w0 * g[18 * GTS] + q.w1 * g[18 * GTS + 1]) + q.w2 * g[18 * GTS + 2];
+                        const double Bz = (q.w0 * g[27 * GTS] + q.w1 * g[27 * GTS + 1]) + q.w2 * g[27 * GTS + 2];
+                        Hnn[k] = A - (vx * Bx + vy * By + vz * Bz);
+                    }
+                } else
 #pragma unroll
                 for (int k = 0; k < 9; k++) {
-                    const double *g = Gt + k * GT_STRIDE + kl;
+                    const double *g = Gt + k * GTS + kl;
                     const double A = omp * g[0] + phi * g[1];
-                    const double Bx = omp * g[9 * GT_STRIDE] + phi * g[9 * GT_STRIDE + 1];
-                    const double By = omp * g[18 * GT_STRIDE] + phi * g[18 * GT_STRIDE + 1];
-                    const double Bz = omp * g[27 * GT_STRIDE] + phi * g[27 * GT_STRIDE + 1];
+                    const double Bx = omp * g[9 * GTS] + phi * g[9 * GTS + 1];
+                    const double By = omp * g[18 * GTS] + phi * g[18 * GTS + 1];
+                    const double Bz = omp * g[27 * GTS] + phi * g[27 * GTS + 1];
                     Hnn[k] = A - (vx * Bx + vy * By + vz * Bz);
                 }
                 // stage state y, and the base the next state is built on:
@@ -353,23 +403,64 @@ stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ si
                 X[k] = 0.0;
         }
 
-        // deposit with the next-stage weights: cell m gets (1 - phi') of its
-        // own particle and phi' of the particle one lane to the left
-        const double omph = 1.0 - ph;
+        if (SH == 2) {
+            // quadratic deposit with the next-stage weights: the particle at
+            // anchor m feeds cells m - 1 + up' .. m + 1 + up', so cell m
+            // takes w0' w1' w2' of lanes (m + 1, m, m - 1) when up' = 0 and
+            // of lanes (m, m - 1, m - 2) when up' = 1 (one-lane DPP moves);
+            // what leaves the tile goes to the edge partials: one cell on
+            // the left (lane 0), two on the right (the last active lanes)
+            const Quad q = quad_weights(ph);
 #pragma unroll
-        for (int k = 0; k < 9; k++) {
-            double xl = lane_below(X[k]);
-            xl = (lane == 0) ? 0.0 : xl;
-            const double xc = omph * X[k] + ph * xl;
-            acc[k] += xc;
-            acc[9 + k] += vx * xc;
-            acc[18 + k] += vy * xc;
-            acc[27 + k] += vz * xc;
-        }
-        if (lane == nact - 1) {
+            for (int k = 0; k < 9; k++) {
+                const double x = X[k];
+                double s1 = lane_below(x);
+                s1 = (lane == 0) ? 0.0 : s1;
+                double a, b, c;
+                if (q.up) {
+                    double s2 = lane_below(s1);
+                    s2 = (lane == 0) ? 0.0 : s2;
+                    a = x;
+                    b = s1;
+                    c = s2;
+                } else {
+                    double xa = lane_above(x);
+                    xa = (lane == TILE - 1) ? 0.0 : xa;
+                    a = xa;
+                    b = x;
+                    c = s1;
+                }
+                const double xc = (q.w0 * a + q.w1 * b) + q.w2 * c;
+                acc[k] += xc;
+                acc[9 + k] += vx * xc;
+                acc[18 + k] += vy * xc;
+                acc[27 + k] += vz * xc;
+                if (lane == nact - 1) {
+                    eb[((d - dbeg) * NE + 0) * 9 + k] = q.up ? q.w1 * x + q.w2 * s1 : q.w2 * x;
+                    eb[((d - dbeg) * NE + 1) * 9 + k] = q.up ? q.w2 * x : 0.0;
+                }
+                if (lane == 0)
+                    eb[((d - dbeg) * NE + 2) * 9 + k] = q.up ? 0.0 : q.w0 * x;
+            }
+        } else {
+            // deposit with the next-stage weights: cell m gets (1 - phi') of
+            // its own particle and phi' of the particle one lane to the left
+            const double omph = 1.0 - ph;
 #pragma unroll
-            for (int k = 0; k < 9; k++)
-                eb[(d - dbeg) * 9 + k] = ph * X[k];
+            for (int k = 0; k < 9; k++) {
+                double xl = lane_below(X[k]);
+                xl = (lane == 0) ? 0.0 : xl;
+                const double xc = omph * X[k] + ph * xl;
+                acc[k] += xc;
+                acc[9 + k] += vx * xc;
+                acc[18 + k] += vy * xc;
+                acc[27 + k] += vz * xc;
+            }
+            if (lane == nact - 1) {
+#pragma unroll
+                for (int k = 0; k < 9; k++)
+                    eb[(d - dbeg) * 9 + k] = ph * X[k];
+            }
         }
     }
 
@@ -384,17 +475,18 @@ stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ si
         }
         __syncthreads();
     }
-    // edge partial of each wave: lanes 0..35 sum their component over the
-    // wave's directions
-    double *esum = smem + NG * TILE;  // [nwaves][NG]
-    if (lane < NG) {
-        const int comp = lane % 9, grp = lane / 9;
+    // edge partials of each wave: one lane per (edge, moment component)
+    // sums over the wave's directions
+    double *esum = smem + NG * TILE;  // [nwaves][NE][NG]
+    for (int q = lane; q < NE * NG; q += TILE) {
+        const int e = q / NG, r = q - e * NG;
+        const int comp = r % 9, grp = r / 9;
         double s = 0.0;
         for (int d = dbeg; d < dend; ++d) {
             const double coef = (grp == 0) ? 1.0 : (grp == 1) ? S.vx[d] : (grp == 2) ? S.vy[d] : S.vz[d];
-            s += coef * eb[(d - dbeg) * 9 + comp];
+            s += coef * eb[((d - dbeg) * NE + e) * 9 + comp];
         }
-        esum[wave * NG + lane] = s;
+        esum[(wave * NE + e) * NG + r] = s;
     }
     __syncthreads();
 
@@ -404,11 +496,12 @@ stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ si
         const int k = idx / TILE, l = idx - k * TILE;
         gst(part + (size_t)k * ntc + tile0 + l, redb[idx]);
     }
-    if (threadIdx.x < NG) {
+    for (int q = threadIdx.x; q < NE * NG; q += blockDim.x) {
+        const int e = q / NG, r = q - e * NG;
         double s = 0.0;
         for (int w = 0; w < nwaves; ++w)
-            s += esum[w * NG + threadIdx.x];
-        gst(S.edge + ((size_t)wi.group * NG + threadIdx.x) * S.ntile + wi.tile, s);
+            s += esum[(w * NE + e) * NG + r];
+        gst(S.edge + (((size_t)wi.group * NG + r) * NE + e) * S.ntile + wi.tile, s);
     }
 }
 
@@ -765,7 +858,32 @@ reduce1d_kernel(const RedItem *__restrict__ items, const SimDesc *__restrict__ s
         }
         for (; g < ng; ++g)
             s += gld(pp + (size_t)g * gstride);
-        if (l == 0) {
+        if (S.shape == 2) {
+            // quadratic: a tile's right-edge cells are the first two after
+            // it (the second lies two tiles on when the next tile has one
+            // cell), its left-edge cell the last before it; with one tile
+            // or very few cells they fold onto the tile itself.  Candidate
+            // sources in a fixed order: tiles T-2, T-1, T, T+1 (each once).
+            const int j = tile0 + l;
+            int cand[4] = {(it.tile + 2 * ntile - 2) % ntile, (it.tile + ntile - 1) % ntile, it.tile,
+                           (it.tile + 1) % ntile};
+            for (int ci = 0; ci < 4; ++ci) {
+                const int src = cand[ci];
+                bool seen = false;
+                for (int cj = 0; cj < ci; ++cj)
+                    seen = seen || (cand[cj] == src);
+                if (seen)
+                    continue;
+                const int t0s = src * TILE, nas = min(TILE, nc - t0s);
+                for (int e = 0; e < 3; ++e) {
+                    const int target = (e < 2) ? (t0s + nas + e) % nc : (t0s + nc - 1) % nc;
+                    if (target != j)
+                        continue;
+                    for (int g2 = 0; g2 < ng; ++g2)
+                        s += gld(S.edge + (((size_t)g2 * NG + k) * 3 + e) * ntile + src);
+                }
+            }
+        } else if (l == 0) {
             const int tprev = (it.tile + ntile - 1) % ntile;
             const double *ep = S.edge + (size_t)k * ntile + tprev;
             const size_t estride = (size_t)NG * ntile;
@@ -914,32 +1032,44 @@ __global__ void fill_state_kernel(const SimDesc *sims, int sim)
             S.Y[k * S.np + p] = (k == 0 || k == 9) ? 1.0 : 0.0;
 }
 
-size_t stage1d_smem_bytes(int waves, int max_dpw)
+size_t stage1d_smem_bytes(int waves, int max_dpw, int shape)
 {
-    size_t tile = (size_t)NG * GT_STRIDE;
-    size_t red = (size_t)NG * TILE + (size_t)waves * NG;
+    const size_t ne = n_edges(shape);
+    size_t tile = (size_t)NG * gt_stride(shape);
+    size_t red = (size_t)NG * TILE + (size_t)waves * NG * ne;
     size_t gslot = tile > red ? tile : red;
     const size_t dpg = (size_t)waves * max_dpw;
     // grid slot, edge buffers, phi table, (r, delta) table
-    return (gslot + dpg * 9 + dpg * 2) * sizeof(double) + dpg * 2 * sizeof(int);
+    return (gslot + dpg * 9 * ne + dpg * 2) * sizeof(double) + dpg * 2 * sizeof(int);
 }
 
-hipError_t launch_stage1d(int mode, const WorkItem *work, int nwork, const SimDesc *sims,
-                          int waves, int max_dpw, hipStream_t s)
+template <int SH>
+static hipError_t launch_stage1d_sh(int mode, const WorkItem *work, int nwork, const SimDesc *sims,
+                                    int waves, int max_dpw, hipStream_t s)
 {
     const dim3 grid(nwork), block(waves * TILE);
-    const size_t smem = stage1d_smem_bytes(waves, max_dpw);
+    const size_t smem = stage1d_smem_bytes(waves, max_dpw, SH);
     switch (mode) {
-    case M_S1: stage1d_kernel<M_S1><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
-    case M_S2: stage1d_kernel<M_S2><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
-    case M_S3: stage1d_kernel<M_S3><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
-    case M_S4: stage1d_kernel<M_S4><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
-    case M_DEPOSIT: stage1d_kernel<M_DEPOSIT><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
-    case M_MOM_NU: stage1d_kernel<M_MOM_NU><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
-    case M_MOM_NUBAR: stage1d_kernel<M_MOM_NUBAR><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
+    case M_S1: stage1d_kernel<M_S1, SH><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
+    case M_S2: stage1d_kernel<M_S2, SH><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
+    case M_S3: stage1d_kernel<M_S3, SH><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
+    case M_S4: stage1d_kernel<M_S4, SH><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
+    case M_DEPOSIT: stage1d_kernel<M_DEPOSIT, SH><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
+    case M_MOM_NU: stage1d_kernel<M_MOM_NU, SH><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
+    case M_MOM_NUBAR: stage1d_kernel<M_MOM_NUBAR, SH><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_stage1d(int mode, const WorkItem *work, int nwork, const SimDesc *sims,
+                          int waves, int max_dpw, int shape, hipStream_t s)
+{
+    if (shape == 2)
+        return launch_stage1d_sh<2>(mode, work, nwork, sims, waves, max_dpw, s);
+    if (shape == 1)
+        return launch_stage1d_sh<1>(mode, work, nwork, sims, waves, max_dpw, s);
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_reduce1d(const RedItem *items, int nitems, const SimDesc *sims, int which,

@@ -555,7 +555,7 @@ static int validate(const fpic_config &c)
     if (!c.dirs || !c.N || !c.Nbar)
         return fail(FPIC_EINVAL, "dirs, N and Nbar must be non-null host arrays");
     if (c.shape_order != 1)
-        return fail(FPIC_EUNSUPPORTED, "only shape_order 1 (cloud in cell) is implemented");
+        return fail(FPIC_EUNSUPPORTED, "3D boxes take shape_order 1 (cloud in cell) only");
     if (!(c.dt > 0.0) || !std::isfinite(c.dt))
         return fail(FPIC_EINVAL, "dt must be positive and finite");
     for (int a = 0; a < 3; ++a)

@@ -16,9 +16,17 @@ constexpr int TILE = 64;
 // Combined moments per cell: A = n - nbar^* (9 packed reals), then
 // B_x, B_y, B_z = f_i - fbar_i^* (9 each).
 constexpr int NG = 36;
-// Staged grid tile: cells tile*TILE-1 .. tile*TILE+65 (67 cells, padded).
+// Staged grid tile: cells tile*TILE-1 .. tile*TILE+65 (67 cells, padded)
+// for the linear shape function; tile*TILE-2 .. tile*TILE+66 for the
+// quadratic one (gt_cells(sh)).
 constexpr int GT_CELLS = 67;
 constexpr int GT_STRIDE = 68;
+constexpr int gt_cells(int sh) { return TILE + 2 * sh + 1; }
+constexpr int gt_stride(int sh) { return gt_cells(sh) + 1; }
+// Edge partials per tile and direction group: the linear deposit leaves the
+// tile only to the right (one cell); the quadratic one two cells to the
+// right and one to the left (slots 0, 1: right; 2: left).
+constexpr int n_edges(int sh) { return sh == 2 ? 3 : 1; }
 constexpr int MAX_WAVES = 4;
 // Reals stored per Runge-Kutta slope.  A slope k = -i[H, rho] is traceless
 // (the trace of a commutator vanishes), so its first diagonal entry is kept
@@ -50,6 +58,8 @@ struct SimDesc {
     int32_t ngroup;  // direction groups = workgroups per tile
     int32_t dpw;     // directions per wave
     int32_t dpg;     // directions per group = waves * dpw
+    int32_t shape;   // shape-function order: 1 linear, 2 quadratic
+    int32_t pad_;
     int64_t np;      // particles = ndir * ncell
     double dt;       // time step
     double dz;       // cell width
@@ -66,7 +76,7 @@ struct SimDesc {
     // box ping-pongs two buffers: {g0, g1, g0, g1, g0}.
     double *G[5];
     double *part;                // [ngroup][36][ntile*TILE] per-group partials
-    double *edge;                // [ngroup][36][ntile] right-edge partials
+    double *edge;                // [ngroup][36][n_edges][ntile] edge partials
     double *red;                 // [nred][18] scratch for reductions
     int64_t *step;               // current step number
     // adjoint (reverse-mode) buffers, null outside the adjoint
@@ -87,7 +97,7 @@ struct RedItem {
 
 // Launchers (fpic_1d.hip).
 hipError_t launch_stage1d(int mode, const WorkItem *work, int nwork, const SimDesc *sims,
-                          int waves, int max_dpw, hipStream_t s);
+                          int waves, int max_dpw, int shape, hipStream_t s);
 hipError_t launch_reduce1d(const RedItem *items, int nitems, const SimDesc *sims, int which,
                            double *override_out, int tick, hipStream_t s);
 // adjoint kernels: kind 4 = sources of stage 4 and their deposit; kind 3, 2,
@@ -106,7 +116,7 @@ hipError_t launch_totals(const SimDesc *sims, int sim, int nblk, double *out18, 
 hipError_t launch_check(const SimDesc *sims, int sim, int nblk, double *out2, hipStream_t s);
 hipError_t launch_fill_state(const SimDesc *sims, int sim, hipStream_t s);
 
-size_t stage1d_smem_bytes(int waves, int max_dpw);
+size_t stage1d_smem_bytes(int waves, int max_dpw, int shape);
 
 // Record msg as the calling thread's last error and return code.
 int fail(int code, const std::string &msg);

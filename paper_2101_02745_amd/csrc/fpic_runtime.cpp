@@ -64,7 +64,7 @@ struct SimPlan {
 };
 
 struct Plan {
-    int nsim = 0, waves = 0, max_dpw = 0, spg = 0;
+    int nsim = 0, waves = 0, max_dpw = 0, spg = 0, shape = 1;
     std::vector<SimPlan> sims;
     size_t o_desc = 0, o_work = 0, o_red = 0, o_scratch = 0, total = 0;
     int nwork = 0, nred = 0;
@@ -83,8 +83,9 @@ int validate_1d(const fpic_config &c, int idx)
         return bad("ndir must be >= 1");
     if (!c.dirs || !c.N || !c.Nbar)
         return bad("dirs, N and Nbar must be non-null host arrays");
-    if (c.shape_order != 1)
-        return fail(FPIC_EUNSUPPORTED, "only shape_order 1 (cloud in cell) is implemented");
+    if (c.shape_order != 1 && c.shape_order != 2)
+        return fail(FPIC_EUNSUPPORTED,
+                    "shape_order must be 1 (linear, cloud in cell) or 2 (quadratic)");
     for (int a = 0; a < 3; ++a)
         if (!(c.dx[a] > 0.0) || !std::isfinite(c.dx[a]))
             return bad("cell widths must be positive and finite");
@@ -139,9 +140,12 @@ int make_plan(int nsim, const fpic_config *cfgs, const fpic_tuning *tune, Plan &
             return rc;
         if (!is_1d(cfgs[i]))
             return fail(FPIC_EINVAL, "batches hold 1D boxes only (ncell = {1, 1, nz})");
+        if (cfgs[i].shape_order != cfgs[0].shape_order)
+            return fail(FPIC_EINVAL, "the boxes of a batch must share one shape_order");
     }
     P = Plan();
     P.nsim = nsim;
+    P.shape = cfgs[0].shape_order;
     P.waves = (tune && tune->waves) ? tune->waves : 4;
     if (P.waves != 1 && P.waves != 2 && P.waves != 4)
         return fail(FPIC_EINVAL, "waves must be 1, 2 or 4");
@@ -181,7 +185,7 @@ int make_plan(int nsim, const fpic_config *cfgs, const fpic_tuning *tune, Plan &
         s.o_G0 = cv.take(sizeof(double) * NG * s.ncell);
         s.o_G1 = cv.take(sizeof(double) * NG * s.ncell);
         s.o_part = cv.take(sizeof(double) * (size_t)s.ngroup * NG * s.ntile * TILE);
-        s.o_edge = cv.take(sizeof(double) * (size_t)s.ngroup * NG * s.ntile);
+        s.o_edge = cv.take(sizeof(double) * (size_t)s.ngroup * NG * n_edges(P.shape) * s.ntile);
         s.o_step = cv.take(sizeof(int64_t));
         P.nwork += s.ntile * s.ngroup;
         P.nred += s.ntile;
@@ -238,7 +242,7 @@ int capture_steps(fpic_batch *b, int nsteps, hipGraphExec_t *exec)
     hipError_t err = hipSuccess;
     for (int s = 0; s < nsteps && err == hipSuccess; ++s)
         for (int st = M_S1; st <= M_S4 && err == hipSuccess; ++st) {
-            err = launch_stage1d(st, b->dwork, P.nwork, b->ddesc, P.waves, P.max_dpw, b->cap);
+            err = launch_stage1d(st, b->dwork, P.nwork, b->ddesc, P.waves, P.max_dpw, P.shape, b->cap);
             if (err == hipSuccess)
                 err = launch_reduce1d(b->dred, P.nred, b->ddesc, st, nullptr,
                                       st == M_S4 ? 1 : 0, b->cap);
@@ -347,6 +351,7 @@ int batch_build(int nsim, const fpic_config *cfgs, const fpic_tuning *tune, void
         D.ngroup = s.ngroup;
         D.dpw = s.dpw;
         D.dpg = s.dpw * P.waves;
+        D.shape = P.shape;
         D.np = s.np;
         D.dt = c.dt;
         D.dz = c.dx[2];
@@ -475,7 +480,7 @@ int batch_set_state(fpic_batch *b, int sim, const double *state, int64_t step0)
     HIPCHECK(launch_set_step(b->ddesc, sim, sim + 1, step0, b->stream));
     int off, n, roff, rn;
     sim_work(b, sim, &off, &n, &roff, &rn);
-    HIPCHECK(launch_stage1d(M_DEPOSIT, b->dwork + off, n, b->ddesc, b->plan.waves, b->plan.max_dpw,
+    HIPCHECK(launch_stage1d(M_DEPOSIT, b->dwork + off, n, b->ddesc, b->plan.waves, b->plan.max_dpw, b->plan.shape,
                             b->stream));
     HIPCHECK(launch_reduce1d(b->dred + roff, rn, b->ddesc, 0, nullptr, 0, b->stream));
     b->state_set[sim] = true;
@@ -665,9 +670,9 @@ int fpic_moments(fpic_ctx *c, double *out)
     int off, n, roff, rn;
     sim_work(b, 0, &off, &n, &roff, &rn);
     const int nc = b->plan.sims[0].ncell;
-    HIPCHECK(launch_stage1d(M_MOM_NU, b->dwork + off, n, b->ddesc, b->plan.waves, b->plan.max_dpw, b->stream));
+    HIPCHECK(launch_stage1d(M_MOM_NU, b->dwork + off, n, b->ddesc, b->plan.waves, b->plan.max_dpw, b->plan.shape, b->stream));
     HIPCHECK(launch_reduce1d(b->dred + roff, rn, b->ddesc, RED_OUT, out, 0, b->stream));
-    HIPCHECK(launch_stage1d(M_MOM_NUBAR, b->dwork + off, n, b->ddesc, b->plan.waves, b->plan.max_dpw, b->stream));
+    HIPCHECK(launch_stage1d(M_MOM_NUBAR, b->dwork + off, n, b->ddesc, b->plan.waves, b->plan.max_dpw, b->plan.shape, b->stream));
     HIPCHECK(launch_reduce1d(b->dred + roff, rn, b->ddesc, RED_OUT, out + (size_t)NG * nc, 0, b->stream));
     return FPIC_OK;
 }
@@ -765,7 +770,7 @@ int fpic_profile(fpic_ctx *c, int32_t nsteps, double *ms)
     for (int n = 0; n < nsteps && !rc; ++n) {
         hipError_t err = hipEventRecord(ev[0], b->stream);
         for (int st = M_S1; st <= M_S4 && err == hipSuccess; ++st) {
-            err = launch_stage1d(st, b->dwork, P.nwork, b->ddesc, P.waves, P.max_dpw, b->stream);
+            err = launch_stage1d(st, b->dwork, P.nwork, b->ddesc, P.waves, P.max_dpw, P.shape, b->stream);
             if (err == hipSuccess)
                 err = hipEventRecord(ev[2 * st - 1], b->stream);
             if (err == hipSuccess)
@@ -826,6 +831,8 @@ int adj_check_cfg(fpic_ctx *c, const fpic_adjoint_cfg *a)
         return fail(FPIC_EINVAL, "adjoint: null argument");
     if (c->c3 || !c->b || c->b->plan.nsim != 1)
         return fail(FPIC_EUNSUPPORTED, "the adjoint covers single 1D boxes");
+    if (c->b->plan.shape != 1)
+        return fail(FPIC_EUNSUPPORTED, "the adjoint covers the linear shape function (shape_order 1)");
     if (a->nsteps < 1 || a->ckpt_every < 1)
         return fail(FPIC_EINVAL, "adjoint: nsteps and ckpt_every must be >= 1");
     return FPIC_OK;
@@ -868,7 +875,7 @@ int adj_graph(fpic_batch *b, bool reverse, int len, hipGraphExec_t *out)
         rc = capture(b->cap, [&]() -> hipError_t {
             for (int j = 0; j < len; ++j)
                 for (int st = M_S1; st <= M_S4; ++st) {
-                    hipError_t e = launch_stage1d(st, b->dwork, P.nwork, F + j, P.waves, P.max_dpw, b->cap);
+                    hipError_t e = launch_stage1d(st, b->dwork, P.nwork, F + j, P.waves, P.max_dpw, P.shape, b->cap);
                     if (e == hipSuccess)
                         e = launch_reduce1d(b->dred, P.nred, F + j, st, nullptr, st == M_S4 ? 1 : 0, b->cap);
                     if (e != hipSuccess)
@@ -1037,7 +1044,7 @@ int fpic_adjoint_backward(fpic_ctx *c, const double *dLdy_end, double *dLdy0, do
         // states, slopes and moment grids
         HIPCHECK(hipMemcpyAsync(segY, ckpt + st * seg, sizeof(double) * st, hipMemcpyDeviceToDevice, s));
         HIPCHECK(launch_set_step(F, 0, 1, n0, s));
-        HIPCHECK(launch_stage1d(M_DEPOSIT, b->dwork + off, n, F, P.waves, P.max_dpw, s));
+        HIPCHECK(launch_stage1d(M_DEPOSIT, b->dwork + off, n, F, P.waves, P.max_dpw, P.shape, s));
         HIPCHECK(launch_reduce1d(b->dred + roff, rn, F, 0, nullptr, 0, s));
         hipGraphExec_t g = nullptr;
         int rc = adj_graph(b, false, len, &g);
@@ -1111,7 +1118,7 @@ int fpic_autotune(int32_t nsim, const fpic_config *cfgs, void *workspace, size_t
                 }
                 int off, n, roff, rn;
                 sim_work(b, i, &off, &n, &roff, &rn);
-                (void)launch_stage1d(M_DEPOSIT, b->dwork + off, n, b->ddesc, P.waves, P.max_dpw, s);
+                (void)launch_stage1d(M_DEPOSIT, b->dwork + off, n, b->ddesc, P.waves, P.max_dpw, P.shape, s);
                 (void)launch_reduce1d(b->dred + roff, rn, b->ddesc, 0, nullptr, 0, s);
                 b->state_set[i] = true;
             }

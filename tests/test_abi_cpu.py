@@ -82,7 +82,8 @@ def test_workspace_size_is_consistent(lib):
     ({"dt": 5.0}, _lib.FPIC_EUNSUPPORTED),       # crosses a cell per stage
     ({"dt": -0.1}, _lib.FPIC_EINVAL),
     ({"dt": float("nan")}, _lib.FPIC_EINVAL),
-    ({"shape_order": 2}, _lib.FPIC_EUNSUPPORTED),
+    ({"shape_order": 3}, _lib.FPIC_EUNSUPPORTED),
+    ({"shape_order": 2, "ncell": [4, 4, 4]}, _lib.FPIC_EUNSUPPORTED),   # 3D: linear only
     ({"hvac": [0.0, 1.0] + [0.0] * 16}, _lib.FPIC_EINVAL),   # not Hermitian
     ({"vmat": [0.0, float("inf"), 0.0]}, _lib.FPIC_EINVAL),
     ({"vmat": [0.0, float("inf"), 0.0], "ncell": [4, 4, 4]}, _lib.FPIC_EINVAL),   # 3D path
@@ -119,3 +120,20 @@ def test_null_arguments(lib):
     assert lib.fpic_step(None, 1) == _lib.FPIC_EINVAL
     assert lib.fpic_sync(None) == _lib.FPIC_EINVAL
     lib.fpic_destroy(None)          # no-op
+
+
+def test_quadratic_shape_accepted_in_1d(lib):
+    hc = cfg_of(shape_order=2)
+    rc, n = ws_bytes(lib, hc)
+    assert rc == 0
+    rc1, n1 = ws_bytes(lib, cfg_of())
+    assert rc1 == 0 and n > n1          # three edge partials per tile instead of one
+
+
+def test_batch_needs_one_shape_order(lib):
+    a, b = cfg_of(), cfg_of(shape_order=2)
+    cfgs = (_lib.Config * 2)(a.c, b.c)
+    n = C.c_size_t()
+    rc = lib.fpic_batch_workspace_bytes(2, cfgs, None, C.byref(n))
+    assert rc == _lib.FPIC_EINVAL
+    assert b"shape_order" in lib.fpic_last_error()
