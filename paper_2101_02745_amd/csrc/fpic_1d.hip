@@ -879,8 +879,20 @@ reduce1d_kernel(const RedItem *__restrict__ items, const SimDesc *__restrict__ s
                     const int target = (e < 2) ? (t0s + nas + e) % nc : (t0s + nc - 1) % nc;
                     if (target != j)
                         continue;
-                    for (int g2 = 0; g2 < ng; ++g2)
-                        s += gld(S.edge + (((size_t)g2 * NG + k) * 3 + e) * ntile + src);
+                    const double *ep = S.edge + ((size_t)k * 3 + e) * ntile + src;
+                    const size_t estride = (size_t)NG * 3 * ntile;
+                    int g2 = 0;
+                    for (; g2 + 8 <= ng; g2 += 8) {
+                        double v[8];
+#pragma unroll
+                        for (int q = 0; q < 8; ++q)
+                            v[q] = gld(ep + (size_t)(g2 + q) * estride);
+#pragma unroll
+                        for (int q = 0; q < 8; ++q)
+                            s += v[q];
+                    }
+                    for (; g2 < ng; ++g2)
+                        s += gld(ep + (size_t)g2 * estride);
                 }
             }
         } else if (l == 0) {
