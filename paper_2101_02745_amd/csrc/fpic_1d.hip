@@ -544,10 +544,11 @@ __device__ __forceinline__ double wave_sum(double v)
 // stage kernels.
 __device__ __forceinline__ double stage_c(int s) { return s == 1 ? 0.0 : (s == 4 ? 1.0 : 0.5); }
 
-template <bool DO_B, bool DO_A, int SB, int SA>
+template <bool DO_B, bool DO_A, int SB, int SA, int SH>
 __global__ void __launch_bounds__(MAX_WAVES * TILE)
 adj1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ sims, int max_dpw)
 {
+    constexpr int GTC = gt_cells(SH), GTS = gt_stride(SH), NE = n_edges(SH);
     extern __shared__ double smem[];
     const WorkItem wi = work[blockIdx.x];
     const SimDesc S = sims[wi.sim];
@@ -568,11 +569,11 @@ adj1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ sims
 
     // LDS: [Gamma tile | reduction] [stage-SA grid tile] [edge buffers]
     //      [phi_anchor, phi_B per direction] [r, delta per direction]
-    const int gslot = max(NG * GT_STRIDE, NG * TILE + nwaves * NG);
+    const int gslot = max(NG * GTS, NG * TILE + nwaves * NG * NE);
     double *GtB = smem;
     double *GtA = smem + gslot;
-    double *eb = smem + 2 * gslot + wave * max_dpw * 9;
-    double *tphi = smem + 2 * gslot + nwaves * max_dpw * 9;
+    double *eb = smem + 2 * gslot + wave * max_dpw * 9 * NE;
+    double *tphi = smem + 2 * gslot + nwaves * max_dpw * 9 * NE;
     int *tint = (int *)(tphi + 2 * nwaves * max_dpw);
 
     const int dgrp0 = wi.group * S.dpg;
@@ -592,17 +593,21 @@ adj1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ sims
             }
         }
     }
-    for (int idx = threadIdx.x; idx < NG * GT_CELLS; idx += blockDim.x) {
-        const int comp = idx / GT_CELLS;
-        const int k = idx - comp * GT_CELLS;
-        int cell = tile0 - 1 + k;
-        cell = (cell < 0) ? cell + nc : cell;
-        cell = (nc < GT_CELLS) ? cell % nc : (cell >= nc ? cell - nc : cell);
+    for (int idx = threadIdx.x; idx < NG * GTC; idx += blockDim.x) {
+        const int comp = idx / GTC;
+        const int k = idx - comp * GTC;
+        int cell = tile0 - SH + k;
+        if (nc < GTC) {
+            cell %= nc;
+            cell = (cell < 0) ? cell + nc : cell;
+        } else {
+            cell = (cell < 0) ? cell + nc : (cell >= nc ? cell - nc : cell);
+        }
         const size_t at = (size_t)comp * nc + cell;
         if (DO_B)
-            GtB[comp * GT_STRIDE + k] = gld(S.GA + at);
+            GtB[comp * GTS + k] = gld(S.GA + at);
         if (DO_A)
-            GtA[comp * GT_STRIDE + k] = gld(S.G[SA - 1] + at);
+            GtA[comp * GTS + k] = gld(S.G[SA - 1] + at);
     }
     __syncthreads();
 
@@ -647,17 +652,30 @@ adj1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ sims
         double sN = 0.0, sNb = 0.0;
         if (DO_B) {
             // gather the deposited sources at t_SB: dX = Gamma_A + Omega.Gamma_B
-            const int kl = lane - tint[2 * j + 1] + 1;
+            const int kl = lane - tint[2 * j + 1] + SH;
             const double phB = tphi[2 * j + 1], omB = 1.0 - phB;
             double dX[9];
+            if (SH == 2) {
+                const Quad q = quad_weights(phB);
 #pragma unroll
-            for (int k = 0; k < 9; k++) {
-                const double *g = GtB + k * GT_STRIDE + kl;
-                const double A = omB * g[0] + phB * g[1];
-                const double Bx = omB * g[9 * GT_STRIDE] + phB * g[9 * GT_STRIDE + 1];
-                const double By = omB * g[18 * GT_STRIDE] + phB * g[18 * GT_STRIDE + 1];
-                const double Bz = omB * g[27 * GT_STRIDE] + phB * g[27 * GT_STRIDE + 1];
-                dX[k] = A + (vx * Bx + vy * By + vz * Bz);
+                for (int k = 0; k < 9; k++) {
+                    const double *g = GtB + k * GTS + kl - 1 + q.up;
+                    const double A = (q.w0 * g[0] + q.w1 * g[1]) + q.w2 * g[2];
+                    const double Bx = (q.w0 * g[9 * GTS] + q.w1 * g[9 * GTS + 1]) + q.w2 * g[9 * GTS + 2];
+                    const double By = (q.w0 * g[18 * GTS] + q.w1 * g[18 * GTS + 1]) + q.w2 * g[18 * GTS + 2];
+                    const double Bz = (q.w0 * g[27 * GTS] + q.w1 * g[27 * GTS + 1]) + q.w2 * g[27 * GTS + 2];
+                    dX[k] = A + (vx * Bx + vy * By + vz * Bz);
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < 9; k++) {
+                    const double *g = GtB + k * GTS + kl;
+                    const double A = omB * g[0] + phB * g[1];
+                    const double Bx = omB * g[9 * GTS] + phB * g[9 * GTS + 1];
+                    const double By = omB * g[18 * GTS] + phB * g[18 * GTS + 1];
+                    const double Bz = omB * g[27 * GTS] + phB * g[27 * GTS + 1];
+                    dX[k] = A + (vx * Bx + vy * By + vz * Bz);
+                }
             }
             if (active) {
                 double kb1 = 0.0, kb2 = 0.0, kb10 = 0.0, kb11 = 0.0;
@@ -706,14 +724,27 @@ adj1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ sims
             double X[9];
             // interpolate the stage-SA grid at t_SA (the anchor time)
             double Hnn[9];
+            if (SH == 2) {
+                const Quad q = quad_weights(phA);
 #pragma unroll
-            for (int k = 0; k < 9; k++) {
-                const double *g = GtA + k * GT_STRIDE + lane + 1;
-                const double A = omA * g[0] + phA * g[1];
-                const double Bx = omA * g[9 * GT_STRIDE] + phA * g[9 * GT_STRIDE + 1];
-                const double By = omA * g[18 * GT_STRIDE] + phA * g[18 * GT_STRIDE + 1];
-                const double Bz = omA * g[27 * GT_STRIDE] + phA * g[27 * GT_STRIDE + 1];
-                Hnn[k] = A - (vx * Bx + vy * By + vz * Bz);
+                for (int k = 0; k < 9; k++) {
+                    const double *g = GtA + k * GTS + lane + 1 + q.up;
+                    const double A = (q.w0 * g[0] + q.w1 * g[1]) + q.w2 * g[2];
+                    const double Bx = (q.w0 * g[9 * GTS] + q.w1 * g[9 * GTS + 1]) + q.w2 * g[9 * GTS + 2];
+                    const double By = (q.w0 * g[18 * GTS] + q.w1 * g[18 * GTS + 1]) + q.w2 * g[18 * GTS + 2];
+                    const double Bz = (q.w0 * g[27 * GTS] + q.w1 * g[27 * GTS + 1]) + q.w2 * g[27 * GTS + 2];
+                    Hnn[k] = A - (vx * Bx + vy * By + vz * Bz);
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < 9; k++) {
+                    const double *g = GtA + k * GTS + lane + 1;
+                    const double A = omA * g[0] + phA * g[1];
+                    const double Bx = omA * g[9 * GTS] + phA * g[9 * GTS + 1];
+                    const double By = omA * g[18 * GTS] + phA * g[18 * GTS + 1];
+                    const double Bz = omA * g[27 * GTS] + phA * g[27 * GTS + 1];
+                    Hnn[k] = A - (vx * Bx + vy * By + vz * Bz);
+                }
             }
             if (active) {
                 const double c1 = (SA == 1 || SA == 4) ? dt / 6.0 : dt / 3.0;
@@ -759,22 +790,58 @@ adj1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ sims
                 for (int k = 0; k < 9; k++)
                     X[k] = 0.0;
             }
-            // deposit the sources at t_SA: cell m gets (1 - phi) of its own
-            // particle and phi of the particle one lane to the left
+            if (SH == 2) {
+                // quadratic deposit at t_SA, as in the stage kernels
+                const Quad q = quad_weights(phA);
 #pragma unroll
-            for (int k = 0; k < 9; k++) {
-                double xl = lane_below(X[k]);
-                xl = (lane == 0) ? 0.0 : xl;
-                const double xc = omA * X[k] + phA * xl;
-                acc[k] += xc;
-                acc[9 + k] -= vx * xc;
-                acc[18 + k] -= vy * xc;
-                acc[27 + k] -= vz * xc;
-            }
-            if (lane == nact - 1) {
+                for (int k = 0; k < 9; k++) {
+                    const double x = X[k];
+                    double s1 = lane_below(x);
+                    s1 = (lane == 0) ? 0.0 : s1;
+                    double a, b, cc;
+                    if (q.up) {
+                        double s2 = lane_below(s1);
+                        s2 = (lane == 0) ? 0.0 : s2;
+                        a = x;
+                        b = s1;
+                        cc = s2;
+                    } else {
+                        double xa = lane_above(x);
+                        xa = (lane == TILE - 1) ? 0.0 : xa;
+                        a = xa;
+                        b = x;
+                        cc = s1;
+                    }
+                    const double xc = (q.w0 * a + q.w1 * b) + q.w2 * cc;
+                    acc[k] += xc;
+                    acc[9 + k] -= vx * xc;
+                    acc[18 + k] -= vy * xc;
+                    acc[27 + k] -= vz * xc;
+                    if (lane == nact - 1) {
+                        eb[((d - dbeg) * NE + 0) * 9 + k] = q.up ? q.w1 * x + q.w2 * s1 : q.w2 * x;
+                        eb[((d - dbeg) * NE + 1) * 9 + k] = q.up ? q.w2 * x : 0.0;
+                    }
+                    if (lane == 0)
+                        eb[((d - dbeg) * NE + 2) * 9 + k] = q.up ? 0.0 : q.w0 * x;
+                }
+            } else {
+                // deposit the sources at t_SA: cell m gets (1 - phi) of its
+                // own particle and phi of the particle one lane to the left
 #pragma unroll
-                for (int k = 0; k < 9; k++)
-                    eb[(d - dbeg) * 9 + k] = phA * X[k];
+                for (int k = 0; k < 9; k++) {
+                    double xl = lane_below(X[k]);
+                    xl = (lane == 0) ? 0.0 : xl;
+                    const double xc = omA * X[k] + phA * xl;
+                    acc[k] += xc;
+                    acc[9 + k] -= vx * xc;
+                    acc[18 + k] -= vy * xc;
+                    acc[27 + k] -= vz * xc;
+                }
+                if (lane == nact - 1) {
+#pragma unroll
+                    for (int k = 0; k < 9; k++)
+                        eb[(d - dbeg) * 9 + k] = phA * X[k];
+                }
             }
         }
     }
@@ -792,15 +859,16 @@ adj1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ sims
         }
         __syncthreads();
     }
-    double *esum = smem + NG * TILE;
-    if (lane < NG) {
-        const int comp = lane % 9, grp = lane / 9;
+    double *esum = smem + NG * TILE;  // [nwaves][NE][NG]
+    for (int q = lane; q < NE * NG; q += TILE) {
+        const int e = q / NG, r = q - e * NG;
+        const int comp = r % 9, grp = r / 9;
         double sacc = 0.0;
         for (int d = dbeg; d < dend; ++d) {
             const double coef = (grp == 0) ? 1.0 : (grp == 1) ? -S.vx[d] : (grp == 2) ? -S.vy[d] : -S.vz[d];
-            sacc += coef * eb[(d - dbeg) * 9 + comp];
+            sacc += coef * eb[((d - dbeg) * NE + e) * 9 + comp];
         }
-        esum[wave * NG + lane] = sacc;
+        esum[(wave * NE + e) * NG + r] = sacc;
     }
     __syncthreads();
     const int ntc = S.ntile * TILE;
@@ -809,11 +877,12 @@ adj1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ sims
         const int k = idx / TILE, l = idx - k * TILE;
         gst(part + (size_t)k * ntc + tile0 + l, redb[idx]);
     }
-    if (threadIdx.x < NG) {
+    for (int q = threadIdx.x; q < NE * NG; q += blockDim.x) {
+        const int e = q / NG, r = q - e * NG;
         double sacc = 0.0;
         for (int w = 0; w < nwaves; ++w)
-            sacc += esum[w * NG + threadIdx.x];
-        gst(S.edge + ((size_t)wi.group * NG + threadIdx.x) * S.ntile + wi.tile, sacc);
+            sacc += esum[(w * NE + e) * NG + r];
+        gst(S.edge + (((size_t)wi.group * NG + r) * NE + e) * S.ntile + wi.tile, sacc);
     }
 }
 
@@ -1091,31 +1160,43 @@ hipError_t launch_reduce1d(const RedItem *items, int nitems, const SimDesc *sims
     return hipGetLastError();
 }
 
-size_t adj1d_smem_bytes(int waves, int max_dpw)
+size_t adj1d_smem_bytes(int waves, int max_dpw, int shape)
 {
-    size_t tile = (size_t)NG * GT_STRIDE;
-    size_t red = (size_t)NG * TILE + (size_t)waves * NG;
+    const size_t ne = n_edges(shape);
+    size_t tile = (size_t)NG * gt_stride(shape);
+    size_t red = (size_t)NG * TILE + (size_t)waves * NG * ne;
     size_t gslot = tile > red ? tile : red;
     const size_t dpg = (size_t)waves * max_dpw;
-    return (2 * gslot + dpg * 9 + dpg * 2) * sizeof(double) + dpg * 2 * sizeof(int);
+    return (2 * gslot + dpg * 9 * ne + dpg * 2) * sizeof(double) + dpg * 2 * sizeof(int);
 }
 
 // kind 4: stage 4 sources; 3, 2, 1: gather of stage kind+1 fused with the
 // sources of stage kind; 0: gather of stage 1
-hipError_t launch_adj1d(int kind, const WorkItem *work, int nwork, const SimDesc *sims, int waves,
-                        int max_dpw, hipStream_t s)
+template <int SH>
+static hipError_t launch_adj1d_sh(int kind, const WorkItem *work, int nwork, const SimDesc *sims,
+                                  int waves, int max_dpw, hipStream_t s)
 {
     const dim3 grid(nwork), block(waves * TILE);
-    const size_t smem = adj1d_smem_bytes(waves, max_dpw);
+    const size_t smem = adj1d_smem_bytes(waves, max_dpw, SH);
     switch (kind) {
-    case 4: adj1d_kernel<false, true, 5, 4><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
-    case 3: adj1d_kernel<true, true, 4, 3><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
-    case 2: adj1d_kernel<true, true, 3, 2><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
-    case 1: adj1d_kernel<true, true, 2, 1><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
-    case 0: adj1d_kernel<true, false, 1, 0><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
+    case 4: adj1d_kernel<false, true, 5, 4, SH><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
+    case 3: adj1d_kernel<true, true, 4, 3, SH><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
+    case 2: adj1d_kernel<true, true, 3, 2, SH><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
+    case 1: adj1d_kernel<true, true, 2, 1, SH><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
+    case 0: adj1d_kernel<true, false, 1, 0, SH><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_adj1d(int kind, const WorkItem *work, int nwork, const SimDesc *sims, int waves,
+                        int max_dpw, int shape, hipStream_t s)
+{
+    if (shape == 2)
+        return launch_adj1d_sh<2>(kind, work, nwork, sims, waves, max_dpw, s);
+    if (shape == 1)
+        return launch_adj1d_sh<1>(kind, work, nwork, sims, waves, max_dpw, s);
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_tick(const SimDesc *sims, int64_t delta, hipStream_t s)

@@ -105,7 +105,7 @@ hipError_t launch_reduce1d(const RedItem *items, int nitems, const SimDesc *sims
 // weight gradients) fused with the sources of stage kind; kind 0 = gather of
 // the sources of stage 1
 hipError_t launch_adj1d(int kind, const WorkItem *work, int nwork, const SimDesc *sims, int waves,
-                        int max_dpw, hipStream_t s);
+                        int max_dpw, int shape, hipStream_t s);
 hipError_t launch_fill(double *p, size_t n, double v, hipStream_t s);
 hipError_t launch_tick(const SimDesc *sims, int64_t delta, hipStream_t s);
 hipError_t launch_tile_sum(const double *src, int ndir, int ntile, double scale, double *dst,

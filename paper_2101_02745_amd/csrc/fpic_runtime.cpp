@@ -831,8 +831,6 @@ int adj_check_cfg(fpic_ctx *c, const fpic_adjoint_cfg *a)
         return fail(FPIC_EINVAL, "adjoint: null argument");
     if (c->c3 || !c->b || c->b->plan.nsim != 1)
         return fail(FPIC_EUNSUPPORTED, "the adjoint covers single 1D boxes");
-    if (c->b->plan.shape != 1)
-        return fail(FPIC_EUNSUPPORTED, "the adjoint covers the linear shape function (shape_order 1)");
     if (a->nsteps < 1 || a->ckpt_every < 1)
         return fail(FPIC_EINVAL, "adjoint: nsteps and ckpt_every must be >= 1");
     return FPIC_OK;
@@ -890,7 +888,7 @@ int adj_graph(fpic_batch *b, bool reverse, int len, hipGraphExec_t *out)
                 // sources of stage s) for s = 3, 2, 1, then the gather of
                 // stage 1; each source deposit is closed by a reduction
                 for (int kind = 4; kind >= 0; --kind) {
-                    hipError_t e = launch_adj1d(kind, b->dwork, P.nwork, R + j, P.waves, P.max_dpw, b->cap);
+                    hipError_t e = launch_adj1d(kind, b->dwork, P.nwork, R + j, P.waves, P.max_dpw, P.shape, b->cap);
                     if (e == hipSuccess && kind > 0)
                         e = launch_reduce1d(b->dred, P.nred, R + j, RED_GA, nullptr, 0, b->cap);
                     if (e != hipSuccess)

@@ -144,12 +144,26 @@ def test_quadratic_two_beam_growth_on_gpu(torch_dev):
     assert abs(rate - 2 * mu) / (2 * mu) < 4.3e-3, rate
 
 
-def test_quadratic_adjoint_not_supported(torch_dev):
+@pytest.mark.parametrize("ncell,ndir,nsteps,ckpt,tuning", [
+    (70, 26, 7, 3, None),
+    (65, 8, 5, 5, {"waves": 2, "dirs_per_wave": 2}),
+    (2, 26, 4, 2, None),
+])
+def test_quadratic_adjoint_matches_reference(torch_dev, ncell, ndir, nsteps, ckpt, tuning):
     from paper_2101_02745_amd.sim import Sim
-    from paper_2101_02745_amd._lib import FpicError, FPIC_EUNSUPPORTED
-    w = box(40, 6)
-    sim = Sim.from_workload(w)
-    sim.set_state(w.state0())
-    with pytest.raises(FpicError) as ei:
-        sim.adjoint_forward(4, 2)
-    assert ei.value.code == FPIC_EUNSUPPORTED
+    w = box(ncell, ndir, seed=11)
+    rng = np.random.default_rng(ncell + 1)
+    c = rng.normal(size=(18, ndir, ncell))
+    s0 = w.state0()
+    P = Problem.from_workload(w)
+    g_ref, gN_ref, gNb_ref = P.adjoint(s0, nsteps, c, n0=2)
+    sim = Sim.from_workload(w, tuning=tuning)
+    sim.set_state(s0, step0=2)
+    sim.adjoint_forward(nsteps, ckpt)
+    g0, gN, gNb = sim.adjoint_backward(c)
+
+    def normwise(a, b):
+        return np.abs(np.asarray(a) - np.asarray(b)).max() / np.abs(np.asarray(b)).max()
+    assert normwise(g0.cpu().numpy(), g_ref) < 1e-10
+    assert normwise(gN, gN_ref) < 1e-10
+    assert normwise(gNb, gNb_ref) < 1e-10

@@ -102,3 +102,32 @@ def test_p12a_adjoint_with_matter():
         fd = (loss(P, st + h * v, nsteps, c) - loss(P, st - h * v, nsteps, c)) / (2 * h)
         ad = float(np.sum(g0 * v))
         assert abs(fd - ad) <= 1e-7 * max(1.0, abs(ad)), (fd, ad)
+
+
+def test_p12a_adjoint_quadratic_shape():
+    """The reverse mode with the quadratic shape function against central
+    differences (state and weights)."""
+    rng = np.random.default_rng(24)
+    P0, st = small_problem(rng, ncell=6)
+    P = Problem(P0.ncell, P0.dx, P0.dirs, P0.N, P0.Nbar, np.zeros((3, 3)), P0.dt, shape_order=2)
+    P.hvac[:] = P0.hvac
+    nsteps = 5
+    c = rng.normal(size=st.shape)
+    g0, gN, gNb = P.adjoint(st, nsteps, c)
+    h = 1e-6
+    for _ in range(3):
+        v = rng.normal(size=st.shape)
+        fd = (loss(P, st + h * v, nsteps, c) - loss(P, st - h * v, nsteps, c)) / (2 * h)
+        ad = float(np.sum(g0 * v))
+        assert abs(fd - ad) <= 1e-7 * max(1.0, abs(ad)), (fd, ad)
+    d = 2
+    hh = h * abs(P.N[d])
+    Ns = []
+    for sgn in (1, -1):
+        N = P.N.copy()
+        N[d] += sgn * hh
+        Q = Problem(P.ncell, P.dx, P.dirs, N, P.Nbar.copy(), np.zeros((3, 3)), P.dt, shape_order=2)
+        Q.hvac[:] = P.hvac
+        Ns.append(loss(Q, st, nsteps, c))
+    fd = (Ns[0] - Ns[1]) / (2 * hh)
+    assert abs(fd - gN[d]) <= 1e-6 * max(1.0, abs(gN[d])), (fd, gN[d])
