@@ -7,13 +7,13 @@
  * What one step computes (Sec. II.B-II.C):
  *   for each of the four stages of classical RK4 (Sec. II.C),
  *     - deposit every particle's density matrices onto the grid with the
- *       linear (cloud-in-cell) shape function (Sec. II.B.1,
+ *       linear (cloud-in-cell) or quadratic shape function (Sec. II.B.1,
  *       eq. pic_deposition), combined as n - nbar^* and f - fbar^*;
  *     - interpolate those moments back to every particle with the same
  *       weights (Sec. II.B.2, eq. pic_interpolation) and form
- *       H = H_vac + (n - nbar^*) - Omega.(f - fbar^*) and
- *       Hbar = H_vac^* - [(n - nbar^*) - Omega.(f - fbar^*)]^*
- *       (Sec. II.A, eq. potentials; matter term zero);
+ *       H = H_vac + diag(V) + (n - nbar^*) - Omega.(f - fbar^*) and
+ *       Hbar = H_vac^* - diag(V) - [(n - nbar^*) - Omega.(f - fbar^*)]^*
+ *       (Sec. II.A, eq. potentials; V the background matter potential);
  *     - evaluate d rho/dt = -i [H, rho], d rhobar/dt = -i [Hbar, rhobar]
  *       (eq. eom) and form the next stage state.
  *
@@ -60,7 +60,8 @@ typedef void *fpic_stream; /* hipStream_t */
 
 /* A periodic box with one particle per direction per cell. */
 typedef struct fpic_config {
-    int32_t ncell[3];    /* cells along x, y, z; a 1D box is {1, 1, nz} */
+    int32_t ncell[3];    /* cells along x, y, z; a 1D box is {1, 1, nz};
+                            any other shape is a 3D box and needs nx <= 64 */
     double dx[3];        /* cell widths (cell volume dx*dy*dz) */
     int32_t ndir;        /* directions = particles per cell */
     const double *dirs;  /* host [ndir][3] unit vectors Omega_d */
@@ -75,7 +76,9 @@ typedef struct fpic_config {
                             0 = no matter */
     double dt;           /* time step; a stage may move no particle by a
                             whole cell: dt/2 * max|Omega_a| < dx_a */
-    int32_t shape_order; /* 1 (linear, cloud-in-cell) */
+    int32_t shape_order; /* 1 linear (cloud in cell); 2 quadratic
+                            (triangular-shaped cloud, Sec. II.B.1; 1D
+                            boxes, batches and the adjoint only) */
     int32_t flags;       /* reserved, 0 */
 } fpic_config;
 
@@ -137,7 +140,8 @@ void fpic_destroy(fpic_ctx *ctx);
 /* SYNC.  Measurement: advance nsteps steps launching each kernel on its own
  * (outside the graph) with HIP events between launches, and return the mean
  * milliseconds per launch (host ms[8]) of: stage 1, its reduction, stage 2,
- * its reduction, stage 3, its reduction, stage 4, its reduction. */
+ * its reduction, stage 3, its reduction, stage 4, its reduction (3D boxes:
+ * each stage's particle kernel, then its deposit kernel). */
 int fpic_profile(fpic_ctx *ctx, int32_t nsteps, double *ms);
 
 /* Message of the calling thread's last failed call ("" if none). */
@@ -167,7 +171,7 @@ int fpic_batch_sync(fpic_batch *b);
 void fpic_batch_destroy(fpic_batch *b);
 
 /* ---------------------------------------------------------------------
- * Reverse mode (1D boxes).  A hand-written discrete adjoint of the RK4
+ * Reverse mode (1D boxes, either shape order).  A hand-written discrete adjoint of the RK4
  * steps above (deposit, interpolation, Hamiltonians, commutators, stage
  * updates), with checkpointing: the forward pass stores the state every
  * ckpt_every steps; the backward pass recomputes each segment (storing its
