@@ -142,6 +142,19 @@ def measure_3d(steps=20):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = sim.profile(3)
+    del sim
+    # the same box with the quadratic shape function, same launch shape
+    import dataclasses
+    wq = dataclasses.replace(w, shape_order=2)
+    simq = Sim.from_workload(wq, tuning=tune)
+    simq.set_state(wq.state0())
+    simq.step(2)
+    torch.cuda.synchronize()
+    tq = time.perf_counter()
+    simq.step(8)
+    torch.cuda.synchronize()
+    wall_q = (time.perf_counter() - tq) / 8
+    del simq
     P = w.nparticles
     part_ms = [ms[0], ms[2], ms[4], ms[6]]
     dep_ms = [ms[1], ms[3], ms[5], ms[7]]
@@ -156,7 +169,8 @@ def measure_3d(steps=20):
             "deposit_kernel_GBs": [dep_bytes / (t * 1e-3) / 1e9 for t in dep_ms],
             "alg_bytes_per_step": step_bytes,
             "step_frac_of_hbm_peak": step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
-            "step_frac_of_fused_floor": STEP_BYTES * P / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS}
+            "step_frac_of_fused_floor": STEP_BYTES * P / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "quadratic_shape": {"ms_per_step": 1e3 * wall_q, "value": P / wall_q}}
 
 
 def measure_quadratic(tuning, steps=200):

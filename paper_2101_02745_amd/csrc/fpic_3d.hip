@@ -50,6 +50,8 @@ struct Desc3 {
     double *X;              // [9][ndir][ncell] deposit sources
     double *G[2];           // [36][ncell]: stage s reads G[(s-1)&1]
     int64_t *step;
+    int32_t shape;          // shape-function order: 1 linear, 2 quadratic
+    int32_t pad_;
 };
 
 typedef __attribute__((address_space(1))) double gdouble;
@@ -421,6 +423,267 @@ static unsigned deposit_blocks(const Desc3 &h)
     return (unsigned)(((h.n[1] + DEP_PY - 1) / DEP_PY) * ((h.n[2] + DEP_PZ - 1) / DEP_PZ));
 }
 
+// ---------------------------------------------------------------------------
+// Quadratic (triangular-shaped cloud) shape function, Sec. II.B.1.  Along
+// each axis a particle spreads over its nearest cell centre and the two
+// neighbours with weights (1/2 - xi)^2 / 2, 3/4 - xi^2, (1/2 + xi)^2 / 2,
+// xi = x - x_nearest in [-1/2, 1/2) (each operation rounded once, as the CPU
+// reference forms them); a one-cell axis gives (0, 1, 0).  The particle
+// kernel's workgroup owns one row of *nearest* cells; the nine grid rows it
+// interpolates from are read through the caches (nine rows of 36 components
+// do not fit the 160 KB LDS at 64 cells per row).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void axis_quad(double v, double t, double dx, int n, int *r, double w[3])
+{
+#pragma clang fp contract(off)
+    if (n == 1) {
+        *r = 0;
+        w[0] = 0.0;
+        w[1] = 1.0;
+        w[2] = 0.0;
+        return;
+    }
+    const double u = (v * t) / dx;
+    const double fl = floor(u);
+    const double phi = u - fl;
+    const int up = phi < 0.5 ? 0 : 1;
+    const double xi = up ? phi - 1.0 : phi;
+    w[0] = 0.5 * ((0.5 - xi) * (0.5 - xi));
+    w[1] = 0.75 - xi * xi;
+    w[2] = 0.5 * ((0.5 + xi) * (0.5 + xi));
+    const double nd = (double)n;
+    const double near = fl + (double)up;
+    double q = near - nd * floor(near / nd);
+    if (q < 0.0)
+        q += nd;
+    if (q >= nd)
+        q -= nd;
+    *r = (int)q;
+}
+
+__device__ __forceinline__ int wrap(int i, int n)
+{
+    i %= n;
+    return i < 0 ? i + n : i;
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(MAX_WAVES3 * W)
+particle3q_kernel(const Desc3 *__restrict__ dp, int dpw, int nitems)
+{
+    const Desc3 S = *dp;
+    const int lane = threadIdx.x & (W - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / W);
+    const int nwaves = blockDim.x / W;
+    const int item = blockIdx.x;
+    if (item >= nitems)
+        return;
+    const int nx = S.n[0], ny = S.n[1], nz = S.n[2];
+    const int nrows = ny * nz;
+    const int row = item % nrows, grp = item / nrows;
+    const int y0 = row % ny, z0 = row / ny;
+    const bool active = lane < nx;
+    const int64_t n = *S.step;
+    const double dt = S.dt;
+    double t_cur = 0.0;
+    if (MODE == 2 || MODE == 3)
+        t_cur = stage_time(n, dt, 0.5);
+    else if (MODE == 4)
+        t_cur = stage_time(n, dt, 1.0);
+    else
+        t_cur = stage_time(n, dt, 0.0);
+    const double *Gin = S.G[(MODE - 1) & 1];
+    const double *Kp = (MODE == 2) ? S.K1 : (MODE == 3) ? S.K2 : S.K3;
+    const int dbeg = (grp * nwaves + wave) * dpw, dend = min(dbeg + dpw, S.ndir);
+    const int xl = (lane + nx - 1) % (nx < 1 ? 1 : nx), xr = (lane + 1) % (nx < 1 ? 1 : nx);
+    // the nine grid rows around the nearest row (y0, z0): row q = 3 c + b is
+    // (y0 + b - 1, z0 + c - 1); cell offsets fit 32 bits (ncell <= 2^30)
+    int rowoff[9];
+#pragma unroll
+    for (int c = 0; c < 3; c++)
+#pragma unroll
+        for (int b = 0; b < 3; b++)
+            rowoff[3 * c + b] = (wrap(z0 + c - 1, nz) * ny + wrap(y0 + b - 1, ny)) * nx + (active ? lane : 0);
+
+    for (int d = dbeg; d < dend; ++d) {
+        const double vx = S.v[0][d], vy = S.v[1][d], vz = S.v[2][d];
+        const double wN = S.wN[d], wNb = S.wNb[d];
+        int rx, ry, rz;
+        double wx[3], wy[3], wz[3];
+        axis_quad(vx, t_cur, S.dx[0], nx, &rx, wx);
+        axis_quad(vy, t_cur, S.dx[1], ny, &ry, wy);
+        axis_quad(vz, t_cur, S.dx[2], nz, &rz, wz);
+        const int cx = wrap(lane - rx, nx), cy = wrap(y0 - ry, ny), cz = wrap(z0 - rz, nz);
+        const int64_t c = ((int64_t)cz * ny + cy) * nx + (active ? cx : 0);
+        const int64_t p = (int64_t)d * S.ncell + c;
+        double Y[18];
+#pragma unroll
+        for (int k = 0; k < 18; k++)
+            Y[k] = active ? gld(S.Y + k * S.np + p) : 0.0;
+        double Hnn[9];
+#pragma unroll
+        for (int k = 0; k < 9; k++)
+            Hnn[k] = 0.0;
+#pragma unroll 1
+        for (int grp4 = 0; grp4 < 4; grp4++) {
+            const double coef = (grp4 == 0) ? 1.0 : (grp4 == 1) ? -vx : (grp4 == 2) ? -vy : -vz;
+            const double *g = Gin + (int64_t)(9 * grp4) * S.ncell;
+            // y/z interpolation row by row (nine loads in flight per row)
+            double r[9];
+#pragma unroll
+            for (int k = 0; k < 9; k++)
+                r[k] = 0.0;
+#pragma unroll 1
+            for (int q = 0; q < 9; q++) {
+                const int b = q % 3, cc = q / 3;
+                int ro = rowoff[0];
+#pragma unroll
+                for (int qq = 1; qq < 9; qq++)
+                    ro = (q == qq) ? rowoff[qq] : ro;
+                const double wq = wy[b] * wz[cc];
+#pragma unroll
+                for (int k = 0; k < 9; k++)
+                    r[k] += wq * (active ? gld(g + (int64_t)k * S.ncell + ro) : 0.0);
+            }
+#pragma unroll
+            for (int k = 0; k < 9; k++) {
+                const double nl = lane_get(r[k], xl), nr = lane_get(r[k], xr);
+                Hnn[k] += coef * ((wx[0] * nl + wx[1] * r[k]) + wx[2] * nr);
+            }
+        }
+        double yv[18], base[18], yn[18];
+        if (MODE == 1) {
+#pragma unroll
+            for (int k = 0; k < 18; k++)
+                yv[k] = base[k] = Y[k];
+        } else if (MODE == 4) {
+            const double h6 = dt / 6.0;
+            double k1[18], k2[18], k3[18];
+            load_slope(S.K1, S.np, p, active, k1);
+            load_slope(S.K2, S.np, p, active, k2);
+            load_slope(S.K3, S.np, p, active, k3);
+#pragma unroll
+            for (int k = 0; k < 18; k++) {
+                yv[k] = Y[k] + dt * k3[k];
+                base[k] = Y[k] + h6 * ((k1[k] + 2.0 * k2[k]) + 2.0 * k3[k]);
+            }
+        } else {
+            double kp[18];
+            load_slope(Kp, S.np, p, active, kp);
+#pragma unroll
+            for (int k = 0; k < 18; k++) {
+                yv[k] = Y[k] + 0.5 * dt * kp[k];
+                base[k] = Y[k];
+            }
+        }
+        double H[9], Hb[9], kk[18];
+#pragma unroll
+        for (int k = 0; k < 9; k++) {
+            H[k] = S.hvac[k] + Hnn[k];
+            const double hb = S.hvacb[k] - Hnn[k];
+            Hb[k] = (k == 4 || k == 6 || k == 8) ? -hb : hb;
+        }
+        commutator(H, yv, kk);
+        commutator(Hb, yv + 9, kk + 9);
+        if (MODE == 4) {
+            const double h6 = dt / 6.0;
+#pragma unroll
+            for (int k = 0; k < 18; k++) {
+                yn[k] = base[k] + h6 * kk[k];
+                if (active)
+                    gst(S.Y + k * S.np + p, yn[k]);
+            }
+        } else {
+            double *Ko = (MODE == 1) ? S.K1 : (MODE == 2) ? S.K2 : S.K3;
+            const double an = (MODE == 3) ? dt : 0.5 * dt;
+#pragma unroll
+            for (int k = 0; k < 18; k++) {
+                if (active && k != 0 && k != 9)
+                    gst(Ko + kslot(k) * S.np + p, kk[k]);
+                yn[k] = base[k] + an * kk[k];
+            }
+        }
+        if (active) {
+#pragma unroll
+            for (int k = 0; k < 9; k++) {
+                const double x = (k == 4 || k == 6 || k == 8) ? wN * yn[k] + wNb * yn[9 + k]
+                                                              : wN * yn[k] - wNb * yn[9 + k];
+                gst(S.X + k * S.np + p, x);
+            }
+        }
+    }
+}
+
+// Quadratic deposit: destination cell (x, y, z) takes weight
+// wx[i] wy[j] wz[k] from the particle whose nearest cell is
+// (x - i + 1, y - j + 1, z - k + 1), i, j, k = 0..2: nine source rows in y
+// and z, then the lanes one right and one left in x.
+__global__ void __launch_bounds__(DEP_WAVES * W)
+deposit3q_kernel(const Desc3 *__restrict__ dp, int half_steps, int out_buf)
+{
+    const Desc3 S = *dp;
+    const int lane = threadIdx.x & (W - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / W);
+    const int nx = S.n[0], ny = S.n[1], nz = S.n[2];
+    const int npy = (ny + DEP_PY - 1) / DEP_PY;
+    const int y = (blockIdx.x % npy) * DEP_PY + wave % DEP_PY;
+    const int z = (blockIdx.x / npy) * DEP_PZ + wave / DEP_PY;
+    if (y >= ny || z >= nz)
+        return;  // no workgroup barrier in this kernel
+    const bool active = lane < nx;
+    const int64_t n0 = *S.step;
+    double t;
+    if (half_steps == 3)
+        t = stage_time(n0 + 1, S.dt, 0.0);
+    else
+        t = stage_time(n0, S.dt, 0.5 * half_steps);
+    const int xl = (lane + nx - 1) % (nx < 1 ? 1 : nx), xr = (lane + 1) % (nx < 1 ? 1 : nx);
+    double acc[NG];
+#pragma unroll
+    for (int q = 0; q < NG; q++)
+        acc[q] = 0.0;
+    for (int d = 0; d < S.ndir; ++d) {
+        const double vx = S.v[0][d], vy = S.v[1][d], vz = S.v[2][d];
+        int rx, ry, rz;
+        double wx[3], wy[3], wz[3];
+        axis_quad(vx, t, S.dx[0], nx, &rx, wx);
+        axis_quad(vy, t, S.dx[1], ny, &ry, wy);
+        axis_quad(vz, t, S.dx[2], nz, &rz, wz);
+        const int xs = active ? wrap(lane - rx, nx) : 0;
+        double Xyz[9];
+#pragma unroll
+        for (int k = 0; k < 9; k++)
+            Xyz[k] = 0.0;
+#pragma unroll 1
+        for (int kk = 0; kk < 3; kk++)
+#pragma unroll
+            for (int j = 0; j < 3; j++) {
+                const int yy = wrap(y - j + 1 - ry, ny), zz = wrap(z - kk + 1 - rz, nz);
+                const double w = wy[j] * wz[kk];
+                const double *xp = S.X + (int64_t)d * S.ncell + ((int64_t)zz * ny + yy) * nx + xs;
+#pragma unroll
+                for (int k = 0; k < 9; k++)
+                    Xyz[k] += w * (active ? gld(xp + (int64_t)k * S.np) : 0.0);
+            }
+#pragma unroll
+        for (int k = 0; k < 9; k++) {
+            const double right = lane_get(Xyz[k], xr), left = lane_get(Xyz[k], xl);
+            const double xc = (wx[0] * right + wx[1] * Xyz[k]) + wx[2] * left;
+            acc[k] += xc;
+            acc[9 + k] += vx * xc;
+            acc[18 + k] += vy * xc;
+            acc[27 + k] += vz * xc;
+        }
+    }
+    if (active) {
+        double *G = out_buf ? S.G[1] : S.G[0];
+        const int64_t cell = ((int64_t)z * ny + y) * nx + lane;
+#pragma unroll
+        for (int q = 0; q < NG; q++)
+            gst(G + (int64_t)q * S.ncell + cell, acc[q]);
+    }
+}
+
 // moments of neutrinos (which = 0) or antineutrinos (1) at the current step
 // time, written to out[36][ncell] (deposits N rho or Nbar rhobar alone)
 __global__ void __launch_bounds__(256)
@@ -554,8 +817,9 @@ static int validate(const fpic_config &c)
         return fail(FPIC_EUNSUPPORTED, "3D boxes need nx <= 64 (the x axis of a box fits one wave)");
     if (!c.dirs || !c.N || !c.Nbar)
         return fail(FPIC_EINVAL, "dirs, N and Nbar must be non-null host arrays");
-    if (c.shape_order != 1)
-        return fail(FPIC_EUNSUPPORTED, "3D boxes take shape_order 1 (cloud in cell) only");
+    if (c.shape_order != 1 && c.shape_order != 2)
+        return fail(FPIC_EUNSUPPORTED,
+                    "shape_order must be 1 (linear, cloud in cell) or 2 (quadratic)");
     if (!(c.dt > 0.0) || !std::isfinite(c.dt))
         return fail(FPIC_EINVAL, "dt must be positive and finite");
     for (int a = 0; a < 3; ++a)
@@ -658,18 +922,55 @@ int workspace_bytes(const fpic_config &cfg, const fpic_tuning *tune, size_t *byt
     return FPIC_OK;
 }
 
+// stage `mode` (1..4; 5 = deposit sources of the current state) of the
+// particle kernels, and the deposit of the sources, for the box's shape order
+static void launch_particle(const Ctx3D *c, int mode, hipStream_t s)
+{
+    const dim3 pgrid(c->nitems), pblk(c->waves * W);
+    const bool q = c->h.shape == 2;
+    switch (mode) {
+    case 1:
+        if (q) particle3q_kernel<1><<<pgrid, pblk, 0, s>>>(c->d, c->dpw, c->nitems);
+        else particle3d_kernel<1><<<pgrid, pblk, 0, s>>>(c->d, c->dpw, c->nitems);
+        break;
+    case 2:
+        if (q) particle3q_kernel<2><<<pgrid, pblk, 0, s>>>(c->d, c->dpw, c->nitems);
+        else particle3d_kernel<2><<<pgrid, pblk, 0, s>>>(c->d, c->dpw, c->nitems);
+        break;
+    case 3:
+        if (q) particle3q_kernel<3><<<pgrid, pblk, 0, s>>>(c->d, c->dpw, c->nitems);
+        else particle3d_kernel<3><<<pgrid, pblk, 0, s>>>(c->d, c->dpw, c->nitems);
+        break;
+    case 4:
+        if (q) particle3q_kernel<4><<<pgrid, pblk, 0, s>>>(c->d, c->dpw, c->nitems);
+        else particle3d_kernel<4><<<pgrid, pblk, 0, s>>>(c->d, c->dpw, c->nitems);
+        break;
+    default:  // no interpolation: the same for both shapes
+        particle3d_kernel<5><<<pgrid, pblk, 0, s>>>(c->d, c->dpw, c->nitems);
+        break;
+    }
+}
+
+static void launch_deposit(const Ctx3D *c, const Desc3 *dd, int half_steps, int out_buf, hipStream_t s)
+{
+    const dim3 dgrid(deposit_blocks(c->h)), blk(DEP_WAVES * W);
+    if (c->h.shape == 2)
+        deposit3q_kernel<<<dgrid, blk, 0, s>>>(dd, half_steps, out_buf);
+    else
+        deposit3d_kernel<<<dgrid, blk, 0, s>>>(dd, half_steps, out_buf);
+}
+
 static hipError_t launch_step(Ctx3D *c, hipStream_t s)
 {
-    const dim3 pgrid(c->nitems), pblk(c->waves * W), dgrid(deposit_blocks(c->h)), blk(DEP_WAVES * W);
     // stage s reads G[(s-1)&1]; its deposit writes G[s&1]
-    particle3d_kernel<1><<<pgrid, pblk, 0, s>>>(c->d, c->dpw, c->nitems);
-    deposit3d_kernel<<<dgrid, blk, 0, s>>>(c->d, 1, 1);
-    particle3d_kernel<2><<<pgrid, pblk, 0, s>>>(c->d, c->dpw, c->nitems);
-    deposit3d_kernel<<<dgrid, blk, 0, s>>>(c->d, 1, 0);
-    particle3d_kernel<3><<<pgrid, pblk, 0, s>>>(c->d, c->dpw, c->nitems);
-    deposit3d_kernel<<<dgrid, blk, 0, s>>>(c->d, 2, 1);
-    particle3d_kernel<4><<<pgrid, pblk, 0, s>>>(c->d, c->dpw, c->nitems);
-    deposit3d_kernel<<<dgrid, blk, 0, s>>>(c->d, 3, 0);
+    launch_particle(c, 1, s);
+    launch_deposit(c, c->d, 1, 1, s);
+    launch_particle(c, 2, s);
+    launch_deposit(c, c->d, 1, 0, s);
+    launch_particle(c, 3, s);
+    launch_deposit(c, c->d, 2, 1, s);
+    launch_particle(c, 4, s);
+    launch_deposit(c, c->d, 3, 0, s);
     tick3d<<<1, 64, 0, s>>>(c->d);
     return hipGetLastError();
 }
@@ -732,6 +1033,7 @@ int create(const fpic_config &cfg, const fpic_tuning *tune, void *ws, size_t byt
     D.ncell = (int64_t)cfg.ncell[0] * cfg.ncell[1] * cfg.ncell[2];
     D.np = D.ncell * nd;
     D.dt = cfg.dt;
+    D.shape = cfg.shape_order;
     const double *h = cfg.hvac;
     const double hv[9] = {h[0], h[8], h[16], h[2], h[3], h[4], h[5], h[10], h[11]};
     for (int k = 0; k < 9; ++k) {
@@ -784,9 +1086,8 @@ int set_state(Ctx3D *c, const double *state, int64_t step0)
     HIPCHECK(hipMemcpyAsync(c->h.Y, state, sizeof(double) * 18 * c->h.np, hipMemcpyDeviceToDevice, c->stream));
     set_step3d<<<1, 64, 0, c->stream>>>(c->d, step0);
     HIPCHECK(hipGetLastError());
-    const dim3 pgrid(c->nitems), pblk(c->waves * W), dgrid(deposit_blocks(c->h)), blk(DEP_WAVES * W);
-    particle3d_kernel<5><<<pgrid, pblk, 0, c->stream>>>(c->d, c->dpw, c->nitems);
-    deposit3d_kernel<<<dgrid, blk, 0, c->stream>>>(c->d, 0, 0);
+    launch_particle(c, 5, c->stream);
+    launch_deposit(c, c->d, 0, 0, c->stream);
     HIPCHECK(hipGetLastError());
     c->state_set = true;
     return FPIC_OK;
@@ -825,13 +1126,12 @@ int moments(Ctx3D *c, double *out)
     // the deposit kernel writes G[out_buf]; point a copy of the descriptor
     // at the caller's buffer
     Desc3 D = c->h;
-    const dim3 dgrid(deposit_blocks(c->h)), blk(DEP_WAVES * W);
     for (int which = 0; which < 2; ++which) {
         D.G[0] = out + (size_t)which * NG * c->h.ncell;
         HIPCHECK(hipMemcpyAsync(c->scratch, &D, sizeof D, hipMemcpyHostToDevice, c->stream));
         const Desc3 *dd = reinterpret_cast<const Desc3 *>(c->scratch);
         momsrc3d_kernel<<<1024, 256, 0, c->stream>>>(dd, which);
-        deposit3d_kernel<<<dgrid, blk, 0, c->stream>>>(dd, 0, 0);
+        launch_deposit(c, dd, 0, 0, c->stream);
         HIPCHECK(hipGetLastError());
         HIPCHECK(hipStreamSynchronize(c->stream));   // D is a host temporary
     }
@@ -887,7 +1187,6 @@ int profile(Ctx3D *c, int nsteps, double *ms)
 {
     if (!c->state_set)
         return fail(FPIC_ESTATE, "profile before set_state");
-    const dim3 pgrid(c->nitems), pblk(c->waves * W), dgrid(deposit_blocks(c->h)), blk(DEP_WAVES * W);
     hipEvent_t ev[9];
     for (auto &e : ev)
         HIPCHECK(hipEventCreate(&e));
@@ -896,21 +1195,21 @@ int profile(Ctx3D *c, int nsteps, double *ms)
     int rc = FPIC_OK;
     for (int n = 0; n < nsteps && !rc; ++n) {
         (void)hipEventRecord(ev[0], s);
-        particle3d_kernel<1><<<pgrid, pblk, 0, s>>>(c->d, c->dpw, c->nitems);
+        launch_particle(c, 1, s);
         (void)hipEventRecord(ev[1], s);
-        deposit3d_kernel<<<dgrid, blk, 0, s>>>(c->d, 1, 1);
+        launch_deposit(c, c->d, 1, 1, s);
         (void)hipEventRecord(ev[2], s);
-        particle3d_kernel<2><<<pgrid, pblk, 0, s>>>(c->d, c->dpw, c->nitems);
+        launch_particle(c, 2, s);
         (void)hipEventRecord(ev[3], s);
-        deposit3d_kernel<<<dgrid, blk, 0, s>>>(c->d, 1, 0);
+        launch_deposit(c, c->d, 1, 0, s);
         (void)hipEventRecord(ev[4], s);
-        particle3d_kernel<3><<<pgrid, pblk, 0, s>>>(c->d, c->dpw, c->nitems);
+        launch_particle(c, 3, s);
         (void)hipEventRecord(ev[5], s);
-        deposit3d_kernel<<<dgrid, blk, 0, s>>>(c->d, 2, 1);
+        launch_deposit(c, c->d, 2, 1, s);
         (void)hipEventRecord(ev[6], s);
-        particle3d_kernel<4><<<pgrid, pblk, 0, s>>>(c->d, c->dpw, c->nitems);
+        launch_particle(c, 4, s);
         (void)hipEventRecord(ev[7], s);
-        deposit3d_kernel<<<dgrid, blk, 0, s>>>(c->d, 3, 0);
+        launch_deposit(c, c->d, 3, 0, s);
         tick3d<<<1, 64, 0, s>>>(c->d);
         (void)hipEventRecord(ev[8], s);
         hipError_t err = hipGetLastError();

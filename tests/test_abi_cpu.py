@@ -83,7 +83,7 @@ def test_workspace_size_is_consistent(lib):
     ({"dt": -0.1}, _lib.FPIC_EINVAL),
     ({"dt": float("nan")}, _lib.FPIC_EINVAL),
     ({"shape_order": 3}, _lib.FPIC_EUNSUPPORTED),
-    ({"shape_order": 2, "ncell": [4, 4, 4]}, _lib.FPIC_EUNSUPPORTED),   # 3D: linear only
+    ({"shape_order": 3, "ncell": [4, 4, 4]}, _lib.FPIC_EUNSUPPORTED),   # 3D path
     ({"hvac": [0.0, 1.0] + [0.0] * 16}, _lib.FPIC_EINVAL),   # not Hermitian
     ({"vmat": [0.0, float("inf"), 0.0]}, _lib.FPIC_EINVAL),
     ({"vmat": [0.0, float("inf"), 0.0], "ncell": [4, 4, 4]}, _lib.FPIC_EINVAL),   # 3D path

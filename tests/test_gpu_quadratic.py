@@ -167,3 +167,46 @@ def test_quadratic_adjoint_matches_reference(torch_dev, ncell, ndir, nsteps, ckp
     assert normwise(g0.cpu().numpy(), g_ref) < 1e-10
     assert normwise(gN, gN_ref) < 1e-10
     assert normwise(gNb, gNb_ref) < 1e-10
+
+
+@pytest.mark.parametrize("ncell,ndir,tuning,step0", [
+    ((8, 6, 5), 26, None, 2),
+    ((13, 7, 3), 26, {"waves": 2, "dirs_per_wave": 5}, 41),
+    ((16, 1, 8), 26, None, 2),      # one-cell axis in y
+    ((1, 12, 10), 6, None, 300),    # one-cell axis in x
+    ((2, 2, 9), 92, None, 5),       # two-cell axes: the stencil folds
+    ((64, 3, 4), 92, {"waves": 4, "dirs_per_wave": 7}, 333),
+])
+def test_quadratic_3d_parity(torch_dev, ncell, ndir, tuning, step0):
+    from paper_2101_02745_amd.sim import Sim
+    w = quad(I.Workload(name="q3", ncell=ncell, length=tuple(0.5 * n for n in ncell), ndir=ndir,
+                        dt=0.1, steps=0, f=0.1, fbar=-0.2, nbar_over_n=1.2,
+                        nhat=(0.5, 0.0, 0.8660254037844386), seed=3, alpha=1e-2))
+    sim, P, got, ref = run_pair(w, 4, tuning=tuning, step0=step0)
+    assert_parity(got, ref, what=f"quadratic 3D {ncell}")
+    mom = sim.moments().cpu().numpy()
+    mref = P.moments(ref, (step0 + 4) * w.dt)
+    assert np.abs(mom - mref).max() <= 1e-12 * np.abs(mref).max()
+    assert sim.check(1e-12) < 1e-13
+
+
+def test_quadratic_3d_full_size_homogeneous(torch_dev):
+    """The full 64^3 x 92 box with the quadratic shape, from a state that is
+    the same in every cell: the weights sum to one, so the method reduces
+    exactly to one cell holding the 92 directions (the reference computes
+    it); every particle of the GPU run is compared with it."""
+    import torch
+    from paper_2101_02745_amd.sim import Sim
+    w = quad(I.workload("3d_64x92"))
+    one = quad(I.Workload(name="one", ncell=(1, 1, 1), length=w.dx, ndir=w.ndir, dt=w.dt, steps=0,
+                          f=w.f, fbar=w.fbar, nbar_over_n=w.nbar_over_n, nhat=w.nhat, seed=7,
+                          alpha=0.05))
+    s1 = one.state0()
+    ref = Problem.from_workload(one).step(s1, 4)
+    sim = Sim.from_workload(w)
+    sim.set_state(torch.from_numpy(s1).cuda().expand(18, w.ndir, w.ncell_total).contiguous())
+    sim.step(4)
+    got = sim.get_state()
+    for k in range(18):
+        dev = (got[k] - torch.from_numpy(ref[k]).cuda()).abs().max().item()
+        assert dev <= 1e-12 * max(1.0, np.abs(ref).max()), (k, dev)
