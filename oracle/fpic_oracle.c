@@ -43,9 +43,18 @@
  * product and sum rounded once (this file is compiled with
  * -ffp-contract=off).
  *
+ * General placement.  A problem may instead list npart particles with their
+ * own positions x0 at t = 0, directions and weights (the general particle
+ * form of Sec. II.B: particles anywhere in the box, any number per cell).
+ * The position at time t is again x0 + Omega t; cell centres sit at
+ * (j + 1/2) dx, so along each axis u = x / dx - 1/2, the first cell is
+ * floor(u) (periodic) and phi = u - floor(u).  Which cell a particle is
+ * stored with does not enter: every particle is deposited and interpolated
+ * where it is.
+ *
  * State layout: state[18][ndir][ncell], see the input-generator module; the
  * particle with direction d starting in cell c is (d, c); cells are numbered
- * x fastest.
+ * x fastest.  With general placement: state[18][npart].
  */
 #include <complex.h>
 #include <math.h>
@@ -69,6 +78,13 @@ typedef struct {
     double dt;
     const double *Vmat; /* [3] matter potential V_e, V_mu, V_tau, or NULL (none) */
     int32_t shape_order; /* 1 linear (cloud in cell), 2 quadratic */
+    /* general placement: when pos0 is not NULL the particles are these
+     * npart ones and ndir, dirs, N, Nbar are not used */
+    int64_t npart;
+    const double *pos0;  /* [npart][3] positions at t = 0 */
+    const double *pdirs; /* [npart][3] unit vectors Omega */
+    const double *pN;    /* [npart] neutrinos per particle */
+    const double *pNbar; /* [npart] antineutrinos per particle */
 } oracle_problem;
 
 /* ------------------------------------------------------------------ */
@@ -83,6 +99,27 @@ static int64_t pmod(int64_t a, int64_t n)
 {
     int64_t r = a % n;
     return r < 0 ? r + n : r;
+}
+
+static int64_t nparticles(const oracle_problem *P)
+{
+    return P->pos0 ? P->npart : P->ndir * ncell_total(P);
+}
+
+/* Direction and weights of particle p (lattice: p = d * ncell + c). */
+static const double *particle_dir(const oracle_problem *P, int64_t p)
+{
+    return P->pos0 ? P->pdirs + 3 * p : P->dirs + 3 * (p / ncell_total(P));
+}
+
+static double particle_N(const oracle_problem *P, int64_t p)
+{
+    return P->pos0 ? P->pN[p] : P->N[p / ncell_total(P)];
+}
+
+static double particle_Nbar(const oracle_problem *P, int64_t p)
+{
+    return P->pos0 ? P->pNbar[p] : P->Nbar[p / ncell_total(P)];
 }
 
 /* Unpack the 9 stored reals (diagonal, then Re/Im of the e-mu, e-tau and
@@ -184,13 +221,13 @@ static int quadratic_axis(int64_t left, double phi, int64_t n, int64_t *first, d
     return 3;
 }
 
-/* Cells touched by particle (d, c) at time t and their weights w_pj: the
+/* Cells touched by particle p at time t and their weights w_pj: the
  * tensor product of the per-axis weights of the shape function of order
  * P->shape_order (1 linear, 2 quadratic; Sec. II.B.1). */
-static void shape_stencil(const oracle_problem *P, int64_t d, int64_t c, double t,
-                          stencil *S)
+static void shape_stencil(const oracle_problem *P, int64_t p, double t, stencil *S)
 {
-    const int64_t nx = P->ncell[0], ny = P->ncell[1];
+    const int64_t nx = P->ncell[0], ny = P->ncell[1], nc = ncell_total(P);
+    const int64_t d = p / nc, c = p % nc;
     int64_t home[3] = {c % nx, (c / nx) % ny, c / (nx * ny)};
     int64_t first[3];
     double wa[3][3];
@@ -202,10 +239,20 @@ static void shape_stencil(const oracle_problem *P, int64_t d, int64_t c, double 
             cnt[a] = 1;
             continue;
         }
-        double u = (P->dirs[3 * d + a] * t) / P->dx[a];
-        double fl = floor(u);
-        double phi = u - fl;
-        int64_t left = pmod(home[a] + (int64_t)fl, P->ncell[a]);
+        double u, fl, phi;
+        int64_t left;
+        if (P->pos0) {
+            const double x = P->pos0[3 * p + a] + P->pdirs[3 * p + a] * t;
+            u = x / P->dx[a] - 0.5;
+            fl = floor(u);
+            phi = u - fl;
+            left = pmod((int64_t)fl, P->ncell[a]);
+        } else {
+            u = (P->dirs[3 * d + a] * t) / P->dx[a];
+            fl = floor(u);
+            phi = u - fl;
+            left = pmod(home[a] + (int64_t)fl, P->ncell[a]);
+        }
         cnt[a] = (P->shape_order == 2) ? quadratic_axis(left, phi, P->ncell[a], &first[a], wa[a])
                                        : linear_axis(left, phi, P->ncell[a], &first[a], wa[a]);
     }
@@ -238,32 +285,30 @@ typedef struct {
 static void deposit(const oracle_problem *P, const double *state, double t,
                     moments *grid)
 {
-    const int64_t nc = ncell_total(P), nd = P->ndir, np = nc * nd;
+    const int64_t nc = ncell_total(P), np = nparticles(P);
     const double dV = P->dx[0] * P->dx[1] * P->dx[2];
     memset(grid, 0, sizeof(moments) * (size_t)nc);
-    for (int64_t d = 0; d < nd; d++) {
-        const double *v = P->dirs + 3 * d;
-        for (int64_t c = 0; c < nc; c++) {
-            const int64_t p = d * nc + c;
-            cplx rho[3][3], rhob[3][3];
-            unpack(state + p, np, rho);
-            unpack(state + 9 * np + p, np, rhob);
-            stencil S;
-            shape_stencil(P, d, c, t, &S);
-            for (int s = 0; s < S.n; s++) {
-                moments *g = grid + S.cell[s];
-                const double wN = S.w[s] * P->N[d];
-                const double wNb = S.w[s] * P->Nbar[d];
-                for (int i = 0; i < 3; i++)
-                    for (int j = 0; j < 3; j++) {
-                        g->n[i][j] += wN * rho[i][j];
-                        g->nb[i][j] += wNb * rhob[i][j];
-                        for (int a = 0; a < 3; a++) {
-                            g->f[a][i][j] += wN * rho[i][j] * v[a];
-                            g->fb[a][i][j] += wNb * rhob[i][j] * v[a];
-                        }
+    for (int64_t p = 0; p < np; p++) {
+        const double *v = particle_dir(P, p);
+        const double N = particle_N(P, p), Nb = particle_Nbar(P, p);
+        cplx rho[3][3], rhob[3][3];
+        unpack(state + p, np, rho);
+        unpack(state + 9 * np + p, np, rhob);
+        stencil S;
+        shape_stencil(P, p, t, &S);
+        for (int s = 0; s < S.n; s++) {
+            moments *g = grid + S.cell[s];
+            const double wN = S.w[s] * N;
+            const double wNb = S.w[s] * Nb;
+            for (int i = 0; i < 3; i++)
+                for (int j = 0; j < 3; j++) {
+                    g->n[i][j] += wN * rho[i][j];
+                    g->nb[i][j] += wNb * rhob[i][j];
+                    for (int a = 0; a < 3; a++) {
+                        g->f[a][i][j] += wN * rho[i][j] * v[a];
+                        g->fb[a][i][j] += wNb * rhob[i][j] * v[a];
                     }
-            }
+                }
         }
     }
     for (int64_t c = 0; c < nc; c++) {
@@ -333,7 +378,7 @@ static void hamiltonians(const moments *m, const double *v, cplx Hv[3][3], const
 static void rhs(const oracle_problem *P, const double *state, double t,
                 moments *grid, double *out)
 {
-    const int64_t nc = ncell_total(P), nd = P->ndir, np = nc * nd;
+    const int64_t np = nparticles(P);
     cplx Hv[3][3];
     double Vm[3];
     load_hvac(P, Hv);
@@ -343,10 +388,9 @@ static void rhs(const oracle_problem *P, const double *state, double t,
 #pragma omp parallel for schedule(static)
 #endif
     for (int64_t p = 0; p < np; p++) {
-        const int64_t d = p / nc, c = p % nc;
-        const double *v = P->dirs + 3 * d;
+        const double *v = particle_dir(P, p);
         stencil S;
-        shape_stencil(P, d, c, t, &S);
+        shape_stencil(P, p, t, &S);
         moments m;
         interpolate(grid, &S, &m);
         cplx H[3][3], Hb[3][3];
@@ -398,7 +442,7 @@ int oracle_rhs(const oracle_problem *P, const double *state, double t, double *o
  * (time n0 * dt). */
 int oracle_step(const oracle_problem *P, double *state, int64_t n0, int64_t nsteps)
 {
-    const int64_t len = 18 * P->ndir * ncell_total(P);
+    const int64_t len = 18 * nparticles(P);
     const double dt = P->dt;
     moments *grid = malloc(sizeof(moments) * (size_t)ncell_total(P));
     double *k = malloc(sizeof(double) * (size_t)len);
@@ -466,10 +510,10 @@ int oracle_moments(const oracle_problem *P, const double *state, double t, doubl
 int oracle_gather(const oracle_problem *P, const double *G, int64_t ncomp, double t,
                   double *out)
 {
-    const int64_t nc = ncell_total(P), nd = P->ndir, np = nc * nd;
+    const int64_t nc = ncell_total(P), np = nparticles(P);
     for (int64_t p = 0; p < np; p++) {
         stencil S;
-        shape_stencil(P, p / nc, p % nc, t, &S);
+        shape_stencil(P, p, t, &S);
         for (int64_t q = 0; q < ncomp; q++) {
             double s = 0.0;
             for (int i = 0; i < S.n; i++)
@@ -483,16 +527,13 @@ int oracle_gather(const oracle_problem *P, const double *G, int64_t ncomp, doubl
 /* Sum over particles of N rho and Nbar rhobar: out[2][9] packed reals. */
 int oracle_flavor_totals(const oracle_problem *P, const double *state, double *out)
 {
-    const int64_t nc = ncell_total(P), nd = P->ndir, np = nc * nd;
+    const int64_t np = nparticles(P);
     for (int k = 0; k < 18; k++)
         out[k] = 0.0;
-    for (int64_t d = 0; d < nd; d++)
-        for (int64_t c = 0; c < nc; c++) {
-            const int64_t p = d * nc + c;
-            for (int k = 0; k < 9; k++) {
-                out[k] += P->N[d] * state[k * np + p];
-                out[9 + k] += P->Nbar[d] * state[(9 + k) * np + p];
-            }
+    for (int64_t p = 0; p < np; p++)
+        for (int k = 0; k < 9; k++) {
+            out[k] += particle_N(P, p) * state[k * np + p];
+            out[9 + k] += particle_Nbar(P, p) * state[(9 + k) * np + p];
         }
     return 0;
 }
@@ -550,10 +591,10 @@ static void rhs_vjp(const oracle_problem *P, const double *y, double t, const do
     memset(cot, 0, sizeof(moments) * (size_t)nc);
     /* commutators, Hamiltonians and the transpose of the interpolation */
     for (int64_t p = 0; p < np; p++) {
-        const int64_t d = p / nc, c = p % nc;
+        const int64_t d = p / nc;
         const double *v = P->dirs + 3 * d;
         stencil S;
-        shape_stencil(P, d, c, t, &S);
+        shape_stencil(P, p, t, &S);
         moments m;
         interpolate(grid, &S, &m);
         cplx H[3][3], Hb[3][3];
@@ -594,10 +635,10 @@ static void rhs_vjp(const oracle_problem *P, const double *y, double t, const do
     }
     /* transpose of the deposition: n_j = sum_q w N rho_q / dV etc. */
     for (int64_t p = 0; p < np; p++) {
-        const int64_t d = p / nc, c = p % nc;
+        const int64_t d = p / nc;
         const double *v = P->dirs + 3 * d;
         stencil S;
-        shape_stencil(P, d, c, t, &S);
+        shape_stencil(P, p, t, &S);
         cplx Z[3][3], Zb[3][3];
         for (int i = 0; i < 3; i++)
             for (int j = 0; j < 3; j++) {
@@ -643,6 +684,8 @@ static void rhs_vjp(const oracle_problem *P, const double *y, double t, const do
 int oracle_adjoint(const oracle_problem *P, const double *state0, int64_t n0, int64_t nsteps,
                    double *lam, double *gN, double *gNb)
 {
+    if (P->pos0)
+        return -2; /* the reverse mode covers the lattice placement only */
     const int64_t nc = ncell_total(P), len = 18 * P->ndir * nc;
     const double dt = P->dt;
     double *traj = malloc(sizeof(double) * (size_t)len * (size_t)(nsteps + 1));

@@ -23,6 +23,9 @@ Contents
   for the uniform draws U in [-1, 1].
 * Named workloads (``workload(name)``) with the sizes used by the tests and
   the benchmark.
+* General particle placement (``ParticleWorkload``, ``particle_workload``):
+  particles anywhere in the box, several per cell, with their own positions,
+  directions and weights.
 
 State layout shared by every consumer: ``state[18][ndir][ncell]`` float64.
 Component k of the 18 is
@@ -419,3 +422,131 @@ def scaled(w: Workload, ncell: Optional[tuple] = None,
         d["steps"] = steps
     d.update(kw)
     return Workload(**d)
+
+
+# ---------------------------------------------------------------------------
+# General particle placement
+# ---------------------------------------------------------------------------
+def uniform01(seed: int, stream: int, index: np.ndarray) -> np.ndarray:
+    """Uniform draws in [0, 1): the top 53 bits of SplitMix64 output."""
+    x = splitmix64_stream(seed, stream, index)
+    return (x >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+
+
+@dataclasses.dataclass
+class ParticleWorkload:
+    """Particles anywhere in the periodic box (the general particle form of
+    Sec. II.B), ``ppc`` per cell on average.
+
+    placement ``"random"``: every particle uniform over the whole box;
+    ``"stratified"``: exactly ``ppc`` particles per cell, each uniform within
+    its cell (particle p in cell p // ppc).  Particle p moves along
+    direction p mod ndir of the direction set, so every direction carries
+    the same number of particles; its weights follow the same angular
+    distribution as the lattice workloads, divided over ppc particles per
+    cell.  Positions are given at t = 0; draws come from SplitMix64 stream
+    2000 + axis of ``seed``.  State layout ``state[18][np]``.
+    """
+    name: str
+    ncell: tuple
+    length: tuple
+    ppc: int
+    ndir: int
+    dt: float
+    steps: int
+    placement: str = "random"
+    nbar_over_n: float = 1.0
+    f: float = 0.0
+    fbar: float = -1.0 / 3.0
+    nhat: tuple = (0.0, 0.0, 1.0)
+    seed: int = 1
+    sim: int = 0
+    alpha: float = 1e-6
+    vacuum: bool = True
+    vmat: tuple = (0.0, 0.0, 0.0)
+    shape_order: int = 1
+
+    @property
+    def ncell_total(self) -> int:
+        return int(self.ncell[0] * self.ncell[1] * self.ncell[2])
+
+    @property
+    def nparticles(self) -> int:
+        return self.ppc * self.ncell_total
+
+    @property
+    def dx(self) -> tuple:
+        return tuple(float(self.length[a]) / self.ncell[a] for a in range(3))
+
+    @property
+    def dV(self) -> float:
+        dx = self.dx
+        return dx[0] * dx[1] * dx[2]
+
+    def positions(self) -> np.ndarray:
+        """[np][3] positions at t = 0, each inside [0, length)."""
+        n = self.nparticles
+        idx = np.arange(n, dtype=np.uint64)
+        out = np.empty((n, 3))
+        if self.placement == "random":
+            for a in range(3):
+                out[:, a] = self.length[a] * uniform01(self.seed, 2000 + a, idx)
+        elif self.placement == "stratified":
+            nx, ny = self.ncell[0], self.ncell[1]
+            c = np.arange(n) // self.ppc
+            home = (c % nx, (c // nx) % ny, c // (nx * ny))
+            for a in range(3):
+                out[:, a] = (home[a] + uniform01(self.seed, 2000 + a, idx)) * self.dx[a]
+        else:
+            raise ValueError(f"unknown placement {self.placement!r}")
+        return out
+
+    def dirs(self) -> np.ndarray:
+        """[np][3] unit direction of every particle."""
+        table = directions(self.ndir)
+        return np.ascontiguousarray(table[np.arange(self.nparticles) % self.ndir])
+
+    def weights(self):
+        """(N, Nbar), [np] each."""
+        Nd, Nbd = particle_weights(directions(self.ndir), self.dV, 1.0, self.f,
+                                   self.nbar_over_n, self.fbar, self.nhat)
+        scale = self.ndir / self.ppc   # the table divides by ndir
+        d = np.arange(self.nparticles) % self.ndir
+        return np.ascontiguousarray(Nd[d] * scale), np.ascontiguousarray(Nbd[d] * scale)
+
+    def hvac(self) -> np.ndarray:
+        if not self.vacuum:
+            return np.zeros((3, 3), dtype=np.complex128)
+        return vacuum_hamiltonian()
+
+    def state0(self) -> np.ndarray:
+        """[18][np] seeded near-electron-flavor state."""
+        st = initial_state(1, self.nparticles, self.seed, self.sim, self.alpha)
+        return st.reshape(NCOMP, self.nparticles)
+
+
+def particle_workload(name: str) -> ParticleWorkload:
+    """Named general-placement workloads.
+
+    * ``1d_2048x378_random``: the 2048-cell, L = 64 pi box with 774,144
+      particles (378 per cell on average) at uniform random positions, one
+      378-direction set shared round-robin, dt 0.1
+    * ``1d_64x16_random``: 64 cells, L = 12.8, 16 particles per cell at
+      random positions, 26 directions, dt 0.1 (small cases)
+    * ``3d_32x92_random``: 32^3 cells, L = 32 per side, 92 particles per
+      cell at random positions, 92 directions, dt 0.2, the 3D flux setup
+    """
+    s30 = math.sin(math.radians(30.0))
+    c30 = math.cos(math.radians(30.0))
+    table = {
+        "1d_2048x378_random": _one_d(2048, 64.0 * math.pi, ppc=378, ndir=378, dt=0.1,
+                                     steps=5000, seed=2),
+        "1d_64x16_random": _one_d(64, 12.8, ppc=16, ndir=26, dt=0.1, steps=200,
+                                  seed=6),
+        "3d_32x92_random": dict(ncell=(32, 32, 32), length=(32.0, 32.0, 32.0), ppc=92,
+                                ndir=92, dt=0.2, steps=200, nbar_over_n=1.2, f=0.1,
+                                fbar=-0.2, nhat=(s30, 0.0, c30), seed=3),
+    }
+    if name not in table:
+        raise KeyError(f"unknown workload {name!r}; have {sorted(table)}")
+    return ParticleWorkload(name=name, **table[name])

@@ -37,8 +37,8 @@ MUTANTS = {
                                        "w[0] = 0.5 * ((0.5 + xi) * (0.5 + xi));"),
     "flux_wrong_axis": ("g->f[a][i][j] += wN * rho[i][j] * v[a];",
                         "g->f[a][i][j] += wN * rho[i][j] * v[2];"),
-    "advection_backwards": ("int64_t left = pmod(home[a] + (int64_t)fl, P->ncell[a]);",
-                            "int64_t left = pmod(home[a] - (int64_t)fl, P->ncell[a]);"),
+    "advection_backwards": ("left = pmod(home[a] + (int64_t)fl, P->ncell[a]);",
+                            "left = pmod(home[a] - (int64_t)fl, P->ncell[a]);"),
     "rk4_k2_weight": ("ks[i] = ks[i] + 2.0 * k[i];\n            ys[i] = state[i] + (0.5 * dt) * k[i];",
                       "ks[i] = ks[i] + k[i];\n            ys[i] = state[i] + (0.5 * dt) * k[i];"),
     "rk4_stage_time": ("rhs(P, ys, stage_time(n, dt, 1.0), grid, k);",
@@ -47,6 +47,12 @@ MUTANTS = {
     "gather_weight_dropped": ("out->n[i][j] += w * g->n[i][j];",
                               "out->n[i][j] += g->n[i][j];"),
     "matter_sign": ("H[a][a] += Vm[a];", "H[a][a] -= Vm[a];"),
+    # general placement
+    "general_cell_centre_offset": ("u = x / P->dx[a] - 0.5;", "u = x / P->dx[a];"),
+    "general_drift_sign": ("const double x = P->pos0[3 * p + a] + P->pdirs[3 * p + a] * t;",
+                           "const double x = P->pos0[3 * p + a] - P->pdirs[3 * p + a] * t;"),
+    "general_nbar_weight": ("return P->pos0 ? P->pNbar[p] : P->Nbar[p / ncell_total(P)];",
+                            "return P->pos0 ? P->pN[p] : P->Nbar[p / ncell_total(P)];"),
     "antinu_matter_sign": ("Hb[a][a] -= Vm[a];", "Hb[a][a] += Vm[a];"),
     # reverse mode
     "adjoint_rho_cotangent_sign": ("commutator_rhs(Gc, H, Xr);", "commutator_rhs(H, Gc, Xr);"),
@@ -76,7 +82,8 @@ def test_pins_catch_mutant(name, tmp_path):
                         "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle_pins.py"),
                         os.path.join(ROOT, "tests", "test_oracle_invariants.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_adjoint.py")],
+                        os.path.join(ROOT, "tests", "test_oracle_adjoint.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_particles.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True,
                        timeout=600)
     assert r.returncode != 0, f"no pin caught mutant {name}:\n{r.stdout[-2000:]}"
