@@ -52,6 +52,13 @@ class AdjointCfg(C.Structure):
     _fields_ = [("nsteps", C.c_int64), ("ckpt_every", C.c_int32), ("reserved", C.c_int32)]
 
 
+class PConfig(C.Structure):
+    _fields_ = [("ncell", C.c_int32 * 3), ("dx", C.c_double * 3), ("npart", C.c_int64),
+                ("hvac", C.c_double * 18), ("vmat", C.c_double * 3), ("dt", C.c_double),
+                ("shape_order", C.c_int32), ("sort_every", C.c_int32), ("flags", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
 EXPORTS = {
     # name: (restype, argtypes)
     "fpic_workspace_bytes": (C.c_int, [C.POINTER(Config), C.POINTER(Tuning), C.POINTER(C.c_size_t)]),
@@ -84,6 +91,21 @@ EXPORTS = {
                                                C.POINTER(C.c_size_t)]),
     "fpic_adjoint_forward": (C.c_int, [C.c_void_p, C.POINTER(AdjointCfg), C.c_void_p, C.c_size_t]),
     "fpic_adjoint_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, _dp, _dp]),
+    # general particle placement (include/fpic_particles.h)
+    "fpic_particles_workspace_bytes": (C.c_int, [C.POINTER(PConfig), C.POINTER(C.c_size_t)]),
+    "fpic_particles_create": (C.c_int, [C.POINTER(PConfig), C.c_void_p, C.c_size_t, C.c_void_p,
+                                        C.POINTER(C.c_void_p)]),
+    "fpic_particles_set": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_int64]),
+    "fpic_particles_get_state": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "fpic_particles_step": (C.c_int, [C.c_void_p, C.c_int64]),
+    "fpic_particles_moments": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "fpic_particles_flavor_totals": (C.c_int, [C.c_void_p, _dp]),
+    "fpic_particles_check": (C.c_int, [C.c_void_p, C.c_double, _dp]),
+    "fpic_particles_get_step": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
+    "fpic_particles_sync": (C.c_int, [C.c_void_p]),
+    "fpic_particles_profile": (C.c_int, [C.c_void_p, C.c_int32, _dp]),
+    "fpic_particles_destroy": (None, [C.c_void_p]),
 }
 
 _lib = None
@@ -165,3 +187,22 @@ def tuning(t) -> Tuning:
     out.dirs_per_wave = int(t.get("dirs_per_wave", 0))
     out.steps_per_graph = int(t.get("steps_per_graph", 0))
     return out
+
+
+def pconfig(ncell, dx, npart, hvac, dt, shape_order=1, vmat=None, sort_every=0) -> PConfig:
+    """PConfig for a general-placement box (hvac: 3x3 complex)."""
+    H = np.asarray(hvac, dtype=np.complex128).reshape(3, 3)
+    h = np.empty(18)
+    h[0::2] = H.real.ravel()
+    h[1::2] = H.imag.ravel()
+    c = PConfig()
+    c.ncell[:] = [int(x) for x in ncell]
+    c.dx[:] = [float(x) for x in dx]
+    c.npart = int(npart)
+    c.hvac[:] = h.tolist()
+    c.vmat[:] = [0.0, 0.0, 0.0] if vmat is None else [float(x) for x in vmat]
+    c.dt = float(dt)
+    c.shape_order = int(shape_order)
+    c.sort_every = int(sort_every)
+    c.flags = 0
+    return c

@@ -27,11 +27,16 @@
 #include <vector>
 
 #include "fpic_3d.h"
+#include "fpic_device.h"
 #include "fpic_internal.h"
 
 namespace fpic3d {
 
+using fpic::commutator;
 using fpic::fail;
+using fpic::gld;
+using fpic::gst;
+using fpic::stage_time;
 
 constexpr int NG = 36;
 constexpr int W = 64;
@@ -53,17 +58,6 @@ struct Desc3 {
     int32_t shape;          // shape-function order: 1 linear, 2 quadratic
     int32_t pad_;
 };
-
-typedef __attribute__((address_space(1))) double gdouble;
-__device__ __forceinline__ double gld(const double *p) { return *(const gdouble *)p; }
-__device__ __forceinline__ void gst(double *p, double v) { *(gdouble *)p = v; }
-
-__device__ __forceinline__ double stage_time(int64_t n, double dt, double c)
-{
-#pragma clang fp contract(off)
-    const double tn = (double)n * dt;
-    return tn + c * dt;
-}
 
 // integer shift (mod n) and fraction along one axis; one-cell axes: (0, 0)
 __device__ __forceinline__ void axis_shift(double v, double t, double dx, int n, int *r, double *phi)
@@ -103,35 +97,6 @@ __device__ __forceinline__ void load_slope(const double *K, int64_t np, int64_t 
 __device__ __forceinline__ double lane_get(double v, int src)
 {
     return __shfl(v, src, W);
-}
-
-__device__ __forceinline__ void commutator(const double h[9], const double r[9], double k[9])
-{
-    const double h0 = h[0], h1 = h[1], h2 = h[2];
-    const double ar = h[3], ai = h[4], br = h[5], bi = h[6], cr = h[7], ci = h[8];
-    const double p0 = r[0], p1 = r[1], p2 = r[2];
-    const double xr = r[3], xi = r[4], yr = r[5], yi = r[6], zr = r[7], zi = r[8];
-    k[1] = 2.0 * ((ar * xi - ai * xr) + (ci * zr - cr * zi));
-    k[2] = 2.0 * ((br * yi - bi * yr) + (cr * zi - ci * zr));
-    k[0] = -(k[1] + k[2]);  // traceless: slopes are stored without k_00
-    const double c01r = h0 * xr + ar * p1 + (br * zr + bi * zi);
-    const double c01i = h0 * xi + ai * p1 + (bi * zr - br * zi);
-    const double c10r = ar * p0 + h1 * xr + (cr * yr + ci * yi);
-    const double c10i = -ai * p0 - h1 * xi + (ci * yr - cr * yi);
-    k[3] = c01i + c10i;
-    k[4] = c10r - c01r;
-    const double c02r = h0 * yr + (ar * zr - ai * zi) + br * p2;
-    const double c02i = h0 * yi + (ar * zi + ai * zr) + bi * p2;
-    const double c20r = br * p0 + (cr * xr - ci * xi) + h2 * yr;
-    const double c20i = -bi * p0 - (cr * xi + ci * xr) - h2 * yi;
-    k[5] = c02i + c20i;
-    k[6] = c20r - c02r;
-    const double c12r = (ar * yr + ai * yi) + h1 * zr + cr * p2;
-    const double c12i = (ar * yi - ai * yr) + h1 * zi + ci * p2;
-    const double c21r = (br * xr + bi * xi) + cr * p1 + h2 * zr;
-    const double c21i = (br * xi - bi * xr) - ci * p1 - h2 * zi;
-    k[7] = c12i + c21i;
-    k[8] = c21r - c12r;
 }
 
 // MODE 1..4: Runge-Kutta stages; 5: deposit sources of the current state.

@@ -1,0 +1,1177 @@
+// General particle placement (include/fpic_particles.h): particles anywhere
+// in the periodic box, any number per cell, each with its own position at
+// t = 0, direction and weights.
+//
+// Layout.  Structure of arrays in two sets A and B: the state Y[18][np],
+// positions pos[3][np], directions v[3][np], weights wN = N/dV, wNb = Nbar/dV
+// and the caller's index pid.  The particles are kept sorted by cell: a
+// counting sort (count, scan, scatter) moves every particle from the current
+// set to the other one every `sort_every` steps.  Slopes K1..K3 keep 16
+// reals per particle (the traceless form of fpic_internal.h).
+//
+// One launch per Runge-Kutta stage; a workgroup takes 256 consecutive
+// particles (one per thread).  Per particle the thread forms the stage
+// state, interpolates the 36 combined moments of the grid at its stage
+// position (the grid is small and read through the caches), builds H and
+// Hbar (eq. potentials, Sec. II.A conventions), the commutator slopes
+// (eq. eom) and the next stage state, and deposits that state with the
+// next-stage weights (eq. pic_deposition).  Because the particles are sorted
+// by cell, a workgroup's particles cover a small box of cells: it
+// accumulates their deposits in LDS (FP64 LDS atomics) over that box and
+// adds the box into the grid with global FP64 atomics.  A workgroup whose
+// box exceeds SPAN_MAX cells (particles spread out) adds straight to the
+// grid.  Three grid buffers rotate: stage s of step n reads G[(4n+s-1) % 3],
+// deposits into G[(4n+s) % 3] and clears G[(4n+s+1) % 3] for the next
+// stage.
+//
+// Positions: x(t) = x0 + Omega t per axis, u = x / dx - 1/2, first cell
+// floor(u), fraction u - floor(u); every operation rounded once, the same
+// formulas as the CPU reference.
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "fpic_device.h"
+#include "fpic_internal.h"
+#include "fpic_particles.h"
+
+namespace fpicp {
+
+using fpic::commutator;
+using fpic::fail;
+using fpic::gld;
+using fpic::gst;
+using fpic::load_slope;
+using fpic::Quad;
+using fpic::quad_weights;
+using fpic::stage_time;
+using fpic::store_slope;
+
+constexpr int NG = 36;
+constexpr int BLK = 256;            // particles (threads) per workgroup
+constexpr int NWAVE = BLK / 64;
+constexpr int SPAN_MAX = 128;       // cells of a workgroup's LDS deposit box
+constexpr int kRedBlk = 256;        // blocks of the diagnostic reductions
+
+enum : int { PM_DEPOSIT = 5, PM_MOM_NU = 6, PM_MOM_NUBAR = 7 };
+
+struct PDesc {
+    int32_t n[3];
+    int32_t shape;
+    int64_t ncell, np;
+    double dt, dx[3];
+    double hvac[9];   // constant part of H: vacuum + matter, packed
+    double hvacb[9];  // of Hbar before conjugation: vacuum - matter
+    // current particle set
+    double *pos, *v, *wN, *wNb;
+    int32_t *pid;
+    double *Y;
+    // the set the next sort writes
+    double *pos2, *v2, *wN2, *wNb2, *Y2;
+    int32_t *pid2;
+    double *K1, *K2, *K3;
+    double *G0, *G1, *G2;
+    int64_t *step;
+    int32_t *cnt, *cur;  // [ncell] sort counters
+};
+
+// n-periodic index of an integer-valued double (|i| < 2^52)
+__device__ __forceinline__ int wrap_cell(double i, int n)
+{
+    const double nd = (double)n;
+    double r = i - nd * floor(i / nd);
+    if (r < 0.0)
+        r += nd;
+    if (r >= nd)
+        r -= nd;
+    return (int)r;
+}
+
+// Along one axis at time t: first cell of the shape function's stencil
+// (periodic) and its weights; SH = 1: cells L, L + 1 with (1 - phi, phi);
+// SH = 2: cells L + up - 1 .. L + up + 1 with the quadratic weights.  An
+// axis with one cell keeps every particle in cell 0 with weight 1.
+template <int SH>
+__device__ __forceinline__ void axis_stencil(double x0, double v, double t, double dx, int n,
+                                             int *first, double w[3])
+{
+#pragma clang fp contract(off)
+    if (n == 1) {
+        *first = 0;
+        w[0] = 1.0;
+        w[1] = 0.0;
+        w[2] = 0.0;
+        return;
+    }
+    const double x = x0 + v * t;
+    const double u = x / dx - 0.5;
+    const double fl = floor(u);
+    const double phi = u - fl;
+    if (SH == 2) {
+        const Quad q = quad_weights(phi);
+        *first = wrap_cell(fl + (double)(q.up - 1), n);
+        w[0] = q.w0;
+        w[1] = q.w1;
+        w[2] = q.w2;
+    } else {
+        *first = wrap_cell(fl, n);
+        w[0] = 1.0 - phi;
+        w[1] = phi;
+        w[2] = 0.0;
+    }
+}
+
+// offset of cell c from the reference cell r on an n-periodic axis, in
+// (-n/2, n/2]
+__device__ __forceinline__ int periodic_offset(int c, int r, int n)
+{
+    int o = c - r;
+    if (2 * o > n)
+        o -= n;
+    else if (2 * o <= -n)
+        o += n;
+    return o;
+}
+
+__device__ __forceinline__ int wrap_int(int c, int n)
+{
+    c %= n;
+    return c < 0 ? c + n : c;
+}
+
+// MODE 1..4: Runge-Kutta stages; PM_DEPOSIT: deposit the current state at
+// the current time into the buffer stage 1 reads; PM_MOM_NU / PM_MOM_NUBAR:
+// deposit N rho or Nbar rhobar alone into outG (moment diagnostics).
+template <int MODE, int SH, bool D3>
+__global__ void __launch_bounds__(BLK) pstage_kernel(const PDesc *__restrict__ dp, double *outG)
+{
+    constexpr int SW = SH + 1;  // stencil cells per axis
+    __shared__ double acc[NG * SPAN_MAX];
+    __shared__ int sred[NWAVE][6];
+    __shared__ int sref[3];
+    const PDesc S = *dp;
+    const int64_t np = S.np;
+    const int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
+    const bool active = i < np;
+    const int64_t ip = active ? i : 0;
+    const int64_t n = *S.step;
+    const double dt = S.dt;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+
+    double t_cur = 0.0, t_nxt;
+    if (MODE == 1) {
+        t_cur = stage_time(n, dt, 0.0);
+        t_nxt = stage_time(n, dt, 0.5);
+    } else if (MODE == 2) {
+        t_cur = stage_time(n, dt, 0.5);
+        t_nxt = stage_time(n, dt, 0.5);
+    } else if (MODE == 3) {
+        t_cur = stage_time(n, dt, 0.5);
+        t_nxt = stage_time(n, dt, 1.0);
+    } else if (MODE == 4) {
+        t_cur = stage_time(n, dt, 1.0);
+        t_nxt = stage_time(n + 1, dt, 0.0);
+    } else {
+        t_nxt = stage_time(n, dt, 0.0);
+    }
+
+    // grid buffers (selects, no indexing into the descriptor copy)
+    double *Gin = nullptr, *Gout, *Gclr = nullptr;
+    if (MODE <= 4) {
+        const int r = (int)((4 * n + MODE - 1) % 3);
+        Gin = r == 0 ? S.G0 : (r == 1 ? S.G1 : S.G2);
+        Gout = r == 0 ? S.G1 : (r == 1 ? S.G2 : S.G0);
+        Gclr = r == 0 ? S.G2 : (r == 1 ? S.G0 : S.G1);
+    } else if (MODE == PM_DEPOSIT) {
+        const int r = (int)((4 * n) % 3);
+        Gout = r == 0 ? S.G0 : (r == 1 ? S.G1 : S.G2);
+    } else {
+        Gout = outG;
+    }
+    if (MODE <= 4) {
+        // clear the buffer the next stage deposits into (nothing reads or
+        // writes it during this launch)
+        const int64_t len = (int64_t)NG * S.ncell;
+        for (int64_t q = i; q < len; q += (int64_t)gridDim.x * BLK)
+            gst(Gclr + q, 0.0);
+    }
+
+    const double vx = gld(S.v + ip), vy = gld(S.v + np + ip), vz = gld(S.v + 2 * np + ip);
+    const double px = D3 ? gld(S.pos + ip) : 0.0;
+    const double py = D3 ? gld(S.pos + np + ip) : 0.0;
+    const double pz = gld(S.pos + 2 * np + ip);
+    const double wN = gld(S.wN + ip), wNb = gld(S.wNb + ip);
+    const int nx = S.n[0], ny = S.n[1], nz = S.n[2];
+    const int64_t nc = S.ncell;
+
+    double X[9];
+#pragma unroll
+    for (int k = 0; k < 9; k++)
+        X[k] = 0.0;
+    if (active) {
+        double Y[18];
+#pragma unroll
+        for (int k = 0; k < 18; k++)
+            Y[k] = gld(S.Y + k * np + i);
+        if (MODE == PM_DEPOSIT) {
+#pragma unroll
+            for (int k = 0; k < 9; k++)
+                X[k] = (k == 4 || k == 6 || k == 8) ? wN * Y[k] + wNb * Y[9 + k]
+                                                    : wN * Y[k] - wNb * Y[9 + k];
+        } else if (MODE == PM_MOM_NU) {
+#pragma unroll
+            for (int k = 0; k < 9; k++)
+                X[k] = wN * Y[k];
+        } else if (MODE == PM_MOM_NUBAR) {
+#pragma unroll
+            for (int k = 0; k < 9; k++)
+                X[k] = wNb * Y[9 + k];
+        } else {
+            // interpolate the grid at the current position
+            int fx = 0, fy = 0, fz;
+            double wx[3] = {1.0, 0.0, 0.0}, wy[3] = {1.0, 0.0, 0.0}, wz[3];
+            axis_stencil<SH>(pz, vz, t_cur, S.dx[2], nz, &fz, wz);
+            if (D3) {
+                axis_stencil<SH>(px, vx, t_cur, S.dx[0], nx, &fx, wx);
+                axis_stencil<SH>(py, vy, t_cur, S.dx[1], ny, &fy, wy);
+            }
+            double A[9], Bx[9], By[9], Bz[9];
+#pragma unroll
+            for (int k = 0; k < 9; k++)
+                A[k] = Bx[k] = By[k] = Bz[k] = 0.0;
+#pragma unroll
+            for (int bz = 0; bz < SW; bz++)
+#pragma unroll
+                for (int by = 0; by < (D3 ? SW : 1); by++)
+#pragma unroll
+                    for (int bx = 0; bx < (D3 ? SW : 1); bx++) {
+                        const double w = D3 ? (wx[bx] * wy[by]) * wz[bz] : wz[bz];
+                        const int cz = wrap_int(fz + bz, nz);
+                        const int cy = D3 ? wrap_int(fy + by, ny) : 0;
+                        const int cx = D3 ? wrap_int(fx + bx, nx) : 0;
+                        const double *g = Gin + ((int64_t)cz * ny + cy) * nx + cx;
+#pragma unroll
+                        for (int k = 0; k < 9; k++) {
+                            A[k] += w * gld(g + (int64_t)k * nc);
+                            Bx[k] += w * gld(g + (int64_t)(9 + k) * nc);
+                            By[k] += w * gld(g + (int64_t)(18 + k) * nc);
+                            Bz[k] += w * gld(g + (int64_t)(27 + k) * nc);
+                        }
+                    }
+            double Hnn[9];
+#pragma unroll
+            for (int k = 0; k < 9; k++)
+                Hnn[k] = A[k] - (vx * Bx[k] + vy * By[k] + vz * Bz[k]);
+            // stage state y and the base of the next state (Y for stages
+            // 1-3, Y + dt/6 (k1 + 2 k2 + 2 k3) for stage 4)
+            double y[18], base[18];
+            if (MODE == 1) {
+#pragma unroll
+                for (int k = 0; k < 18; k++)
+                    y[k] = base[k] = Y[k];
+            } else if (MODE == 4) {
+                const double h6 = dt / 6.0;
+                double k1[18], k2[18], k3[18];
+                load_slope(S.K1, np, i, k1);
+                load_slope(S.K2, np, i, k2);
+                load_slope(S.K3, np, i, k3);
+#pragma unroll
+                for (int k = 0; k < 18; k++) {
+                    y[k] = Y[k] + dt * k3[k];
+                    const double ks = (k1[k] + 2.0 * k2[k]) + 2.0 * k3[k];
+                    base[k] = Y[k] + h6 * ks;
+                }
+            } else {
+                const double a = 0.5 * dt;
+                double kp[18];
+                load_slope(MODE == 2 ? S.K1 : S.K2, np, i, kp);
+#pragma unroll
+                for (int k = 0; k < 18; k++) {
+                    y[k] = Y[k] + a * kp[k];
+                    base[k] = Y[k];
+                }
+            }
+            double H[9], Hb[9], kk[18];
+#pragma unroll
+            for (int k = 0; k < 9; k++) {
+                H[k] = S.hvac[k] + Hnn[k];
+                const double hb = S.hvacb[k] - Hnn[k];
+                Hb[k] = (k == 4 || k == 6 || k == 8) ? -hb : hb;
+            }
+            commutator(H, y, kk);
+            commutator(Hb, y + 9, kk + 9);
+            double yn[18];
+            if (MODE == 4) {
+                const double h6 = dt / 6.0;
+#pragma unroll
+                for (int k = 0; k < 18; k++) {
+                    yn[k] = base[k] + h6 * kk[k];
+                    gst(S.Y + k * np + i, yn[k]);
+                }
+            } else {
+                double *Ko = MODE == 1 ? S.K1 : (MODE == 2 ? S.K2 : S.K3);
+                const double an = MODE == 3 ? dt : 0.5 * dt;
+                store_slope(Ko, np, i, kk);
+#pragma unroll
+                for (int k = 0; k < 18; k++)
+                    yn[k] = base[k] + an * kk[k];
+            }
+#pragma unroll
+            for (int k = 0; k < 9; k++)
+                X[k] = (k == 4 || k == 6 || k == 8) ? wN * yn[k] + wNb * yn[9 + k]
+                                                    : wN * yn[k] - wNb * yn[9 + k];
+        }
+    }
+
+    // ---- deposit with the next-stage weights ---------------------------
+    int fx = 0, fy = 0, fz;
+    double wx[3] = {1.0, 0.0, 0.0}, wy[3] = {1.0, 0.0, 0.0}, wz[3];
+    axis_stencil<SH>(pz, vz, t_nxt, S.dx[2], nz, &fz, wz);
+    if (D3) {
+        axis_stencil<SH>(px, vx, t_nxt, S.dx[0], nx, &fx, wx);
+        axis_stencil<SH>(py, vy, t_nxt, S.dx[1], ny, &fy, wy);
+    }
+    // box of cells the workgroup touches, relative to thread 0's stencil
+    if (threadIdx.x == 0) {
+        sref[0] = fx;
+        sref[1] = fy;
+        sref[2] = fz;
+    }
+    __syncthreads();
+    const int rx = sref[0], ry = sref[1], rz = sref[2];
+    const int ox = periodic_offset(fx, rx, nx), oy = periodic_offset(fy, ry, ny);
+    const int oz = periodic_offset(fz, rz, nz);
+    int m[6] = {active ? ox : INT_MAX, active ? oy : INT_MAX, active ? oz : INT_MAX,
+                active ? ox : INT_MIN, active ? oy : INT_MIN, active ? oz : INT_MIN};
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1) {
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            m[a] = min(m[a], __shfl_xor(m[a], s, 64));
+            m[3 + a] = max(m[3 + a], __shfl_xor(m[3 + a], s, 64));
+        }
+    }
+    if (lane == 0)
+#pragma unroll
+        for (int a = 0; a < 6; a++)
+            sred[wave][a] = m[a];
+    __syncthreads();
+    int lo[3], hi[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        lo[a] = sred[0][a];
+        hi[a] = sred[0][3 + a];
+        for (int w = 1; w < NWAVE; w++) {
+            lo[a] = min(lo[a], sred[w][a]);
+            hi[a] = max(hi[a], sred[w][3 + a]);
+        }
+    }
+    const int sx = D3 ? hi[0] - lo[0] + SW : 1;
+    const int sy = D3 ? hi[1] - lo[1] + SW : 1;
+    const int sz = hi[2] - lo[2] + SW;
+    const int64_t box = (int64_t)sx * sy * sz;
+
+    if (box <= SPAN_MAX) {
+        const int cells = (int)box;
+        for (int q = threadIdx.x; q < NG * cells; q += BLK)
+            acc[q] = 0.0;
+        __syncthreads();
+        if (active) {
+#pragma unroll
+            for (int bz = 0; bz < SW; bz++)
+#pragma unroll
+                for (int by = 0; by < (D3 ? SW : 1); by++)
+#pragma unroll
+                    for (int bx = 0; bx < (D3 ? SW : 1); bx++) {
+                        const double w = D3 ? (wx[bx] * wy[by]) * wz[bz] : wz[bz];
+                        const int idx = ((oz - lo[2] + bz) * sy + (D3 ? oy - lo[1] + by : 0)) * sx +
+                                        (D3 ? ox - lo[0] + bx : 0);
+#pragma unroll
+                        for (int k = 0; k < 9; k++) {
+                            const double xc = w * X[k];
+                            atomicAdd(&acc[k * cells + idx], xc);
+                            atomicAdd(&acc[(9 + k) * cells + idx], vx * xc);
+                            atomicAdd(&acc[(18 + k) * cells + idx], vy * xc);
+                            atomicAdd(&acc[(27 + k) * cells + idx], vz * xc);
+                        }
+                    }
+        }
+        __syncthreads();
+        for (int q = threadIdx.x; q < NG * cells; q += BLK) {
+            const double val = acc[q];
+            if (val != 0.0) {
+                const int comp = q / cells, l = q - comp * cells;
+                const int lx = l % sx, ly = (l / sx) % sy, lz = l / (sx * sy);
+                const int cz = wrap_int(rz + lo[2] + lz, nz);
+                const int cy = D3 ? wrap_int(ry + lo[1] + ly, ny) : 0;
+                const int cx = D3 ? wrap_int(rx + lo[0] + lx, nx) : 0;
+                unsafeAtomicAdd(Gout + (int64_t)comp * nc + ((int64_t)cz * ny + cy) * nx + cx, val);
+            }
+        }
+    } else if (active) {
+        // spread-out workgroup: straight to the grid
+#pragma unroll
+        for (int bz = 0; bz < SW; bz++)
+#pragma unroll
+            for (int by = 0; by < (D3 ? SW : 1); by++)
+#pragma unroll
+                for (int bx = 0; bx < (D3 ? SW : 1); bx++) {
+                    const double w = D3 ? (wx[bx] * wy[by]) * wz[bz] : wz[bz];
+                    const int cz = wrap_int(fz + bz, nz);
+                    const int cy = D3 ? wrap_int(fy + by, ny) : 0;
+                    const int cx = D3 ? wrap_int(fx + bx, nx) : 0;
+                    double *g = Gout + ((int64_t)cz * ny + cy) * nx + cx;
+#pragma unroll
+                    for (int k = 0; k < 9; k++) {
+                        const double xc = w * X[k];
+                        unsafeAtomicAdd(g + (int64_t)k * nc, xc);
+                        unsafeAtomicAdd(g + (int64_t)(9 + k) * nc, vx * xc);
+                        unsafeAtomicAdd(g + (int64_t)(18 + k) * nc, vy * xc);
+                        unsafeAtomicAdd(g + (int64_t)(27 + k) * nc, vz * xc);
+                    }
+                }
+    }
+}
+
+__global__ void tick_kernel(const PDesc *dp)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        *dp->step += 1;
+}
+
+__global__ void set_step_kernel(const PDesc *dp, int64_t v)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        *dp->step = v;
+}
+
+__global__ void fill_f64(double *p, int64_t n)
+{
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * blockDim.x)
+        p[q] = 0.0;
+}
+
+__global__ void fill_i32(int32_t *p, int64_t n)
+{
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * blockDim.x)
+        p[q] = 0;
+}
+
+// ---- redistribution: counting sort by cell ----------------------------
+// Sort key: the cell whose centre is the nearest one at or below the
+// particle along each axis (the linear stencil's first cell) at the start
+// of the current step; cells numbered x fastest.
+__device__ __forceinline__ int sort_key(const PDesc &S, int64_t i, double t)
+{
+    int c[3] = {0, 0, 0};
+    double w[3];
+    const int ax0 = (S.n[0] > 1 || S.n[1] > 1) ? 0 : 2;  // 1D boxes: z only
+    for (int a = ax0; a < 3; a++)
+        axis_stencil<1>(gld(S.pos + a * S.np + i), gld(S.v + a * S.np + i), t, S.dx[a], S.n[a], &c[a], w);
+    return (c[2] * S.n[1] + c[1]) * S.n[0] + c[0];
+}
+
+// Runs of equal keys in consecutive lanes (the particles are nearly sorted)
+// are counted with one atomic each.  key < 0 marks an inactive lane.
+struct Run {
+    bool leader;
+    int len, rank, src;
+};
+
+__device__ __forceinline__ Run lane_run(int key)
+{
+    const int lane = threadIdx.x & 63;
+    const int prev = __shfl_up(key, 1, 64);
+    const bool lead = (lane == 0) || (prev != key);
+    const unsigned long long mask = __ballot(lead);
+    const unsigned long long above = (lane == 63) ? 0ull : (mask & ~((2ull << lane) - 1ull));
+    const int next = above ? __builtin_ctzll(above) : 64;
+    const unsigned long long upto = mask & ((2ull << lane) - 1ull);  // lane 63: all bits
+    const int src = 63 - __builtin_clzll(upto);
+    Run r;
+    r.leader = lead;
+    r.len = next - lane;
+    r.rank = lane - src;
+    r.src = src;
+    return r;
+}
+
+__global__ void __launch_bounds__(BLK) sort_count_kernel(const PDesc *__restrict__ dp)
+{
+    const PDesc &S = *dp;
+    const int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
+    const double t = stage_time(*S.step, S.dt, 0.0);
+    const int key = i < S.np ? sort_key(S, i, t) : -1;
+    const Run r = lane_run(key);
+    if (r.leader && key >= 0)
+        atomicAdd(S.cnt + key, r.len);
+}
+
+// exclusive scan of cnt into cur (one workgroup of 1024 threads)
+__global__ void __launch_bounds__(1024) sort_scan_kernel(const PDesc *__restrict__ dp)
+{
+    const PDesc &S = *dp;
+    __shared__ int64_t part[1024];
+    const int64_t nc = S.ncell;
+    const int64_t per = (nc + 1023) / 1024;
+    const int64_t b = threadIdx.x * per, e = min(nc, b + per);
+    int64_t s = 0;
+    for (int64_t c = b; c < e; c++)
+        s += S.cnt[c];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int64_t add = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0;
+        __syncthreads();
+        part[threadIdx.x] += add;
+        __syncthreads();
+    }
+    int64_t run = part[threadIdx.x] - s;
+    for (int64_t c = b; c < e; c++) {
+        const int32_t k = S.cnt[c];
+        S.cur[c] = (int32_t)run;
+        run += k;
+    }
+}
+
+template <bool D3>
+__global__ void __launch_bounds__(BLK) sort_scatter_kernel(const PDesc *__restrict__ dp)
+{
+    const PDesc &S = *dp;
+    const int64_t np = S.np;
+    const int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
+    const double t = stage_time(*S.step, S.dt, 0.0);
+    const int key = i < np ? sort_key(S, i, t) : -1;
+    const Run r = lane_run(key);
+    int base = 0;
+    if (r.leader && key >= 0)
+        base = atomicAdd(S.cur + key, r.len);
+    base = __shfl(base, r.src, 64);
+    if (key < 0)
+        return;
+    const int64_t j = base + r.rank;
+#pragma unroll
+    for (int k = 0; k < 18; k++)
+        gst(S.Y2 + k * np + j, gld(S.Y + k * np + i));
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        if (D3 || a == 2)
+            gst(S.pos2 + a * np + j, gld(S.pos + a * np + i));
+        gst(S.v2 + a * np + j, gld(S.v + a * np + i));
+    }
+    gst(S.wN2 + j, gld(S.wN + i));
+    gst(S.wNb2 + j, gld(S.wNb + i));
+    S.pid2[j] = S.pid[i];
+}
+
+// ---- loading, unloading, diagnostics ---------------------------------
+__global__ void load_kernel(const PDesc *__restrict__ dp, const double *pos0, const double *dirs,
+                            const double *N, const double *Nb, const double *state, double inv_dV,
+                            int *bad)
+{
+    const PDesc &S = *dp;
+    const int64_t np = S.np;
+    int nbad = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < np;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double v2 = 0.0;
+        for (int a = 0; a < 3; a++) {
+            const double x = pos0[a * np + i], v = dirs[a * np + i];
+            if (!isfinite(x))
+                nbad++;
+            v2 += v * v;
+            S.pos[a * np + i] = x;
+            S.v[a * np + i] = v;
+        }
+        if (!isfinite(v2) || fabs(v2 - 1.0) > 1e-9)
+            nbad++;
+        if (!isfinite(N[i]) || !isfinite(Nb[i]))
+            nbad++;
+        S.wN[i] = N[i] * inv_dV;
+        S.wNb[i] = Nb[i] * inv_dV;
+        S.pid[i] = (int32_t)i;
+        for (int k = 0; k < 18; k++)
+            S.Y[k * np + i] = state[k * np + i];
+    }
+    if (nbad)
+        atomicAdd(bad, nbad);
+}
+
+__global__ void unload_kernel(const PDesc *__restrict__ dp, double *out)
+{
+    const PDesc &S = *dp;
+    const int64_t np = S.np;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < np;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = S.pid[i];
+        for (int k = 0; k < 18; k++)
+            out[k * np + j] = S.Y[k * np + i];
+    }
+}
+
+__global__ void __launch_bounds__(256) totals_kernel(const PDesc *__restrict__ dp, double *partial)
+{
+    const PDesc &S = *dp;
+    __shared__ double sh[18][256];
+    double s[18];
+    for (int k = 0; k < 18; k++)
+        s[k] = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < S.np;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double wN = S.wN[i], wNb = S.wNb[i];
+        for (int k = 0; k < 9; k++) {
+            s[k] += wN * S.Y[k * S.np + i];
+            s[9 + k] += wNb * S.Y[(9 + k) * S.np + i];
+        }
+    }
+    for (int k = 0; k < 18; k++)
+        sh[k][threadIdx.x] = s[k];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h)
+            for (int k = 0; k < 18; k++)
+                sh[k][threadIdx.x] += sh[k][threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x < 18)
+        partial[blockIdx.x * 18 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+__global__ void __launch_bounds__(256) check_kernel(const PDesc *__restrict__ dp, double *partial)
+{
+    const PDesc &S = *dp;
+    __shared__ double sh[3][256];
+    double e0 = 0.0, e1 = 0.0, bad = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < S.np;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double v[18];
+        for (int k = 0; k < 18; k++) {
+            v[k] = S.Y[k * S.np + i];
+            if (!isfinite(v[k]))
+                bad += 1.0;
+        }
+        e0 = fmax(e0, fabs(v[0] + v[1] + v[2] - 1.0));
+        e1 = fmax(e1, fabs(v[9] + v[10] + v[11] - 1.0));
+    }
+    sh[0][threadIdx.x] = e0;
+    sh[1][threadIdx.x] = e1;
+    sh[2][threadIdx.x] = bad;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            sh[0][threadIdx.x] = fmax(sh[0][threadIdx.x], sh[0][threadIdx.x + h]);
+            sh[1][threadIdx.x] = fmax(sh[1][threadIdx.x], sh[1][threadIdx.x + h]);
+            sh[2][threadIdx.x] += sh[2][threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 3; q++)
+            partial[blockIdx.x * 3 + q] = sh[q][0];
+}
+
+__global__ void finish_kernel(const double *partial, int nblk, int width, int is_check, double *out)
+{
+    const int k = threadIdx.x;
+    if (k >= width)
+        return;
+    double s = 0.0;
+    for (int b = 0; b < nblk; b++) {
+        const double v = partial[(size_t)b * width + k];
+        s = (is_check && k < 2) ? fmax(s, v) : s + v;
+    }
+    out[k] = s;
+}
+
+// ------------------------------------------------------------------ host
+#define HIPCHECK(x)                                                                     \
+    do {                                                                                \
+        hipError_t e_ = (x);                                                            \
+        if (e_ != hipSuccess)                                                           \
+            return fail(FPIC_EHIP, std::string(#x) + ": " + hipGetErrorString(e_));    \
+    } while (0)
+
+static size_t al(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Layout {
+    size_t set[2][6];  // Y, pos, v, wN, wNb, pid of sets A and B
+    size_t K1, K2, K3, G[3], cnt, cur, step, desc, scratch, flag, total;
+};
+
+static int validate(const fpic_pconfig &c)
+{
+    if (c.ncell[0] < 1 || c.ncell[1] < 1 || c.ncell[2] < 1)
+        return fail(FPIC_EINVAL, "cell counts must be >= 1");
+    if ((int64_t)c.ncell[0] * c.ncell[1] * c.ncell[2] > ((int64_t)1 << 30))
+        return fail(FPIC_EINVAL, "too many cells");
+    if (c.npart < 1 || c.npart > INT32_MAX)
+        return fail(FPIC_EINVAL, "npart must be in 1 .. 2^31 - 1");
+    if (c.shape_order != 1 && c.shape_order != 2)
+        return fail(FPIC_EUNSUPPORTED, "shape_order must be 1 (linear) or 2 (quadratic)");
+    if (c.sort_every < 0 || c.sort_every > 1024)
+        return fail(FPIC_EINVAL, "sort_every must be in 0 .. 1024");
+    if (!(c.dt > 0.0) || !std::isfinite(c.dt))
+        return fail(FPIC_EINVAL, "dt must be positive and finite");
+    for (int a = 0; a < 3; ++a)
+        if (!(c.dx[a] > 0.0) || !std::isfinite(c.dx[a]))
+            return fail(FPIC_EINVAL, "cell widths must be positive and finite");
+    double hmax = 0.0;
+    for (int i = 0; i < 18; ++i) {
+        if (!std::isfinite(c.hvac[i]))
+            return fail(FPIC_EINVAL, "hvac has a non-finite entry");
+        hmax = std::max(hmax, std::fabs(c.hvac[i]));
+    }
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(c.vmat[a]))
+            return fail(FPIC_EINVAL, "vmat has a non-finite entry");
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            const double re = c.hvac[2 * (3 * i + j)], im = c.hvac[2 * (3 * i + j) + 1];
+            const double rt = c.hvac[2 * (3 * j + i)], it = c.hvac[2 * (3 * j + i) + 1];
+            if (std::fabs(re - rt) + std::fabs(im + it) > 1e-12 * (1.0 + hmax))
+                return fail(FPIC_EINVAL, "hvac is not Hermitian");
+        }
+    return FPIC_OK;
+}
+
+static int layout(const fpic_pconfig &c, Layout &L)
+{
+    int rc = validate(c);
+    if (rc)
+        return rc;
+    const size_t np = (size_t)c.npart;
+    const size_t nc = (size_t)c.ncell[0] * c.ncell[1] * c.ncell[2];
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        off = al(off);
+        const size_t o = off;
+        off += b;
+        return o;
+    };
+    const size_t d = sizeof(double);
+    for (int s = 0; s < 2; ++s) {
+        L.set[s][0] = take(d * 18 * np);
+        L.set[s][1] = take(d * 3 * np);
+        L.set[s][2] = take(d * 3 * np);
+        L.set[s][3] = take(d * np);
+        L.set[s][4] = take(d * np);
+        L.set[s][5] = take(sizeof(int32_t) * np);
+    }
+    L.K1 = take(d * fpic::NK * np);
+    L.K2 = take(d * fpic::NK * np);
+    L.K3 = take(d * fpic::NK * np);
+    for (int g = 0; g < 3; ++g)
+        L.G[g] = take(d * NG * nc);
+    L.cnt = take(sizeof(int32_t) * nc);
+    L.cur = take(sizeof(int32_t) * nc);
+    L.step = take(sizeof(int64_t));
+    L.desc = take(2 * sizeof(PDesc));
+    L.scratch = take(d * (18 * kRedBlk + 3 * kRedBlk + 32));
+    L.flag = take(sizeof(int32_t) * 4);
+    L.total = al(off);
+    return FPIC_OK;
+}
+
+}  // namespace fpicp
+
+using namespace fpicp;
+
+struct fpic_pctx {
+    PDesc h[2];          // parity p: current set p, the sort writes set 1 - p
+    PDesc *d[2] = {nullptr, nullptr};
+    char *ws = nullptr;
+    hipStream_t stream = nullptr, cap = nullptr;
+    int spg = 4;         // steps between sorts (= steps per graph)
+    int par = 0;         // set holding the particles after the enqueued work
+    int sh = 1;
+    bool d3 = false;
+    unsigned nblk = 1;   // stage workgroups
+    double dV = 1.0;
+    double *scratch = nullptr, *hbuf = nullptr;
+    int32_t *flag = nullptr;
+    hipGraphExec_t g[2] = {nullptr, nullptr};
+    bool state_set = false;
+};
+
+namespace fpicp {
+
+template <int SH, bool D3>
+static void launch_mode_t(const fpic_pctx *c, int mode, const PDesc *dd, double *out, hipStream_t s)
+{
+    const dim3 grid(c->nblk), blk(BLK);
+    switch (mode) {
+    case 1: pstage_kernel<1, SH, D3><<<grid, blk, 0, s>>>(dd, out); break;
+    case 2: pstage_kernel<2, SH, D3><<<grid, blk, 0, s>>>(dd, out); break;
+    case 3: pstage_kernel<3, SH, D3><<<grid, blk, 0, s>>>(dd, out); break;
+    case 4: pstage_kernel<4, SH, D3><<<grid, blk, 0, s>>>(dd, out); break;
+    case PM_DEPOSIT: pstage_kernel<PM_DEPOSIT, SH, D3><<<grid, blk, 0, s>>>(dd, out); break;
+    case PM_MOM_NU: pstage_kernel<PM_MOM_NU, SH, D3><<<grid, blk, 0, s>>>(dd, out); break;
+    default: pstage_kernel<PM_MOM_NUBAR, SH, D3><<<grid, blk, 0, s>>>(dd, out); break;
+    }
+}
+
+static void launch_mode(const fpic_pctx *c, int mode, const PDesc *dd, double *out, hipStream_t s)
+{
+    if (c->sh == 2) {
+        if (c->d3) launch_mode_t<2, true>(c, mode, dd, out, s);
+        else launch_mode_t<2, false>(c, mode, dd, out, s);
+    } else {
+        if (c->d3) launch_mode_t<1, true>(c, mode, dd, out, s);
+        else launch_mode_t<1, false>(c, mode, dd, out, s);
+    }
+}
+
+static void launch_step(const fpic_pctx *c, int par, hipStream_t s)
+{
+    for (int m = 1; m <= 4; ++m)
+        launch_mode(c, m, c->d[par], nullptr, s);
+    tick_kernel<<<1, 64, 0, s>>>(c->d[par]);
+}
+
+// counting sort of the particles in set par into set 1 - par
+static void launch_sort(const fpic_pctx *c, int par, hipStream_t s)
+{
+    const PDesc &H = c->h[par];
+    const PDesc *dd = c->d[par];
+    fill_i32<<<std::max<int64_t>(1, std::min<int64_t>(1024, (H.ncell + 255) / 256)), 256, 0, s>>>(H.cnt, H.ncell);
+    sort_count_kernel<<<c->nblk, BLK, 0, s>>>(dd);
+    sort_scan_kernel<<<1, 1024, 0, s>>>(dd);
+    if (c->d3)
+        sort_scatter_kernel<true><<<c->nblk, BLK, 0, s>>>(dd);
+    else
+        sort_scatter_kernel<false><<<c->nblk, BLK, 0, s>>>(dd);
+}
+
+static int capture(fpic_pctx *c, int par, hipGraphExec_t *exec)
+{
+    HIPCHECK(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < c->spg; ++k)
+        launch_step(c, par, c->cap);
+    launch_sort(c, par, c->cap);
+    hipError_t err = hipGetLastError();
+    hipGraph_t gr = nullptr;
+    hipError_t e2 = hipStreamEndCapture(c->cap, &gr);
+    if (err != hipSuccess) {
+        if (gr)
+            (void)hipGraphDestroy(gr);
+        return fail(FPIC_EHIP, std::string("launch during capture: ") + hipGetErrorString(err));
+    }
+    HIPCHECK(e2);
+    hipError_t e3 = hipGraphInstantiate(exec, gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    HIPCHECK(e3);
+    return FPIC_OK;
+}
+
+}  // namespace fpicp
+
+extern "C" {
+
+int fpic_particles_workspace_bytes(const fpic_pconfig *cfg, size_t *bytes)
+{
+    if (!cfg || !bytes)
+        return fail(FPIC_EINVAL, "null argument");
+    Layout L;
+    int rc = layout(*cfg, L);
+    if (rc)
+        return rc;
+    *bytes = L.total;
+    return FPIC_OK;
+}
+
+int fpic_particles_create(const fpic_pconfig *cfg, void *workspace, size_t bytes, fpic_stream stream,
+                          fpic_pctx **out)
+{
+    if (!cfg || !out)
+        return fail(FPIC_EINVAL, "null argument");
+    *out = nullptr;
+    Layout L;
+    int rc = layout(*cfg, L);
+    if (rc)
+        return rc;
+    if (!workspace || bytes < L.total || reinterpret_cast<uintptr_t>(workspace) % 256)
+        return fail(FPIC_EINVAL, "workspace missing, too small or misaligned");
+    fpic_pctx *c = new fpic_pctx();
+    c->ws = static_cast<char *>(workspace);
+    c->stream = static_cast<hipStream_t>(stream);
+    c->spg = cfg->sort_every ? cfg->sort_every : 4;
+    c->sh = cfg->shape_order;
+    c->d3 = !(cfg->ncell[0] == 1 && cfg->ncell[1] == 1);
+    c->nblk = (unsigned)((cfg->npart + BLK - 1) / BLK);
+    c->dV = cfg->dx[0] * cfg->dx[1] * cfg->dx[2];
+    auto P = [&](size_t o) { return reinterpret_cast<double *>(c->ws + o); };
+    auto I = [&](size_t o) { return reinterpret_cast<int32_t *>(c->ws + o); };
+    for (int p = 0; p < 2; ++p) {
+        PDesc &D = c->h[p];
+        std::memset(&D, 0, sizeof D);
+        for (int a = 0; a < 3; ++a) {
+            D.n[a] = cfg->ncell[a];
+            D.dx[a] = cfg->dx[a];
+        }
+        D.shape = cfg->shape_order;
+        D.ncell = (int64_t)cfg->ncell[0] * cfg->ncell[1] * cfg->ncell[2];
+        D.np = cfg->npart;
+        D.dt = cfg->dt;
+        const double *h = cfg->hvac;
+        const double hv[9] = {h[0], h[8], h[16], h[2], h[3], h[4], h[5], h[10], h[11]};
+        for (int k = 0; k < 9; ++k) {
+            D.hvac[k] = hv[k] + (k < 3 ? cfg->vmat[k] : 0.0);
+            D.hvacb[k] = hv[k] - (k < 3 ? cfg->vmat[k] : 0.0);
+        }
+        const int s = p, t = 1 - p;
+        D.Y = P(L.set[s][0]);
+        D.pos = P(L.set[s][1]);
+        D.v = P(L.set[s][2]);
+        D.wN = P(L.set[s][3]);
+        D.wNb = P(L.set[s][4]);
+        D.pid = I(L.set[s][5]);
+        D.Y2 = P(L.set[t][0]);
+        D.pos2 = P(L.set[t][1]);
+        D.v2 = P(L.set[t][2]);
+        D.wN2 = P(L.set[t][3]);
+        D.wNb2 = P(L.set[t][4]);
+        D.pid2 = I(L.set[t][5]);
+        D.K1 = P(L.K1);
+        D.K2 = P(L.K2);
+        D.K3 = P(L.K3);
+        D.G0 = P(L.G[0]);
+        D.G1 = P(L.G[1]);
+        D.G2 = P(L.G[2]);
+        D.cnt = I(L.cnt);
+        D.cur = I(L.cur);
+        D.step = reinterpret_cast<int64_t *>(c->ws + L.step);
+        c->d[p] = reinterpret_cast<PDesc *>(c->ws + L.desc) + p;
+    }
+    c->scratch = P(L.scratch);
+    c->flag = I(L.flag);
+    hipError_t e = hipMemcpy(c->d[0], c->h, sizeof(PDesc) * 2, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipHostMalloc(reinterpret_cast<void **>(&c->hbuf), sizeof(double) * 64, hipHostMallocDefault);
+    if (e == hipSuccess)
+        e = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        fpic_particles_destroy(c);
+        return fail(FPIC_EHIP, std::string("create: ") + hipGetErrorString(e));
+    }
+    rc = capture(c, 0, &c->g[0]);
+    if (!rc)
+        rc = capture(c, 1, &c->g[1]);
+    if (rc) {
+        fpic_particles_destroy(c);
+        return rc;
+    }
+    *out = c;
+    return FPIC_OK;
+}
+
+int fpic_particles_set(fpic_pctx *c, const double *pos0, const double *dirs, const double *N,
+                       const double *Nbar, const double *state, int64_t step0)
+{
+    if (!c || !pos0 || !dirs || !N || !Nbar || !state)
+        return fail(FPIC_EINVAL, "set: null argument");
+    if (step0 < 0)
+        return fail(FPIC_EINVAL, "set: step0 must be >= 0");
+    hipStream_t s = c->stream;
+    c->par = 0;
+    const PDesc &H = c->h[0];
+    fill_i32<<<1, 64, 0, s>>>(c->flag, 4);
+    const unsigned nb = (unsigned)std::min<int64_t>(2048, (H.np + 255) / 256);
+    load_kernel<<<nb, 256, 0, s>>>(c->d[0], pos0, dirs, N, Nbar, state, 1.0 / c->dV, c->flag);
+    set_step_kernel<<<1, 64, 0, s>>>(c->d[0], step0);
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipMemcpyAsync(c->hbuf, c->flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    int32_t bad = 0;
+    std::memcpy(&bad, c->hbuf, sizeof bad);
+    if (bad) {
+        c->state_set = false;
+        return fail(FPIC_EINVAL, "set: non-finite position or weight, or a direction that is "
+                                 "not a unit vector");
+    }
+    launch_sort(c, 0, s);
+    c->par = 1;
+    const int64_t glen = (int64_t)NG * H.ncell;
+    const unsigned gb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, (glen + 255) / 256));
+    fill_f64<<<gb, 256, 0, s>>>(H.G0, glen);
+    fill_f64<<<gb, 256, 0, s>>>(H.G1, glen);
+    fill_f64<<<gb, 256, 0, s>>>(H.G2, glen);
+    launch_mode(c, PM_DEPOSIT, c->d[c->par], nullptr, s);
+    HIPCHECK(hipGetLastError());
+    c->state_set = true;
+    return FPIC_OK;
+}
+
+int fpic_particles_get_state(fpic_pctx *c, double *state)
+{
+    if (!c || !state)
+        return fail(FPIC_EINVAL, "get_state: null argument");
+    if (!c->state_set)
+        return fail(FPIC_ESTATE, "get_state before set");
+    const unsigned nb = (unsigned)std::min<int64_t>(2048, (c->h[0].np + 255) / 256);
+    unload_kernel<<<nb, 256, 0, c->stream>>>(c->d[c->par], state);
+    HIPCHECK(hipGetLastError());
+    return FPIC_OK;
+}
+
+int fpic_particles_step(fpic_pctx *c, int64_t nsteps)
+{
+    if (!c || nsteps < 0)
+        return fail(FPIC_EINVAL, "step: bad argument");
+    if (!c->state_set)
+        return fail(FPIC_ESTATE, "step before set");
+    int64_t left = nsteps;
+    while (left >= c->spg) {
+        HIPCHECK(hipGraphLaunch(c->g[c->par], c->stream));
+        c->par ^= 1;
+        left -= c->spg;
+    }
+    if (left > 0) {
+        for (int64_t k = 0; k < left; ++k)
+            launch_step(c, c->par, c->stream);
+        launch_sort(c, c->par, c->stream);
+        HIPCHECK(hipGetLastError());
+        c->par ^= 1;
+    }
+    return FPIC_OK;
+}
+
+int fpic_particles_moments(fpic_pctx *c, double *out)
+{
+    if (!c || !out)
+        return fail(FPIC_EINVAL, "moments: null argument");
+    if (!c->state_set)
+        return fail(FPIC_ESTATE, "moments before set");
+    const int64_t len = (int64_t)2 * NG * c->h[0].ncell;
+    const unsigned gb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, (len + 255) / 256));
+    fill_f64<<<gb, 256, 0, c->stream>>>(out, len);
+    launch_mode(c, PM_MOM_NU, c->d[c->par], out, c->stream);
+    launch_mode(c, PM_MOM_NUBAR, c->d[c->par], out + (size_t)NG * c->h[0].ncell, c->stream);
+    HIPCHECK(hipGetLastError());
+    return FPIC_OK;
+}
+
+int fpic_particles_flavor_totals(fpic_pctx *c, double *out)
+{
+    if (!c || !out)
+        return fail(FPIC_EINVAL, "flavor_totals: null argument");
+    if (!c->state_set)
+        return fail(FPIC_ESTATE, "flavor_totals before set");
+    double *part = c->scratch + 32;
+    totals_kernel<<<kRedBlk, 256, 0, c->stream>>>(c->d[c->par], part);
+    finish_kernel<<<1, 64, 0, c->stream>>>(part, kRedBlk, 18, 0, c->scratch);
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipMemcpyAsync(c->hbuf, c->scratch, sizeof(double) * 18, hipMemcpyDeviceToHost, c->stream));
+    HIPCHECK(hipStreamSynchronize(c->stream));
+    for (int k = 0; k < 18; ++k)
+        out[k] = c->hbuf[k] * c->dV;
+    return FPIC_OK;
+}
+
+int fpic_particles_check(fpic_pctx *c, double tol, double *max_trace_err)
+{
+    if (!c)
+        return fail(FPIC_EINVAL, "null context");
+    if (!c->state_set)
+        return fail(FPIC_ESTATE, "check before set");
+    double *part = c->scratch + 32 + 18 * kRedBlk;
+    check_kernel<<<kRedBlk, 256, 0, c->stream>>>(c->d[c->par], part);
+    finish_kernel<<<1, 64, 0, c->stream>>>(part, kRedBlk, 3, 1, c->scratch);
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipMemcpyAsync(c->hbuf, c->scratch, sizeof(double) * 3, hipMemcpyDeviceToHost, c->stream));
+    HIPCHECK(hipStreamSynchronize(c->stream));
+    const double e = std::max(c->hbuf[0], c->hbuf[1]);
+    if (max_trace_err)
+        *max_trace_err = e;
+    if (c->hbuf[2] > 0.0)
+        return fail(FPIC_ENUMERIC, "state holds NaN or Inf entries");
+    if (!(e <= tol))
+        return fail(FPIC_ENUMERIC, "trace drift exceeds the tolerance");
+    return FPIC_OK;
+}
+
+int fpic_particles_get_step(fpic_pctx *c, int64_t *step)
+{
+    if (!c || !step)
+        return fail(FPIC_EINVAL, "null argument");
+    HIPCHECK(hipMemcpyAsync(c->hbuf, c->h[0].step, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+    HIPCHECK(hipStreamSynchronize(c->stream));
+    std::memcpy(step, c->hbuf, sizeof(int64_t));
+    return FPIC_OK;
+}
+
+int fpic_particles_sync(fpic_pctx *c)
+{
+    if (!c)
+        return fail(FPIC_EINVAL, "null context");
+    HIPCHECK(hipStreamSynchronize(c->stream));
+    return FPIC_OK;
+}
+
+int fpic_particles_profile(fpic_pctx *c, int32_t nsteps, double *ms)
+{
+    if (!c || !ms || nsteps < 1)
+        return fail(FPIC_EINVAL, "profile: bad argument");
+    if (!c->state_set)
+        return fail(FPIC_ESTATE, "profile before set");
+    hipEvent_t ev[6];
+    for (auto &e : ev)
+        HIPCHECK(hipEventCreate(&e));
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    hipStream_t s = c->stream;
+    int rc = FPIC_OK;
+    for (int n = 0; n < nsteps && !rc; ++n) {
+        const int p = c->par;
+        (void)hipEventRecord(ev[0], s);
+        for (int m = 1; m <= 4; ++m) {
+            launch_mode(c, m, c->d[p], nullptr, s);
+            if (m == 4)
+                tick_kernel<<<1, 64, 0, s>>>(c->d[p]);
+            (void)hipEventRecord(ev[m], s);
+        }
+        launch_sort(c, p, s);
+        (void)hipEventRecord(ev[5], s);
+        c->par ^= 1;
+        hipError_t err = hipGetLastError();
+        if (err == hipSuccess)
+            err = hipEventSynchronize(ev[5]);
+        for (int k = 0; k < 5 && err == hipSuccess; ++k) {
+            float t = 0.f;
+            err = hipEventElapsedTime(&t, ev[k], ev[k + 1]);
+            acc[k] += t;
+        }
+        float tt = 0.f;
+        if (err == hipSuccess)
+            err = hipEventElapsedTime(&tt, ev[0], ev[5]);
+        acc[5] += tt;
+        if (err != hipSuccess)
+            rc = fail(FPIC_EHIP, std::string("profile: ") + hipGetErrorString(err));
+    }
+    for (auto &e : ev)
+        (void)hipEventDestroy(e);
+    for (int k = 0; k < 6; ++k)
+        ms[k] = acc[k] / nsteps;
+    return rc;
+}
+
+void fpic_particles_destroy(fpic_pctx *c)
+{
+    if (!c)
+        return;
+    if (c->stream)
+        (void)hipStreamSynchronize(c->stream);
+    for (auto &g : c->g)
+        if (g)
+            (void)hipGraphExecDestroy(g);
+    if (c->cap)
+        (void)hipStreamDestroy(c->cap);
+    if (c->hbuf)
+        (void)hipHostFree(c->hbuf);
+    delete c;
+}
+
+}  // extern "C"
