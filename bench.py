@@ -34,6 +34,12 @@ GRID_B = 36 * 8         # bytes of one cell's combined moments
 STAGE_BYTES = {1: STATE_B + SLOPE_B, 2: STATE_B + 2 * SLOPE_B, 3: STATE_B + 2 * SLOPE_B,
                4: 2 * STATE_B + 3 * SLOPE_B}
 STEP_BYTES = sum(STAGE_BYTES.values())   # 1744 B per particle-step
+# general placement (1D): every stage also reads the particle's own z
+# position at t = 0, direction and two weights; a sort reads the key inputs
+# (z, Omega_z) twice and moves state, z, direction, weights and index
+PSTATIC_B = (1 + 3 + 2) * 8
+PSTAGE_BYTES = {s: b + PSTATIC_B for s, b in STAGE_BYTES.items()}
+PSORT_BYTES = 2 * 16 + 2 * (STATE_B + PSTATIC_B + 4)
 
 
 def kernel_source_hash():
@@ -239,6 +245,44 @@ def measure_batch(steps=100, nsim=64):
             "ratio": ts / tb, "sims_with_negative_weights": neg}
 
 
+def measure_particles(steps=200, sort_every=4):
+    """General placement: the 2048-cell, 64 pi box with 774,144 particles at
+    uniform random positions (378 per cell on average), sorted by cell every
+    `sort_every` steps inside the timed region."""
+    import torch
+    from paper_2101_02745_amd import inputs as I
+    from paper_2101_02745_amd.particles import ParticleSim
+    w = I.particle_workload("1d_2048x378_random")
+    sim = ParticleSim.from_workload(w, sort_every=sort_every)
+    sim.set_workload(w)
+    sim.step(4 * sort_every)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = sim.profile(10)
+    P = w.nparticles
+    grid = 2 * GRID_B * w.ncell_total
+    stage_bytes = [PSTAGE_BYTES[s] * P + grid for s in (1, 2, 3, 4)]
+    step_bytes = sum(stage_bytes) + PSORT_BYTES * P / sort_every
+    ms_step = 1e3 * wall / steps
+    dom = max(range(4), key=lambda k: ms[k])
+    sim.close()
+    return {"workload": w.name, "particles": P, "steps": steps, "sort_every": sort_every,
+            "value": P * steps / wall, "unit": "particle-steps/s", "ms_per_step": ms_step,
+            "stage_ms": list(ms[:4]), "sort_ms": ms[4],
+            "stage_GBs": [b / (t * 1e-3) / 1e9 for b, t in zip(stage_bytes, ms[:4])],
+            "sort_GBs": PSORT_BYTES * P / (ms[4] * 1e-3) / 1e9,
+            "roofline": {"bound": "hbm", "kernel": f"pstage_kernel<{dom + 1}>",
+                         "achieved": stage_bytes[dom] / (ms[dom] * 1e-3) / 1e9,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": stage_bytes[dom] / (ms[dom] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                         "alg_bytes_per_launch": stage_bytes[dom], "ms_per_launch": ms[dom]},
+            "alg_bytes_per_step": step_bytes,
+            "step_frac_of_hbm_peak": step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -250,10 +294,11 @@ def main():
                     help="skip the adjoint and batch measurements")
     ap.add_argument("--tuning", default="",
                     help="JSON launch shape; default: autotune on the device first")
-    ap.add_argument("--probe", default="", choices=["", "copy", "kernels", "adjoint"],
+    ap.add_argument("--probe", default="", choices=["", "copy", "kernels", "adjoint", "particles"],
                     help="counter-collection modes: 'copy' runs a plain 1 GiB device copy "
                          "(the reference for HBM byte counters); 'kernels' runs 5 steps "
-                         "with every kernel launched on its own, then exits")
+                         "with every kernel launched on its own, then exits; 'particles' "
+                         "times the general-placement box")
     args = ap.parse_args()
     if args.probe == "copy":
         import torch
@@ -264,6 +309,10 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"probe": "copy", "bytes_read": src.numel() * 8,
                           "bytes_written": dst.numel() * 8, "launches": 5}), flush=True)
+        return
+    if args.probe == "particles":
+        r = measure_particles(steps=20)
+        print(json.dumps({"probe": "particles", **r}), flush=True)
         return
     if args.probe == "adjoint":
         r = measure_adjoint(steps=200, ckpt=50, tune=json.loads(args.tuning) if args.tuning else None)
@@ -352,6 +401,9 @@ def main():
         print("[bench] quadratic shape on the same box", file=sys.stderr, flush=True)
         rec["quadratic"] = measure_quadratic(sim.tune.as_dict() if sim.tune else None)
         print(f"[bench] quadratic: {rec['quadratic']}", file=sys.stderr, flush=True)
+        print("[bench] general particle placement", file=sys.stderr, flush=True)
+        rec["general_placement"] = measure_particles()
+        print(f"[bench] general placement: {rec['general_placement']}", file=sys.stderr, flush=True)
         print("[bench] batched vs sequential (64 uneven 1D boxes)", file=sys.stderr, flush=True)
         rec["batch"] = measure_batch()
         print(f"[bench] batch: {rec['batch']}", file=sys.stderr, flush=True)

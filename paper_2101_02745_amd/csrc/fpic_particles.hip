@@ -19,7 +19,7 @@
 // by cell, a workgroup's particles cover a small box of cells: it
 // accumulates their deposits in LDS (FP64 LDS atomics) over that box and
 // adds the box into the grid with global FP64 atomics.  A workgroup whose
-// box exceeds SPAN_MAX cells (particles spread out) adds straight to the
+// box does not fit its LDS (particles spread out) adds straight to the
 // grid.  Three grid buffers rotate: stage s of step n reads G[(4n+s-1) % 3],
 // deposits into G[(4n+s) % 3] and clears G[(4n+s+1) % 3] for the next
 // stage.
@@ -53,7 +53,8 @@ using fpic::store_slope;
 constexpr int NG = 36;
 constexpr int BLK = 256;            // particles (threads) per workgroup
 constexpr int NWAVE = BLK / 64;
-constexpr int SPAN_MAX = 128;       // cells of a workgroup's LDS deposit box
+constexpr int ACC_DOUBLES = 6144;   // LDS of the deposit box accumulators (48 KB)
+constexpr int MAX_COPIES = 32;      // replicas of the box accumulator
 constexpr int kRedBlk = 256;        // blocks of the diagnostic reductions
 
 enum : int { PM_DEPOSIT = 5, PM_MOM_NU = 6, PM_MOM_NUBAR = 7 };
@@ -142,14 +143,68 @@ __device__ __forceinline__ int wrap_int(int c, int n)
     return c < 0 ? c + n : c;
 }
 
+// Box of cells covered by the stencils of a workgroup's active particles
+// (first cells f, SW cells per axis), as offsets from thread 0's first cell
+// on each periodic axis.  Every thread of the workgroup must call it.
+struct Box {
+    int ref[3], lo[3], s[3];
+    int64_t cells;
+};
+
+template <int SW, bool D3>
+__device__ __forceinline__ Box block_box(const int f[3], bool active, const int n[3],
+                                         int (*sred)[6], int *sref, int o[3])
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();  // earlier readers of sref, sred and the LDS box are done
+    if (threadIdx.x == 0)
+        for (int a = 0; a < 3; a++)
+            sref[a] = f[a];
+    __syncthreads();
+    Box b;
+    int m[6];
+    for (int a = 0; a < 3; a++) {
+        b.ref[a] = sref[a];
+        o[a] = periodic_offset(f[a], b.ref[a], n[a]);
+        m[a] = active ? o[a] : INT_MAX;
+        m[3 + a] = active ? o[a] : INT_MIN;
+    }
+#pragma unroll
+    for (int sh = 32; sh >= 1; sh >>= 1)
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            m[a] = min(m[a], __shfl_xor(m[a], sh, 64));
+            m[3 + a] = max(m[3 + a], __shfl_xor(m[3 + a], sh, 64));
+        }
+    if (lane == 0)
+        for (int a = 0; a < 6; a++)
+            sred[wave][a] = m[a];
+    __syncthreads();
+    for (int a = 0; a < 3; a++) {
+        int lo = sred[0][a], hi = sred[0][3 + a];
+        for (int w = 1; w < NWAVE; w++) {
+            lo = min(lo, sred[w][a]);
+            hi = max(hi, sred[w][3 + a]);
+        }
+        const bool used = D3 || a == 2;
+        b.lo[a] = used ? lo : 0;
+        b.s[a] = used ? hi - lo + SW : 1;
+        if (!used)
+            o[a] = 0;
+    }
+    b.cells = (int64_t)b.s[0] * b.s[1] * b.s[2];
+    return b;
+}
+
 // MODE 1..4: Runge-Kutta stages; PM_DEPOSIT: deposit the current state at
 // the current time into the buffer stage 1 reads; PM_MOM_NU / PM_MOM_NUBAR:
 // deposit N rho or Nbar rhobar alone into outG (moment diagnostics).
 template <int MODE, int SH, bool D3>
-__global__ void __launch_bounds__(BLK) pstage_kernel(const PDesc *__restrict__ dp, double *outG)
+__global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(SH == 1 ? 2 : 1)))
+pstage_kernel(const PDesc *__restrict__ dp, double *outG)
 {
     constexpr int SW = SH + 1;  // stencil cells per axis
-    __shared__ double acc[NG * SPAN_MAX];
+    __shared__ double acc[ACC_DOUBLES];
     __shared__ int sred[NWAVE][6];
     __shared__ int sref[3];
     const PDesc S = *dp;
@@ -159,7 +214,7 @@ __global__ void __launch_bounds__(BLK) pstage_kernel(const PDesc *__restrict__ d
     const int64_t ip = active ? i : 0;
     const int64_t n = *S.step;
     const double dt = S.dt;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
 
     double t_cur = 0.0, t_nxt;
     if (MODE == 1) {
@@ -207,6 +262,40 @@ __global__ void __launch_bounds__(BLK) pstage_kernel(const PDesc *__restrict__ d
     const int nx = S.n[0], ny = S.n[1], nz = S.n[2];
     const int64_t nc = S.ncell;
 
+    const int nn[3] = {nx, ny, nz};
+
+    // stencil at the current position.  Stages 1-3 stage the grid cells
+    // their particles interpolate from in LDS when they fit; stage 4, which
+    // streams the most particle data, reads them through the caches (the
+    // staging barrier would hold its streams back).
+    int gf[3] = {0, 0, 0}, go[3] = {0, 0, 0};
+    double gw[3][3] = {{1.0, 0.0, 0.0}, {1.0, 0.0, 0.0}, {1.0, 0.0, 0.0}};
+    Box gb = {};
+    bool g_lds = false;
+    if (MODE <= 4) {
+        axis_stencil<SH>(pz, vz, t_cur, S.dx[2], nz, &gf[2], gw[2]);
+        if (D3) {
+            axis_stencil<SH>(px, vx, t_cur, S.dx[0], nx, &gf[0], gw[0]);
+            axis_stencil<SH>(py, vy, t_cur, S.dx[1], ny, &gf[1], gw[1]);
+        }
+    }
+    if (MODE <= 3) {
+        gb = block_box<SW, D3>(gf, active, nn, sred, sref, go);
+        g_lds = gb.cells * NG <= ACC_DOUBLES;
+        if (g_lds) {
+            const int cells = (int)gb.cells;
+            for (int q = threadIdx.x; q < NG * cells; q += BLK) {
+                const int comp = q / cells, l = q - comp * cells;
+                const int lx = l % gb.s[0], ly = (l / gb.s[0]) % gb.s[1], lz = l / (gb.s[0] * gb.s[1]);
+                const int cz = wrap_int(gb.ref[2] + gb.lo[2] + lz, nz);
+                const int cy = D3 ? wrap_int(gb.ref[1] + gb.lo[1] + ly, ny) : 0;
+                const int cx = D3 ? wrap_int(gb.ref[0] + gb.lo[0] + lx, nx) : 0;
+                acc[q] = gld(Gin + (int64_t)comp * nc + ((int64_t)cz * ny + cy) * nx + cx);
+            }
+            __syncthreads();
+        }
+    }
+
     double X[9];
 #pragma unroll
     for (int k = 0; k < 9; k++)
@@ -230,37 +319,53 @@ __global__ void __launch_bounds__(BLK) pstage_kernel(const PDesc *__restrict__ d
             for (int k = 0; k < 9; k++)
                 X[k] = wNb * Y[9 + k];
         } else {
-            // interpolate the grid at the current position
-            int fx = 0, fy = 0, fz;
-            double wx[3] = {1.0, 0.0, 0.0}, wy[3] = {1.0, 0.0, 0.0}, wz[3];
-            axis_stencil<SH>(pz, vz, t_cur, S.dx[2], nz, &fz, wz);
-            if (D3) {
-                axis_stencil<SH>(px, vx, t_cur, S.dx[0], nx, &fx, wx);
-                axis_stencil<SH>(py, vy, t_cur, S.dx[1], ny, &fy, wy);
-            }
+            // interpolate the grid at the current position: from the LDS
+            // box when it was staged, else from the grid in memory
             double A[9], Bx[9], By[9], Bz[9];
 #pragma unroll
             for (int k = 0; k < 9; k++)
                 A[k] = Bx[k] = By[k] = Bz[k] = 0.0;
+            if (g_lds) {
+                const int cells = (int)gb.cells;
 #pragma unroll
-            for (int bz = 0; bz < SW; bz++)
+                for (int bz = 0; bz < SW; bz++)
 #pragma unroll
-                for (int by = 0; by < (D3 ? SW : 1); by++)
+                    for (int by = 0; by < (D3 ? SW : 1); by++)
 #pragma unroll
-                    for (int bx = 0; bx < (D3 ? SW : 1); bx++) {
-                        const double w = D3 ? (wx[bx] * wy[by]) * wz[bz] : wz[bz];
-                        const int cz = wrap_int(fz + bz, nz);
-                        const int cy = D3 ? wrap_int(fy + by, ny) : 0;
-                        const int cx = D3 ? wrap_int(fx + bx, nx) : 0;
-                        const double *g = Gin + ((int64_t)cz * ny + cy) * nx + cx;
+                        for (int bx = 0; bx < (D3 ? SW : 1); bx++) {
+                            const double w = D3 ? (gw[0][bx] * gw[1][by]) * gw[2][bz] : gw[2][bz];
+                            const double *g = acc + ((go[2] - gb.lo[2] + bz) * gb.s[1] +
+                                                     (go[1] - gb.lo[1] + by)) * gb.s[0] +
+                                              (go[0] - gb.lo[0] + bx);
 #pragma unroll
-                        for (int k = 0; k < 9; k++) {
-                            A[k] += w * gld(g + (int64_t)k * nc);
-                            Bx[k] += w * gld(g + (int64_t)(9 + k) * nc);
-                            By[k] += w * gld(g + (int64_t)(18 + k) * nc);
-                            Bz[k] += w * gld(g + (int64_t)(27 + k) * nc);
+                            for (int k = 0; k < 9; k++) {
+                                A[k] += w * g[k * cells];
+                                Bx[k] += w * g[(9 + k) * cells];
+                                By[k] += w * g[(18 + k) * cells];
+                                Bz[k] += w * g[(27 + k) * cells];
+                            }
                         }
-                    }
+            } else {
+#pragma unroll
+                for (int bz = 0; bz < SW; bz++)
+#pragma unroll
+                    for (int by = 0; by < (D3 ? SW : 1); by++)
+#pragma unroll
+                        for (int bx = 0; bx < (D3 ? SW : 1); bx++) {
+                            const double w = D3 ? (gw[0][bx] * gw[1][by]) * gw[2][bz] : gw[2][bz];
+                            const int cz = wrap_int(gf[2] + bz, nz);
+                            const int cy = D3 ? wrap_int(gf[1] + by, ny) : 0;
+                            const int cx = D3 ? wrap_int(gf[0] + bx, nx) : 0;
+                            const double *g = Gin + ((int64_t)cz * ny + cy) * nx + cx;
+#pragma unroll
+                            for (int k = 0; k < 9; k++) {
+                                A[k] += w * gld(g + (int64_t)k * nc);
+                                Bx[k] += w * gld(g + (int64_t)(9 + k) * nc);
+                                By[k] += w * gld(g + (int64_t)(18 + k) * nc);
+                                Bz[k] += w * gld(g + (int64_t)(27 + k) * nc);
+                            }
+                        }
+            }
             double Hnn[9];
 #pragma unroll
             for (int k = 0; k < 9; k++)
@@ -327,87 +432,61 @@ __global__ void __launch_bounds__(BLK) pstage_kernel(const PDesc *__restrict__ d
     }
 
     // ---- deposit with the next-stage weights ---------------------------
-    int fx = 0, fy = 0, fz;
-    double wx[3] = {1.0, 0.0, 0.0}, wy[3] = {1.0, 0.0, 0.0}, wz[3];
-    axis_stencil<SH>(pz, vz, t_nxt, S.dx[2], nz, &fz, wz);
+    int df[3] = {0, 0, 0}, o[3];
+    double dw[3][3] = {{1.0, 0.0, 0.0}, {1.0, 0.0, 0.0}, {1.0, 0.0, 0.0}};
+    axis_stencil<SH>(pz, vz, t_nxt, S.dx[2], nz, &df[2], dw[2]);
     if (D3) {
-        axis_stencil<SH>(px, vx, t_nxt, S.dx[0], nx, &fx, wx);
-        axis_stencil<SH>(py, vy, t_nxt, S.dx[1], ny, &fy, wy);
+        axis_stencil<SH>(px, vx, t_nxt, S.dx[0], nx, &df[0], dw[0]);
+        axis_stencil<SH>(py, vy, t_nxt, S.dx[1], ny, &df[1], dw[1]);
     }
-    // box of cells the workgroup touches, relative to thread 0's stencil
-    if (threadIdx.x == 0) {
-        sref[0] = fx;
-        sref[1] = fy;
-        sref[2] = fz;
-    }
-    __syncthreads();
-    const int rx = sref[0], ry = sref[1], rz = sref[2];
-    const int ox = periodic_offset(fx, rx, nx), oy = periodic_offset(fy, ry, ny);
-    const int oz = periodic_offset(fz, rz, nz);
-    int m[6] = {active ? ox : INT_MAX, active ? oy : INT_MAX, active ? oz : INT_MAX,
-                active ? ox : INT_MIN, active ? oy : INT_MIN, active ? oz : INT_MIN};
-#pragma unroll
-    for (int s = 32; s >= 1; s >>= 1) {
-#pragma unroll
-        for (int a = 0; a < 3; a++) {
-            m[a] = min(m[a], __shfl_xor(m[a], s, 64));
-            m[3 + a] = max(m[3 + a], __shfl_xor(m[3 + a], s, 64));
-        }
-    }
-    if (lane == 0)
-#pragma unroll
-        for (int a = 0; a < 6; a++)
-            sred[wave][a] = m[a];
-    __syncthreads();
-    int lo[3], hi[3];
-#pragma unroll
-    for (int a = 0; a < 3; a++) {
-        lo[a] = sred[0][a];
-        hi[a] = sred[0][3 + a];
-        for (int w = 1; w < NWAVE; w++) {
-            lo[a] = min(lo[a], sred[w][a]);
-            hi[a] = max(hi[a], sred[w][3 + a]);
-        }
-    }
-    const int sx = D3 ? hi[0] - lo[0] + SW : 1;
-    const int sy = D3 ? hi[1] - lo[1] + SW : 1;
-    const int sz = hi[2] - lo[2] + SW;
-    const int64_t box = (int64_t)sx * sy * sz;
+    const Box db = block_box<SW, D3>(df, active, nn, sred, sref, o);
+    const int sx = db.s[0], sy = db.s[1];
+    const int64_t box = db.cells;
 
-    if (box <= SPAN_MAX) {
+    if (box * NG <= ACC_DOUBLES) {
+        // R copies of the box accumulator, lane l adding into copy l % R:
+        // lanes of a dense workgroup target the same few cells, and the
+        // copies spread their atomics over distinct addresses.  A copy holds
+        // an odd number of doubles, so the copies start in different banks.
         const int cells = (int)box;
-        for (int q = threadIdx.x; q < NG * cells; q += BLK)
+        const int cstride = NG * cells + 1;
+        int R = MAX_COPIES;
+        while (R > 1 && R * cstride > ACC_DOUBLES)
+            R >>= 1;
+        for (int q = threadIdx.x; q < R * cstride; q += BLK)
             acc[q] = 0.0;
         __syncthreads();
         if (active) {
+            double *mine = acc + (lane & (R - 1)) * cstride;
 #pragma unroll
             for (int bz = 0; bz < SW; bz++)
 #pragma unroll
                 for (int by = 0; by < (D3 ? SW : 1); by++)
 #pragma unroll
                     for (int bx = 0; bx < (D3 ? SW : 1); bx++) {
-                        const double w = D3 ? (wx[bx] * wy[by]) * wz[bz] : wz[bz];
-                        const int idx = ((oz - lo[2] + bz) * sy + (D3 ? oy - lo[1] + by : 0)) * sx +
-                                        (D3 ? ox - lo[0] + bx : 0);
+                        const double w = D3 ? (dw[0][bx] * dw[1][by]) * dw[2][bz] : dw[2][bz];
+                        const int idx = ((o[2] - db.lo[2] + bz) * sy + (o[1] - db.lo[1] + by)) * sx + (o[0] - db.lo[0] + bx);
 #pragma unroll
                         for (int k = 0; k < 9; k++) {
                             const double xc = w * X[k];
-                            atomicAdd(&acc[k * cells + idx], xc);
-                            atomicAdd(&acc[(9 + k) * cells + idx], vx * xc);
-                            atomicAdd(&acc[(18 + k) * cells + idx], vy * xc);
-                            atomicAdd(&acc[(27 + k) * cells + idx], vz * xc);
+                            atomicAdd(&mine[k * cells + idx], xc);
+                            atomicAdd(&mine[(9 + k) * cells + idx], vx * xc);
+                            atomicAdd(&mine[(18 + k) * cells + idx], vy * xc);
+                            atomicAdd(&mine[(27 + k) * cells + idx], vz * xc);
                         }
                     }
         }
         __syncthreads();
         for (int q = threadIdx.x; q < NG * cells; q += BLK) {
-            const double val = acc[q];
+            double val = 0.0;
+            for (int r = 0; r < R; r++)
+                val += acc[r * cstride + q];
             if (val != 0.0) {
                 const int comp = q / cells, l = q - comp * cells;
                 const int lx = l % sx, ly = (l / sx) % sy, lz = l / (sx * sy);
-                const int cz = wrap_int(rz + lo[2] + lz, nz);
-                const int cy = D3 ? wrap_int(ry + lo[1] + ly, ny) : 0;
-                const int cx = D3 ? wrap_int(rx + lo[0] + lx, nx) : 0;
+                const int cz = wrap_int(db.ref[2] + db.lo[2] + lz, nz);
+                const int cy = D3 ? wrap_int(db.ref[1] + db.lo[1] + ly, ny) : 0;
+                const int cx = D3 ? wrap_int(db.ref[0] + db.lo[0] + lx, nx) : 0;
                 unsafeAtomicAdd(Gout + (int64_t)comp * nc + ((int64_t)cz * ny + cy) * nx + cx, val);
             }
         }
@@ -419,10 +498,10 @@ __global__ void __launch_bounds__(BLK) pstage_kernel(const PDesc *__restrict__ d
             for (int by = 0; by < (D3 ? SW : 1); by++)
 #pragma unroll
                 for (int bx = 0; bx < (D3 ? SW : 1); bx++) {
-                    const double w = D3 ? (wx[bx] * wy[by]) * wz[bz] : wz[bz];
-                    const int cz = wrap_int(fz + bz, nz);
-                    const int cy = D3 ? wrap_int(fy + by, ny) : 0;
-                    const int cx = D3 ? wrap_int(fx + bx, nx) : 0;
+                    const double w = D3 ? (dw[0][bx] * dw[1][by]) * dw[2][bz] : dw[2][bz];
+                    const int cz = wrap_int(df[2] + bz, nz);
+                    const int cy = D3 ? wrap_int(df[1] + by, ny) : 0;
+                    const int cx = D3 ? wrap_int(df[0] + bx, nx) : 0;
                     double *g = Gout + ((int64_t)cz * ny + cy) * nx + cx;
 #pragma unroll
                     for (int k = 0; k < 9; k++) {
@@ -476,40 +555,73 @@ __device__ __forceinline__ int sort_key(const PDesc &S, int64_t i, double t)
     return (c[2] * S.n[1] + c[1]) * S.n[0] + c[0];
 }
 
-// Runs of equal keys in consecutive lanes (the particles are nearly sorted)
-// are counted with one atomic each.  key < 0 marks an inactive lane.
-struct Run {
-    bool leader;
-    int len, rank, src;
+// The keys of a workgroup's particles (nearly sorted) fall in a short range
+// of the periodic cell numbering: a histogram of that range in LDS takes the
+// per-particle atomics, and the workgroup adds one count per cell to the
+// global counters.  A workgroup whose range exceeds HIST_MAX cells uses
+// global atomics per particle.
+constexpr int HIST_MAX = 8192;
+
+struct KeyRange {
+    int ref, lo, len, off;
 };
 
-__device__ __forceinline__ Run lane_run(int key)
+__device__ __forceinline__ KeyRange key_range(int key, bool active, int nc, int (*sred)[2], int *sref)
 {
-    const int lane = threadIdx.x & 63;
-    const int prev = __shfl_up(key, 1, 64);
-    const bool lead = (lane == 0) || (prev != key);
-    const unsigned long long mask = __ballot(lead);
-    const unsigned long long above = (lane == 63) ? 0ull : (mask & ~((2ull << lane) - 1ull));
-    const int next = above ? __builtin_ctzll(above) : 64;
-    const unsigned long long upto = mask & ((2ull << lane) - 1ull);  // lane 63: all bits
-    const int src = 63 - __builtin_clzll(upto);
-    Run r;
-    r.leader = lead;
-    r.len = next - lane;
-    r.rank = lane - src;
-    r.src = src;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (threadIdx.x == 0)
+        *sref = key;
+    __syncthreads();
+    KeyRange r;
+    r.ref = *sref;
+    r.off = periodic_offset(key, r.ref, nc);
+    int lo = active ? r.off : INT_MAX, hi = active ? r.off : INT_MIN;
+#pragma unroll
+    for (int sh = 32; sh >= 1; sh >>= 1) {
+        lo = min(lo, __shfl_xor(lo, sh, 64));
+        hi = max(hi, __shfl_xor(hi, sh, 64));
+    }
+    if (lane == 0) {
+        sred[wave][0] = lo;
+        sred[wave][1] = hi;
+    }
+    __syncthreads();
+    lo = sred[0][0];
+    hi = sred[0][1];
+    for (int w = 1; w < NWAVE; w++) {
+        lo = min(lo, sred[w][0]);
+        hi = max(hi, sred[w][1]);
+    }
+    r.lo = lo;
+    r.len = hi - lo + 1;
     return r;
 }
 
 __global__ void __launch_bounds__(BLK) sort_count_kernel(const PDesc *__restrict__ dp)
 {
+    __shared__ int hist[HIST_MAX];
+    __shared__ int sred[NWAVE][2];
+    __shared__ int sref;
     const PDesc &S = *dp;
+    const int nc = (int)S.ncell;
     const int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
+    const bool active = i < S.np;
     const double t = stage_time(*S.step, S.dt, 0.0);
-    const int key = i < S.np ? sort_key(S, i, t) : -1;
-    const Run r = lane_run(key);
-    if (r.leader && key >= 0)
-        atomicAdd(S.cnt + key, r.len);
+    const int key = active ? sort_key(S, i, t) : 0;
+    const KeyRange r = key_range(key, active, nc, sred, &sref);
+    if (r.len <= HIST_MAX) {
+        for (int j = threadIdx.x; j < r.len; j += BLK)
+            hist[j] = 0;
+        __syncthreads();
+        if (active)
+            atomicAdd(&hist[r.off - r.lo], 1);
+        __syncthreads();
+        for (int j = threadIdx.x; j < r.len; j += BLK)
+            if (hist[j])
+                atomicAdd(S.cnt + wrap_int(r.ref + r.lo + j, nc), hist[j]);
+    } else if (active) {
+        atomicAdd(S.cnt + key, 1);
+    }
 }
 
 // exclusive scan of cnt into cur (one workgroup of 1024 threads)
@@ -542,19 +654,37 @@ __global__ void __launch_bounds__(1024) sort_scan_kernel(const PDesc *__restrict
 template <bool D3>
 __global__ void __launch_bounds__(BLK) sort_scatter_kernel(const PDesc *__restrict__ dp)
 {
+    __shared__ int hist[HIST_MAX];
+    __shared__ int sred[NWAVE][2];
+    __shared__ int sref;
     const PDesc &S = *dp;
     const int64_t np = S.np;
+    const int nc = (int)S.ncell;
     const int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
+    const bool active = i < np;
     const double t = stage_time(*S.step, S.dt, 0.0);
-    const int key = i < np ? sort_key(S, i, t) : -1;
-    const Run r = lane_run(key);
-    int base = 0;
-    if (r.leader && key >= 0)
-        base = atomicAdd(S.cur + key, r.len);
-    base = __shfl(base, r.src, 64);
-    if (key < 0)
+    const int key = active ? sort_key(S, i, t) : 0;
+    const KeyRange r = key_range(key, active, nc, sred, &sref);
+    int base;
+    if (r.len <= HIST_MAX) {
+        // rank within the workgroup's particles of the same cell, then one
+        // reservation per cell in the global cursor
+        for (int jj = threadIdx.x; jj < r.len; jj += BLK)
+            hist[jj] = 0;
+        __syncthreads();
+        const int rank = active ? atomicAdd(&hist[r.off - r.lo], 1) : 0;
+        __syncthreads();
+        for (int jj = threadIdx.x; jj < r.len; jj += BLK)
+            if (hist[jj])
+                hist[jj] = atomicAdd(S.cur + wrap_int(r.ref + r.lo + jj, nc), hist[jj]);
+        __syncthreads();
+        base = active ? hist[r.off - r.lo] + rank : 0;
+    } else {
+        base = active ? atomicAdd(S.cur + key, 1) : 0;
+    }
+    if (!active)
         return;
-    const int64_t j = base + r.rank;
+    const int64_t j = base;
 #pragma unroll
     for (int k = 0; k < 18; k++)
         gst(S.Y2 + k * np + j, gld(S.Y + k * np + i));
