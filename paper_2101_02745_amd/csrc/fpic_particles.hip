@@ -143,6 +143,12 @@ __device__ __forceinline__ int wrap_int(int c, int n)
     return c < 0 ? c + n : c;
 }
 
+// w[b] for a run-time b in 0..2, without indexing a private array
+__device__ __forceinline__ double pick(const double w[3], int b)
+{
+    return b == 0 ? w[0] : (b == 1 ? w[1] : w[2]);
+}
+
 // Box of cells covered by the stencils of a workgroup's active particles
 // (first cells f, SW cells per axis), as offsets from thread 0's first cell
 // on each periodic axis.  Every thread of the workgroup must call it.
@@ -457,24 +463,29 @@ pstage_kernel(const PDesc *__restrict__ dp, double *outG)
             acc[q] = 0.0;
         __syncthreads();
         if (active) {
+            // each lane walks its stencil corners starting at its own
+            // offset, so one instruction's lanes target different corners
             double *mine = acc + (lane & (R - 1)) * cstride;
+            constexpr int NCORNER = D3 ? SW * SW * SW : SW;
+            const int rot = lane % NCORNER;
 #pragma unroll
-            for (int bz = 0; bz < SW; bz++)
+            for (int j = 0; j < NCORNER; j++) {
+                int c = j + rot;
+                c = c >= NCORNER ? c - NCORNER : c;
+                const int bx = D3 ? c % SW : 0;
+                const int by = D3 ? (c / SW) % SW : 0;
+                const int bz = D3 ? c / (SW * SW) : c;
+                const double w = D3 ? (pick(dw[0], bx) * pick(dw[1], by)) * pick(dw[2], bz) : pick(dw[2], bz);
+                const int idx = ((o[2] - db.lo[2] + bz) * sy + (o[1] - db.lo[1] + by)) * sx + (o[0] - db.lo[0] + bx);
 #pragma unroll
-                for (int by = 0; by < (D3 ? SW : 1); by++)
-#pragma unroll
-                    for (int bx = 0; bx < (D3 ? SW : 1); bx++) {
-                        const double w = D3 ? (dw[0][bx] * dw[1][by]) * dw[2][bz] : dw[2][bz];
-                        const int idx = ((o[2] - db.lo[2] + bz) * sy + (o[1] - db.lo[1] + by)) * sx + (o[0] - db.lo[0] + bx);
-#pragma unroll
-                        for (int k = 0; k < 9; k++) {
-                            const double xc = w * X[k];
-                            atomicAdd(&mine[k * cells + idx], xc);
-                            atomicAdd(&mine[(9 + k) * cells + idx], vx * xc);
-                            atomicAdd(&mine[(18 + k) * cells + idx], vy * xc);
-                            atomicAdd(&mine[(27 + k) * cells + idx], vz * xc);
-                        }
-                    }
+                for (int k = 0; k < 9; k++) {
+                    const double xc = w * X[k];
+                    atomicAdd(&mine[k * cells + idx], xc);
+                    atomicAdd(&mine[(9 + k) * cells + idx], vx * xc);
+                    atomicAdd(&mine[(18 + k) * cells + idx], vy * xc);
+                    atomicAdd(&mine[(27 + k) * cells + idx], vz * xc);
+                }
+            }
         }
         __syncthreads();
         for (int q = threadIdx.x; q < NG * cells; q += BLK) {
