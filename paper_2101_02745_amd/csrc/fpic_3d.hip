@@ -432,6 +432,19 @@ __device__ __forceinline__ int wrap(int i, int n)
     return i < 0 ? i + n : i;
 }
 
+// w[b] for a run-time b in 0..2, without indexing a private array
+__device__ __forceinline__ double pick3(const double w[3], int b)
+{
+    return b == 0 ? w[0] : (b == 1 ? w[1] : w[2]);
+}
+
+// Directions per gather block: each load of a grid row serves the block's
+// directions (the nine rows are shared by every particle of the workgroup
+// but do not fit in LDS, so they come through the caches).  Two for stages
+// 1-3; stage 4 holds three slopes and keeps one (more would spill).
+template <int MODE>
+constexpr int qdb() { return MODE == 4 ? 1 : 2; }
+
 template <int MODE>
 __global__ void __launch_bounds__(MAX_WAVES3 * W)
 particle3q_kernel(const Desc3 *__restrict__ dp, int dpw, int nitems)
@@ -470,34 +483,39 @@ particle3q_kernel(const Desc3 *__restrict__ dp, int dpw, int nitems)
         for (int b = 0; b < 3; b++)
             rowoff[3 * c + b] = (wrap(z0 + c - 1, nz) * ny + wrap(y0 + b - 1, ny)) * nx + (active ? lane : 0);
 
-    for (int d = dbeg; d < dend; ++d) {
-        const double vx = S.v[0][d], vy = S.v[1][d], vz = S.v[2][d];
-        const double wN = S.wN[d], wNb = S.wNb[d];
-        int rx, ry, rz;
-        double wx[3], wy[3], wz[3];
-        axis_quad(vx, t_cur, S.dx[0], nx, &rx, wx);
-        axis_quad(vy, t_cur, S.dx[1], ny, &ry, wy);
-        axis_quad(vz, t_cur, S.dx[2], nz, &rz, wz);
-        const int cx = wrap(lane - rx, nx), cy = wrap(y0 - ry, ny), cz = wrap(z0 - rz, nz);
-        const int64_t c = ((int64_t)cz * ny + cy) * nx + (active ? cx : 0);
-        const int64_t p = (int64_t)d * S.ncell + c;
-        double Y[18];
+    constexpr int QDB = qdb<MODE>();
+    for (int d0 = dbeg; d0 < dend; d0 += QDB) {
+        // weights of the block's directions (past the end: the last one
+        // again, not stored)
+        double vb[QDB][3], wxb[QDB][3], wyb[QDB][3], wzb[QDB][3];
+        int rxb[QDB], ryb[QDB], rzb[QDB];
 #pragma unroll
-        for (int k = 0; k < 18; k++)
-            Y[k] = active ? gld(S.Y + k * S.np + p) : 0.0;
-        double Hnn[9];
+        for (int j = 0; j < QDB; j++) {
+            const int d = min(d0 + j, dend - 1);
+            vb[j][0] = S.v[0][d];
+            vb[j][1] = S.v[1][d];
+            vb[j][2] = S.v[2][d];
+            axis_quad(vb[j][0], t_cur, S.dx[0], nx, &rxb[j], wxb[j]);
+            axis_quad(vb[j][1], t_cur, S.dx[1], ny, &ryb[j], wyb[j]);
+            axis_quad(vb[j][2], t_cur, S.dx[2], nz, &rzb[j], wzb[j]);
+        }
+        double Hb4[QDB][9];
 #pragma unroll
-        for (int k = 0; k < 9; k++)
-            Hnn[k] = 0.0;
-#pragma unroll 1
-        for (int grp4 = 0; grp4 < 4; grp4++) {
-            const double coef = (grp4 == 0) ? 1.0 : (grp4 == 1) ? -vx : (grp4 == 2) ? -vy : -vz;
-            const double *g = Gin + (int64_t)(9 * grp4) * S.ncell;
-            // y/z interpolation row by row (nine loads in flight per row)
-            double r[9];
+        for (int j = 0; j < QDB; j++)
 #pragma unroll
             for (int k = 0; k < 9; k++)
-                r[k] = 0.0;
+                Hb4[j][k] = 0.0;
+#pragma unroll 1
+        for (int grp4 = 0; grp4 < 4; grp4++) {
+            const double *g = Gin + (int64_t)(9 * grp4) * S.ncell;
+            // y/z interpolation row by row, each row load used by every
+            // direction of the block
+            double r[QDB][9];
+#pragma unroll
+            for (int j = 0; j < QDB; j++)
+#pragma unroll
+                for (int k = 0; k < 9; k++)
+                    r[j][k] = 0.0;
 #pragma unroll 1
             for (int q = 0; q < 9; q++) {
                 const int b = q % 3, cc = q / 3;
@@ -505,75 +523,121 @@ particle3q_kernel(const Desc3 *__restrict__ dp, int dpw, int nitems)
 #pragma unroll
                 for (int qq = 1; qq < 9; qq++)
                     ro = (q == qq) ? rowoff[qq] : ro;
-                const double wq = wy[b] * wz[cc];
+                double gv[9];
 #pragma unroll
                 for (int k = 0; k < 9; k++)
-                    r[k] += wq * (active ? gld(g + (int64_t)k * S.ncell + ro) : 0.0);
+                    gv[k] = active ? gld(g + (int64_t)k * S.ncell + ro) : 0.0;
+#pragma unroll
+                for (int j = 0; j < QDB; j++) {
+                    const double wq = pick3(wyb[j], b) * pick3(wzb[j], cc);
+#pragma unroll
+                    for (int k = 0; k < 9; k++)
+                        r[j][k] += wq * gv[k];
+                }
             }
 #pragma unroll
-            for (int k = 0; k < 9; k++) {
-                const double nl = lane_get(r[k], xl), nr = lane_get(r[k], xr);
-                Hnn[k] += coef * ((wx[0] * nl + wx[1] * r[k]) + wx[2] * nr);
+            for (int j = 0; j < QDB; j++) {
+                const double coef = (grp4 == 0) ? 1.0 : -pick3(vb[j], grp4 - 1);
+#pragma unroll
+                for (int k = 0; k < 9; k++) {
+                    const double nl = lane_get(r[j][k], xl), nr = lane_get(r[j][k], xr);
+                    Hb4[j][k] += coef * ((wxb[j][0] * nl + wxb[j][1] * r[j][k]) + wxb[j][2] * nr);
+                }
             }
         }
-        double yv[18], base[18], yn[18];
-        if (MODE == 1) {
+
+#pragma unroll 1
+        for (int j = 0; j < QDB; j++) {
+            const int d = d0 + j;
+            if (d >= dend)
+                break;
+            const double wN = S.wN[d], wNb = S.wNb[d];
+            int rx = rxb[0], ry = ryb[0], rz = rzb[0];
+            double Hnn[9];
+#pragma unroll
+            for (int k = 0; k < 9; k++)
+                Hnn[k] = Hb4[0][k];
+#pragma unroll
+            for (int jj = 1; jj < QDB; jj++) {
+                const bool m = j == jj;
+                rx = m ? rxb[jj] : rx;
+                ry = m ? ryb[jj] : ry;
+                rz = m ? rzb[jj] : rz;
+#pragma unroll
+                for (int k = 0; k < 9; k++)
+                    Hnn[k] = m ? Hb4[jj][k] : Hnn[k];
+            }
+            const int cx = wrap(lane - rx, nx), cy = wrap(y0 - ry, ny), cz = wrap(z0 - rz, nz);
+            const int64_t c = ((int64_t)cz * ny + cy) * nx + (active ? cx : 0);
+            const int64_t p = (int64_t)d * S.ncell + c;
+            double Y[18];
 #pragma unroll
             for (int k = 0; k < 18; k++)
-                yv[k] = base[k] = Y[k];
-        } else if (MODE == 4) {
-            const double h6 = dt / 6.0;
-            double k1[18], k2[18], k3[18];
-            load_slope(S.K1, S.np, p, active, k1);
-            load_slope(S.K2, S.np, p, active, k2);
-            load_slope(S.K3, S.np, p, active, k3);
+                Y[k] = active ? gld(S.Y + k * S.np + p) : 0.0;
+            double yv[18], base[18], yn[18];
+            if (MODE == 1) {
 #pragma unroll
-            for (int k = 0; k < 18; k++) {
-                yv[k] = Y[k] + dt * k3[k];
-                base[k] = Y[k] + h6 * ((k1[k] + 2.0 * k2[k]) + 2.0 * k3[k]);
+                for (int k = 0; k < 18; k++)
+                    yv[k] = base[k] = Y[k];
+            } else if (MODE == 4) {
+                // slopes one at a time into (k1 + 2 k2) + 2 k3 (fewer live
+                // registers than holding all three)
+                const double h6 = dt / 6.0;
+                double ks[18], kt[18];
+                load_slope(S.K1, S.np, p, active, ks);
+                load_slope(S.K2, S.np, p, active, kt);
+#pragma unroll
+                for (int k = 0; k < 18; k++)
+                    ks[k] = ks[k] + 2.0 * kt[k];
+                load_slope(S.K3, S.np, p, active, kt);
+#pragma unroll
+                for (int k = 0; k < 18; k++) {
+                    yv[k] = Y[k] + dt * kt[k];
+                    base[k] = Y[k] + h6 * (ks[k] + 2.0 * kt[k]);
+                }
+            } else {
+                double kp[18];
+                load_slope(Kp, S.np, p, active, kp);
+#pragma unroll
+                for (int k = 0; k < 18; k++) {
+                    yv[k] = Y[k] + 0.5 * dt * kp[k];
+                    base[k] = Y[k];
+                }
             }
-        } else {
-            double kp[18];
-            load_slope(Kp, S.np, p, active, kp);
-#pragma unroll
-            for (int k = 0; k < 18; k++) {
-                yv[k] = Y[k] + 0.5 * dt * kp[k];
-                base[k] = Y[k];
-            }
-        }
-        double H[9], Hb[9], kk[18];
-#pragma unroll
-        for (int k = 0; k < 9; k++) {
-            H[k] = S.hvac[k] + Hnn[k];
-            const double hb = S.hvacb[k] - Hnn[k];
-            Hb[k] = (k == 4 || k == 6 || k == 8) ? -hb : hb;
-        }
-        commutator(H, yv, kk);
-        commutator(Hb, yv + 9, kk + 9);
-        if (MODE == 4) {
-            const double h6 = dt / 6.0;
-#pragma unroll
-            for (int k = 0; k < 18; k++) {
-                yn[k] = base[k] + h6 * kk[k];
-                if (active)
-                    gst(S.Y + k * S.np + p, yn[k]);
-            }
-        } else {
-            double *Ko = (MODE == 1) ? S.K1 : (MODE == 2) ? S.K2 : S.K3;
-            const double an = (MODE == 3) ? dt : 0.5 * dt;
-#pragma unroll
-            for (int k = 0; k < 18; k++) {
-                if (active && k != 0 && k != 9)
-                    gst(Ko + kslot(k) * S.np + p, kk[k]);
-                yn[k] = base[k] + an * kk[k];
-            }
-        }
-        if (active) {
+            double H[9], Hb[9], kk[18];
 #pragma unroll
             for (int k = 0; k < 9; k++) {
-                const double x = (k == 4 || k == 6 || k == 8) ? wN * yn[k] + wNb * yn[9 + k]
-                                                              : wN * yn[k] - wNb * yn[9 + k];
-                gst(S.X + k * S.np + p, x);
+                H[k] = S.hvac[k] + Hnn[k];
+                const double hb = S.hvacb[k] - Hnn[k];
+                Hb[k] = (k == 4 || k == 6 || k == 8) ? -hb : hb;
+            }
+            commutator(H, yv, kk);
+            commutator(Hb, yv + 9, kk + 9);
+            if (MODE == 4) {
+                const double h6 = dt / 6.0;
+#pragma unroll
+                for (int k = 0; k < 18; k++) {
+                    yn[k] = base[k] + h6 * kk[k];
+                    if (active)
+                        gst(S.Y + k * S.np + p, yn[k]);
+                }
+            } else {
+                double *Ko = (MODE == 1) ? S.K1 : (MODE == 2) ? S.K2 : S.K3;
+                const double an = (MODE == 3) ? dt : 0.5 * dt;
+#pragma unroll
+                for (int k = 0; k < 18; k++) {
+                    if (active && k != 0 && k != 9)
+                        gst(Ko + kslot(k) * S.np + p, kk[k]);
+                    yn[k] = base[k] + an * kk[k];
+                }
+            }
+            if (active) {
+#pragma unroll
+                for (int k = 0; k < 9; k++) {
+                    const double x = (k == 4 || k == 6 || k == 8) ? wN * yn[k] + wNb * yn[9 + k]
+                                                                  : wN * yn[k] - wNb * yn[9 + k];
+                    gst(S.X + k * S.np + p, x);
+                }
             }
         }
     }
