@@ -250,7 +250,7 @@ def measure_batch(steps=100, nsim=64):
             "ratio": ts / tb, "sims_with_negative_weights": neg}
 
 
-def measure_particles(steps=200, sort_every=4):
+def measure_particles(steps=200, sort_every=4, with_3d=True):
     """General placement: the 2048-cell, 64 pi box with 774,144 particles at
     uniform random positions (378 per cell on average), sorted by cell every
     `sort_every` steps inside the timed region."""
@@ -287,7 +287,31 @@ def measure_particles(steps=200, sort_every=4):
                          "frac": stage_bytes[dom] / (ms[dom] * 1e-3) / 1e9 / HBM_PEAK_GBS,
                          "alg_bytes_per_launch": stage_bytes[dom], "ms_per_launch": ms[dom]},
             "alg_bytes_per_step": step_bytes,
-            "step_frac_of_hbm_peak": step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS}
+            "step_frac_of_hbm_peak": step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "box3d": measure_particles_3d() if with_3d else None}
+
+
+def measure_particles_3d(steps=16, sort_every=4):
+    """General placement in 3D: 32^3 cells, 92 particles per cell on average
+    at random positions (3,014,656 particles)."""
+    import torch
+    from paper_2101_02745_amd import inputs as I
+    from paper_2101_02745_amd.particles import ParticleSim
+    w = I.particle_workload("3d_32x92_random")
+    sim = ParticleSim.from_workload(w, sort_every=sort_every)
+    sim.set_workload(w)
+    sim.step(2 * sort_every)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = sim.profile(3)
+    sim.close()
+    return {"workload": w.name, "particles": w.nparticles, "steps": steps,
+            "sort_every": sort_every, "value": w.nparticles * steps / wall,
+            "unit": "particle-steps/s", "ms_per_step": 1e3 * wall / steps,
+            "stage_ms": list(ms[:4]), "sort_ms": ms[4]}
 
 
 def main():
@@ -318,7 +342,7 @@ def main():
                           "bytes_written": dst.numel() * 8, "launches": 5}), flush=True)
         return
     if args.probe == "particles":
-        r = measure_particles(steps=20)
+        r = measure_particles(steps=20, with_3d=False)
         print(json.dumps({"probe": "particles", **r}), flush=True)
         return
     if args.probe == "adjoint":

@@ -180,3 +180,36 @@ def test_rejects_bad_particles(torch_dev):
         sim.set(pos, w.dirs(), N, Nb, w.state0())
     with pytest.raises(FpicError, match="before set"):
         sim.step(1)
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_lattice_positions_match_lattice_path(torch_dev, order):
+    """Particles placed at the cell centres with the direction table are the
+    lattice workload; the general path (positions, atomics, sorting) and the
+    lattice path (implicit positions, fixed-order deposit) then agree at the
+    parity tolerance.  Both are compared with the reference as well."""
+    import dataclasses
+    from paper_2101_02745_amd.particles import ParticleSim
+    from paper_2101_02745_amd.sim import Sim
+    w = dataclasses.replace(I.scaled(I.workload("1d_512x128"), ncell=(1, 1, 96), ndir=26),
+                            shape_order=order, alpha=1e-3)
+    nd, nc = w.ndir, w.ncell_total
+    z = (np.arange(nc) + 0.5) * w.dx[2]
+    pos = np.zeros((nd * nc, 3))
+    pos[:, 0] = pos[:, 1] = 0.5
+    pos[:, 2] = np.tile(z, nd)
+    dirs = np.repeat(w.dirs(), nc, axis=0)
+    N, Nb = w.weights()
+    st = w.state0()
+    lat = Sim.from_workload(w)
+    lat.set_state(st)
+    lat.step(9)
+    gen = ParticleSim(w.ncell, w.dx, nd * nc, w.hvac(), w.dt, order, sort_every=3)
+    gen.set(pos, dirs, np.repeat(N, nc), np.repeat(Nb, nc), st.reshape(18, -1))
+    gen.step(9)
+    a = lat.get_state().cpu().numpy().reshape(18, -1)
+    b = gen.get_state().cpu().numpy()
+    assert_parity(b, a, what=f"general vs lattice, order {order}")
+    ref = ParticleProblem(w.ncell, w.dx, pos, dirs, np.repeat(N, nc), np.repeat(Nb, nc),
+                          w.hvac(), w.dt, shape_order=order).step(st.reshape(18, -1), 9)
+    assert_parity(b, ref, what="general vs reference")
