@@ -16,9 +16,10 @@
  *
  * Redistribution (Sec. II.C: particles are regrouped by cell as they move).
  * The library keeps its particles sorted by cell for locality: every
- * `sort_every` steps (and after the last step of every fpic_particles_step
- * call) a counting sort moves each particle's data next to the other
- * particles of its cell.  The order is internal: states go in and come out
+ * `sort_every` steps (and at the last step of every fpic_particles_step
+ * call) the last Runge-Kutta stage writes each particle next to the other
+ * particles of its new cell (a counting sort whose counts are taken before
+ * that stage).  The order is internal: states go in and come out
  * in the caller's particle order.  Deposits add into the grid with
  * floating-point atomics, so results agree run to run only up to rounding
  * (sums in a different order).
@@ -100,8 +101,9 @@ int fpic_particles_sync(fpic_pctx *ctx);
 
 /* SYNC.  Measurement: advance nsteps steps launching each kernel on its own
  * with HIP events between launches, sorting after every step; host ms[6]:
- * mean milliseconds of stage 1, 2, 3, 4 (with the step counter update), the
- * sort (counting, scan, scatter), and the whole step. */
+ * mean milliseconds of stage 1, 2, 3, 4 (which also moves every particle to
+ * its sorted place, and updates the step counter), the sort's counting and
+ * scan, and the whole step. */
 int fpic_particles_profile(fpic_pctx *ctx, int32_t nsteps, double *ms);
 
 /* Free the context's host objects and graphs (not the workspace). */

@@ -57,7 +57,7 @@ constexpr int ACC_DOUBLES = 6144;   // LDS of the deposit box accumulators (48 K
 constexpr int MAX_COPIES = 32;      // replicas of the box accumulator
 constexpr int kRedBlk = 256;        // blocks of the diagnostic reductions
 
-enum : int { PM_DEPOSIT = 5, PM_MOM_NU = 6, PM_MOM_NUBAR = 7 };
+enum : int { PM_DEPOSIT = 5, PM_MOM_NU = 6, PM_MOM_NUBAR = 7, PM_S4_SORT = 8 };
 
 struct PDesc {
     int32_t n[3];
@@ -202,7 +202,68 @@ __device__ __forceinline__ Box block_box(const int f[3], bool active, const int 
     return b;
 }
 
-// MODE 1..4: Runge-Kutta stages; PM_DEPOSIT: deposit the current state at
+// ---- redistribution: counting sort by cell ----------------------------
+// Sort key: the cell whose centre is the nearest one at or below the
+// particle along each axis (the linear stencil's first cell) at the start
+// of the current step; cells numbered x fastest.
+__device__ __forceinline__ int sort_key(const PDesc &S, int64_t i, double t)
+{
+    double w[3];
+    int cx = 0, cy = 0, cz;
+    axis_stencil<1>(gld(S.pos + 2 * S.np + i), gld(S.v + 2 * S.np + i), t, S.dx[2], S.n[2], &cz, w);
+    if (S.n[0] > 1 || S.n[1] > 1) {  // 3D boxes (1D boxes hold z positions only)
+        axis_stencil<1>(gld(S.pos + i), gld(S.v + i), t, S.dx[0], S.n[0], &cx, w);
+        axis_stencil<1>(gld(S.pos + S.np + i), gld(S.v + S.np + i), t, S.dx[1], S.n[1], &cy, w);
+    }
+    return (cz * S.n[1] + cy) * S.n[0] + cx;
+}
+
+// The keys of a workgroup's particles (nearly sorted) fall in a short range
+// of the periodic cell numbering: a histogram of that range in LDS takes the
+// per-particle atomics, and the workgroup adds one count per cell to the
+// global counters.  A workgroup whose range exceeds HIST_MAX cells uses
+// global atomics per particle.
+constexpr int HIST_MAX = 8192;
+
+struct KeyRange {
+    int ref, lo, len, off;
+};
+
+__device__ __forceinline__ KeyRange key_range(int key, bool active, int nc, int (*sred)[2], int *sref)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (threadIdx.x == 0)
+        *sref = key;
+    __syncthreads();
+    KeyRange r;
+    r.ref = *sref;
+    r.off = periodic_offset(key, r.ref, nc);
+    int lo = active ? r.off : INT_MAX, hi = active ? r.off : INT_MIN;
+#pragma unroll
+    for (int sh = 32; sh >= 1; sh >>= 1) {
+        lo = min(lo, __shfl_xor(lo, sh, 64));
+        hi = max(hi, __shfl_xor(hi, sh, 64));
+    }
+    if (lane == 0) {
+        sred[wave][0] = lo;
+        sred[wave][1] = hi;
+    }
+    __syncthreads();
+    lo = sred[0][0];
+    hi = sred[0][1];
+    for (int w = 1; w < NWAVE; w++) {
+        lo = min(lo, sred[w][0]);
+        hi = max(hi, sred[w][1]);
+    }
+    r.lo = lo;
+    r.len = hi - lo + 1;
+    return r;
+}
+
+// MODE 1..4: Runge-Kutta stages; PM_S4_SORT: stage 4 that also moves every
+// particle to its place in the cell order of the next step (the counts and
+// offsets come from sort_count_kernel and sort_scan_kernel beforehand), so a
+// sort needs no pass of its own; PM_DEPOSIT: deposit the current state at
 // the current time into the buffer stage 1 reads; PM_MOM_NU / PM_MOM_NUBAR:
 // deposit N rho or Nbar rhobar alone into outG (moment diagnostics).
 template <int MODE, int SH, bool D3>
@@ -210,6 +271,8 @@ __global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(SH == 
 pstage_kernel(const PDesc *__restrict__ dp, double *outG)
 {
     constexpr int SW = SH + 1;  // stencil cells per axis
+    constexpr bool RK = MODE <= 4 || MODE == PM_S4_SORT;
+    constexpr int STG = MODE == PM_S4_SORT ? 4 : MODE;  // Runge-Kutta stage
     __shared__ double acc[ACC_DOUBLES];
     __shared__ int sred[NWAVE][6];
     __shared__ int sref[3];
@@ -232,7 +295,7 @@ pstage_kernel(const PDesc *__restrict__ dp, double *outG)
     } else if (MODE == 3) {
         t_cur = stage_time(n, dt, 0.5);
         t_nxt = stage_time(n, dt, 1.0);
-    } else if (MODE == 4) {
+    } else if (STG == 4) {
         t_cur = stage_time(n, dt, 1.0);
         t_nxt = stage_time(n + 1, dt, 0.0);
     } else {
@@ -241,8 +304,8 @@ pstage_kernel(const PDesc *__restrict__ dp, double *outG)
 
     // grid buffers (selects, no indexing into the descriptor copy)
     double *Gin = nullptr, *Gout, *Gclr = nullptr;
-    if (MODE <= 4) {
-        const int r = (int)((4 * n + MODE - 1) % 3);
+    if (RK) {
+        const int r = (int)((4 * n + STG - 1) % 3);
         Gin = r == 0 ? S.G0 : (r == 1 ? S.G1 : S.G2);
         Gout = r == 0 ? S.G1 : (r == 1 ? S.G2 : S.G0);
         Gclr = r == 0 ? S.G2 : (r == 1 ? S.G0 : S.G1);
@@ -252,7 +315,7 @@ pstage_kernel(const PDesc *__restrict__ dp, double *outG)
     } else {
         Gout = outG;
     }
-    if (MODE <= 4) {
+    if (RK) {
         // clear the buffer the next stage deposits into (nothing reads or
         // writes it during this launch)
         const int64_t len = (int64_t)NG * S.ncell;
@@ -278,7 +341,7 @@ pstage_kernel(const PDesc *__restrict__ dp, double *outG)
     double gw[3][3] = {{1.0, 0.0, 0.0}, {1.0, 0.0, 0.0}, {1.0, 0.0, 0.0}};
     Box gb = {};
     bool g_lds = false;
-    if (MODE <= 4) {
+    if (RK) {
         axis_stencil<SH>(pz, vz, t_cur, S.dx[2], nz, &gf[2], gw[2]);
         if (D3) {
             axis_stencil<SH>(px, vx, t_cur, S.dx[0], nx, &gf[0], gw[0]);
@@ -302,7 +365,7 @@ pstage_kernel(const PDesc *__restrict__ dp, double *outG)
         }
     }
 
-    double X[9];
+    double X[9], Ynew[18];
 #pragma unroll
     for (int k = 0; k < 9; k++)
         X[k] = 0.0;
@@ -383,7 +446,7 @@ pstage_kernel(const PDesc *__restrict__ dp, double *outG)
 #pragma unroll
                 for (int k = 0; k < 18; k++)
                     y[k] = base[k] = Y[k];
-            } else if (MODE == 4) {
+            } else if (STG == 4) {
                 const double h6 = dt / 6.0;
                 double k1[18], k2[18], k3[18];
                 load_slope(S.K1, np, i, k1);
@@ -415,12 +478,14 @@ pstage_kernel(const PDesc *__restrict__ dp, double *outG)
             commutator(H, y, kk);
             commutator(Hb, y + 9, kk + 9);
             double yn[18];
-            if (MODE == 4) {
+            if (STG == 4) {
                 const double h6 = dt / 6.0;
 #pragma unroll
                 for (int k = 0; k < 18; k++) {
                     yn[k] = base[k] + h6 * kk[k];
-                    gst(S.Y + k * np + i, yn[k]);
+                    if (MODE == 4)
+                        gst(S.Y + k * np + i, yn[k]);
+                    Ynew[k] = yn[k];
                 }
             } else {
                 double *Ko = MODE == 1 ? S.K1 : (MODE == 2 ? S.K2 : S.K3);
@@ -524,6 +589,50 @@ pstage_kernel(const PDesc *__restrict__ dp, double *outG)
                     }
                 }
     }
+
+    if (MODE == PM_S4_SORT) {
+        // move the particle to its place in the next step's cell order:
+        // rank within the workgroup's particles of the same cell (LDS
+        // histogram in the deposit buffer), one reservation per cell
+        __shared__ int ksred[NWAVE][2];
+        __shared__ int ksref;
+        const int ncl = (int)nc;
+        const int key = active ? sort_key(S, i, t_nxt) : 0;
+        __syncthreads();  // the deposit box is no longer read
+        const KeyRange kr = key_range(key, active, ncl, ksred, &ksref);
+        int *hist = reinterpret_cast<int *>(acc);
+        int64_t j;
+        if (kr.len <= 2 * ACC_DOUBLES) {
+            for (int q = threadIdx.x; q < kr.len; q += BLK)
+                hist[q] = 0;
+            __syncthreads();
+            const int rank = active ? atomicAdd(&hist[kr.off - kr.lo], 1) : 0;
+            __syncthreads();
+            for (int q = threadIdx.x; q < kr.len; q += BLK)
+                if (hist[q])
+                    hist[q] = atomicAdd(S.cur + wrap_int(kr.ref + kr.lo + q, ncl), hist[q]);
+            __syncthreads();
+            j = active ? hist[kr.off - kr.lo] + rank : 0;
+        } else {
+            j = active ? atomicAdd(S.cur + key, 1) : 0;
+        }
+        if (active) {
+#pragma unroll
+            for (int k = 0; k < 18; k++)
+                gst(S.Y2 + k * np + j, Ynew[k]);
+            if (D3) {
+                gst(S.pos2 + j, px);
+                gst(S.pos2 + np + j, py);
+            }
+            gst(S.pos2 + 2 * np + j, pz);
+            gst(S.v2 + j, vx);
+            gst(S.v2 + np + j, vy);
+            gst(S.v2 + 2 * np + j, vz);
+            gst(S.wN2 + j, wN);
+            gst(S.wNb2 + j, wNb);
+            S.pid2[j] = S.pid[i];
+        }
+    }
 }
 
 __global__ void tick_kernel(const PDesc *dp)
@@ -552,63 +661,9 @@ __global__ void fill_i32(int32_t *p, int64_t n)
         p[q] = 0;
 }
 
-// ---- redistribution: counting sort by cell ----------------------------
-// Sort key: the cell whose centre is the nearest one at or below the
-// particle along each axis (the linear stencil's first cell) at the start
-// of the current step; cells numbered x fastest.
-__device__ __forceinline__ int sort_key(const PDesc &S, int64_t i, double t)
-{
-    int c[3] = {0, 0, 0};
-    double w[3];
-    const int ax0 = (S.n[0] > 1 || S.n[1] > 1) ? 0 : 2;  // 1D boxes: z only
-    for (int a = ax0; a < 3; a++)
-        axis_stencil<1>(gld(S.pos + a * S.np + i), gld(S.v + a * S.np + i), t, S.dx[a], S.n[a], &c[a], w);
-    return (c[2] * S.n[1] + c[1]) * S.n[0] + c[0];
-}
-
-// The keys of a workgroup's particles (nearly sorted) fall in a short range
-// of the periodic cell numbering: a histogram of that range in LDS takes the
-// per-particle atomics, and the workgroup adds one count per cell to the
-// global counters.  A workgroup whose range exceeds HIST_MAX cells uses
-// global atomics per particle.
-constexpr int HIST_MAX = 8192;
-
-struct KeyRange {
-    int ref, lo, len, off;
-};
-
-__device__ __forceinline__ KeyRange key_range(int key, bool active, int nc, int (*sred)[2], int *sref)
-{
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (threadIdx.x == 0)
-        *sref = key;
-    __syncthreads();
-    KeyRange r;
-    r.ref = *sref;
-    r.off = periodic_offset(key, r.ref, nc);
-    int lo = active ? r.off : INT_MAX, hi = active ? r.off : INT_MIN;
-#pragma unroll
-    for (int sh = 32; sh >= 1; sh >>= 1) {
-        lo = min(lo, __shfl_xor(lo, sh, 64));
-        hi = max(hi, __shfl_xor(hi, sh, 64));
-    }
-    if (lane == 0) {
-        sred[wave][0] = lo;
-        sred[wave][1] = hi;
-    }
-    __syncthreads();
-    lo = sred[0][0];
-    hi = sred[0][1];
-    for (int w = 1; w < NWAVE; w++) {
-        lo = min(lo, sred[w][0]);
-        hi = max(hi, sred[w][1]);
-    }
-    r.lo = lo;
-    r.len = hi - lo + 1;
-    return r;
-}
-
-__global__ void __launch_bounds__(BLK) sort_count_kernel(const PDesc *__restrict__ dp)
+// dstep = 1 counts the cells of the next step's start (before the stage 4
+// that moves the particles), 0 those of the current step.
+__global__ void __launch_bounds__(BLK) sort_count_kernel(const PDesc *__restrict__ dp, int dstep)
 {
     __shared__ int hist[HIST_MAX];
     __shared__ int sred[NWAVE][2];
@@ -617,7 +672,7 @@ __global__ void __launch_bounds__(BLK) sort_count_kernel(const PDesc *__restrict
     const int nc = (int)S.ncell;
     const int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
     const bool active = i < S.np;
-    const double t = stage_time(*S.step, S.dt, 0.0);
+    const double t = stage_time(*S.step + dstep, S.dt, 0.0);
     const int key = active ? sort_key(S, i, t) : 0;
     const KeyRange r = key_range(key, active, nc, sred, &sref);
     if (r.len <= HIST_MAX) {
@@ -950,6 +1005,7 @@ static void launch_mode_t(const fpic_pctx *c, int mode, const PDesc *dd, double 
     case 2: pstage_kernel<2, SH, D3><<<grid, blk, 0, s>>>(dd, out); break;
     case 3: pstage_kernel<3, SH, D3><<<grid, blk, 0, s>>>(dd, out); break;
     case 4: pstage_kernel<4, SH, D3><<<grid, blk, 0, s>>>(dd, out); break;
+    case PM_S4_SORT: pstage_kernel<PM_S4_SORT, SH, D3><<<grid, blk, 0, s>>>(dd, out); break;
     case PM_DEPOSIT: pstage_kernel<PM_DEPOSIT, SH, D3><<<grid, blk, 0, s>>>(dd, out); break;
     case PM_MOM_NU: pstage_kernel<PM_MOM_NU, SH, D3><<<grid, blk, 0, s>>>(dd, out); break;
     default: pstage_kernel<PM_MOM_NUBAR, SH, D3><<<grid, blk, 0, s>>>(dd, out); break;
@@ -967,21 +1023,38 @@ static void launch_mode(const fpic_pctx *c, int mode, const PDesc *dd, double *o
     }
 }
 
-static void launch_step(const fpic_pctx *c, int par, hipStream_t s)
-{
-    for (int m = 1; m <= 4; ++m)
-        launch_mode(c, m, c->d[par], nullptr, s);
-    tick_kernel<<<1, 64, 0, s>>>(c->d[par]);
-}
-
-// counting sort of the particles in set par into set 1 - par
-static void launch_sort(const fpic_pctx *c, int par, hipStream_t s)
+// cell counts and offsets of set par (dstep = 1: at the next step's start)
+static void launch_count_scan(const fpic_pctx *c, int par, int dstep, hipStream_t s)
 {
     const PDesc &H = c->h[par];
     const PDesc *dd = c->d[par];
     fill_i32<<<std::max<int64_t>(1, std::min<int64_t>(1024, (H.ncell + 255) / 256)), 256, 0, s>>>(H.cnt, H.ncell);
-    sort_count_kernel<<<c->nblk, BLK, 0, s>>>(dd);
+    sort_count_kernel<<<c->nblk, BLK, 0, s>>>(dd, dstep);
     sort_scan_kernel<<<1, 1024, 0, s>>>(dd);
+}
+
+// Stages 1-4 of one step on set par and the step counter; with sort_after,
+// stage 4 writes the particles into set 1 - par in the next step's cell
+// order (the caller flips the parity).
+static void launch_step(const fpic_pctx *c, int par, bool sort_after, hipStream_t s)
+{
+    for (int m = 1; m <= 3; ++m)
+        launch_mode(c, m, c->d[par], nullptr, s);
+    if (sort_after) {
+        launch_count_scan(c, par, 1, s);
+        launch_mode(c, PM_S4_SORT, c->d[par], nullptr, s);
+    } else {
+        launch_mode(c, 4, c->d[par], nullptr, s);
+    }
+    tick_kernel<<<1, 64, 0, s>>>(c->d[par]);
+}
+
+// counting sort of the particles in set par into set 1 - par, in a pass of
+// its own (after loading)
+static void launch_sort(const fpic_pctx *c, int par, hipStream_t s)
+{
+    const PDesc *dd = c->d[par];
+    launch_count_scan(c, par, 0, s);
     if (c->d3)
         sort_scatter_kernel<true><<<c->nblk, BLK, 0, s>>>(dd);
     else
@@ -992,8 +1065,7 @@ static int capture(fpic_pctx *c, int par, hipGraphExec_t *exec)
 {
     HIPCHECK(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
     for (int k = 0; k < c->spg; ++k)
-        launch_step(c, par, c->cap);
-    launch_sort(c, par, c->cap);
+        launch_step(c, par, k == c->spg - 1, c->cap);
     hipError_t err = hipGetLastError();
     hipGraph_t gr = nullptr;
     hipError_t e2 = hipStreamEndCapture(c->cap, &gr);
@@ -1173,8 +1245,7 @@ int fpic_particles_step(fpic_pctx *c, int64_t nsteps)
     }
     if (left > 0) {
         for (int64_t k = 0; k < left; ++k)
-            launch_step(c, c->par, c->stream);
-        launch_sort(c, c->par, c->stream);
+            launch_step(c, c->par, k == left - 1, c->stream);
         HIPCHECK(hipGetLastError());
         c->par ^= 1;
     }
@@ -1268,22 +1339,25 @@ int fpic_particles_profile(fpic_pctx *c, int32_t nsteps, double *ms)
     for (int n = 0; n < nsteps && !rc; ++n) {
         const int p = c->par;
         (void)hipEventRecord(ev[0], s);
-        for (int m = 1; m <= 4; ++m) {
+        for (int m = 1; m <= 3; ++m) {
             launch_mode(c, m, c->d[p], nullptr, s);
-            if (m == 4)
-                tick_kernel<<<1, 64, 0, s>>>(c->d[p]);
             (void)hipEventRecord(ev[m], s);
         }
-        launch_sort(c, p, s);
+        launch_count_scan(c, p, 1, s);
+        (void)hipEventRecord(ev[4], s);
+        launch_mode(c, PM_S4_SORT, c->d[p], nullptr, s);
+        tick_kernel<<<1, 64, 0, s>>>(c->d[p]);
         (void)hipEventRecord(ev[5], s);
         c->par ^= 1;
         hipError_t err = hipGetLastError();
         if (err == hipSuccess)
             err = hipEventSynchronize(ev[5]);
+        // intervals: stages 1-3, count and scan, stage 4 (with the move)
+        const int slot[5] = {0, 1, 2, 4, 3};
         for (int k = 0; k < 5 && err == hipSuccess; ++k) {
             float t = 0.f;
             err = hipEventElapsedTime(&t, ev[k], ev[k + 1]);
-            acc[k] += t;
+            acc[slot[k]] += t;
         }
         float tt = 0.f;
         if (err == hipSuccess)
