@@ -616,7 +616,9 @@ pstage_kernel(const PDesc *__restrict__ dp, double *outG)
         } else {
             j = active ? atomicAdd(S.cur + key, 1) : 0;
         }
-        if (active) {
+        // j < np whenever the counts were taken from the same keys (they are:
+        // same inputs, same arithmetic); the guard keeps any mismatch in bounds
+        if (active && j >= 0 && j < np) {
 #pragma unroll
             for (int k = 0; k < 18; k++)
                 gst(S.Y2 + k * np + j, Ynew[k]);
@@ -748,7 +750,7 @@ __global__ void __launch_bounds__(BLK) sort_scatter_kernel(const PDesc *__restri
     } else {
         base = active ? atomicAdd(S.cur + key, 1) : 0;
     }
-    if (!active)
+    if (!active || base < 0 || base >= np)
         return;
     const int64_t j = base;
 #pragma unroll
