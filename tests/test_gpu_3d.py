@@ -63,12 +63,15 @@ def test_3d_parity(torch_dev, ncell, ndir, tuning, step0):
 
 
 def test_3d_full_size_homogeneous(torch_dev):
-    """The full 64^3 x 92 box (24,117,248 particles) in the benchmark's launch
-    shape, started from a state that is the same in every cell: the method
-    then reduces exactly to one cell holding the 92 directions, which the
-    reference computes; every particle of the GPU run is compared with it."""
+    """The full 64^3 x 92 box (24,117,248 particles), in the launch shape the
+    benchmark times (autotuned on the device, as bench.py does) and in the
+    built-in one, started from a state that is the same in every cell: the
+    method then reduces exactly to one cell holding the 92 directions, which
+    the reference computes; every particle of the GPU run is compared with
+    it."""
     import torch
-    from paper_2101_02745_amd.sim import Sim
+    from paper_2101_02745_amd._lib import HostConfig
+    from paper_2101_02745_amd.sim import Sim, autotune
     w = I.workload("3d_64x92")
     one = I.Workload(name="one", ncell=(1, 1, 1), length=w.dx, ndir=w.ndir, dt=w.dt, steps=0,
                      f=w.f, fbar=w.fbar, nbar_over_n=w.nbar_over_n, nhat=w.nhat, seed=7,
@@ -77,15 +80,19 @@ def test_3d_full_size_homogeneous(torch_dev):
     P1 = Problem.from_workload(one)
     nsteps = 6
     ref = P1.step(s1, nsteps)
-    sim = Sim.from_workload(w)
-    s_full = torch.from_numpy(s1).cuda().expand(18, w.ndir, w.ncell_total).contiguous()
-    sim.set_state(s_full)
-    sim.step(nsteps)
-    got = sim.get_state()
-    for k in range(18):
-        dev = (got[k] - torch.from_numpy(ref[k]).cuda()).abs().max().item()
-        assert dev <= 1e-12 * max(1.0, np.abs(ref).max()), (k, dev)
-    assert sim.check(1e-12) < 1e-13
+    tuned, _ = autotune([HostConfig.from_workload(w)])
+    for tuning in (tuned, None):
+        sim = Sim.from_workload(w, tuning=tuning)
+        s_full = torch.from_numpy(s1).cuda().expand(18, w.ndir, w.ncell_total).contiguous()
+        sim.set_state(s_full)
+        sim.step(nsteps)
+        got = sim.get_state()
+        for k in range(18):
+            dev = (got[k] - torch.from_numpy(ref[k]).cuda()).abs().max().item()
+            assert dev <= 1e-12 * max(1.0, np.abs(ref).max()), (k, dev, tuning)
+        assert sim.check(1e-12) < 1e-13
+        del sim, got, s_full
+        torch.cuda.empty_cache()
 
 
 def test_3d_full_size_lepton_number(torch_dev):

@@ -213,12 +213,23 @@ def test_two_beam_growth_on_gpu(torch_dev):
 
 
 def test_full_size_1d_2048x378(torch_dev):
-    """The benchmark's workload at full size (774,144 particles) in the
-    benchmark's launch shape: every output of two steps against the
+    """The benchmark's workload at full size (774,144 particles), in the
+    launch shape the benchmark times (autotuned on the device, as bench.py
+    does) and in the built-in one: every output of two steps against the
     reference."""
+    from paper_2101_02745_amd._lib import HostConfig
+    from paper_2101_02745_amd.sim import autotune
     w = I.workload("1d_2048x378")
-    _, _, got, ref = run_pair(w, 2)
-    assert_parity(got, ref, what="2048x378")
+    tuned, _ = autotune([HostConfig.from_workload(w)])
+    ref = None
+    for tuning in (tuned, None):
+        sim, P = make(w, tuning=tuning)
+        s0 = w.state0()
+        sim.set_state(s0)
+        sim.step(2)
+        if ref is None:
+            ref = P.step(s0, 2)
+        assert_parity(sim.get_state().cpu().numpy(), ref, what=f"2048x378 {tuning}")
 
 
 def test_batch_matches_single_runs(torch_dev):
