@@ -156,12 +156,15 @@ def test_lepton_number_conserved(torch_dev):
     assert np.abs(t1[0][1] - t0[0][1]) > 1e-6 * np.abs(N).sum()   # flavor moved
 
 
-def test_full_size_box(torch_dev):
-    """The 2048-cell box with 774,144 particles at random positions, two
-    steps (one sort in between), every element against the reference."""
+@pytest.mark.parametrize("sort_every,nsteps,chunks", [(1, 1, 2), (4, 4, 1)])
+def test_full_size_box(torch_dev, sort_every, nsteps, chunks):
+    """The 2048-cell box with 774,144 particles at random positions, every
+    element against the reference: two steps sorting after each, and four
+    steps sorting after the fourth as the benchmark does (three plain
+    stage-4 launches, one sorting one)."""
     w = I.particle_workload("1d_2048x378_random")
-    _, _, got, ref = run(w, 1, sort_every=1, chunks=2)
-    assert_parity(got, ref, what="1d_2048x378_random")
+    _, _, got, ref = run(w, nsteps, sort_every=sort_every, chunks=chunks)
+    assert_parity(got, ref, what=f"1d_2048x378_random, sort every {sort_every}")
 
 
 def test_rejects_bad_particles(torch_dev):
