@@ -246,11 +246,12 @@ stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ si
                     for (int k = 0; k < 18; k++)
                         y[k] = base[k] = Y[k];
                 } else if (MODE == M_S4) {
+                    // last reads of the three slopes: streaming loads
                     const double h6 = dt / 6.0;
                     double k1[18], k2[18], k3[18];
-                    load_slope(S.K1, np, p, k1);
-                    load_slope(S.K2, np, p, k2);
-                    load_slope(S.K3, np, p, k3);
+                    load_slope<true>(S.K1, np, p, k1);
+                    load_slope<true>(S.K2, np, p, k2);
+                    load_slope<true>(S.K3, np, p, k3);
 #pragma unroll
                     for (int k = 0; k < 18; k++) {
                         y[k] = Y[k] + dt * k3[k];
@@ -284,12 +285,18 @@ stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ si
 #pragma unroll
                     for (int k = 0; k < 18; k++) {
                         yn[k] = base[k] + h6 * kk[k];
-                        gst(S.Yout + k * np + p, yn[k]);
+                        gst_nt(S.Yout + k * np + p, yn[k]);
                     }
                 } else {
                     double *Ko = (MODE == M_S1) ? S.K1 : (MODE == M_S2) ? S.K2 : S.K3;
                     const double an = (MODE == M_S3) ? dt : 0.5 * dt;
-                    store_slope(Ko, np, p, kk);
+                    // cache policy of the slope stores (measured on the
+                    // 2048-cell, 378-direction box): k1 and k3 are read
+                    // again by the next kernel and stay cached; k2 streams
+                    if (MODE == M_S2)
+                        store_slope<true>(Ko, np, p, kk);
+                    else
+                        store_slope<false>(Ko, np, p, kk);
 #pragma unroll
                     for (int k = 0; k < 18; k++)
                         yn[k] = base[k] + an * kk[k];

@@ -84,12 +84,14 @@ __device__ __forceinline__ void axis_shift(double v, double t, double dx, int n,
 // the negated sums of the next two and are not stored).
 __device__ __forceinline__ int kslot(int c) { return c < 9 ? c - 1 : c - 2; }
 
+// NT: streaming (nontemporal) loads, for the last read of a slope
+template <bool NT = false>
 __device__ __forceinline__ void load_slope(const double *K, int64_t np, int64_t p, bool active, double k[18])
 {
 #pragma unroll
     for (int c = 1; c < 18; c++)
         if (c != 9)
-            k[c] = active ? gld(K + kslot(c) * np + p) : 0.0;
+            k[c] = active ? (NT ? fpic::gld_nt(K + kslot(c) * np + p) : gld(K + kslot(c) * np + p)) : 0.0;
     k[0] = -(k[1] + k[2]);
     k[9] = -(k[10] + k[11]);
 }
@@ -220,9 +222,9 @@ particle3d_kernel(const Desc3 *__restrict__ dp, int dpw, int nitems)
             } else if (MODE == 4) {
                 const double h6 = dt / 6.0;
                 double k1[18], k2[18], k3[18];
-                load_slope(S.K1, S.np, p, active, k1);
-                load_slope(S.K2, S.np, p, active, k2);
-                load_slope(S.K3, S.np, p, active, k3);
+                load_slope<true>(S.K1, S.np, p, active, k1);
+                load_slope<true>(S.K2, S.np, p, active, k2);
+                load_slope<true>(S.K3, S.np, p, active, k3);
 #pragma unroll
                 for (int k = 0; k < 18; k++) {
                     yv[k] = Y[k] + dt * k3[k];
@@ -253,15 +255,19 @@ particle3d_kernel(const Desc3 *__restrict__ dp, int dpw, int nitems)
                 for (int k = 0; k < 18; k++) {
                     yn[k] = base[k] + h6 * kk[k];
                     if (active)
-                        gst(S.Y + k * S.np + p, yn[k]);
+                        fpic::gst_nt(S.Y + k * S.np + p, yn[k]);
                 }
             } else {
                 double *Ko = (MODE == 1) ? S.K1 : (MODE == 2) ? S.K2 : S.K3;
                 const double an = (MODE == 3) ? dt : 0.5 * dt;
 #pragma unroll
                 for (int k = 0; k < 18; k++) {
-                    if (active && k != 0 && k != 9)
-                        gst(Ko + kslot(k) * S.np + p, kk[k]);
+                    if (active && k != 0 && k != 9) {
+                        if (MODE == 2)  // k2 streams; k1 and k3 stay cached (as in 1D)
+                            fpic::gst_nt(Ko + kslot(k) * S.np + p, kk[k]);
+                        else
+                            gst(Ko + kslot(k) * S.np + p, kk[k]);
+                    }
                     yn[k] = base[k] + an * kk[k];
                 }
             }
@@ -584,12 +590,12 @@ particle3q_kernel(const Desc3 *__restrict__ dp, int dpw, int nitems)
                 // registers than holding all three)
                 const double h6 = dt / 6.0;
                 double ks[18], kt[18];
-                load_slope(S.K1, S.np, p, active, ks);
-                load_slope(S.K2, S.np, p, active, kt);
+                load_slope<true>(S.K1, S.np, p, active, ks);
+                load_slope<true>(S.K2, S.np, p, active, kt);
 #pragma unroll
                 for (int k = 0; k < 18; k++)
                     ks[k] = ks[k] + 2.0 * kt[k];
-                load_slope(S.K3, S.np, p, active, kt);
+                load_slope<true>(S.K3, S.np, p, active, kt);
 #pragma unroll
                 for (int k = 0; k < 18; k++) {
                     yv[k] = Y[k] + dt * kt[k];
@@ -619,15 +625,19 @@ particle3q_kernel(const Desc3 *__restrict__ dp, int dpw, int nitems)
                 for (int k = 0; k < 18; k++) {
                     yn[k] = base[k] + h6 * kk[k];
                     if (active)
-                        gst(S.Y + k * S.np + p, yn[k]);
+                        fpic::gst_nt(S.Y + k * S.np + p, yn[k]);
                 }
             } else {
                 double *Ko = (MODE == 1) ? S.K1 : (MODE == 2) ? S.K2 : S.K3;
                 const double an = (MODE == 3) ? dt : 0.5 * dt;
 #pragma unroll
                 for (int k = 0; k < 18; k++) {
-                    if (active && k != 0 && k != 9)
-                        gst(Ko + kslot(k) * S.np + p, kk[k]);
+                    if (active && k != 0 && k != 9) {
+                        if (MODE == 2)  // k2 streams; k1 and k3 stay cached (as in 1D)
+                            fpic::gst_nt(Ko + kslot(k) * S.np + p, kk[k]);
+                        else
+                            gst(Ko + kslot(k) * S.np + p, kk[k]);
+                    }
                     yn[k] = base[k] + an * kk[k];
                 }
             }

@@ -86,28 +86,40 @@ __device__ __forceinline__ void commutator(const double h[9], const double r[9],
 typedef __attribute__((address_space(1))) double gdouble;
 __device__ __forceinline__ double gld(const double *p) { return *(const gdouble *)p; }
 __device__ __forceinline__ void gst(double *p, double v) { *(gdouble *)p = v; }
+// Nontemporal forms (streaming cache policy) for data not re-read soon.
+__device__ __forceinline__ double gld_nt(const double *p)
+{
+    return __builtin_nontemporal_load((const gdouble *)p);
+}
+__device__ __forceinline__ void gst_nt(double *p, double v) { __builtin_nontemporal_store(v, (gdouble *)p); }
 
 // Slopes in memory: NK reals per particle, component c of the packed 18 at
 // slot c - 1 (c = 1..8) or c - 2 (c = 10..17); components 0 and 9 are the
 // negated sums of the next two.
 __device__ __forceinline__ int kslot(int c) { return c < 9 ? c - 1 : c - 2; }
 
+template <bool NT = false>
 __device__ __forceinline__ void load_slope(const double *K, int64_t np, int64_t p, double k[18])
 {
 #pragma unroll
     for (int c = 1; c < 18; c++)
         if (c != 9)
-            k[c] = gld(K + kslot(c) * np + p);
+            k[c] = NT ? gld_nt(K + kslot(c) * np + p) : gld(K + kslot(c) * np + p);
     k[0] = -(k[1] + k[2]);
     k[9] = -(k[10] + k[11]);
 }
 
+template <bool NT = false>
 __device__ __forceinline__ void store_slope(double *K, int64_t np, int64_t p, const double k[18])
 {
 #pragma unroll
     for (int c = 1; c < 18; c++)
-        if (c != 9)
-            gst(K + kslot(c) * np + p, k[c]);
+        if (c != 9) {
+            if (NT)
+                gst_nt(K + kslot(c) * np + p, k[c]);
+            else
+                gst(K + kslot(c) * np + p, k[c]);
+        }
 }
 
 }  // namespace fpic

@@ -449,9 +449,9 @@ pstage_kernel(const PDesc *__restrict__ dp, double *outG)
             } else if (STG == 4) {
                 const double h6 = dt / 6.0;
                 double k1[18], k2[18], k3[18];
-                load_slope(S.K1, np, i, k1);
-                load_slope(S.K2, np, i, k2);
-                load_slope(S.K3, np, i, k3);
+                load_slope<true>(S.K1, np, i, k1);
+                load_slope<true>(S.K2, np, i, k2);
+                load_slope<true>(S.K3, np, i, k3);
 #pragma unroll
                 for (int k = 0; k < 18; k++) {
                     y[k] = Y[k] + dt * k3[k];
@@ -484,13 +484,16 @@ pstage_kernel(const PDesc *__restrict__ dp, double *outG)
                 for (int k = 0; k < 18; k++) {
                     yn[k] = base[k] + h6 * kk[k];
                     if (MODE == 4)
-                        gst(S.Y + k * np + i, yn[k]);
+                        fpic::gst_nt(S.Y + k * np + i, yn[k]);
                     Ynew[k] = yn[k];
                 }
             } else {
                 double *Ko = MODE == 1 ? S.K1 : (MODE == 2 ? S.K2 : S.K3);
                 const double an = MODE == 3 ? dt : 0.5 * dt;
-                store_slope(Ko, np, i, kk);
+                if (MODE == 2)  // k2 streams; k1 and k3 stay cached
+                    store_slope<true>(Ko, np, i, kk);
+                else
+                    store_slope<false>(Ko, np, i, kk);
 #pragma unroll
                 for (int k = 0; k < 18; k++)
                     yn[k] = base[k] + an * kk[k];
