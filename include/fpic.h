@@ -89,7 +89,13 @@ typedef struct fpic_tuning {
                                 (1D boxes and batches); 1, 2, 4 or 8 (3D) */
     int32_t dirs_per_wave;   /* directions each wave sweeps, >= 1 */
     int32_t steps_per_graph; /* steps captured in one hipGraph, >= 1 */
-    int32_t reserved;
+    int32_t cache_policy;    /* 1D boxes and batches: 1 default caching; 2
+                                streaming (nontemporal) loads and stores for
+                                the data a stage does not read again soon,
+                                which pays when one box's arrays overflow the
+                                256 MB Infinity Cache; 0 chooses by size
+                                (streaming for a single box of >= 64 MB of
+                                state).  3D boxes always stream. */
 } fpic_tuning;
 
 typedef struct fpic_ctx fpic_ctx;

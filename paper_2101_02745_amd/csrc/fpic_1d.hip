@@ -86,10 +86,15 @@ __device__ __forceinline__ int pmod_dbl(double i, int n)
     return (int)r;
 }
 
+// NT: streaming (nontemporal) cache policy for the data a stage does not
+// read again soon (the last reads of the slopes in stage 4, the new state,
+// k2); the default policy keeps everything cacheable.  Streaming pays when
+// the arrays overflow the Infinity Cache (a large single box), not for
+// smaller working sets (chosen per context, see fpic_tuning.cache_policy).
 // SH: shape-function order, 1 (linear) or 2 (quadratic).  The staged grid
 // tile holds cells tile*64 - SH .. tile*64 + 64 + SH; the quadratic deposit
 // reaches one cell left of the tile and two right of it (edge partials).
-template <int MODE, int SH>
+template <int MODE, int SH, bool NT>
 __global__ void __launch_bounds__(MAX_WAVES * TILE)
 stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ sims, int max_dpw)
 {
@@ -246,12 +251,12 @@ stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ si
                     for (int k = 0; k < 18; k++)
                         y[k] = base[k] = Y[k];
                 } else if (MODE == M_S4) {
-                    // last reads of the three slopes: streaming loads
+                    // last reads of the three slopes
                     const double h6 = dt / 6.0;
                     double k1[18], k2[18], k3[18];
-                    load_slope<true>(S.K1, np, p, k1);
-                    load_slope<true>(S.K2, np, p, k2);
-                    load_slope<true>(S.K3, np, p, k3);
+                    load_slope<NT>(S.K1, np, p, k1);
+                    load_slope<NT>(S.K2, np, p, k2);
+                    load_slope<NT>(S.K3, np, p, k3);
 #pragma unroll
                     for (int k = 0; k < 18; k++) {
                         y[k] = Y[k] + dt * k3[k];
@@ -285,18 +290,18 @@ stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ si
 #pragma unroll
                     for (int k = 0; k < 18; k++) {
                         yn[k] = base[k] + h6 * kk[k];
-                        gst_nt(S.Yout + k * np + p, yn[k]);
+                        if (NT)
+                            gst_nt(S.Yout + k * np + p, yn[k]);
+                        else
+                            gst(S.Yout + k * np + p, yn[k]);
                     }
                 } else {
                     double *Ko = (MODE == M_S1) ? S.K1 : (MODE == M_S2) ? S.K2 : S.K3;
                     const double an = (MODE == M_S3) ? dt : 0.5 * dt;
-                    // cache policy of the slope stores (measured on the
-                    // 2048-cell, 378-direction box): k1 and k3 are read
-                    // again by the next kernel and stay cached; k2 streams
-                    if (MODE == M_S2)
-                        store_slope<true>(Ko, np, p, kk);
-                    else
-                        store_slope<false>(Ko, np, p, kk);
+                    // with streaming, k2 streams; k1 and k3, read again by
+                    // the very next kernel, stay cached (measured on the
+                    // 2048-cell, 378-direction box)
+                    store_slope<NT && MODE == M_S2>(Ko, np, p, kk);
 #pragma unroll
                     for (int k = 0; k < 18; k++)
                         yn[k] = base[k] + an * kk[k];
@@ -1033,32 +1038,34 @@ size_t stage1d_smem_bytes(int waves, int max_dpw, int shape)
     return (gslot + dpg * 9 * ne + dpg * 2) * sizeof(double) + dpg * 2 * sizeof(int);
 }
 
-template <int SH>
+template <int SH, bool NT>
 static hipError_t launch_stage1d_sh(int mode, const WorkItem *work, int nwork, const SimDesc *sims,
                                     int waves, int max_dpw, hipStream_t s)
 {
     const dim3 grid(nwork), block(waves * TILE);
     const size_t smem = stage1d_smem_bytes(waves, max_dpw, SH);
     switch (mode) {
-    case M_S1: stage1d_kernel<M_S1, SH><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
-    case M_S2: stage1d_kernel<M_S2, SH><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
-    case M_S3: stage1d_kernel<M_S3, SH><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
-    case M_S4: stage1d_kernel<M_S4, SH><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
-    case M_DEPOSIT: stage1d_kernel<M_DEPOSIT, SH><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
-    case M_MOM_NU: stage1d_kernel<M_MOM_NU, SH><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
-    case M_MOM_NUBAR: stage1d_kernel<M_MOM_NUBAR, SH><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
+    case M_S1: stage1d_kernel<M_S1, SH, NT><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
+    case M_S2: stage1d_kernel<M_S2, SH, NT><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
+    case M_S3: stage1d_kernel<M_S3, SH, NT><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
+    case M_S4: stage1d_kernel<M_S4, SH, NT><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
+    case M_DEPOSIT: stage1d_kernel<M_DEPOSIT, SH, false><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
+    case M_MOM_NU: stage1d_kernel<M_MOM_NU, SH, false><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
+    case M_MOM_NUBAR: stage1d_kernel<M_MOM_NUBAR, SH, false><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_stage1d(int mode, const WorkItem *work, int nwork, const SimDesc *sims,
-                          int waves, int max_dpw, int shape, hipStream_t s)
+                          int waves, int max_dpw, int shape, bool stream_policy, hipStream_t s)
 {
     if (shape == 2)
-        return launch_stage1d_sh<2>(mode, work, nwork, sims, waves, max_dpw, s);
+        return stream_policy ? launch_stage1d_sh<2, true>(mode, work, nwork, sims, waves, max_dpw, s)
+                             : launch_stage1d_sh<2, false>(mode, work, nwork, sims, waves, max_dpw, s);
     if (shape == 1)
-        return launch_stage1d_sh<1>(mode, work, nwork, sims, waves, max_dpw, s);
+        return stream_policy ? launch_stage1d_sh<1, true>(mode, work, nwork, sims, waves, max_dpw, s)
+                             : launch_stage1d_sh<1, false>(mode, work, nwork, sims, waves, max_dpw, s);
     return hipErrorInvalidValue;
 }
 

@@ -96,8 +96,10 @@ struct RedItem {
 };
 
 // Launchers (fpic_1d.hip).
+// stream_policy: streaming cache policy for the data a stage does not read
+// again soon (large boxes), else the default policy
 hipError_t launch_stage1d(int mode, const WorkItem *work, int nwork, const SimDesc *sims,
-                          int waves, int max_dpw, int shape, hipStream_t s);
+                          int waves, int max_dpw, int shape, bool stream_policy, hipStream_t s);
 hipError_t launch_reduce1d(const RedItem *items, int nitems, const SimDesc *sims, int which,
                            double *override_out, int tick, hipStream_t s);
 // adjoint kernels: kind 4 = sources of stage 4 and their deposit; kind 3, 2,

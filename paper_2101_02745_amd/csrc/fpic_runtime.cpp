@@ -65,6 +65,7 @@ struct SimPlan {
 
 struct Plan {
     int nsim = 0, waves = 0, max_dpw = 0, spg = 0, shape = 1;
+    bool nt = false;  // streaming cache policy in the stage kernels
     std::vector<SimPlan> sims;
     size_t o_desc = 0, o_work = 0, o_red = 0, o_scratch = 0, total = 0;
     int nwork = 0, nred = 0;
@@ -152,6 +153,18 @@ int make_plan(int nsim, const fpic_config *cfgs, const fpic_tuning *tune, Plan &
     P.spg = (tune && tune->steps_per_graph) ? tune->steps_per_graph : 8;
     if (P.spg < 1 || P.spg > 256)
         return fail(FPIC_EINVAL, "steps_per_graph must be in 1..256");
+    const int policy = tune ? tune->cache_policy : 0;
+    if (policy < 0 || policy > 2)
+        return fail(FPIC_EINVAL, "cache_policy must be 0, 1 or 2");
+    if (policy == 0) {
+        // streaming pays when one box's arrays overflow the 256 MB Infinity
+        // Cache (measured: the 2048 x 378 box gains 14%, a 512 x 128 box and
+        // the 64-box batch lose 2-4%)
+        const int64_t np0 = (int64_t)cfgs[0].ncell[2] * cfgs[0].ndir;
+        P.nt = nsim == 1 && np0 * 18 * (int64_t)sizeof(double) >= (int64_t)64 << 20;
+    } else {
+        P.nt = policy == 2;
+    }
     int64_t wavedirs = 0;
     for (int i = 0; i < nsim; ++i)
         wavedirs += (int64_t)((cfgs[i].ncell[2] + TILE - 1) / TILE) * cfgs[i].ndir;
@@ -242,7 +255,7 @@ int capture_steps(fpic_batch *b, int nsteps, hipGraphExec_t *exec)
     hipError_t err = hipSuccess;
     for (int s = 0; s < nsteps && err == hipSuccess; ++s)
         for (int st = M_S1; st <= M_S4 && err == hipSuccess; ++st) {
-            err = launch_stage1d(st, b->dwork, P.nwork, b->ddesc, P.waves, P.max_dpw, P.shape, b->cap);
+            err = launch_stage1d(st, b->dwork, P.nwork, b->ddesc, P.waves, P.max_dpw, P.shape, P.nt, b->cap);
             if (err == hipSuccess)
                 err = launch_reduce1d(b->dred, P.nred, b->ddesc, st, nullptr,
                                       st == M_S4 ? 1 : 0, b->cap);
@@ -481,7 +494,7 @@ int batch_set_state(fpic_batch *b, int sim, const double *state, int64_t step0)
     int off, n, roff, rn;
     sim_work(b, sim, &off, &n, &roff, &rn);
     HIPCHECK(launch_stage1d(M_DEPOSIT, b->dwork + off, n, b->ddesc, b->plan.waves, b->plan.max_dpw, b->plan.shape,
-                            b->stream));
+                            b->plan.nt, b->stream));
     HIPCHECK(launch_reduce1d(b->dred + roff, rn, b->ddesc, 0, nullptr, 0, b->stream));
     b->state_set[sim] = true;
     return FPIC_OK;
@@ -670,9 +683,9 @@ int fpic_moments(fpic_ctx *c, double *out)
     int off, n, roff, rn;
     sim_work(b, 0, &off, &n, &roff, &rn);
     const int nc = b->plan.sims[0].ncell;
-    HIPCHECK(launch_stage1d(M_MOM_NU, b->dwork + off, n, b->ddesc, b->plan.waves, b->plan.max_dpw, b->plan.shape, b->stream));
+    HIPCHECK(launch_stage1d(M_MOM_NU, b->dwork + off, n, b->ddesc, b->plan.waves, b->plan.max_dpw, b->plan.shape, b->plan.nt, b->stream));
     HIPCHECK(launch_reduce1d(b->dred + roff, rn, b->ddesc, RED_OUT, out, 0, b->stream));
-    HIPCHECK(launch_stage1d(M_MOM_NUBAR, b->dwork + off, n, b->ddesc, b->plan.waves, b->plan.max_dpw, b->plan.shape, b->stream));
+    HIPCHECK(launch_stage1d(M_MOM_NUBAR, b->dwork + off, n, b->ddesc, b->plan.waves, b->plan.max_dpw, b->plan.shape, b->plan.nt, b->stream));
     HIPCHECK(launch_reduce1d(b->dred + roff, rn, b->ddesc, RED_OUT, out + (size_t)NG * nc, 0, b->stream));
     return FPIC_OK;
 }
@@ -770,7 +783,7 @@ int fpic_profile(fpic_ctx *c, int32_t nsteps, double *ms)
     for (int n = 0; n < nsteps && !rc; ++n) {
         hipError_t err = hipEventRecord(ev[0], b->stream);
         for (int st = M_S1; st <= M_S4 && err == hipSuccess; ++st) {
-            err = launch_stage1d(st, b->dwork, P.nwork, b->ddesc, P.waves, P.max_dpw, P.shape, b->stream);
+            err = launch_stage1d(st, b->dwork, P.nwork, b->ddesc, P.waves, P.max_dpw, P.shape, P.nt, b->stream);
             if (err == hipSuccess)
                 err = hipEventRecord(ev[2 * st - 1], b->stream);
             if (err == hipSuccess)
@@ -873,7 +886,7 @@ int adj_graph(fpic_batch *b, bool reverse, int len, hipGraphExec_t *out)
         rc = capture(b->cap, [&]() -> hipError_t {
             for (int j = 0; j < len; ++j)
                 for (int st = M_S1; st <= M_S4; ++st) {
-                    hipError_t e = launch_stage1d(st, b->dwork, P.nwork, F + j, P.waves, P.max_dpw, P.shape, b->cap);
+                    hipError_t e = launch_stage1d(st, b->dwork, P.nwork, F + j, P.waves, P.max_dpw, P.shape, P.nt, b->cap);
                     if (e == hipSuccess)
                         e = launch_reduce1d(b->dred, P.nred, F + j, st, nullptr, st == M_S4 ? 1 : 0, b->cap);
                     if (e != hipSuccess)
@@ -1042,7 +1055,7 @@ int fpic_adjoint_backward(fpic_ctx *c, const double *dLdy_end, double *dLdy0, do
         // states, slopes and moment grids
         HIPCHECK(hipMemcpyAsync(segY, ckpt + st * seg, sizeof(double) * st, hipMemcpyDeviceToDevice, s));
         HIPCHECK(launch_set_step(F, 0, 1, n0, s));
-        HIPCHECK(launch_stage1d(M_DEPOSIT, b->dwork + off, n, F, P.waves, P.max_dpw, P.shape, s));
+        HIPCHECK(launch_stage1d(M_DEPOSIT, b->dwork + off, n, F, P.waves, P.max_dpw, P.shape, P.nt, s));
         HIPCHECK(launch_reduce1d(b->dred + roff, rn, F, 0, nullptr, 0, s));
         hipGraphExec_t g = nullptr;
         int rc = adj_graph(b, false, len, &g);
@@ -1078,6 +1091,61 @@ int fpic_adjoint_backward(fpic_ctx *c, const double *dLdy_end, double *dLdy0, do
 
 extern "C" {
 // ------------------------------------------------------------- autotuning
+// Milliseconds per step of one candidate launch shape (or < 0 when it does
+// not fit the workspace or makes too many partial sums).
+static int time_candidate(int nsim, const fpic_config *cfgs, const fpic_tuning &t, void *workspace,
+                          size_t bytes, fpic_stream stream, double *ms_out)
+{
+    *ms_out = -1.0;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Plan P;
+    if (make_plan(nsim, cfgs, &t, P))
+        return fail(FPIC_EINVAL, g_err);
+    if (P.total > bytes)
+        return FPIC_OK;
+    // skip shapes whose partial sums would dwarf the grid
+    for (auto &sp : P.sims)
+        if (sp.ngroup > 96)
+            return FPIC_OK;
+    fpic_batch *b = nullptr;
+    int rc = batch_build(nsim, cfgs, &t, workspace, bytes, stream, &b);
+    if (rc)
+        return rc;
+    for (int i = 0; i < nsim; ++i) {
+        hipError_t e = launch_fill_state(b->ddesc, i, s);
+        if (e != hipSuccess) {
+            fpic_batch_destroy(b);
+            return fail(FPIC_EHIP, hipGetErrorString(e));
+        }
+        int off, n, roff, rn;
+        sim_work(b, i, &off, &n, &roff, &rn);
+        (void)launch_stage1d(M_DEPOSIT, b->dwork + off, n, b->ddesc, P.waves, P.max_dpw, P.shape, P.nt, s);
+        (void)launch_reduce1d(b->dred + roff, rn, b->ddesc, 0, nullptr, 0, s);
+        b->state_set[i] = true;
+    }
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    int rc2 = batch_step(b, 8);
+    (void)hipEventRecord(e0, s);
+    const int nrep = 16;
+    if (!rc2)
+        rc2 = batch_step(b, nrep);
+    (void)hipEventRecord(e1, s);
+    hipError_t es = hipEventSynchronize(e1);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    fpic_batch_destroy(b);
+    if (rc2)
+        return rc2;
+    if (es != hipSuccess)
+        return fail(FPIC_EHIP, hipGetErrorString(es));
+    *ms_out = ms / nrep;
+    return FPIC_OK;
+}
+
 int fpic_autotune(int32_t nsim, const fpic_config *cfgs, void *workspace, size_t bytes,
                   fpic_stream stream, fpic_tuning *best, double *ms_per_step)
 {
@@ -1085,62 +1153,21 @@ int fpic_autotune(int32_t nsim, const fpic_config *cfgs, void *workspace, size_t
         return fail(FPIC_EINVAL, "best is null");
     if (nsim == 1 && cfgs && !is_1d(cfgs[0]))
         return fpic3d::autotune(cfgs[0], workspace, bytes, stream, best, ms_per_step);
-    hipStream_t s = static_cast<hipStream_t>(stream);
     double best_ms = 1e300;
     fpic_tuning bt{};
     int tried = 0;
+    // launch shapes with the size-chosen cache policy, then the other two
+    // policies for the best shape
     for (int waves : {1, 2, 4})
         for (int dpw : {1, 2, 3, 4, 6, 8, 12, 16, 24, 32}) {
-            fpic_tuning t{waves, dpw, 8, 0};
-            Plan P;
-            if (make_plan(nsim, cfgs, &t, P))
-                return fail(FPIC_EINVAL, g_err);
-            if (P.total > bytes)
-                continue;
-            // skip shapes whose partial sums would dwarf the grid
-            bool too_many = false;
-            for (auto &sp : P.sims)
-                if (sp.ngroup > 96)
-                    too_many = true;
-            if (too_many)
-                continue;
-            fpic_batch *b = nullptr;
-            int rc = batch_build(nsim, cfgs, &t, workspace, bytes, stream, &b);
+            const fpic_tuning t{waves, dpw, 8, 0};
+            double per;
+            int rc = time_candidate(nsim, cfgs, t, workspace, bytes, stream, &per);
             if (rc)
                 return rc;
-            for (int i = 0; i < nsim; ++i) {
-                hipError_t e = launch_fill_state(b->ddesc, i, s);
-                if (e != hipSuccess) {
-                    fpic_batch_destroy(b);
-                    return fail(FPIC_EHIP, hipGetErrorString(e));
-                }
-                int off, n, roff, rn;
-                sim_work(b, i, &off, &n, &roff, &rn);
-                (void)launch_stage1d(M_DEPOSIT, b->dwork + off, n, b->ddesc, P.waves, P.max_dpw, P.shape, s);
-                (void)launch_reduce1d(b->dred + roff, rn, b->ddesc, 0, nullptr, 0, s);
-                b->state_set[i] = true;
-            }
-            hipEvent_t e0, e1;
-            (void)hipEventCreate(&e0);
-            (void)hipEventCreate(&e1);
-            int rc2 = batch_step(b, 8);
-            (void)hipEventRecord(e0, s);
-            const int nrep = 16;
-            if (!rc2)
-                rc2 = batch_step(b, nrep);
-            (void)hipEventRecord(e1, s);
-            hipError_t es = hipEventSynchronize(e1);
-            float ms = 0.f;
-            (void)hipEventElapsedTime(&ms, e0, e1);
-            (void)hipEventDestroy(e0);
-            (void)hipEventDestroy(e1);
-            fpic_batch_destroy(b);
-            if (rc2)
-                return rc2;
-            if (es != hipSuccess)
-                return fail(FPIC_EHIP, hipGetErrorString(es));
+            if (per < 0.0)
+                continue;
             ++tried;
-            const double per = ms / nrep;
             if (per < best_ms) {
                 best_ms = per;
                 bt = t;
@@ -1148,6 +1175,18 @@ int fpic_autotune(int32_t nsim, const fpic_config *cfgs, void *workspace, size_t
         }
     if (!tried)
         return fail(FPIC_EINVAL, "workspace too small for every candidate shape");
+    for (int policy : {1, 2}) {
+        fpic_tuning t = bt;
+        t.cache_policy = policy;
+        double per;
+        int rc = time_candidate(nsim, cfgs, t, workspace, bytes, stream, &per);
+        if (rc)
+            return rc;
+        if (per >= 0.0 && per < best_ms) {
+            best_ms = per;
+            bt = t;
+        }
+    }
     *best = bt;
     if (ms_per_step)
         *ms_per_step = best_ms;

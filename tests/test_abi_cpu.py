@@ -108,6 +108,11 @@ def test_bad_tuning_rejected(lib):
     assert rc == _lib.FPIC_EINVAL
     rc, _ = ws_bytes(lib, hc, {"steps_per_graph": 1000})
     assert rc == _lib.FPIC_EINVAL
+    rc, _ = ws_bytes(lib, hc, {"cache_policy": 3})
+    assert rc == _lib.FPIC_EINVAL
+    for policy in (0, 1, 2):
+        rc, _ = ws_bytes(lib, hc, {"cache_policy": policy})
+        assert rc == _lib.FPIC_OK
 
 
 def test_batch_rejects_3d(lib):

@@ -394,3 +394,13 @@ def test_through_saturation(torch_dev):
         assert np.abs((t[0] - t[1] * sgn) - L0).max() < 1e-13 * scale
     ree = (P.N[:, None] * ref[0]).sum() / (P.N.sum() * w.ncell_total)
     assert ree < 0.8, ree           # the instability has saturated
+
+
+@pytest.mark.parametrize("policy", [1, 2])
+def test_cache_policies(torch_dev, policy):
+    """Both cache policies of the stage kernels (default caching and
+    streaming) give the reference's result."""
+    w = I.scaled(I.workload("1d_2048x378"), ncell=(1, 1, 150), ndir=92)
+    tuning = {"waves": 4, "dirs_per_wave": 3, "steps_per_graph": 4, "cache_policy": policy}
+    _, _, got, ref = run_pair(w, 9, tuning=tuning)
+    assert_parity(got, ref, what=f"cache policy {policy}")
