@@ -145,7 +145,7 @@ stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ si
     for (int j = threadIdx.x; j < S.dpg; j += blockDim.x) {
         const int d = dgrp0 + j;
         if (d < S.ndir) {
-            const double vz = S.vz[d];
+            const double vz = tld(S.vz, d);
             const Shift sn = shift_of(vz, t_nxt, dz);
             const Shift sc = shift_of(vz, t_cur, dz);
             tphi[2 * j + 0] = sc.phi;
@@ -188,8 +188,8 @@ stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ si
 
     for (int d = dbeg; d < dend; ++d) {
         const int j = d - dgrp0;
-        const double vx = S.vx[d], vy = S.vy[d], vz = S.vz[d];
-        const double wN = S.wN[d], wNb = S.wNb[d];
+        const double vx = tld(S.vx, d), vy = tld(S.vy, d), vz = tld(S.vz, d);
+        const double wN = tld(S.wN, d), wNb = tld(S.wNb, d);
         const double ph = tphi[2 * j + 1];
         const int r = tint[2 * j + 0];
         int c = m - r;
@@ -397,7 +397,7 @@ stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ si
         const int comp = r % 9, grp = r / 9;
         double s = 0.0;
         for (int d = dbeg; d < dend; ++d) {
-            const double coef = (grp == 0) ? 1.0 : (grp == 1) ? S.vx[d] : (grp == 2) ? S.vy[d] : S.vz[d];
+            const double coef = (grp == 0) ? 1.0 : (grp == 1) ? tld(S.vx, d) : (grp == 2) ? tld(S.vy, d) : tld(S.vz, d);
             s += coef * eb[((d - dbeg) * NE + e) * 9 + comp];
         }
         esum[(wave * NE + e) * NG + r] = s;
@@ -494,11 +494,11 @@ adj1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ sims
     for (int j = threadIdx.x; j < S.dpg; j += blockDim.x) {
         const int d = dgrp0 + j;
         if (d < S.ndir) {
-            const Shift sa = shift_of(S.vz[d], tanc, dz);
+            const Shift sa = shift_of(tld(S.vz, d), tanc, dz);
             tphi[2 * j + 0] = sa.phi;
             tint[2 * j + 0] = pmod_dbl((double)sa.i, nc);
             if (DO_A && DO_B) {
-                const Shift sb = shift_of(S.vz[d], tB, dz);
+                const Shift sb = shift_of(tld(S.vz, d), tB, dz);
                 tphi[2 * j + 1] = sb.phi;
                 tint[2 * j + 1] = max(-1, min(1, (int)(sa.i - sb.i)));
             } else {
@@ -549,8 +549,8 @@ adj1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ sims
     const int dend = min(dbeg + S.dpw, S.ndir);
     for (int d = dbeg; d < dend; ++d) {
         const int j = d - dgrp0;
-        const double vx = S.vx[d], vy = S.vy[d], vz = S.vz[d];
-        const double wN = S.wN[d], wNb = S.wNb[d];
+        const double vx = tld(S.vx, d), vy = tld(S.vy, d), vz = tld(S.vz, d);
+        const double wN = tld(S.wN, d), wNb = tld(S.wNb, d);
         const double phA = tphi[2 * j + 0], omA = 1.0 - phA;
         int c = m - tint[2 * j + 0];
         if (c < 0)
@@ -779,7 +779,7 @@ adj1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ sims
         const int comp = r % 9, grp = r / 9;
         double sacc = 0.0;
         for (int d = dbeg; d < dend; ++d) {
-            const double coef = (grp == 0) ? 1.0 : (grp == 1) ? -S.vx[d] : (grp == 2) ? -S.vy[d] : -S.vz[d];
+            const double coef = (grp == 0) ? 1.0 : (grp == 1) ? -tld(S.vx, d) : (grp == 2) ? -tld(S.vy, d) : -tld(S.vz, d);
             sacc += coef * eb[((d - dbeg) * NE + e) * 9 + comp];
         }
         esum[(wave * NE + e) * NG + r] = sacc;
@@ -938,7 +938,7 @@ totals_kernel(const SimDesc *sims, int sim, double *partial)
         double s = 0.0;
         for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < S.np; p += stride) {
             const int d = (int)(p / S.ncell);
-            const double w = (k < 9) ? S.Nw[d] : S.Nbw[d];
+            const double w = (k < 9) ? tld(S.Nw, d) : tld(S.Nbw, d);
             s += w * S.Y[k * S.np + p];
         }
         sh[threadIdx.x] = s;

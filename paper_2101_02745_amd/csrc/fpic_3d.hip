@@ -37,6 +37,7 @@ using fpic::fail;
 using fpic::gld;
 using fpic::gst;
 using fpic::stage_time;
+using fpic::tld;
 
 constexpr int NG = 36;
 constexpr int W = 64;
@@ -157,8 +158,8 @@ particle3d_kernel(const Desc3 *__restrict__ dp, int dpw, int nitems)
     }
 
     for (int d = dbeg; d < dend; ++d) {
-        const double vx = S.v[0][d], vy = S.v[1][d], vz = S.v[2][d];
-        const double wN = S.wN[d], wNb = S.wNb[d];
+        const double vx = tld(S.v[0], d), vy = tld(S.v[1], d), vz = tld(S.v[2], d);
+        const double wN = tld(S.wN, d), wNb = tld(S.wNb, d);
         int rx = 0, ry = 0, rz = 0;
         double fx = 0.0, fy = 0.0, fz = 0.0;
         int64_t c;
@@ -287,31 +288,39 @@ particle3d_kernel(const Desc3 *__restrict__ dp, int dpw, int nitems)
 // (cnext_num / 2 steps after step n's start; 2 means the next step).
 // Each wave owns one x-row of destination cells and sweeps every direction
 // in ascending order; per direction it interpolates the sources of the four
-// rows in y and z (pull_dir), then in x with the lane to the left
-// (accumulate).
+// rows in y and z, then in x with the lane to the left (accumulate).  The
+// loop is software-pipelined: the 36 source values of direction d + 1 (four
+// rows, nine components) are loaded while direction d is summed.
 struct Pull {
     double X[9];       // sources interpolated in y and z at the lane's x
     double fx, vx, vy, vz;
 };
 
-__device__ __forceinline__ void pull_dir(const Desc3 &S, int d, double t, int y, int z, int lane,
-                                         bool active, Pull &o)
+// One direction's shifts and its 36 raw source values for the wave's row.
+// Lanes past the row (lane >= nx) load cell 0 of the row (never used).
+struct DepDir {
+    double vx, vy, vz, fx, fy, fz;
+    double raw[36];  // [2 cz + cy][9]
+};
+
+__device__ __forceinline__ void dep_load(const Desc3 &S, int d, double t, int y, int z, int lane,
+                                         DepDir &o)
 {
     const int nx = S.n[0], ny = S.n[1], nz = S.n[2];
-    o.vx = S.v[0][d];
-    o.vy = S.v[1][d];
-    o.vz = S.v[2][d];
+    o.vx = tld(S.v[0], d);
+    o.vy = tld(S.v[1], d);
+    o.vz = tld(S.v[2], d);
     int rx, ry, rz;
-    double fy, fz;
     axis_shift(o.vx, t, S.dx[0], nx, &rx, &o.fx);
-    axis_shift(o.vy, t, S.dx[1], ny, &ry, &fy);
-    axis_shift(o.vz, t, S.dx[2], nz, &rz, &fz);
+    axis_shift(o.vy, t, S.dx[1], ny, &ry, &o.fy);
+    axis_shift(o.vz, t, S.dx[2], nz, &rz, &o.fz);
+    // the same for the whole wave: row addresses in scalar registers
+    rx = __builtin_amdgcn_readfirstlane(rx);
+    ry = __builtin_amdgcn_readfirstlane(ry);
+    rz = __builtin_amdgcn_readfirstlane(rz);
     int xs = lane - rx;
     xs = (xs < 0) ? xs + nx : xs;
-    xs = active ? xs : 0;
-#pragma unroll
-    for (int k = 0; k < 9; k++)
-        o.X[k] = 0.0;
+    xs = (lane < nx) ? xs : 0;
 #pragma unroll
     for (int cz = 0; cz < 2; cz++)
 #pragma unroll
@@ -321,11 +330,32 @@ __device__ __forceinline__ void pull_dir(const Desc3 &S, int d, double t, int y,
             yy = (yy < 0) ? yy + ny : yy;
             zz = (zz < 0) ? zz + nz : zz;
             zz = (zz < 0) ? zz + nz : zz;
-            const double w = (cy ? fy : 1.0 - fy) * (cz ? fz : 1.0 - fz);
-            const double *xp = S.X + (int64_t)d * S.ncell + ((int64_t)zz * ny + yy) * nx + xs;
+            const double *xp = S.X + (int64_t)d * S.ncell + ((int64_t)zz * ny + yy) * nx;
 #pragma unroll
             for (int k = 0; k < 9; k++)
-                o.X[k] += w * (active ? gld(xp + (int64_t)k * S.np) : 0.0);
+                o.raw[(cz * 2 + cy) * 9 + k] = gld(xp + (int64_t)k * S.np + xs);
+        }
+}
+
+// y/z interpolation of one direction's raw sources (rows in the order
+// cz, cy; inactive lanes take 0)
+__device__ __forceinline__ void pull_dir(const DepDir &c, bool active, Pull &o)
+{
+    o.vx = c.vx;
+    o.vy = c.vy;
+    o.vz = c.vz;
+    o.fx = c.fx;
+#pragma unroll
+    for (int k = 0; k < 9; k++)
+        o.X[k] = 0.0;
+#pragma unroll
+    for (int cz = 0; cz < 2; cz++)
+#pragma unroll
+        for (int cy = 0; cy < 2; cy++) {
+            const double w = (cy ? c.fy : 1.0 - c.fy) * (cz ? c.fz : 1.0 - c.fz);
+#pragma unroll
+            for (int k = 0; k < 9; k++)
+                o.X[k] += w * (active ? c.raw[(cz * 2 + cy) * 9 + k] : 0.0);
         }
 }
 
@@ -375,9 +405,15 @@ deposit3d_kernel(const Desc3 *__restrict__ dp, int half_steps, int out_buf)
 #pragma unroll
     for (int q = 0; q < NG; q++)
         acc[q] = 0.0;
+    DepDir nxt;
+    if (S.ndir > 0)
+        dep_load(S, 0, t, y, z, lane, nxt);
     for (int d = 0; d < S.ndir; ++d) {
+        const DepDir cur = nxt;
+        if (d + 1 < S.ndir)
+            dep_load(S, d + 1, t, y, z, lane, nxt);
         Pull a;
-        pull_dir(S, d, t, y, z, lane, active, a);
+        pull_dir(cur, active, a);
         accumulate(a, left, acc);
     }
     if (active) {
@@ -498,9 +534,9 @@ particle3q_kernel(const Desc3 *__restrict__ dp, int dpw, int nitems)
 #pragma unroll
         for (int j = 0; j < QDB; j++) {
             const int d = min(d0 + j, dend - 1);
-            vb[j][0] = S.v[0][d];
-            vb[j][1] = S.v[1][d];
-            vb[j][2] = S.v[2][d];
+            vb[j][0] = tld(S.v[0], d);
+            vb[j][1] = tld(S.v[1], d);
+            vb[j][2] = tld(S.v[2], d);
             axis_quad(vb[j][0], t_cur, S.dx[0], nx, &rxb[j], wxb[j]);
             axis_quad(vb[j][1], t_cur, S.dx[1], ny, &ryb[j], wyb[j]);
             axis_quad(vb[j][2], t_cur, S.dx[2], nz, &rzb[j], wzb[j]);
@@ -557,7 +593,7 @@ particle3q_kernel(const Desc3 *__restrict__ dp, int dpw, int nitems)
             const int d = d0 + j;
             if (d >= dend)
                 break;
-            const double wN = S.wN[d], wNb = S.wNb[d];
+            const double wN = tld(S.wN, d), wNb = tld(S.wNb, d);
             int rx = rxb[0], ry = ryb[0], rz = rzb[0];
             double Hnn[9];
 #pragma unroll
@@ -682,7 +718,7 @@ deposit3q_kernel(const Desc3 *__restrict__ dp, int half_steps, int out_buf)
     for (int q = 0; q < NG; q++)
         acc[q] = 0.0;
     for (int d = 0; d < S.ndir; ++d) {
-        const double vx = S.v[0][d], vy = S.v[1][d], vz = S.v[2][d];
+        const double vx = tld(S.v[0], d), vy = tld(S.v[1], d), vz = tld(S.v[2], d);
         int rx, ry, rz;
         double wx[3], wy[3], wz[3];
         axis_quad(vx, t, S.dx[0], nx, &rx, wx);
@@ -732,7 +768,7 @@ momsrc3d_kernel(const Desc3 *__restrict__ dp, int which)
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < S.np; p += stride) {
         const int d = (int)(p / S.ncell);
-        const double w = which ? S.wNb[d] : S.wN[d];
+        const double w = which ? tld(S.wNb, d) : tld(S.wN, d);
         for (int k = 0; k < 9; k++)
             gst(S.X + k * S.np + p, w * gld(S.Y + (which * 9 + k) * S.np + p));
     }
@@ -759,7 +795,7 @@ __global__ void __launch_bounds__(256) totals3d(const Desc3 *dp, double *partial
         double s = 0.0;
         for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < S.np; p += stride) {
             const int d = (int)(p / S.ncell);
-            s += ((k < 9) ? S.Nw[d] : S.Nbw[d]) * S.Y[k * S.np + p];
+            s += ((k < 9) ? tld(S.Nw, d) : tld(S.Nbw, d)) * S.Y[k * S.np + p];
         }
         sh[threadIdx.x] = s;
         __syncthreads();

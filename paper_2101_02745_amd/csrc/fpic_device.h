@@ -92,6 +92,13 @@ __device__ __forceinline__ double gld_nt(const double *p)
     return __builtin_nontemporal_load((const gdouble *)p);
 }
 __device__ __forceinline__ void gst_nt(double *p, double v) { __builtin_nontemporal_store(v, (gdouble *)p); }
+// Read-only tables (direction components, weights), which no kernel writes
+// while another reads them: read through the constant address space, so at
+// a wave-uniform index they become scalar loads.  A flat load (generic
+// pointer) would make the wave wait for every vector load and store it has
+// in flight, e.g. the previous direction's stores.
+typedef const __attribute__((address_space(4))) double cdouble;
+__device__ __forceinline__ double tld(const double *p, int64_t i) { return ((const cdouble *)p)[i]; }
 
 // Slopes in memory: NK reals per particle, component c of the packed 18 at
 // slot c - 1 (c = 1..8) or c - 2 (c = 10..17); components 0 and 9 are the
