@@ -99,6 +99,18 @@ __device__ __forceinline__ void gst_nt(double *p, double v) { __builtin_nontempo
 // in flight, e.g. the previous direction's stores.
 typedef const __attribute__((address_space(4))) double cdouble;
 __device__ __forceinline__ double tld(const double *p, int64_t i) { return ((const cdouble *)p)[i]; }
+// Device-scope relaxed atomics on global memory through address-space-1
+// pointers: global_atomic_* instructions (a generic pointer gives flat
+// atomics, with the same full waits as flat loads).
+typedef __attribute__((address_space(1))) int32_t gint;
+__device__ __forceinline__ void gatomic_add(double *p, double v)
+{
+    __hip_atomic_fetch_add((gdouble *)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int32_t gatomic_add(int32_t *p, int32_t v)
+{
+    return __hip_atomic_fetch_add((gint *)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // Slopes in memory: NK reals per particle, component c of the packed 18 at
 // slot c - 1 (c = 1..8) or c - 2 (c = 10..17); components 0 and 9 are the

@@ -42,6 +42,7 @@ namespace fpicp {
 
 using fpic::commutator;
 using fpic::fail;
+using fpic::gatomic_add;
 using fpic::gld;
 using fpic::gst;
 using fpic::load_slope;
@@ -566,7 +567,7 @@ pstage_kernel(const PDesc *__restrict__ dp, double *outG)
                 const int cz = wrap_int(db.ref[2] + db.lo[2] + lz, nz);
                 const int cy = D3 ? wrap_int(db.ref[1] + db.lo[1] + ly, ny) : 0;
                 const int cx = D3 ? wrap_int(db.ref[0] + db.lo[0] + lx, nx) : 0;
-                unsafeAtomicAdd(Gout + (int64_t)comp * nc + ((int64_t)cz * ny + cy) * nx + cx, val);
+                gatomic_add(Gout + (int64_t)comp * nc + ((int64_t)cz * ny + cy) * nx + cx, val);
             }
         }
     } else if (active) {
@@ -585,10 +586,10 @@ pstage_kernel(const PDesc *__restrict__ dp, double *outG)
 #pragma unroll
                     for (int k = 0; k < 9; k++) {
                         const double xc = w * X[k];
-                        unsafeAtomicAdd(g + (int64_t)k * nc, xc);
-                        unsafeAtomicAdd(g + (int64_t)(9 + k) * nc, vx * xc);
-                        unsafeAtomicAdd(g + (int64_t)(18 + k) * nc, vy * xc);
-                        unsafeAtomicAdd(g + (int64_t)(27 + k) * nc, vz * xc);
+                        gatomic_add(g + (int64_t)k * nc, xc);
+                        gatomic_add(g + (int64_t)(9 + k) * nc, vx * xc);
+                        gatomic_add(g + (int64_t)(18 + k) * nc, vy * xc);
+                        gatomic_add(g + (int64_t)(27 + k) * nc, vz * xc);
                     }
                 }
     }
@@ -613,11 +614,11 @@ pstage_kernel(const PDesc *__restrict__ dp, double *outG)
             __syncthreads();
             for (int q = threadIdx.x; q < kr.len; q += BLK)
                 if (hist[q])
-                    hist[q] = atomicAdd(S.cur + wrap_int(kr.ref + kr.lo + q, ncl), hist[q]);
+                    hist[q] = gatomic_add(S.cur + wrap_int(kr.ref + kr.lo + q, ncl), hist[q]);
             __syncthreads();
             j = active ? hist[kr.off - kr.lo] + rank : 0;
         } else {
-            j = active ? atomicAdd(S.cur + key, 1) : 0;
+            j = active ? gatomic_add(S.cur + key, 1) : 0;
         }
         // j < np whenever the counts were taken from the same keys (they are:
         // same inputs, same arithmetic); the guard keeps any mismatch in bounds
@@ -689,9 +690,9 @@ __global__ void __launch_bounds__(BLK) sort_count_kernel(const PDesc *__restrict
         __syncthreads();
         for (int j = threadIdx.x; j < r.len; j += BLK)
             if (hist[j])
-                atomicAdd(S.cnt + wrap_int(r.ref + r.lo + j, nc), hist[j]);
+                gatomic_add(S.cnt + wrap_int(r.ref + r.lo + j, nc), hist[j]);
     } else if (active) {
-        atomicAdd(S.cnt + key, 1);
+        gatomic_add(S.cnt + key, 1);
     }
 }
 
@@ -747,11 +748,11 @@ __global__ void __launch_bounds__(BLK) sort_scatter_kernel(const PDesc *__restri
         __syncthreads();
         for (int jj = threadIdx.x; jj < r.len; jj += BLK)
             if (hist[jj])
-                hist[jj] = atomicAdd(S.cur + wrap_int(r.ref + r.lo + jj, nc), hist[jj]);
+                hist[jj] = gatomic_add(S.cur + wrap_int(r.ref + r.lo + jj, nc), hist[jj]);
         __syncthreads();
         base = active ? hist[r.off - r.lo] + rank : 0;
     } else {
-        base = active ? atomicAdd(S.cur + key, 1) : 0;
+        base = active ? gatomic_add(S.cur + key, 1) : 0;
     }
     if (!active || base < 0 || base >= np)
         return;
