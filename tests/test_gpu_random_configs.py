@@ -74,3 +74,32 @@ def test_random_config(torch_dev, case):
     tot = sim.flavor_totals()
     tref = P.flavor_totals(ref)
     assert np.abs(tot - tref).max() <= 1e-12 * max(np.abs(tref).max(), 1e-300), what
+
+
+@pytest.mark.parametrize("ndir", [1, 2])
+@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("ncell", [(7, 3, 5), (64, 2, 1)])
+def test_3d_few_directions(torch_dev, ndir, order, ncell):
+    """3D boxes with one or two directions: the deposit's direction loop,
+    which loads each next direction while it sums the current one, runs
+    with no next direction (one) or a single look-ahead (two)."""
+    from paper_2101_02745_amd.sim import Sim
+    from paper_2101_02745_amd._lib import HostConfig
+    rng = np.random.default_rng(77 + ndir + 10 * order)
+    v = rng.normal(size=(ndir, 3))
+    dirs = v / np.linalg.norm(v, axis=1, keepdims=True)
+    dx = (0.7, 0.9, 1.1)
+    dt = 0.2
+    dV = dx[0] * dx[1] * dx[2]
+    N = rng.uniform(0.2, 1.0, ndir) * dV
+    Nb = rng.uniform(0.2, 1.0, ndir) * dV
+    H = I.vacuum_hamiltonian(w21=0.1, w31=0.4, delta=0.5)
+    nc = ncell[0] * ncell[1] * ncell[2]
+    st = I.state_from_seeds(0.05 * rng.uniform(-1, 1, size=(8, ndir, nc)))
+    hc = HostConfig(ncell, dx, dirs, N, Nb, H, dt, shape_order=order)
+    P = Problem(ncell, dx, dirs, N, Nb, H, dt, shape_order=order)
+    sim = Sim(hc)
+    sim.set_state(st, 31)
+    sim.step(5)
+    ref = P.step(st, 5, n0=31)
+    assert_parity(sim.get_state().cpu().numpy(), ref, what=f"{ncell} ndir {ndir} order {order}")
