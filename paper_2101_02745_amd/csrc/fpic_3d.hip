@@ -436,9 +436,9 @@ static unsigned deposit_blocks(const Desc3 &h)
 // neighbours with weights (1/2 - xi)^2 / 2, 3/4 - xi^2, (1/2 + xi)^2 / 2,
 // xi = x - x_nearest in [-1/2, 1/2) (each operation rounded once, as the CPU
 // reference forms them); a one-cell axis gives (0, 1, 0).  The particle
-// kernel's workgroup owns one row of *nearest* cells; the nine grid rows it
-// interpolates from are read through the caches (nine rows of 36 components
-// do not fit the 160 KB LDS at 64 cells per row).
+// kernel's workgroup owns one row of *nearest* cells and stages the nine grid
+// rows it interpolates from in LDS, as the 32 traceless moment components
+// (nine rows of all 36 would not fit the 160 KB at 64 cells per row).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void axis_quad(double v, double t, double dx, int n, int *r, double w[3])
 {
@@ -480,10 +480,9 @@ __device__ __forceinline__ double pick3(const double w[3], int b)
     return b == 0 ? w[0] : (b == 1 ? w[1] : w[2]);
 }
 
-// Directions per gather block: each load of a grid row serves the block's
-// directions (the nine rows are shared by every particle of the workgroup
-// but do not fit in LDS, so they come through the caches).  Two for stages
-// 1-3; stage 4 holds three slopes and keeps one (more would spill).
+// Directions per gather block: each LDS read of a grid row serves the
+// block's directions.  Two for stages 1-3; stage 4 holds three slopes and
+// keeps one (more would spill).
 template <int MODE>
 constexpr int qdb() { return MODE == 4 ? 1 : 2; }
 
@@ -491,6 +490,8 @@ template <int MODE>
 __global__ void __launch_bounds__(MAX_WAVES3 * W)
 particle3q_kernel(const Desc3 *__restrict__ dp, int dpw, int nitems)
 {
+    constexpr int NQ = 32;               // traceless moment components
+    __shared__ double Gq[9 * NQ * W];    // [row q][component][x], 144 KiB
     const Desc3 S = *dp;
     const int lane = threadIdx.x & (W - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / W);
@@ -516,14 +517,36 @@ particle3q_kernel(const Desc3 *__restrict__ dp, int dpw, int nitems)
     const double *Kp = (MODE == 2) ? S.K1 : (MODE == 3) ? S.K2 : S.K3;
     const int dbeg = (grp * nwaves + wave) * dpw, dend = min(dbeg + dpw, S.ndir);
     const int xl = (lane + nx - 1) % (nx < 1 ? 1 : nx), xr = (lane + 1) % (nx < 1 ? 1 : nx);
-    // the nine grid rows around the nearest row (y0, z0): row q = 3 c + b is
-    // (y0 + b - 1, z0 + c - 1); cell offsets fit 32 bits (ncell <= 2^30)
-    int rowoff[9];
+    // Stage the nine grid rows around the nearest row (y0, z0) in LDS, row
+    // q = 3 c + b being (y0 + b - 1, z0 + c - 1).  Only the traceless part of
+    // each of the four 3x3 moment matrices (A, B_x, B_y, B_z) is kept:
+    // m11 - m00, m22 - m00 and the six off-diagonal reals.  Interpolation is
+    // linear, so the interpolated Hamiltonian loses only a multiple of the
+    // identity, which commutes with every state and leaves both commutators
+    // unchanged; 32 components of nine 64-cell rows fit the LDS where 36 do
+    // not.  Columns past the row (x >= nx) hold 0.
+    for (int idx = threadIdx.x; idx < 9 * 4 * W; idx += blockDim.x) {
+        const int x = idx % W, t = idx / W;
+        const int g4 = t % 4, q = t / 4;
+        const int b = q % 3, cc = q / 3;
+        double v[9];
 #pragma unroll
-    for (int c = 0; c < 3; c++)
+        for (int k = 0; k < 9; k++)
+            v[k] = 0.0;
+        if (x < nx) {
+            const int64_t cell = ((int64_t)wrap(z0 + cc - 1, nz) * ny + wrap(y0 + b - 1, ny)) * nx + x;
 #pragma unroll
-        for (int b = 0; b < 3; b++)
-            rowoff[3 * c + b] = (wrap(z0 + c - 1, nz) * ny + wrap(y0 + b - 1, ny)) * nx + (active ? lane : 0);
+            for (int k = 0; k < 9; k++)
+                v[k] = gld(Gin + (int64_t)(9 * g4 + k) * S.ncell + cell);
+        }
+        double *o = Gq + (q * NQ + 8 * g4) * W + x;
+        o[0] = v[1] - v[0];
+        o[W] = v[2] - v[0];
+#pragma unroll
+        for (int k = 3; k < 9; k++)
+            o[(k - 1) * W] = v[k];
+    }
+    __syncthreads();
 
     constexpr int QDB = qdb<MODE>();
     for (int d0 = dbeg; d0 < dend; d0 += QDB) {
@@ -541,39 +564,37 @@ particle3q_kernel(const Desc3 *__restrict__ dp, int dpw, int nitems)
             axis_quad(vb[j][1], t_cur, S.dx[1], ny, &ryb[j], wyb[j]);
             axis_quad(vb[j][2], t_cur, S.dx[2], nz, &rzb[j], wzb[j]);
         }
-        double Hb4[QDB][9];
+        // traceless Hnn: components 1..8 of the packed nine (component 0,
+        // the ee entry, is 0)
+        double Hb4[QDB][8];
 #pragma unroll
         for (int j = 0; j < QDB; j++)
 #pragma unroll
-            for (int k = 0; k < 9; k++)
+            for (int k = 0; k < 8; k++)
                 Hb4[j][k] = 0.0;
 #pragma unroll 1
         for (int grp4 = 0; grp4 < 4; grp4++) {
-            const double *g = Gin + (int64_t)(9 * grp4) * S.ncell;
-            // y/z interpolation row by row, each row load used by every
+            // y/z interpolation row by row from LDS, each read used by every
             // direction of the block
-            double r[QDB][9];
+            double r[QDB][8];
 #pragma unroll
             for (int j = 0; j < QDB; j++)
 #pragma unroll
-                for (int k = 0; k < 9; k++)
+                for (int k = 0; k < 8; k++)
                     r[j][k] = 0.0;
-#pragma unroll 1
+#pragma unroll 3
             for (int q = 0; q < 9; q++) {
                 const int b = q % 3, cc = q / 3;
-                int ro = rowoff[0];
+                const double *gp = Gq + (q * NQ + 8 * grp4) * W + lane;
+                double gv[8];
 #pragma unroll
-                for (int qq = 1; qq < 9; qq++)
-                    ro = (q == qq) ? rowoff[qq] : ro;
-                double gv[9];
-#pragma unroll
-                for (int k = 0; k < 9; k++)
-                    gv[k] = active ? gld(g + (int64_t)k * S.ncell + ro) : 0.0;
+                for (int k = 0; k < 8; k++)
+                    gv[k] = gp[k * W];
 #pragma unroll
                 for (int j = 0; j < QDB; j++) {
                     const double wq = pick3(wyb[j], b) * pick3(wzb[j], cc);
 #pragma unroll
-                    for (int k = 0; k < 9; k++)
+                    for (int k = 0; k < 8; k++)
                         r[j][k] += wq * gv[k];
                 }
             }
@@ -581,7 +602,7 @@ particle3q_kernel(const Desc3 *__restrict__ dp, int dpw, int nitems)
             for (int j = 0; j < QDB; j++) {
                 const double coef = (grp4 == 0) ? 1.0 : -pick3(vb[j], grp4 - 1);
 #pragma unroll
-                for (int k = 0; k < 9; k++) {
+                for (int k = 0; k < 8; k++) {
                     const double nl = lane_get(r[j][k], xl), nr = lane_get(r[j][k], xr);
                     Hb4[j][k] += coef * ((wxb[j][0] * nl + wxb[j][1] * r[j][k]) + wxb[j][2] * nr);
                 }
@@ -596,9 +617,10 @@ particle3q_kernel(const Desc3 *__restrict__ dp, int dpw, int nitems)
             const double wN = tld(S.wN, d), wNb = tld(S.wNb, d);
             int rx = rxb[0], ry = ryb[0], rz = rzb[0];
             double Hnn[9];
+            Hnn[0] = 0.0;
 #pragma unroll
-            for (int k = 0; k < 9; k++)
-                Hnn[k] = Hb4[0][k];
+            for (int k = 1; k < 9; k++)
+                Hnn[k] = Hb4[0][k - 1];
 #pragma unroll
             for (int jj = 1; jj < QDB; jj++) {
                 const bool m = j == jj;
@@ -606,8 +628,8 @@ particle3q_kernel(const Desc3 *__restrict__ dp, int dpw, int nitems)
                 ry = m ? ryb[jj] : ry;
                 rz = m ? rzb[jj] : rz;
 #pragma unroll
-                for (int k = 0; k < 9; k++)
-                    Hnn[k] = m ? Hb4[jj][k] : Hnn[k];
+                for (int k = 1; k < 9; k++)
+                    Hnn[k] = m ? Hb4[jj][k - 1] : Hnn[k];
             }
             const int cx = wrap(lane - rx, nx), cy = wrap(y0 - ry, ny), cz = wrap(z0 - rz, nz);
             const int64_t c = ((int64_t)cz * ny + cy) * nx + (active ? cx : 0);
