@@ -52,8 +52,10 @@ def kernel_source_hash():
 
 
 def particles_source_hash():
-    path = os.path.join(ROOT, "paper_2101_02745_amd", "csrc", "fpic_particles.hip")
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in ("fpic_particles.hip", "fpic_device.h"):
+        h.update(open(os.path.join(ROOT, "paper_2101_02745_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(kernel: str, workload: str, source_hash=None):
