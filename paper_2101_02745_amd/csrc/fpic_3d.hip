@@ -296,8 +296,9 @@ struct Pull {
     double fx, vx, vy, vz;
 };
 
-// One direction's shifts and its 36 raw source values for the wave's row.
-// Lanes past the row (lane >= nx) load cell 0 of the row (never used).
+// One direction's components and interpolation fractions, and its 36 raw
+// source values for the wave's row.  Lanes past the row (lane >= nx) load
+// cell 0 of the row (never used).
 struct DepDir {
     double vx, vy, vz, fx, fy, fz;
     double raw[36];  // [2 cz + cy][9]
