@@ -326,6 +326,8 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="1d_2048x378")
+    ap.add_argument("--shape", type=int, default=0, choices=[0, 1, 2],
+                    help="shape-function order of the workload (0: its own; 1 linear, 2 quadratic)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the adjoint and batch measurements")
@@ -366,6 +368,9 @@ def main():
     from paper_2101_02745_amd.sim import Sim
 
     w = I.workload(args.workload)
+    if args.shape:
+        import dataclasses
+        w = dataclasses.replace(w, shape_order=args.shape)
     tune_ms = None
     if args.tuning:
         tuning = json.loads(args.tuning)
@@ -414,7 +419,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": w.name, "ncell": list(w.ncell), "ndir": w.ndir,
-                   "particles": w.nparticles, "dt": w.dt, "shape": "cic",
+                   "particles": w.nparticles, "dt": w.dt,
+                   "shape": "cic" if w.shape_order == 1 else "tsc",
                    "integrator": "rk4", "launch": sim.tune.as_dict() if sim.tune else "default",
                    "launch_source": "explicit" if args.tuning else "autotuned"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
