@@ -1,20 +1,21 @@
 // 3D periodic boxes: two kernels per Runge-Kutta stage.
 //
 // particle kernel (a workgroup = one x-row of current cells and a group of
-// directions, lane = x): forms the stage state, interpolates the 36 combined
+// directions, lane = x): forms the stage state, interpolates the combined
 // moments at the particle's current position with the trilinear
 // cloud-in-cell weights (y and z first, from the four neighbouring grid rows
 // staged in LDS, then x from the lane one to the right), builds H and Hbar,
 // the commutator slopes and the next stage state, and writes that state's
-// deposit source X = (N/dV) rho - (Nbar/dV) rhobar^* (9 reals per particle).
+// deposit source X = (N/dV) rho - (Nbar/dV) rhobar^* (its traceless part: 8
+// reals per particle, see NXT below).
 //
 // deposit kernel (one wave = one x-row of destination cells, all directions
 // in a fixed order; a workgroup holds a small patch of neighbouring rows):
 // every cell pulls X from the eight particles whose next-stage positions
 // straddle it (four rows in y and z, then the lane one to the left in x)
-// with the same weights, and accumulates the 36 combined moments in
-// registers.  Each cell is written once: no atomics, no partial sums,
-// bitwise reproducible.
+// with the same weights, and accumulates the combined moments (32 traceless
+// components; 36 for the moments diagnostic) in registers.  Each cell is
+// written once: no atomics, no partial sums, bitwise reproducible.
 //
 // Positions are implicit as in 1D: particle (d, c) is at cell c shifted by
 // floor(Omega_a t / dx_a) along each axis with fraction Omega_a t / dx_a minus
@@ -102,6 +103,29 @@ __device__ __forceinline__ double lane_get(double v, int src)
     return __shfl(v, src, W);
 }
 
+// Stage deposits carry the traceless part of each 3x3 source matrix: the
+// interpolated Hamiltonian is needed only up to a multiple of the identity,
+// which commutes with every state and leaves both commutators unchanged.
+// Per particle the source X = (N/dV) rho - (Nbar/dV) rhobar^* is stored as
+// NXT = 8 reals (x11 - x00, x22 - x00 and the six off-diagonal reals), and
+// the stage grids hold NGT = 32 components (A, B_x, B_y, B_z, eight each);
+// the moments diagnostic deposits all nine components of its sources.
+constexpr int NXT = 8, NGT = 4 * NXT;
+
+__device__ __forceinline__ void store_source(const Desc3 &S, int64_t p, double wN, double wNb,
+                                             const double yn[18])
+{
+    double x[9];
+#pragma unroll
+    for (int k = 0; k < 9; k++)
+        x[k] = (k == 4 || k == 6 || k == 8) ? wN * yn[k] + wNb * yn[9 + k] : wN * yn[k] - wNb * yn[9 + k];
+    gst(S.X + p, x[1] - x[0]);
+    gst(S.X + S.np + p, x[2] - x[0]);
+#pragma unroll
+    for (int k = 3; k < 9; k++)
+        gst(S.X + (k - 1) * S.np + p, x[k]);
+}
+
 // MODE 1..4: Runge-Kutta stages; 5: deposit sources of the current state.
 //
 // A workgroup owns one row (y, z) of *current* lower cells and a group of
@@ -118,7 +142,7 @@ template <int MODE>
 __global__ void __launch_bounds__(MAX_WAVES3 * W)
 particle3d_kernel(const Desc3 *__restrict__ dp, int dpw, int nitems)
 {
-    __shared__ double Gt[MODE == 5 ? 1 : 4 * NG * W];  // [row q = 2 cz + cy][comp][x]
+    __shared__ double Gt[MODE == 5 ? 1 : 4 * NGT * W];  // [row q = 2 cz + cy][comp][x]
     const Desc3 S = *dp;
     const int lane = threadIdx.x & (W - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / W);
@@ -146,13 +170,13 @@ particle3d_kernel(const Desc3 *__restrict__ dp, int dpw, int nitems)
     const int right = (lane + 1) % (nx < 1 ? 1 : nx);
 
     if (MODE != 5) {
-        for (int idx = threadIdx.x; idx < 4 * NG * nx; idx += blockDim.x) {
+        for (int idx = threadIdx.x; idx < 4 * NGT * nx; idx += blockDim.x) {
             const int x = idx % nx, t = idx / nx;
-            const int comp = t % NG, q = t / NG;
+            const int comp = t % NGT, q = t / NGT;
             int yy = y0 + (q & 1), zz = z0 + (q >> 1);
             yy = (yy >= ny) ? yy - ny : yy;
             zz = (zz >= nz) ? zz - nz : zz;
-            Gt[(q * NG + comp) * W + x] = gld(Gin + (int64_t)comp * S.ncell + ((int64_t)zz * ny + yy) * nx + x);
+            Gt[(q * NGT + comp) * W + x] = gld(Gin + (int64_t)comp * S.ncell + ((int64_t)zz * ny + yy) * nx + x);
         }
         __syncthreads();
     }
@@ -187,8 +211,9 @@ particle3d_kernel(const Desc3 *__restrict__ dp, int dpw, int nitems)
                 yn[k] = Y[k];
         } else {
             // y/z interpolation from the four staged rows, then x with the
-            // lane to the right (periodic in x); one group of 9 components
-            // (A, B_x, B_y, B_z) at a time: Hnn = A - (vx B_x + vy B_y + vz B_z)
+            // lane to the right (periodic in x); one group of 8 traceless
+            // components (A, B_x, B_y, B_z) at a time:
+            // Hnn = A - (vx B_x + vy B_y + vz B_z), its ee entry 0
             double wyz[4];
 #pragma unroll
             for (int cz = 0; cz < 2; cz++)
@@ -203,15 +228,15 @@ particle3d_kernel(const Desc3 *__restrict__ dp, int dpw, int nitems)
             for (int grp4 = 0; grp4 < 4; grp4++) {
                 const double coef = (grp4 == 0) ? 1.0 : (grp4 == 1) ? -vx : (grp4 == 2) ? -vy : -vz;
 #pragma unroll
-                for (int k = 0; k < 9; k++) {
-                    const double *g = Gt + (9 * grp4 + k) * W + lane;
+                for (int k = 0; k < NXT; k++) {
+                    const double *g = Gt + (NXT * grp4 + k) * W + lane;
                     double r = 0.0;
 #pragma unroll
                     for (int q = 0; q < 4; q++)
-                        r += wyz[q] * (active ? g[q * NG * W] : 0.0);
+                        r += wyz[q] * (active ? g[q * NGT * W] : 0.0);
                     const double nb = lane_get(r, right);
                     const double val = (1.0 - fx) * r + fx * nb;
-                    Hnn[k] += coef * val;
+                    Hnn[k + 1] += coef * val;
                 }
             }
             const double a = (MODE == 4) ? dt : 0.5 * dt;
@@ -273,14 +298,8 @@ particle3d_kernel(const Desc3 *__restrict__ dp, int dpw, int nitems)
                 }
             }
         }
-        if (active) {
-#pragma unroll
-            for (int k = 0; k < 9; k++) {
-                const double x = (k == 4 || k == 6 || k == 8) ? wN * yn[k] + wNb * yn[9 + k]
-                                                              : wN * yn[k] - wNb * yn[9 + k];
-                gst(S.X + k * S.np + p, x);
-            }
-        }
+        if (active)
+            store_source(S, p, wN, wNb, yn);
     }
 }
 
@@ -289,23 +308,28 @@ particle3d_kernel(const Desc3 *__restrict__ dp, int dpw, int nitems)
 // Each wave owns one x-row of destination cells and sweeps every direction
 // in ascending order; per direction it interpolates the sources of the four
 // rows in y and z, then in x with the lane to the left (accumulate).  The
-// loop is software-pipelined: the 36 source values of direction d + 1 (four
-// rows, nine components) are loaded while direction d is summed.
+// loop is software-pipelined: the 4 NC source values of direction d + 1
+// (four rows, NC components) are loaded while direction d is summed.  NC is
+// NXT (traceless stage sources, grid of NGT components) or 9 (moments, grid
+// of 36).
+template <int NC>
 struct Pull {
-    double X[9];       // sources interpolated in y and z at the lane's x
+    double X[NC];      // sources interpolated in y and z at the lane's x
     double fx, vx, vy, vz;
 };
 
-// One direction's components and interpolation fractions, and its 36 raw
+// One direction's components and interpolation fractions, and its 4 NC raw
 // source values for the wave's row.  Lanes past the row (lane >= nx) load
 // cell 0 of the row (never used).
+template <int NC>
 struct DepDir {
     double vx, vy, vz, fx, fy, fz;
-    double raw[36];  // [2 cz + cy][9]
+    double raw[4 * NC];  // [2 cz + cy][NC]
 };
 
+template <int NC>
 __device__ __forceinline__ void dep_load(const Desc3 &S, int d, double t, int y, int z, int lane,
-                                         DepDir &o)
+                                         DepDir<NC> &o)
 {
     const int nx = S.n[0], ny = S.n[1], nz = S.n[2];
     o.vx = tld(S.v[0], d);
@@ -333,21 +357,22 @@ __device__ __forceinline__ void dep_load(const Desc3 &S, int d, double t, int y,
             zz = (zz < 0) ? zz + nz : zz;
             const double *xp = S.X + (int64_t)d * S.ncell + ((int64_t)zz * ny + yy) * nx;
 #pragma unroll
-            for (int k = 0; k < 9; k++)
-                o.raw[(cz * 2 + cy) * 9 + k] = gld(xp + (int64_t)k * S.np + xs);
+            for (int k = 0; k < NC; k++)
+                o.raw[(cz * 2 + cy) * NC + k] = gld(xp + (int64_t)k * S.np + xs);
         }
 }
 
 // y/z interpolation of one direction's raw sources (rows in the order
 // cz, cy; inactive lanes take 0)
-__device__ __forceinline__ void pull_dir(const DepDir &c, bool active, Pull &o)
+template <int NC>
+__device__ __forceinline__ void pull_dir(const DepDir<NC> &c, bool active, Pull<NC> &o)
 {
     o.vx = c.vx;
     o.vy = c.vy;
     o.vz = c.vz;
     o.fx = c.fx;
 #pragma unroll
-    for (int k = 0; k < 9; k++)
+    for (int k = 0; k < NC; k++)
         o.X[k] = 0.0;
 #pragma unroll
     for (int cz = 0; cz < 2; cz++)
@@ -355,21 +380,22 @@ __device__ __forceinline__ void pull_dir(const DepDir &c, bool active, Pull &o)
         for (int cy = 0; cy < 2; cy++) {
             const double w = (cy ? c.fy : 1.0 - c.fy) * (cz ? c.fz : 1.0 - c.fz);
 #pragma unroll
-            for (int k = 0; k < 9; k++)
-                o.X[k] += w * (active ? c.raw[(cz * 2 + cy) * 9 + k] : 0.0);
+            for (int k = 0; k < NC; k++)
+                o.X[k] += w * (active ? c.raw[(cz * 2 + cy) * NC + k] : 0.0);
         }
 }
 
-__device__ __forceinline__ void accumulate(const Pull &o, int left, double acc[NG])
+template <int NC>
+__device__ __forceinline__ void accumulate(const Pull<NC> &o, int left, double acc[4 * NC])
 {
 #pragma unroll
-    for (int k = 0; k < 9; k++) {
+    for (int k = 0; k < NC; k++) {
         const double xl = lane_get(o.X[k], left);
         const double xc = (1.0 - o.fx) * o.X[k] + o.fx * xl;
         acc[k] += xc;
-        acc[9 + k] += o.vx * xc;
-        acc[18 + k] += o.vy * xc;
-        acc[27 + k] += o.vz * xc;
+        acc[NC + k] += o.vx * xc;
+        acc[2 * NC + k] += o.vy * xc;
+        acc[3 * NC + k] += o.vz * xc;
     }
 }
 
@@ -380,6 +406,7 @@ __device__ __forceinline__ void accumulate(const Pull &o, int left, double acc[N
 constexpr int DEP_PY = 2, DEP_PZ = 2;
 constexpr int DEP_WAVES = DEP_PY * DEP_PZ;
 
+template <int NC>
 __global__ void __launch_bounds__(DEP_WAVES * W)
 deposit3d_kernel(const Desc3 *__restrict__ dp, int half_steps, int out_buf)
 {
@@ -402,26 +429,26 @@ deposit3d_kernel(const Desc3 *__restrict__ dp, int half_steps, int out_buf)
     else
         t = stage_time(n0, S.dt, 0.5 * half_steps);
     const int left = (lane + nx - 1) % (nx < 1 ? 1 : nx);
-    double acc[NG];
+    double acc[4 * NC];
 #pragma unroll
-    for (int q = 0; q < NG; q++)
+    for (int q = 0; q < 4 * NC; q++)
         acc[q] = 0.0;
-    DepDir nxt;
+    DepDir<NC> nxt;
     if (S.ndir > 0)
-        dep_load(S, 0, t, y, z, lane, nxt);
+        dep_load<NC>(S, 0, t, y, z, lane, nxt);
     for (int d = 0; d < S.ndir; ++d) {
-        const DepDir cur = nxt;
+        const DepDir<NC> cur = nxt;
         if (d + 1 < S.ndir)
-            dep_load(S, d + 1, t, y, z, lane, nxt);
-        Pull a;
-        pull_dir(cur, active, a);
-        accumulate(a, left, acc);
+            dep_load<NC>(S, d + 1, t, y, z, lane, nxt);
+        Pull<NC> a;
+        pull_dir<NC>(cur, active, a);
+        accumulate<NC>(a, left, acc);
     }
     if (active) {
         double *G = out_buf ? S.G[1] : S.G[0];  // (no dynamic index into the descriptor)
         const int64_t cell = ((int64_t)z * ny + y) * nx + lane;
 #pragma unroll
-        for (int q = 0; q < NG; q++)
+        for (int q = 0; q < 4 * NC; q++)
             gst(G + (int64_t)q * S.ncell + cell, acc[q]);
     }
 }
@@ -491,8 +518,7 @@ template <int MODE>
 __global__ void __launch_bounds__(MAX_WAVES3 * W)
 particle3q_kernel(const Desc3 *__restrict__ dp, int dpw, int nitems)
 {
-    constexpr int NQ = 32;               // traceless moment components
-    __shared__ double Gq[9 * NQ * W];    // [row q][component][x], 144 KiB
+    __shared__ double Gq[9 * NGT * W];   // [row q][component][x], 144 KiB
     const Desc3 S = *dp;
     const int lane = threadIdx.x & (W - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / W);
@@ -519,33 +545,26 @@ particle3q_kernel(const Desc3 *__restrict__ dp, int dpw, int nitems)
     const int dbeg = (grp * nwaves + wave) * dpw, dend = min(dbeg + dpw, S.ndir);
     const int xl = (lane + nx - 1) % (nx < 1 ? 1 : nx), xr = (lane + 1) % (nx < 1 ? 1 : nx);
     // Stage the nine grid rows around the nearest row (y0, z0) in LDS, row
-    // q = 3 c + b being (y0 + b - 1, z0 + c - 1).  Only the traceless part of
-    // each of the four 3x3 moment matrices (A, B_x, B_y, B_z) is kept:
-    // m11 - m00, m22 - m00 and the six off-diagonal reals.  Interpolation is
-    // linear, so the interpolated Hamiltonian loses only a multiple of the
-    // identity, which commutes with every state and leaves both commutators
-    // unchanged; 32 components of nine 64-cell rows fit the LDS where 36 do
-    // not.  Columns past the row (x >= nx) hold 0.
+    // q = 3 c + b being (y0 + b - 1, z0 + c - 1): the 32 traceless moment
+    // components of the stage grid (36 would not fit at 64 cells per row).
+    // Columns past the row (x >= nx) hold 0.
     for (int idx = threadIdx.x; idx < 9 * 4 * W; idx += blockDim.x) {
         const int x = idx % W, t = idx / W;
-        const int g4 = t % 4, q = t / 4;
+        const int g4 = t % 4, q = t / 4;  // eight components of one matrix per task
         const int b = q % 3, cc = q / 3;
-        double v[9];
+        double v[NXT];
 #pragma unroll
-        for (int k = 0; k < 9; k++)
+        for (int k = 0; k < NXT; k++)
             v[k] = 0.0;
         if (x < nx) {
             const int64_t cell = ((int64_t)wrap(z0 + cc - 1, nz) * ny + wrap(y0 + b - 1, ny)) * nx + x;
 #pragma unroll
-            for (int k = 0; k < 9; k++)
-                v[k] = gld(Gin + (int64_t)(9 * g4 + k) * S.ncell + cell);
+            for (int k = 0; k < NXT; k++)
+                v[k] = gld(Gin + (int64_t)(NXT * g4 + k) * S.ncell + cell);
         }
-        double *o = Gq + (q * NQ + 8 * g4) * W + x;
-        o[0] = v[1] - v[0];
-        o[W] = v[2] - v[0];
 #pragma unroll
-        for (int k = 3; k < 9; k++)
-            o[(k - 1) * W] = v[k];
+        for (int k = 0; k < NXT; k++)
+            Gq[(q * NGT + NXT * g4 + k) * W + x] = v[k];
     }
     __syncthreads();
 
@@ -567,35 +586,35 @@ particle3q_kernel(const Desc3 *__restrict__ dp, int dpw, int nitems)
         }
         // traceless Hnn: components 1..8 of the packed nine (component 0,
         // the ee entry, is 0)
-        double Hb4[QDB][8];
+        double Hb4[QDB][NXT];
 #pragma unroll
         for (int j = 0; j < QDB; j++)
 #pragma unroll
-            for (int k = 0; k < 8; k++)
+            for (int k = 0; k < NXT; k++)
                 Hb4[j][k] = 0.0;
 #pragma unroll 1
         for (int grp4 = 0; grp4 < 4; grp4++) {
             // y/z interpolation row by row from LDS, each read used by every
             // direction of the block
-            double r[QDB][8];
+            double r[QDB][NXT];
 #pragma unroll
             for (int j = 0; j < QDB; j++)
 #pragma unroll
-                for (int k = 0; k < 8; k++)
+                for (int k = 0; k < NXT; k++)
                     r[j][k] = 0.0;
 #pragma unroll 3
             for (int q = 0; q < 9; q++) {
                 const int b = q % 3, cc = q / 3;
-                const double *gp = Gq + (q * NQ + 8 * grp4) * W + lane;
-                double gv[8];
+                const double *gp = Gq + (q * NGT + NXT * grp4) * W + lane;
+                double gv[NXT];
 #pragma unroll
-                for (int k = 0; k < 8; k++)
+                for (int k = 0; k < NXT; k++)
                     gv[k] = gp[k * W];
 #pragma unroll
                 for (int j = 0; j < QDB; j++) {
                     const double wq = pick3(wyb[j], b) * pick3(wzb[j], cc);
 #pragma unroll
-                    for (int k = 0; k < 8; k++)
+                    for (int k = 0; k < NXT; k++)
                         r[j][k] += wq * gv[k];
                 }
             }
@@ -603,7 +622,7 @@ particle3q_kernel(const Desc3 *__restrict__ dp, int dpw, int nitems)
             for (int j = 0; j < QDB; j++) {
                 const double coef = (grp4 == 0) ? 1.0 : -pick3(vb[j], grp4 - 1);
 #pragma unroll
-                for (int k = 0; k < 8; k++) {
+                for (int k = 0; k < NXT; k++) {
                     const double nl = lane_get(r[j][k], xl), nr = lane_get(r[j][k], xr);
                     Hb4[j][k] += coef * ((wxb[j][0] * nl + wxb[j][1] * r[j][k]) + wxb[j][2] * nr);
                 }
@@ -700,14 +719,8 @@ particle3q_kernel(const Desc3 *__restrict__ dp, int dpw, int nitems)
                     yn[k] = base[k] + an * kk[k];
                 }
             }
-            if (active) {
-#pragma unroll
-                for (int k = 0; k < 9; k++) {
-                    const double x = (k == 4 || k == 6 || k == 8) ? wN * yn[k] + wNb * yn[9 + k]
-                                                                  : wN * yn[k] - wNb * yn[9 + k];
-                    gst(S.X + k * S.np + p, x);
-                }
-            }
+            if (active)
+                store_source(S, p, wN, wNb, yn);
         }
     }
 }
@@ -716,6 +729,7 @@ particle3q_kernel(const Desc3 *__restrict__ dp, int dpw, int nitems)
 // wx[i] wy[j] wz[k] from the particle whose nearest cell is
 // (x - i + 1, y - j + 1, z - k + 1), i, j, k = 0..2: nine source rows in y
 // and z, then the lanes one right and one left in x.
+template <int NC>
 __global__ void __launch_bounds__(DEP_WAVES * W)
 deposit3q_kernel(const Desc3 *__restrict__ dp, int half_steps, int out_buf)
 {
@@ -736,9 +750,9 @@ deposit3q_kernel(const Desc3 *__restrict__ dp, int half_steps, int out_buf)
     else
         t = stage_time(n0, S.dt, 0.5 * half_steps);
     const int xl = (lane + nx - 1) % (nx < 1 ? 1 : nx), xr = (lane + 1) % (nx < 1 ? 1 : nx);
-    double acc[NG];
+    double acc[4 * NC];
 #pragma unroll
-    for (int q = 0; q < NG; q++)
+    for (int q = 0; q < 4 * NC; q++)
         acc[q] = 0.0;
     for (int d = 0; d < S.ndir; ++d) {
         const double vx = tld(S.v[0], d), vy = tld(S.v[1], d), vz = tld(S.v[2], d);
@@ -748,9 +762,9 @@ deposit3q_kernel(const Desc3 *__restrict__ dp, int half_steps, int out_buf)
         axis_quad(vy, t, S.dx[1], ny, &ry, wy);
         axis_quad(vz, t, S.dx[2], nz, &rz, wz);
         const int xs = active ? wrap(lane - rx, nx) : 0;
-        double Xyz[9];
+        double Xyz[NC];
 #pragma unroll
-        for (int k = 0; k < 9; k++)
+        for (int k = 0; k < NC; k++)
             Xyz[k] = 0.0;
 #pragma unroll 1
         for (int kk = 0; kk < 3; kk++)
@@ -760,24 +774,24 @@ deposit3q_kernel(const Desc3 *__restrict__ dp, int half_steps, int out_buf)
                 const double w = wy[j] * wz[kk];
                 const double *xp = S.X + (int64_t)d * S.ncell + ((int64_t)zz * ny + yy) * nx + xs;
 #pragma unroll
-                for (int k = 0; k < 9; k++)
+                for (int k = 0; k < NC; k++)
                     Xyz[k] += w * (active ? gld(xp + (int64_t)k * S.np) : 0.0);
             }
 #pragma unroll
-        for (int k = 0; k < 9; k++) {
+        for (int k = 0; k < NC; k++) {
             const double right = lane_get(Xyz[k], xr), left = lane_get(Xyz[k], xl);
             const double xc = (wx[0] * right + wx[1] * Xyz[k]) + wx[2] * left;
             acc[k] += xc;
-            acc[9 + k] += vx * xc;
-            acc[18 + k] += vy * xc;
-            acc[27 + k] += vz * xc;
+            acc[NC + k] += vx * xc;
+            acc[2 * NC + k] += vy * xc;
+            acc[3 * NC + k] += vz * xc;
         }
     }
     if (active) {
         double *G = out_buf ? S.G[1] : S.G[0];
         const int64_t cell = ((int64_t)z * ny + y) * nx + lane;
 #pragma unroll
-        for (int q = 0; q < NG; q++)
+        for (int q = 0; q < 4 * NC; q++)
             gst(G + (int64_t)q * S.ncell + cell, acc[q]);
     }
 }
@@ -1049,13 +1063,23 @@ static void launch_particle(const Ctx3D *c, int mode, hipStream_t s)
     }
 }
 
-static void launch_deposit(const Ctx3D *c, const Desc3 *dd, int half_steps, int out_buf, hipStream_t s)
+// The stage deposits (traceless sources, NGT grid components); full = true
+// for the moments diagnostic (all nine source components, 36 per cell).
+static void launch_deposit(const Ctx3D *c, const Desc3 *dd, int half_steps, int out_buf, hipStream_t s,
+                           bool full = false)
 {
     const dim3 dgrid(deposit_blocks(c->h)), blk(DEP_WAVES * W);
-    if (c->h.shape == 2)
-        deposit3q_kernel<<<dgrid, blk, 0, s>>>(dd, half_steps, out_buf);
-    else
-        deposit3d_kernel<<<dgrid, blk, 0, s>>>(dd, half_steps, out_buf);
+    if (c->h.shape == 2) {
+        if (full)
+            deposit3q_kernel<9><<<dgrid, blk, 0, s>>>(dd, half_steps, out_buf);
+        else
+            deposit3q_kernel<NXT><<<dgrid, blk, 0, s>>>(dd, half_steps, out_buf);
+    } else {
+        if (full)
+            deposit3d_kernel<9><<<dgrid, blk, 0, s>>>(dd, half_steps, out_buf);
+        else
+            deposit3d_kernel<NXT><<<dgrid, blk, 0, s>>>(dd, half_steps, out_buf);
+    }
 }
 
 static hipError_t launch_step(Ctx3D *c, hipStream_t s)
@@ -1229,7 +1253,7 @@ int moments(Ctx3D *c, double *out)
         HIPCHECK(hipMemcpyAsync(c->scratch, &D, sizeof D, hipMemcpyHostToDevice, c->stream));
         const Desc3 *dd = reinterpret_cast<const Desc3 *>(c->scratch);
         momsrc3d_kernel<<<1024, 256, 0, c->stream>>>(dd, which);
-        launch_deposit(c, dd, 0, 0, c->stream);
+        launch_deposit(c, dd, 0, 0, c->stream, true);
         HIPCHECK(hipGetLastError());
         HIPCHECK(hipStreamSynchronize(c->stream));   // D is a host temporary
     }
