@@ -28,6 +28,8 @@ METRIC = "particle-steps/s (deposit+gather+RK4) on 1 GPU vs roofline; adjoint/fo
 STATE_B = 18 * 8        # bytes of one particle's state
 SLOPE_B = 16 * 8        # bytes of one stored Runge-Kutta slope (traceless: 8 + 8 reals)
 GRID_B = 36 * 8         # bytes of one cell's combined moments
+SRC3_B = 8 * 8          # 3D: traceless deposit source per particle
+GRID3_B = 32 * 8        # 3D: one cell's traceless combined moments
 # particle bytes per stage kernel in the stage-synchronous Runge-Kutta
 # schedule: stage 1 reads Y, writes k1; stages 2, 3 read Y and the previous
 # slope, write their slope; stage 4 reads Y, k1, k2, k3 and writes Y
@@ -140,7 +142,7 @@ def measure_adjoint(steps=2000, ckpt=50, tune=None):
 
 def measure_3d(steps=20):
     """The 64^3 x 92 box (24,117,248 particles): particle kernels (state
-    passes as in 1D plus a 72-byte deposit source per particle) and the
+    passes as in 1D plus a 64-byte traceless deposit source per particle) and the
     cell-centric deposit kernels (reading the sources)."""
     import torch
     from paper_2101_02745_amd import inputs as I
@@ -173,8 +175,8 @@ def measure_3d(steps=20):
     P = w.nparticles
     part_ms = [ms[0], ms[2], ms[4], ms[6]]
     dep_ms = [ms[1], ms[3], ms[5], ms[7]]
-    part_bytes = [STAGE_BYTES[s] * P + 72 * P for s in (1, 2, 3, 4)]
-    dep_bytes = 72 * P + GRID_B * w.ncell_total
+    part_bytes = [STAGE_BYTES[s] * P + SRC3_B * P for s in (1, 2, 3, 4)]
+    dep_bytes = SRC3_B * P + GRID3_B * w.ncell_total
     step_bytes = sum(part_bytes) + 4 * dep_bytes
     ms_step = 1e3 * wall / steps
     return {"workload": w.name, "particles": P, "steps": steps, "launch": tune,
