@@ -52,6 +52,7 @@ using fpic::stage_time;
 using fpic::store_slope;
 
 constexpr int NG = 36;
+constexpr int NXT = 8;   // traceless source components (stage grids: 4 NXT)
 constexpr int BLK = 256;            // particles (threads) per workgroup
 constexpr int NWAVE = BLK / 64;
 constexpr int ACC_DOUBLES = 6144;   // LDS of the deposit box accumulators (48 KB)
@@ -273,6 +274,13 @@ pstage_kernel(const PDesc *__restrict__ dp, double *outG)
 {
     constexpr int SW = SH + 1;  // stencil cells per axis
     constexpr bool RK = MODE <= 4 || MODE == PM_S4_SORT;
+    // The stage grids hold traceless moments: the interpolated Hamiltonian
+    // is needed only up to a multiple of the identity (it commutes with rho
+    // and rhobar), so each source matrix is deposited as x11 - x00,
+    // x22 - x00 and its six off-diagonal reals (NXT = 8), 32 components per
+    // cell.  The moment diagnostics deposit all nine.
+    constexpr bool FULL = MODE == PM_MOM_NU || MODE == PM_MOM_NUBAR;
+    constexpr int NCS = FULL ? 9 : NXT, NGC = 4 * NCS;
     constexpr int STG = MODE == PM_S4_SORT ? 4 : MODE;  // Runge-Kutta stage
     __shared__ double acc[ACC_DOUBLES];
     __shared__ int sred[NWAVE][6];
@@ -319,7 +327,7 @@ pstage_kernel(const PDesc *__restrict__ dp, double *outG)
     if (RK) {
         // clear the buffer the next stage deposits into (nothing reads or
         // writes it during this launch)
-        const int64_t len = (int64_t)NG * S.ncell;
+        const int64_t len = (int64_t)NGC * S.ncell;
         for (int64_t q = i; q < len; q += (int64_t)gridDim.x * BLK)
             gst(Gclr + q, 0.0);
     }
@@ -351,10 +359,10 @@ pstage_kernel(const PDesc *__restrict__ dp, double *outG)
     }
     if (MODE <= 3) {
         gb = block_box<SW, D3>(gf, active, nn, sred, sref, go);
-        g_lds = gb.cells * NG <= ACC_DOUBLES;
+        g_lds = gb.cells * NGC <= ACC_DOUBLES;
         if (g_lds) {
             const int cells = (int)gb.cells;
-            for (int q = threadIdx.x; q < NG * cells; q += BLK) {
+            for (int q = threadIdx.x; q < NGC * cells; q += BLK) {
                 const int comp = q / cells, l = q - comp * cells;
                 const int lx = l % gb.s[0], ly = (l / gb.s[0]) % gb.s[1], lz = l / (gb.s[0] * gb.s[1]);
                 const int cz = wrap_int(gb.ref[2] + gb.lo[2] + lz, nz);
@@ -391,9 +399,9 @@ pstage_kernel(const PDesc *__restrict__ dp, double *outG)
         } else {
             // interpolate the grid at the current position: from the LDS
             // box when it was staged, else from the grid in memory
-            double A[9], Bx[9], By[9], Bz[9];
+            double A[NXT], Bx[NXT], By[NXT], Bz[NXT];  // traceless
 #pragma unroll
-            for (int k = 0; k < 9; k++)
+            for (int k = 0; k < NXT; k++)
                 A[k] = Bx[k] = By[k] = Bz[k] = 0.0;
             if (g_lds) {
                 const int cells = (int)gb.cells;
@@ -408,11 +416,11 @@ pstage_kernel(const PDesc *__restrict__ dp, double *outG)
                                                      (go[1] - gb.lo[1] + by)) * gb.s[0] +
                                               (go[0] - gb.lo[0] + bx);
 #pragma unroll
-                            for (int k = 0; k < 9; k++) {
+                            for (int k = 0; k < NXT; k++) {
                                 A[k] += w * g[k * cells];
-                                Bx[k] += w * g[(9 + k) * cells];
-                                By[k] += w * g[(18 + k) * cells];
-                                Bz[k] += w * g[(27 + k) * cells];
+                                Bx[k] += w * g[(NXT + k) * cells];
+                                By[k] += w * g[(2 * NXT + k) * cells];
+                                Bz[k] += w * g[(3 * NXT + k) * cells];
                             }
                         }
             } else {
@@ -428,18 +436,20 @@ pstage_kernel(const PDesc *__restrict__ dp, double *outG)
                             const int cx = D3 ? wrap_int(gf[0] + bx, nx) : 0;
                             const double *g = Gin + ((int64_t)cz * ny + cy) * nx + cx;
 #pragma unroll
-                            for (int k = 0; k < 9; k++) {
+                            for (int k = 0; k < NXT; k++) {
                                 A[k] += w * gld(g + (int64_t)k * nc);
-                                Bx[k] += w * gld(g + (int64_t)(9 + k) * nc);
-                                By[k] += w * gld(g + (int64_t)(18 + k) * nc);
-                                Bz[k] += w * gld(g + (int64_t)(27 + k) * nc);
+                                Bx[k] += w * gld(g + (int64_t)(NXT + k) * nc);
+                                By[k] += w * gld(g + (int64_t)(2 * NXT + k) * nc);
+                                Bz[k] += w * gld(g + (int64_t)(3 * NXT + k) * nc);
                             }
                         }
             }
+            // traceless Hnn: its ee entry is 0
             double Hnn[9];
+            Hnn[0] = 0.0;
 #pragma unroll
-            for (int k = 0; k < 9; k++)
-                Hnn[k] = A[k] - (vx * Bx[k] + vy * By[k] + vz * Bz[k]);
+            for (int k = 0; k < NXT; k++)
+                Hnn[k + 1] = A[k] - (vx * Bx[k] + vy * By[k] + vz * Bz[k]);
             // stage state y and the base of the next state (Y for stages
             // 1-3, Y + dt/6 (k1 + 2 k2 + 2 k3) for stage 4)
             double y[18], base[18];
@@ -507,6 +517,19 @@ pstage_kernel(const PDesc *__restrict__ dp, double *outG)
     }
 
     // ---- deposit with the next-stage weights ---------------------------
+    // deposit sources: the traceless part of X for the stage grids
+    double Xd[NCS];
+    if (FULL) {
+#pragma unroll
+        for (int k = 0; k < NCS; k++)
+            Xd[k] = X[k];
+    } else {
+        Xd[0] = X[1] - X[0];
+        Xd[1] = X[2] - X[0];
+#pragma unroll
+        for (int k = 2; k < NCS; k++)
+            Xd[k] = X[k + 1];
+    }
     int df[3] = {0, 0, 0}, o[3];
     double dw[3][3] = {{1.0, 0.0, 0.0}, {1.0, 0.0, 0.0}, {1.0, 0.0, 0.0}};
     axis_stencil<SH>(pz, vz, t_nxt, S.dx[2], nz, &df[2], dw[2]);
@@ -518,13 +541,13 @@ pstage_kernel(const PDesc *__restrict__ dp, double *outG)
     const int sx = db.s[0], sy = db.s[1];
     const int64_t box = db.cells;
 
-    if (box * NG <= ACC_DOUBLES) {
+    if (box * NGC <= ACC_DOUBLES) {
         // R copies of the box accumulator, lane l adding into copy l % R:
         // lanes of a dense workgroup target the same few cells, and the
         // copies spread their atomics over distinct addresses.  A copy holds
         // an odd number of doubles, so the copies start in different banks.
         const int cells = (int)box;
-        const int cstride = NG * cells + 1;
+        const int cstride = NGC * cells + 1;
         int R = MAX_COPIES;
         while (R > 1 && R * cstride > ACC_DOUBLES)
             R >>= 1;
@@ -547,17 +570,17 @@ pstage_kernel(const PDesc *__restrict__ dp, double *outG)
                 const double w = D3 ? (pick(dw[0], bx) * pick(dw[1], by)) * pick(dw[2], bz) : pick(dw[2], bz);
                 const int idx = ((o[2] - db.lo[2] + bz) * sy + (o[1] - db.lo[1] + by)) * sx + (o[0] - db.lo[0] + bx);
 #pragma unroll
-                for (int k = 0; k < 9; k++) {
-                    const double xc = w * X[k];
+                for (int k = 0; k < NCS; k++) {
+                    const double xc = w * Xd[k];
                     atomicAdd(&mine[k * cells + idx], xc);
-                    atomicAdd(&mine[(9 + k) * cells + idx], vx * xc);
-                    atomicAdd(&mine[(18 + k) * cells + idx], vy * xc);
-                    atomicAdd(&mine[(27 + k) * cells + idx], vz * xc);
+                    atomicAdd(&mine[(NCS + k) * cells + idx], vx * xc);
+                    atomicAdd(&mine[(2 * NCS + k) * cells + idx], vy * xc);
+                    atomicAdd(&mine[(3 * NCS + k) * cells + idx], vz * xc);
                 }
             }
         }
         __syncthreads();
-        for (int q = threadIdx.x; q < NG * cells; q += BLK) {
+        for (int q = threadIdx.x; q < NGC * cells; q += BLK) {
             double val = 0.0;
             for (int r = 0; r < R; r++)
                 val += acc[r * cstride + q];
@@ -584,12 +607,12 @@ pstage_kernel(const PDesc *__restrict__ dp, double *outG)
                     const int cx = D3 ? wrap_int(df[0] + bx, nx) : 0;
                     double *g = Gout + ((int64_t)cz * ny + cy) * nx + cx;
 #pragma unroll
-                    for (int k = 0; k < 9; k++) {
-                        const double xc = w * X[k];
+                    for (int k = 0; k < NCS; k++) {
+                        const double xc = w * Xd[k];
                         gatomic_add(g + (int64_t)k * nc, xc);
-                        gatomic_add(g + (int64_t)(9 + k) * nc, vx * xc);
-                        gatomic_add(g + (int64_t)(18 + k) * nc, vy * xc);
-                        gatomic_add(g + (int64_t)(27 + k) * nc, vz * xc);
+                        gatomic_add(g + (int64_t)(NCS + k) * nc, vx * xc);
+                        gatomic_add(g + (int64_t)(2 * NCS + k) * nc, vy * xc);
+                        gatomic_add(g + (int64_t)(3 * NCS + k) * nc, vz * xc);
                     }
                 }
     }
