@@ -29,7 +29,7 @@ STATE_B = 18 * 8        # bytes of one particle's state
 SLOPE_B = 16 * 8        # bytes of one stored Runge-Kutta slope (traceless: 8 + 8 reals)
 GRID_B = 36 * 8         # bytes of one cell's combined moments
 SRC3_B = 8 * 8          # 3D: traceless deposit source per particle
-GRID3_B = 32 * 8        # 3D: one cell's traceless combined moments
+GRID3_B = 32 * 8        # one cell's traceless combined moments (3D and general placement)
 # particle bytes per stage kernel in the stage-synchronous Runge-Kutta
 # schedule: stage 1 reads Y, writes k1; stages 2, 3 read Y and the previous
 # slope, write their slope; stage 4 reads Y, k1, k2, k3 and writes Y
@@ -274,7 +274,7 @@ def measure_particles(steps=200, sort_every=4, with_3d=True):
     wall = time.perf_counter() - t0
     ms = sim.profile(10)
     P = w.nparticles
-    grid = 2 * GRID_B * w.ncell_total
+    grid = 2 * GRID3_B * w.ncell_total  # traceless stage grids
     stage_bytes = [PSTAGE_BYTES[s] * P + grid for s in (1, 2, 3, 4)]
     step_bytes = sum(stage_bytes) + PSORT_BYTES * P / sort_every
     # the per-kernel timings sort after every step: their stage 4 is the
