@@ -54,8 +54,8 @@ struct Desc3 {
     const double *wN, *wNb; // [ndir] N/dV, Nbar/dV
     const double *Nw, *Nbw; // [ndir] N, Nbar
     double *Y, *K1, *K2, *K3;
-    double *X;              // [9][ndir][ncell] deposit sources
-    double *G[2];           // [36][ncell]: stage s reads G[(s-1)&1]
+    double *X;              // [9][ndir][ncell] deposit sources (stages: 8 traceless)
+    double *G[2];           // [36][ncell] (stages: 32 traceless): stage s reads G[(s-1)&1]
     int64_t *step;
     int32_t shape;          // shape-function order: 1 linear, 2 quadratic
     int32_t pad_;

@@ -11,8 +11,10 @@
 //
 // One launch per Runge-Kutta stage; a workgroup takes 256 consecutive
 // particles (one per thread).  Per particle the thread forms the stage
-// state, interpolates the 36 combined moments of the grid at its stage
-// position (the grid is small and read through the caches), builds H and
+// state, interpolates the combined moments of the grid at its stage
+// position (the 32 traceless components, see pstage_kernel; from an LDS
+// copy of the workgroup's cells in stages 1-3, through the caches in
+// stage 4), builds H and
 // Hbar (eq. potentials, Sec. II.A conventions), the commutator slopes
 // (eq. eom) and the next stage state, and deposits that state with the
 // next-stage weights (eq. pic_deposition).  Because the particles are sorted
