@@ -162,3 +162,45 @@ def test_adjoint_with_matter(torch_dev):
     assert normwise(g0.cpu().numpy(), g_ref) < 1e-10
     assert normwise(gN, gN_ref) < 1e-10
     assert normwise(gNb, gNb_ref) < 1e-10
+
+
+def draw_adjoint(case):
+    rng = np.random.default_rng(7000 + case)
+    ncell = int(rng.choice([1, 2, 17, 64, 65, 129]))
+    ndir = int(rng.choice([6, 14, 24, 26, 92]))
+    tuning = None
+    if rng.random() < 0.6:
+        tuning = {"waves": int(rng.choice([1, 2, 4])), "dirs_per_wave": int(rng.integers(1, 7))}
+    w = I.Workload(name=f"adj{case}", ncell=(1, 1, ncell), length=(1.0, 1.0, float(rng.uniform(0.15, 0.4)) * ncell),
+                   ndir=ndir, dt=float(rng.uniform(0.03, 0.12)), steps=0,
+                   f=float(rng.uniform(-0.3, 0.3)), fbar=float(rng.uniform(-0.3, 0.3)),
+                   nbar_over_n=float(rng.uniform(0.5, 1.5)), seed=int(rng.integers(1, 1 << 30)),
+                   alpha=float(10 ** rng.uniform(-3, -1.5)), vacuum=bool(rng.random() < 0.7),
+                   vmat=tuple(float(v) for v in rng.uniform(-0.3, 0.3, 3)) if rng.random() < 0.4 else (0.0, 0.0, 0.0),
+                   shape_order=int(rng.choice([1, 2])))
+    nsteps = int(rng.integers(1, 10))
+    ckpt = int(rng.integers(1, nsteps + 2))
+    step0 = int(rng.integers(0, 2000))
+    cot = rng.normal(size=(18, ndir, ncell))
+    return w, tuning, nsteps, ckpt, step0, cot
+
+
+@pytest.mark.parametrize("case", range(10))
+def test_random_adjoint(torch_dev, case):
+    """Seeded random 1D boxes (sizes, direction sets, shapes, matter and
+    vacuum terms, launch shapes, checkpoint intervals, start steps and
+    cotangents): the HIP reverse mode against the reference adjoint."""
+    from paper_2101_02745_amd.sim import Sim
+    w, tuning, nsteps, ckpt, step0, cot = draw_adjoint(case)
+    s0 = w.state0()
+    P = Problem.from_workload(w)
+    g_ref, gN_ref, gNb_ref = P.adjoint(s0, nsteps, cot, n0=step0)
+    sim = Sim.from_workload(w, tuning=tuning)
+    sim.set_state(s0, step0=step0)
+    sim.adjoint_forward(nsteps, ckpt)
+    g0, gN, gNb = sim.adjoint_backward(cot)
+    what = dict(ncell=w.ncell, ndir=w.ndir, order=w.shape_order, nsteps=nsteps, ckpt=ckpt,
+                step0=step0, tuning=tuning)
+    assert normwise(g0.cpu().numpy(), g_ref) < 1e-10, what
+    assert normwise(gN, gN_ref) < 1e-10, what
+    assert normwise(gNb, gNb_ref) < 1e-10, what
