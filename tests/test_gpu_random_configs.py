@@ -103,3 +103,53 @@ def test_3d_few_directions(torch_dev, ndir, order, ncell):
     sim.step(5)
     ref = P.step(st, 5, n0=31)
     assert_parity(sim.get_state().cpu().numpy(), ref, what=f"{ncell} ndir {ndir} order {order}")
+
+
+def draw_batch(case):
+    rng = np.random.default_rng(9000 + case)
+    nsim = int(rng.integers(2, 8))
+    order = int(rng.choice([1, 2]))
+    sims = []
+    for _ in range(nsim):
+        ncell = (1, 1, int(rng.choice([1, 3, 17, 64, 65, 100, 191])))
+        ndir = int(rng.integers(1, 40))
+        v = rng.normal(size=(ndir, 3))
+        dirs = v / np.linalg.norm(v, axis=1, keepdims=True)
+        dx = (1.0, 1.0, float(rng.uniform(0.3, 1.2)))
+        dt = float(rng.uniform(0.1, 0.95) * min(2 * dx[2] / max(np.abs(dirs[:, 2]).max(), 1e-9), 0.5))
+        N = rng.uniform(-0.3, 1.0, ndir) * dx[2] / ndir
+        Nb = rng.uniform(-0.3, 1.0, ndir) * dx[2] / ndir
+        H = I.vacuum_hamiltonian(w21=0.1, w31=0.4, delta=0.5) if rng.random() < 0.7 else np.zeros((3, 3))
+        vmat = tuple(rng.uniform(-0.5, 0.5, 3)) if rng.random() < 0.5 else None
+        st = I.state_from_seeds(0.05 * rng.uniform(-1, 1, size=(8, ndir, ncell[2])))
+        sims.append(dict(ncell=ncell, dx=dx, dirs=dirs, N=N, Nb=Nb, H=H, vmat=vmat, dt=dt, st=st,
+                         step0=int(rng.integers(0, 3000))))
+    tuning = {"waves": int(rng.choice([1, 2, 4])), "dirs_per_wave": int(rng.integers(1, 7)),
+              "steps_per_graph": int(rng.integers(1, 6)), "cache_policy": int(rng.choice([1, 2]))}
+    return sims, order, tuning, int(rng.integers(1, 9))
+
+
+@pytest.mark.parametrize("case", range(6))
+def test_random_batch(torch_dev, case):
+    """Seeded random batches of 2-7 uneven 1D boxes (sizes, direction sets,
+    weights of either sign, time steps, vacuum and matter terms, their own
+    start steps; one shape order per batch) in random launch shapes and
+    cache policies: every box against the reference."""
+    from paper_2101_02745_amd.sim import Batch
+    from paper_2101_02745_amd._lib import HostConfig
+    sims, order, tuning, nsteps = draw_batch(case)
+    cfgs = [HostConfig(s["ncell"], s["dx"], s["dirs"], s["N"], s["Nb"], s["H"], s["dt"],
+                       shape_order=order, vmat=s["vmat"]) for s in sims]
+    b = Batch(cfgs, tuning=tuning)
+    for i, s in enumerate(sims):
+        b.set_state(i, s["st"], s["step0"])
+    b.step(nsteps)
+    tots = b.flavor_totals()
+    for i, s in enumerate(sims):
+        P = Problem(s["ncell"], s["dx"], s["dirs"], s["N"], s["Nb"], s["H"], s["dt"],
+                    vmat=s["vmat"], shape_order=order)
+        ref = P.step(s["st"], nsteps, n0=s["step0"])
+        what = dict(case=case, box=i, ncell=s["ncell"], ndir=len(s["dirs"]), order=order, tuning=tuning)
+        assert_parity(b.get_state(i).cpu().numpy(), ref, what=str(what))
+        tref = P.flavor_totals(ref)
+        assert np.abs(tots[i] - tref).max() <= 1e-12 * max(np.abs(tref).max(), 1e-300), what
