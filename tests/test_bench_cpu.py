@@ -1,7 +1,7 @@
 """bench.py on the CPU: the one-GPU contract and the traffic records.
 
-* `--gpus` above 1 exits with status 2 and a message (this build measures
-  one GPU; the multi-GPU decomposition is a design note).
+* `--gpus` above 1 exits with status 2 and a message (the benchmark
+  measures one GPU; the multi-GPU decomposition is a design note).
 * The committed HBM traffic records (profiles/traffic.json) are looked up
   only when they were taken on the current kernel source: a record whose
   source hash differs reads as None, so a stale counter figure never reaches
