@@ -49,7 +49,7 @@ def draw(case):
                 nsteps=int(rng.integers(1, 9)))
 
 
-@pytest.mark.parametrize("case", range(16))
+@pytest.mark.parametrize("case", range(24))
 def test_random_particle_config(torch_dev, case):
     from paper_2101_02745_amd.particles import ParticleSim
     c = draw(case)

@@ -56,7 +56,7 @@ def draw(case):
                 tuning=tuning, step0=step0, nsteps=nsteps, dt=dt, st=st)
 
 
-@pytest.mark.parametrize("case", range(40))
+@pytest.mark.parametrize("case", range(64))
 def test_random_config(torch_dev, case):
     from paper_2101_02745_amd.sim import Sim
     from paper_2101_02745_amd._lib import HostConfig
