@@ -256,6 +256,29 @@ def measure_batch(steps=100, nsim=64):
             "ratio": ts / tb, "sims_with_negative_weights": neg}
 
 
+def probe_batch(tuning=None, steps=40):
+    """The 64-box batch alone (no sequential runs), for kernel profiles:
+    5 warm-up steps, then `steps` steps in hipGraphs."""
+    import torch
+    from paper_2101_02745_amd import inputs as I
+    from paper_2101_02745_amd._lib import HostConfig
+    from paper_2101_02745_amd.sim import Batch
+    tuning = tuning or {"waves": 4, "dirs_per_wave": 8, "steps_per_graph": 8}
+    ws = I.batch_workloads(nsim=64, steps=steps)
+    P = sum(w.nparticles for w in ws)
+    b = Batch([HostConfig.from_workload(w) for w in ws], tuning=tuning)
+    for i, w in enumerate(ws):
+        b.set_state(i, w.state0())
+    b.step(5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return {"particles": P, "steps": steps, "launch": tuning, "ms_per_step": 1e3 * wall / steps,
+            "psteps_per_s": P * steps / wall}
+
+
 def measure_particles(steps=200, sort_every=4, with_3d=True):
     """General placement: the 2048-cell, 64 pi box with 774,144 particles at
     uniform random positions (378 per cell on average), sorted by cell every
@@ -335,11 +358,12 @@ def main():
                     help="skip the adjoint and batch measurements")
     ap.add_argument("--tuning", default="",
                     help="JSON launch shape; default: autotune on the device first")
-    ap.add_argument("--probe", default="", choices=["", "copy", "kernels", "adjoint", "particles"],
+    ap.add_argument("--probe", default="", choices=["", "copy", "kernels", "adjoint", "particles", "batch"],
                     help="counter-collection modes: 'copy' runs a plain 1 GiB device copy "
                          "(the reference for HBM byte counters); 'kernels' runs 5 steps "
                          "with every kernel launched on its own, then exits; 'particles' "
-                         "times the general-placement box")
+                         "times the general-placement box; 'batch' steps the 64-box batch "
+                         "in one launch shape (--tuning, else 4 waves x 8 directions)")
     args = ap.parse_args()
     if args.probe == "copy":
         import torch
@@ -354,6 +378,10 @@ def main():
     if args.probe == "particles":
         r = measure_particles(steps=20, with_3d=False)
         print(json.dumps({"probe": "particles", **r}), flush=True)
+        return
+    if args.probe == "batch":
+        r = probe_batch(json.loads(args.tuning) if args.tuning else None)
+        print(json.dumps({"probe": "batch", **r}), flush=True)
         return
     if args.probe == "adjoint":
         r = measure_adjoint(steps=200, ckpt=50, tune=json.loads(args.tuning) if args.tuning else None)
