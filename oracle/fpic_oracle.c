@@ -282,37 +282,100 @@ typedef struct {
     cplx fb[3][3][3];
 } moments;
 
+/* Add particle p's contributions (eq. pic_deposition) into grid g. */
+static void deposit_particle(const oracle_problem *P, const double *state, double t,
+                             int64_t p, moments *grid)
+{
+    const int64_t np = nparticles(P);
+    const double *v = particle_dir(P, p);
+    const double N = particle_N(P, p), Nb = particle_Nbar(P, p);
+    cplx rho[3][3], rhob[3][3];
+    unpack(state + p, np, rho);
+    unpack(state + 9 * np + p, np, rhob);
+    stencil S;
+    shape_stencil(P, p, t, &S);
+    for (int s = 0; s < S.n; s++) {
+        moments *g = grid + S.cell[s];
+        const double wN = S.w[s] * N;
+        const double wNb = S.w[s] * Nb;
+        for (int i = 0; i < 3; i++)
+            for (int j = 0; j < 3; j++) {
+                g->n[i][j] += wN * rho[i][j];
+                g->nb[i][j] += wNb * rhob[i][j];
+                for (int a = 0; a < 3; a++) {
+                    g->f[a][i][j] += wN * rho[i][j] * v[a];
+                    g->fb[a][i][j] += wNb * rhob[i][j] * v[a];
+                }
+            }
+    }
+}
+
+/* Number of particle ranges the deposition sum is split into.  It depends
+ * on the problem size only, never on the thread count: at most 64 ranges of
+ * at least 4096 particles, and at most 4 GiB of range grids.  Problems of
+ * fewer than 8192 particles are summed in one range, in particle order. */
+static int64_t deposit_ranges(const oracle_problem *P)
+{
+    const int64_t np = nparticles(P);
+    const double grid_bytes = (double)sizeof(moments) * (double)ncell_total(P);
+    int64_t k = np / 4096;
+    if (k > 64)
+        k = 64;
+    while (k > 1 && (double)k * grid_bytes > 4294967296.0)
+        k--;
+    return k < 1 ? 1 : k;
+}
+
+/* A grid buffer for deposit(): the moment fields of every cell, followed
+ * by one grid per particle range when there is more than one range. */
+static moments *grid_alloc(const oracle_problem *P)
+{
+    const int64_t nr = deposit_ranges(P);
+    return malloc(sizeof(moments) * (size_t)ncell_total(P) * (size_t)(nr > 1 ? nr + 1 : 1));
+}
+
+/* Moment fields of eq. pic_deposition at time t into grid[0 .. ncell), a
+ * buffer from grid_alloc().  The sum over particles is split into
+ * deposit_ranges() contiguous ranges of the particle index; each range is
+ * summed in particle order into a grid of its own, and the range grids are
+ * then added cell by cell in range order, so the result is the same
+ * whatever the number of threads. */
 static void deposit(const oracle_problem *P, const double *state, double t,
                     moments *grid)
 {
     const int64_t nc = ncell_total(P), np = nparticles(P);
     const double dV = P->dx[0] * P->dx[1] * P->dx[2];
-    memset(grid, 0, sizeof(moments) * (size_t)nc);
-    for (int64_t p = 0; p < np; p++) {
-        const double *v = particle_dir(P, p);
-        const double N = particle_N(P, p), Nb = particle_Nbar(P, p);
-        cplx rho[3][3], rhob[3][3];
-        unpack(state + p, np, rho);
-        unpack(state + 9 * np + p, np, rhob);
-        stencil S;
-        shape_stencil(P, p, t, &S);
-        for (int s = 0; s < S.n; s++) {
-            moments *g = grid + S.cell[s];
-            const double wN = S.w[s] * N;
-            const double wNb = S.w[s] * Nb;
-            for (int i = 0; i < 3; i++)
-                for (int j = 0; j < 3; j++) {
-                    g->n[i][j] += wN * rho[i][j];
-                    g->nb[i][j] += wNb * rhob[i][j];
-                    for (int a = 0; a < 3; a++) {
-                        g->f[a][i][j] += wN * rho[i][j] * v[a];
-                        g->fb[a][i][j] += wNb * rhob[i][j] * v[a];
-                    }
-                }
-        }
+    const int64_t nr = deposit_ranges(P);
+    moments *part = nr > 1 ? grid + nc : grid;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1) if (nr > 1)
+#endif
+    for (int64_t r = 0; r < nr; r++) {
+        const int64_t p0 = np * r / nr, p1 = np * (r + 1) / nr;
+        memset(part + r * nc, 0, sizeof(moments) * (size_t)nc);
+        for (int64_t p = p0; p < p1; p++)
+            deposit_particle(P, state, t, p, part + r * nc);
     }
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) if (nc * nr >= 4096)
+#endif
     for (int64_t c = 0; c < nc; c++) {
         moments *g = grid + c;
+        if (nr > 1) {
+            *g = part[c];
+            for (int64_t r = 1; r < nr; r++) {
+                const moments *q = part + r * nc + c;
+                for (int i = 0; i < 3; i++)
+                    for (int j = 0; j < 3; j++) {
+                        g->n[i][j] += q->n[i][j];
+                        g->nb[i][j] += q->nb[i][j];
+                        for (int a = 0; a < 3; a++) {
+                            g->f[a][i][j] += q->f[a][i][j];
+                            g->fb[a][i][j] += q->fb[a][i][j];
+                        }
+                    }
+            }
+        }
         for (int i = 0; i < 3; i++)
             for (int j = 0; j < 3; j++) {
                 g->n[i][j] /= dV;
@@ -376,7 +439,7 @@ static void hamiltonians(const moments *m, const double *v, cplx Hv[3][3], const
 
 /* Right-hand side of eq. eom for every particle at time t. */
 static void rhs(const oracle_problem *P, const double *state, double t,
-                moments *grid, double *out)
+               moments *grid, double *out)
 {
     const int64_t np = nparticles(P);
     cplx Hv[3][3];
@@ -385,7 +448,7 @@ static void rhs(const oracle_problem *P, const double *state, double t,
     load_vmat(P, Vm);
     deposit(P, state, t, grid);
 #ifdef _OPENMP
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (np >= 4096)
 #endif
     for (int64_t p = 0; p < np; p++) {
         const double *v = particle_dir(P, p);
@@ -430,7 +493,7 @@ int oracle_set_threads(int n)
  * shape. */
 int oracle_rhs(const oracle_problem *P, const double *state, double t, double *out)
 {
-    moments *grid = malloc(sizeof(moments) * (size_t)ncell_total(P));
+    moments *grid = grid_alloc(P);
     if (!grid)
         return -1;
     rhs(P, state, t, grid, out);
@@ -444,7 +507,7 @@ int oracle_step(const oracle_problem *P, double *state, int64_t n0, int64_t nste
 {
     const int64_t len = 18 * nparticles(P);
     const double dt = P->dt;
-    moments *grid = malloc(sizeof(moments) * (size_t)ncell_total(P));
+    moments *grid = grid_alloc(P);
     double *k = malloc(sizeof(double) * (size_t)len);
     double *ks = malloc(sizeof(double) * (size_t)len);
     double *ys = malloc(sizeof(double) * (size_t)len);
@@ -455,24 +518,36 @@ int oracle_step(const oracle_problem *P, double *state, int64_t n0, int64_t nste
     for (int64_t n = n0; n < n0 + nsteps; n++) {
         /* k1 */
         rhs(P, state, stage_time(n, dt, 0.0), grid, k);
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) if (len >= 65536)
+#endif
         for (int64_t i = 0; i < len; i++) {
             ks[i] = k[i];
             ys[i] = state[i] + (0.5 * dt) * k[i];
         }
         /* k2 */
         rhs(P, ys, stage_time(n, dt, 0.5), grid, k);
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) if (len >= 65536)
+#endif
         for (int64_t i = 0; i < len; i++) {
             ks[i] = ks[i] + 2.0 * k[i];
             ys[i] = state[i] + (0.5 * dt) * k[i];
         }
         /* k3 */
         rhs(P, ys, stage_time(n, dt, 0.5), grid, k);
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) if (len >= 65536)
+#endif
         for (int64_t i = 0; i < len; i++) {
             ks[i] = ks[i] + 2.0 * k[i];
             ys[i] = state[i] + dt * k[i];
         }
         /* k4 */
         rhs(P, ys, stage_time(n, dt, 1.0), grid, k);
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) if (len >= 65536)
+#endif
         for (int64_t i = 0; i < len; i++) {
             ks[i] = ks[i] + k[i];
             state[i] = state[i] + (dt / 6.0) * ks[i];
@@ -487,7 +562,7 @@ int oracle_step(const oracle_problem *P, double *state, int64_t n0, int64_t nste
 int oracle_moments(const oracle_problem *P, const double *state, double t, double *out)
 {
     const int64_t nc = ncell_total(P);
-    moments *grid = malloc(sizeof(moments) * (size_t)nc);
+    moments *grid = grid_alloc(P);
     if (!grid)
         return -1;
     deposit(P, state, t, grid);
@@ -689,7 +764,7 @@ int oracle_adjoint(const oracle_problem *P, const double *state0, int64_t n0, in
     const int64_t nc = ncell_total(P), len = 18 * P->ndir * nc;
     const double dt = P->dt;
     double *traj = malloc(sizeof(double) * (size_t)len * (size_t)(nsteps + 1));
-    moments *grid = malloc(sizeof(moments) * (size_t)nc);
+    moments *grid = grid_alloc(P);
     moments *cot = malloc(sizeof(moments) * (size_t)nc);
     double *k = malloc(sizeof(double) * (size_t)len * 3);
     double *ys = malloc(sizeof(double) * (size_t)len * 4);
@@ -703,7 +778,10 @@ int oracle_adjoint(const oracle_problem *P, const double *state0, int64_t n0, in
     memcpy(traj, state0, sizeof(double) * (size_t)len);
     for (int64_t s = 0; s < nsteps; s++) {
         memcpy(traj + (s + 1) * len, traj + s * len, sizeof(double) * (size_t)len);
-        oracle_step(P, traj + (s + 1) * len, n0 + s, 1);
+        if (oracle_step(P, traj + (s + 1) * len, n0 + s, 1)) {
+            free(traj); free(grid); free(cot); free(k); free(ys); free(gs); free(ls); free(lsum);
+            return -1;
+        }
     }
     for (int64_t s = nsteps - 1; s >= 0; s--) {
         const int64_t n = n0 + s;
