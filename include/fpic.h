@@ -216,6 +216,29 @@ int fpic_adjoint_backward(fpic_ctx *ctx, const double *dL_dfinal, double *dL_dst
 int fpic_autotune(int32_t nsim, const fpic_config *cfgs, void *workspace, size_t bytes,
                   fpic_stream stream, fpic_tuning *best, double *ms_per_step);
 
+/* ---------------------------------------------------------------------
+ * For callers that cannot allocate device memory: code under hipGraph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ * --------------------------------------------------------------------- */
+#define FPIC_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20) /* 64 MiB per device */
+
+/* SYNC.  The same as fpic_create (workspace, tune) + fpic_set_state(state,
+ * step0) + fpic_step(nsteps) + fpic_get_state(state) + fpic_destroy, for a
+ * 1D box (ncell = {1, 1, nz}), with identical results, but without any
+ * device allocation and without a caller workspace: state (device,
+ * [18][ndir][ncell], 8-byte aligned) is advanced in place, and every other
+ * buffer lives in a fixed scratch array of FPIC_NOALLOC_SCRATCH_BYTES that
+ * the library holds on each device until the process ends.  The kernels are
+ * launched one by one on `stream`, which must belong to the calling
+ * thread's current device; the call returns when they have finished.
+ * Errors: FPIC_EINVAL for a bad configuration or for a box whose buffers
+ * exceed the scratch size (about 1.5e5 particles); FPIC_EUNSUPPORTED for
+ * 3D boxes.  All calls on one device share its scratch array and leave
+ * their data in it: calls that overlap in time on one device (other
+ * threads, other streams) race and must be serialised by the caller. */
+int fpic_step_noalloc(const fpic_config *cfg, const fpic_tuning *tune, double *state,
+                      int64_t step0, int64_t nsteps, fpic_stream stream);
+
 #ifdef __cplusplus
 }
 #endif

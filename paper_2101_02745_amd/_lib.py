@@ -91,6 +91,8 @@ EXPORTS = {
                                                C.POINTER(C.c_size_t)]),
     "fpic_adjoint_forward": (C.c_int, [C.c_void_p, C.POINTER(AdjointCfg), C.c_void_p, C.c_size_t]),
     "fpic_adjoint_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, _dp, _dp]),
+    "fpic_step_noalloc": (C.c_int, [C.POINTER(Config), C.POINTER(Tuning), C.c_void_p, C.c_int64,
+                                    C.c_int64, C.c_void_p]),
     # general particle placement (include/fpic_particles.h)
     "fpic_particles_workspace_bytes": (C.c_int, [C.POINTER(PConfig), C.POINTER(C.c_size_t)]),
     "fpic_particles_create": (C.c_int, [C.POINTER(PConfig), C.c_void_p, C.c_size_t, C.c_void_p,

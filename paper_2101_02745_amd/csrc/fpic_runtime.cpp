@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -131,7 +132,10 @@ int validate_1d(const fpic_config &c, int idx)
 
 bool is_1d(const fpic_config &c) { return c.ncell[0] == 1 && c.ncell[1] == 1; }
 
-int make_plan(int nsim, const fpic_config *cfgs, const fpic_tuning *tune, Plan &P)
+// external_state: the state array is the caller's (no room for it in the
+// workspace); used by the entry point that allocates nothing.
+int make_plan(int nsim, const fpic_config *cfgs, const fpic_tuning *tune, Plan &P,
+              bool external_state = false)
 {
     if (nsim < 1 || !cfgs)
         return fail(FPIC_EINVAL, "need at least one configuration");
@@ -191,7 +195,7 @@ int make_plan(int nsim, const fpic_config *cfgs, const fpic_tuning *tune, Plan &
         const size_t st = sizeof(double) * 18 * (size_t)s.np;
         const size_t sk = sizeof(double) * NK * (size_t)s.np;
         s.o_tab = cv.take(sizeof(double) * 7 * s.ndir);
-        s.o_Y = cv.take(st);
+        s.o_Y = cv.take(external_state ? 0 : st);
         s.o_K1 = cv.take(sk);
         s.o_K2 = cv.take(sk);
         s.o_K3 = cv.take(sk);
@@ -301,6 +305,140 @@ void xcd_order(const std::vector<WorkItem> &seq, std::vector<WorkItem> &out)
     }
 }
 
+// Host copies of everything a batch uploads into its workspace: the
+// per-simulation direction tables, the descriptors, the work tables (the
+// cost-sorted global table, then one contiguous table per simulation) and
+// the reduction table.  Device pointers in the descriptors point into ws.
+struct HostTables {
+    std::vector<double> tab;           // every simulation's [7][ndir] table
+    std::vector<size_t> tab_off;       // where simulation i's table starts in tab
+    std::vector<SimDesc> desc;
+    std::vector<WorkItem> work;
+    std::vector<RedItem> red;
+    std::vector<int> swork_off, sred_off;
+};
+
+void build_tables(const Plan &P, const fpic_config *cfgs, char *ws, HostTables &T)
+{
+    const int nsim = P.nsim;
+    T = HostTables();
+    T.desc.resize(nsim);
+    std::vector<WorkItem> persim;
+    std::vector<std::pair<int, WorkItem>> costed;
+    for (int i = 0; i < nsim; ++i) {
+        const fpic_config &c = cfgs[i];
+        const SimPlan &s = P.sims[i];
+        const double dV = c.dx[0] * c.dx[1] * c.dx[2];
+        const size_t t0 = T.tab.size();
+        T.tab_off.push_back(t0);
+        T.tab.resize(t0 + 7 * (size_t)s.ndir, 0.0);
+        double *tab = T.tab.data() + t0;
+        for (int d = 0; d < s.ndir; ++d) {
+            tab[0 * s.ndir + d] = c.dirs[3 * d + 0];
+            tab[1 * s.ndir + d] = c.dirs[3 * d + 1];
+            tab[2 * s.ndir + d] = c.dirs[3 * d + 2];
+            tab[3 * s.ndir + d] = c.N[d] / dV;
+            tab[4 * s.ndir + d] = c.Nbar[d] / dV;
+            tab[5 * s.ndir + d] = c.N[d];
+            tab[6 * s.ndir + d] = c.Nbar[d];
+        }
+        SimDesc &D = T.desc[i];
+        std::memset(&D, 0, sizeof D);
+        D.ncell = s.ncell;
+        D.ndir = s.ndir;
+        D.ntile = s.ntile;
+        D.ngroup = s.ngroup;
+        D.dpw = s.dpw;
+        D.dpg = s.dpw * P.waves;
+        D.shape = P.shape;
+        D.np = s.np;
+        D.dt = c.dt;
+        D.dz = c.dx[2];
+        // packed upper triangle of hvac; the matter potential adds to the
+        // diagonal for neutrinos and subtracts for antineutrinos (before
+        // the conjugation that forms Hbar)
+        const double *h = c.hvac;
+        const double hv[9] = {h[0], h[8], h[16], h[2], h[3], h[4], h[5], h[10], h[11]};
+        for (int k = 0; k < 9; ++k) {
+            D.hvac[k] = hv[k] + (k < 3 ? c.vmat[k] : 0.0);
+            D.hvacb[k] = hv[k] - (k < 3 ? c.vmat[k] : 0.0);
+        }
+        const double *tb = reinterpret_cast<const double *>(ws + s.o_tab);
+        D.vx = tb;
+        D.vy = tb + s.ndir;
+        D.vz = tb + 2 * s.ndir;
+        D.wN = tb + 3 * s.ndir;
+        D.wNb = tb + 4 * s.ndir;
+        D.Nw = tb + 5 * s.ndir;
+        D.Nbw = tb + 6 * s.ndir;
+        D.Y = reinterpret_cast<double *>(ws + s.o_Y);
+        D.Yout = D.Y;
+        D.K1 = reinterpret_cast<double *>(ws + s.o_K1);
+        D.K2 = reinterpret_cast<double *>(ws + s.o_K2);
+        D.K3 = reinterpret_cast<double *>(ws + s.o_K3);
+        double *g0 = reinterpret_cast<double *>(ws + s.o_G0);
+        double *g1 = reinterpret_cast<double *>(ws + s.o_G1);
+        D.G[0] = g0;
+        D.G[1] = g1;
+        D.G[2] = g0;
+        D.G[3] = g1;
+        D.G[4] = g0;
+        D.part = reinterpret_cast<double *>(ws + s.o_part);
+        D.edge = reinterpret_cast<double *>(ws + s.o_edge);
+        D.red = reinterpret_cast<double *>(ws + P.o_scratch);
+        D.step = reinterpret_cast<int64_t *>(ws + s.o_step);
+
+        T.swork_off.push_back((int)persim.size());
+        T.sred_off.push_back((int)T.red.size());
+        const int dpg = D.dpg;
+        for (int t = 0; t < s.ntile; ++t) {
+            for (int g = 0; g < s.ngroup; ++g) {
+                WorkItem w{i, t, g, 0};
+                const int nd = std::min(dpg, s.ndir - g * dpg);
+                persim.push_back(w);
+                costed.push_back({nd, w});
+            }
+            T.red.push_back(RedItem{i, t});
+        }
+    }
+    // Longest work first so the tail of the launch holds the short items;
+    // among equals, direction group outer and tile inner, so neighbouring
+    // tiles of one group (which share cache lines at their edges) are
+    // consecutive.
+    std::stable_sort(costed.begin(), costed.end(),
+                     [](const std::pair<int, WorkItem> &a, const std::pair<int, WorkItem> &b2) {
+                         if (a.first != b2.first)
+                             return a.first > b2.first;
+                         if (a.second.sim != b2.second.sim)
+                             return a.second.sim < b2.second.sim;
+                         if (a.second.group != b2.second.group)
+                             return a.second.group < b2.second.group;
+                         return a.second.tile < b2.second.tile;
+                     });
+    {
+        std::vector<WorkItem> seq;
+        for (auto &cw : costed)
+            seq.push_back(cw.second);
+        xcd_order(seq, T.work);
+    }
+    {
+        std::vector<WorkItem> tmp;
+        for (int i = 0; i < nsim; ++i) {
+            // per-simulation tables get the same treatment, simulation by
+            // simulation (each is launched on its own)
+            const SimPlan &s = P.sims[i];
+            std::vector<WorkItem> one;
+            for (int g = 0; g < s.ngroup; ++g)
+                for (int t = 0; t < s.ntile; ++t)
+                    one.push_back(WorkItem{i, t, g, 0});
+            xcd_order(one, tmp);
+            T.work.insert(T.work.end(), tmp.begin(), tmp.end());
+        }
+    }
+    for (int i = 0; i < nsim; ++i)
+        T.swork_off[i] += P.nwork;
+}
+
 int batch_build(int nsim, const fpic_config *cfgs, const fpic_tuning *tune, void *workspace,
                 size_t bytes, fpic_stream stream, fpic_batch **out)
 {
@@ -332,137 +470,27 @@ int batch_build(int nsim, const fpic_config *cfgs, const fpic_tuning *tune, void
         return code;
     };
 
-    // tables and descriptors
-    std::vector<double> tab;
-    b->hdesc.resize(nsim);
-    std::vector<WorkItem> work, persim;
-    std::vector<std::pair<int, WorkItem>> costed;
-    std::vector<RedItem> red;
-    for (int i = 0; i < nsim; ++i) {
-        const fpic_config &c = cfgs[i];
-        const SimPlan &s = P.sims[i];
-        const double dV = c.dx[0] * c.dx[1] * c.dx[2];
-        tab.assign(7 * (size_t)s.ndir, 0.0);
-        for (int d = 0; d < s.ndir; ++d) {
-            tab[0 * s.ndir + d] = c.dirs[3 * d + 0];
-            tab[1 * s.ndir + d] = c.dirs[3 * d + 1];
-            tab[2 * s.ndir + d] = c.dirs[3 * d + 2];
-            tab[3 * s.ndir + d] = c.N[d] / dV;
-            tab[4 * s.ndir + d] = c.Nbar[d] / dV;
-            tab[5 * s.ndir + d] = c.N[d];
-            tab[6 * s.ndir + d] = c.Nbar[d];
-        }
-        hipError_t e = hipMemcpy(b->ws + s.o_tab, tab.data(), sizeof(double) * tab.size(),
-                                 hipMemcpyHostToDevice);
-        if (e != hipSuccess)
-            return cleanup(fail(FPIC_EHIP, std::string("upload tables: ") + hipGetErrorString(e)));
-        SimDesc &D = b->hdesc[i];
-        std::memset(&D, 0, sizeof D);
-        D.ncell = s.ncell;
-        D.ndir = s.ndir;
-        D.ntile = s.ntile;
-        D.ngroup = s.ngroup;
-        D.dpw = s.dpw;
-        D.dpg = s.dpw * P.waves;
-        D.shape = P.shape;
-        D.np = s.np;
-        D.dt = c.dt;
-        D.dz = c.dx[2];
-        // packed upper triangle of hvac; the matter potential adds to the
-        // diagonal for neutrinos and subtracts for antineutrinos (before
-        // the conjugation that forms Hbar)
-        const double *h = c.hvac;
-        const double hv[9] = {h[0], h[8], h[16], h[2], h[3], h[4], h[5], h[10], h[11]};
-        for (int k = 0; k < 9; ++k) {
-            D.hvac[k] = hv[k] + (k < 3 ? c.vmat[k] : 0.0);
-            D.hvacb[k] = hv[k] - (k < 3 ? c.vmat[k] : 0.0);
-        }
-        const double *tb = reinterpret_cast<const double *>(b->ws + s.o_tab);
-        D.vx = tb;
-        D.vy = tb + s.ndir;
-        D.vz = tb + 2 * s.ndir;
-        D.wN = tb + 3 * s.ndir;
-        D.wNb = tb + 4 * s.ndir;
-        D.Nw = tb + 5 * s.ndir;
-        D.Nbw = tb + 6 * s.ndir;
-        D.Y = reinterpret_cast<double *>(b->ws + s.o_Y);
-        D.Yout = D.Y;
-        D.K1 = reinterpret_cast<double *>(b->ws + s.o_K1);
-        D.K2 = reinterpret_cast<double *>(b->ws + s.o_K2);
-        D.K3 = reinterpret_cast<double *>(b->ws + s.o_K3);
-        double *g0 = reinterpret_cast<double *>(b->ws + s.o_G0);
-        double *g1 = reinterpret_cast<double *>(b->ws + s.o_G1);
-        D.G[0] = g0;
-        D.G[1] = g1;
-        D.G[2] = g0;
-        D.G[3] = g1;
-        D.G[4] = g0;
-        D.part = reinterpret_cast<double *>(b->ws + s.o_part);
-        D.edge = reinterpret_cast<double *>(b->ws + s.o_edge);
-        D.red = b->dscratch;
-        D.step = reinterpret_cast<int64_t *>(b->ws + s.o_step);
-
-        b->swork_off.push_back((int)persim.size());
-        b->sred_off.push_back((int)red.size());
-        const int dpg = D.dpg;
-        for (int t = 0; t < s.ntile; ++t) {
-            for (int g = 0; g < s.ngroup; ++g) {
-                WorkItem w{i, t, g, 0};
-                const int nd = std::min(dpg, s.ndir - g * dpg);
-                persim.push_back(w);
-                costed.push_back({nd, w});
-            }
-            red.push_back(RedItem{i, t});
-        }
-    }
-    // Longest work first so the tail of the launch holds the short items;
-    // among equals, direction group outer and tile inner, so neighbouring
-    // tiles of one group (which share cache lines at their edges) are
-    // consecutive.
-    std::stable_sort(costed.begin(), costed.end(),
-                     [](const std::pair<int, WorkItem> &a, const std::pair<int, WorkItem> &b2) {
-                         if (a.first != b2.first)
-                             return a.first > b2.first;
-                         if (a.second.sim != b2.second.sim)
-                             return a.second.sim < b2.second.sim;
-                         if (a.second.group != b2.second.group)
-                             return a.second.group < b2.second.group;
-                         return a.second.tile < b2.second.tile;
-                     });
-    {
-        std::vector<WorkItem> seq;
-        for (auto &cw : costed)
-            seq.push_back(cw.second);
-        xcd_order(seq, work);
-    }
-    {
-        std::vector<WorkItem> tmp;
-        for (int i = 0; i < nsim; ++i) {
-            // per-simulation tables get the same treatment, simulation by
-            // simulation (each is launched on its own)
-            const SimPlan &s = P.sims[i];
-            std::vector<WorkItem> one;
-            for (int g = 0; g < s.ngroup; ++g)
-                for (int t = 0; t < s.ntile; ++t)
-                    one.push_back(WorkItem{i, t, g, 0});
-            xcd_order(one, tmp);
-            work.insert(work.end(), tmp.begin(), tmp.end());
-        }
-    }
-
-    hipError_t e = hipMemcpy(b->ddesc, b->hdesc.data(), sizeof(SimDesc) * nsim, hipMemcpyHostToDevice);
+    HostTables T;
+    build_tables(P, cfgs, b->ws, T);
+    b->hdesc = T.desc;
+    b->swork_off = T.swork_off;
+    b->sred_off = T.sred_off;
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < nsim && e == hipSuccess; ++i)
+        e = hipMemcpy(b->ws + P.sims[i].o_tab, T.tab.data() + T.tab_off[i],
+                      sizeof(double) * 7 * (size_t)P.sims[i].ndir, hipMemcpyHostToDevice);
     if (e == hipSuccess)
-        e = hipMemcpy(b->dwork, work.data(), sizeof(WorkItem) * work.size(), hipMemcpyHostToDevice);
+        e = hipMemcpy(b->ddesc, T.desc.data(), sizeof(SimDesc) * nsim, hipMemcpyHostToDevice);
     if (e == hipSuccess)
-        e = hipMemcpy(b->dred, red.data(), sizeof(RedItem) * red.size(), hipMemcpyHostToDevice);
+        e = hipMemcpy(b->dwork, T.work.data(), sizeof(WorkItem) * T.work.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(b->dred, T.red.data(), sizeof(RedItem) * T.red.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipHostMalloc(reinterpret_cast<void **>(&b->hbuf), sizeof(double) * 64, hipHostMallocDefault);
     if (e == hipSuccess)
         e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
     if (e != hipSuccess)
         return cleanup(fail(FPIC_EHIP, std::string("create: ") + hipGetErrorString(e)));
-    for (int i = 0; i < nsim; ++i)
-        b->swork_off[i] += P.nwork;
 
     rc = capture_steps(b, 1, &b->g1);
     if (!rc && P.spg > 1)
@@ -1190,6 +1218,108 @@ int fpic_autotune(int32_t nsim, const fpic_config *cfgs, void *workspace, size_t
     *best = bt;
     if (ms_per_step)
         *ms_per_step = best_ms;
+    return FPIC_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------- allocation-free entry
+// Device scratch of fpic_step_noalloc: every buffer a 1D box needs besides
+// its state (direction tables, descriptor, work tables, the three stored
+// slopes, the two moment grids, the partial sums and the step counter).
+// Each device the library runs on holds its own copy until the process
+// ends.  In host code `scratch` names a host-side stand-in, not device
+// memory: host code reaches the array only through the address that
+// hipGetSymbolAddress returns on each device (scratch_base below).
+namespace {
+constexpr size_t kScratchBytes = FPIC_NOALLOC_SCRATCH_BYTES;
+}  // namespace
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_base[kMaxDevices];
+
+// The device address of `scratch` on the calling thread's current device,
+// looked up once per device.
+int scratch_base(char **out)
+{
+    int dev = -1;
+    HIPCHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(FPIC_EUNSUPPORTED, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_base[dev]) {
+        void *p = nullptr;
+        HIPCHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p || reinterpret_cast<uintptr_t>(p) % 256)
+            return fail(FPIC_EHIP, "hipGetSymbolAddress gave no 256-byte aligned address");
+        g_scratch_base[dev] = p;
+    }
+    *out = static_cast<char *>(g_scratch_base[dev]);
+    return FPIC_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int fpic_step_noalloc(const fpic_config *cfg, const fpic_tuning *tune, double *state,
+                      int64_t step0, int64_t nsteps, fpic_stream stream)
+{
+    if (!cfg || !state)
+        return fail(FPIC_EINVAL, "step_noalloc: null cfg or state");
+    if (nsteps < 0)
+        return fail(FPIC_EINVAL, "step_noalloc: negative step count");
+    if (reinterpret_cast<uintptr_t>(state) % sizeof(double))
+        return fail(FPIC_EINVAL, "step_noalloc: state must be 8-byte aligned");
+    if (!is_1d(*cfg))
+        return fail(FPIC_EUNSUPPORTED, "step_noalloc: 1D boxes only (ncell = {1, 1, nz})");
+    Plan P;
+    int rc = make_plan(1, cfg, tune, P, true);
+    if (rc)
+        return rc;
+    if (P.total > kScratchBytes) {
+        char buf[200];
+        std::snprintf(buf, sizeof buf,
+                      "step_noalloc: this box needs %zu bytes of scratch; the limit is %zu "
+                      "(use fpic_create with a workspace instead)",
+                      P.total, kScratchBytes);
+        return fail(FPIC_EINVAL, buf);
+    }
+    char *ws = nullptr;
+    rc = scratch_base(&ws);
+    if (rc)
+        return rc;
+    HostTables T;
+    build_tables(P, cfg, ws, T);
+    T.desc[0].Y = state;   // stepped in place
+    T.desc[0].Yout = state;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    SimDesc *ddesc = reinterpret_cast<SimDesc *>(ws + P.o_desc);
+    WorkItem *dwork = reinterpret_cast<WorkItem *>(ws + P.o_work);
+    RedItem *dred = reinterpret_cast<RedItem *>(ws + P.o_red);
+    // stream-ordered uploads: a call queued behind an earlier call on the
+    // same stream sees its own tables
+    HIPCHECK(hipMemcpyAsync(ws + P.sims[0].o_tab, T.tab.data(), sizeof(double) * T.tab.size(),
+                            hipMemcpyHostToDevice, s));
+    HIPCHECK(hipMemcpyAsync(ddesc, T.desc.data(), sizeof(SimDesc), hipMemcpyHostToDevice, s));
+    HIPCHECK(hipMemcpyAsync(dwork, T.work.data(), sizeof(WorkItem) * (size_t)P.nwork,
+                            hipMemcpyHostToDevice, s));
+    HIPCHECK(hipMemcpyAsync(dred, T.red.data(), sizeof(RedItem) * T.red.size(),
+                            hipMemcpyHostToDevice, s));
+    // as fpic_set_state: step counter, then the first-stage moments
+    HIPCHECK(launch_set_step(ddesc, 0, 1, step0, s));
+    HIPCHECK(launch_stage1d(M_DEPOSIT, dwork, P.nwork, ddesc, P.waves, P.max_dpw, P.shape, P.nt, s));
+    HIPCHECK(launch_reduce1d(dred, P.nred, ddesc, 0, nullptr, 0, s));
+    // as fpic_step, one launch per kernel instead of a graph
+    for (int64_t n = 0; n < nsteps; ++n)
+        for (int st = M_S1; st <= M_S4; ++st) {
+            HIPCHECK(launch_stage1d(st, dwork, P.nwork, ddesc, P.waves, P.max_dpw, P.shape, P.nt, s));
+            HIPCHECK(launch_reduce1d(dred, P.nred, ddesc, st, nullptr, st == M_S4 ? 1 : 0, s));
+        }
+    // the host tables above must outlive their copies
+    HIPCHECK(hipStreamSynchronize(s));
     return FPIC_OK;
 }
 

@@ -257,3 +257,20 @@ def autotune(cfgs: Sequence[HostConfig], device: str = "cuda:0", workspace_bytes
                                 _stream_ptr(dev), C.byref(best), C.byref(ms)))
     torch.cuda.synchronize(dev)
     return best.as_dict(), ms.value
+
+
+def step_noalloc(cfg: HostConfig, state: torch.Tensor, nsteps: int, step0: int = 0,
+                 tuning: Optional[dict] = None):
+    """Advance a 1D box's state (contiguous float64 tensor [18][ndir][ncell]
+    on the current device) by nsteps RK4 steps from step number step0, in
+    place, through fpic_step_noalloc: no device memory is allocated, the
+    library's fixed scratch array holds every other buffer."""
+    lib = _lib.load()
+    dev = state.device
+    n = 18 * cfg.ndir * cfg.ncell_total
+    t = _lib.tuning(tuning)
+    with torch.cuda.device(dev):
+        check(lib.fpic_step_noalloc(C.byref(cfg.c), C.byref(t) if t is not None else None,
+                                    _dev_ptr(state, n, dev), int(step0), int(nsteps),
+                                    _stream_ptr(dev)))
+    return state
