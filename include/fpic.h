@@ -77,8 +77,7 @@ typedef struct fpic_config {
     double dt;           /* time step; a stage may move no particle by a
                             whole cell: dt/2 * max|Omega_a| < dx_a */
     int32_t shape_order; /* 1 linear (cloud in cell); 2 quadratic
-                            (triangular-shaped cloud, Sec. II.B.1; 1D
-                            boxes, batches and the adjoint only) */
+                            (triangular-shaped cloud, Sec. II.B.1) */
     int32_t flags;       /* reserved, 0 */
 } fpic_config;
 
@@ -96,6 +95,13 @@ typedef struct fpic_tuning {
                                 256 MB Infinity Cache; 0 chooses by size
                                 (streaming for a single box of >= 64 MB of
                                 state).  3D boxes always stream. */
+    int32_t fused;           /* 3D boxes with the linear shape: 0 or 1 one
+                                kernel per stage that also deposits, through
+                                per-workgroup partial rows and a small
+                                reduction; 2 a particle kernel and a deposit
+                                kernel per stage (waves and dirs_per_wave
+                                apply to these only).  Results differ by
+                                rounding only. */
 } fpic_tuning;
 
 typedef struct fpic_ctx fpic_ctx;
@@ -146,8 +152,10 @@ void fpic_destroy(fpic_ctx *ctx);
 /* SYNC.  Measurement: advance nsteps steps launching each kernel on its own
  * (outside the graph) with HIP events between launches, and return the mean
  * milliseconds per launch (host ms[8]) of: stage 1, its reduction, stage 2,
- * its reduction, stage 3, its reduction, stage 4, its reduction (3D boxes:
- * each stage's particle kernel, then its deposit kernel). */
+ * its reduction, stage 3, its reduction, stage 4, its reduction (3D boxes
+ * with fused stages: each stage kernel, then the reduction of its partial
+ * rows; 3D boxes with separate kernels: each stage's particle kernel, then
+ * its deposit kernel). */
 int fpic_profile(fpic_ctx *ctx, int32_t nsteps, double *ms);
 
 /* Message of the calling thread's last failed call ("" if none). */

@@ -41,11 +41,13 @@ class Config(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("waves", C.c_int32), ("dirs_per_wave", C.c_int32),
-                ("steps_per_graph", C.c_int32), ("cache_policy", C.c_int32)]
+                ("steps_per_graph", C.c_int32), ("cache_policy", C.c_int32),
+                ("fused", C.c_int32)]
 
     def as_dict(self):
         return {"waves": self.waves, "dirs_per_wave": self.dirs_per_wave,
-                "steps_per_graph": self.steps_per_graph, "cache_policy": self.cache_policy}
+                "steps_per_graph": self.steps_per_graph, "cache_policy": self.cache_policy,
+                "fused": self.fused}
 
 
 class AdjointCfg(C.Structure):
@@ -189,6 +191,7 @@ def tuning(t) -> Tuning:
     out.dirs_per_wave = int(t.get("dirs_per_wave", 0))
     out.steps_per_graph = int(t.get("steps_per_graph", 0))
     out.cache_policy = int(t.get("cache_policy", 0))
+    out.fused = int(t.get("fused", 0))
     return out
 
 

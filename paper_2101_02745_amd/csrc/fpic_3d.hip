@@ -43,6 +43,23 @@ using fpic::tld;
 constexpr int NG = 36;
 constexpr int W = 64;
 
+// Parameters of one direction for a fused linear stage, computed once per
+// stage by dirtab3f_kernel: its integer shift at the next stage time, the
+// offset of its current lower cell from the next one in x, its current
+// cloud-in-cell fractions (x, and the y/z weights of the four gather rows),
+// and the deposit coefficients of the next stage: c[4 q + g] = w_q m_g, with
+// w_q the y/z weight of destination row q and m = (1, v_x, v_y, v_z).
+struct FDir {
+    int32_t rxn, ryn, rzn, dxs;
+    int32_t cls, pad_[3];
+    double fx;
+    double wyz[4];
+    double fxn;     // fxn and c are contiguous: the deposit reads them as 17 reals
+    double c[16];
+    double vx, vy, vz, wN, wNb, pad2_[2];
+};
+constexpr int FDIR_DEP = 9;  // offset of fxn in an FDir, in doubles
+
 struct Desc3 {
     int32_t n[3];    // nx, ny, nz
     int32_t ndir;
@@ -59,6 +76,17 @@ struct Desc3 {
     int64_t *step;
     int32_t shape;          // shape-function order: 1 linear, 2 quadratic
     int32_t pad_;
+    // fused linear stages: [4][NGT][ncell] deposit partials, slot q = 2 cz + cy
+    // holding a workgroup's contributions to the row (cy, cz) above its own;
+    // rowmap[b] is the x-row (y + ny z) of workgroup b
+    double *P4;
+    const int32_t *rowmap;
+    // fused linear stages: per-direction parameters of the current stage
+    // (FDir, written by dirtab3f_kernel), the class order of the directions
+    // and the end of each class in it
+    FDir *ftab;
+    int32_t *forder;
+    int32_t *fcls_end;  // [9]
 };
 
 // integer shift (mod n) and fraction along one axis; one-cell axes: (0, 0)
@@ -456,6 +484,464 @@ deposit3d_kernel(const Desc3 *__restrict__ dp, int half_steps, int out_buf)
 static unsigned deposit_blocks(const Desc3 &h)
 {
     return (unsigned)(((h.n[1] + DEP_PY - 1) / DEP_PY) * ((h.n[2] + DEP_PZ - 1) / DEP_PZ));
+}
+
+// ---------------------------------------------------------------------------
+// Fused linear stages: one kernel per Runge-Kutta stage does the particle
+// update and the deposit of the next stage state, plus a small reduction.
+//
+// A workgroup (FW waves) owns one x-row (y0, z0) of *next-stage* lower
+// cells and every direction.  For direction d, lane x takes the particle
+// whose lower cell at the next stage time is (x, y0, z0), so all of the
+// workgroup's particles deposit into the same four rows (y0 + cy, z0 + cz),
+// cy, cz in {0, 1}.  Their current lower cells differ from the next ones by
+// delta in {-1, 0, 1} per axis (no particle crosses a whole cell within a
+// stage); the gather rows (y0 + delta_y + cy, z0 + delta_z + cz) are the
+// four rows staged in LDS when delta_y = delta_z = 0 (stage 2 and 4 always,
+// stages 1 and 3 for the directions that cross no cell face in y or z) and
+// are read from the grid in memory otherwise (wave-uniform).
+//
+// The deposit goes through LDS in rounds of FW directions: every wave
+// forms the traceless source X = (N/dV) rho - (Nbar/dV) rhobar^* of its
+// direction's next stage state and writes it to its LDS slot; after a
+// barrier every wave accumulates one block of the 4 rows x 32 components
+// (row q = wave & 3, component groups 2 (wave >> 2) and 2 (wave >> 2) + 1
+// of A, B_x, B_y, B_z) from all slots in slot order, pulling cell x's share
+// from particles x (weight 1 - fx) and x - 1 (weight fx).  At the end each
+// wave writes its block as the partial (slot q) of its destination row, and
+// reduce3f_kernel adds the four partials of every cell in slot order:
+// no atomics, bitwise reproducible.
+// ---------------------------------------------------------------------------
+constexpr int FW = 8;
+
+__device__ __forceinline__ int near_delta(int d, int n)
+{
+    // a difference of two shifts mod n that is known to be -1, 0 or 1 (mod n)
+    d = (d > 1) ? d - n : d;
+    return (d < -1) ? d + n : d;
+}
+
+// Directions are taken class by class, a class being the pair (delta_y,
+// delta_z) of cell faces crossed in y and z during the stage: first the
+// directions that stay in their rows, then each other class, every class in
+// ascending direction order.  The four gather rows of a class are staged in
+// LDS before its directions, so every gather reads LDS.  The fused kernel
+// takes boxes of at most FMAX_DIRS directions.
+constexpr int FMAX_DIRS = 1024;
+
+// Value of the lane one below, lane 0 taking lane n - 1 (periodic row of n
+// <= 64 cells): DPP wave_shr:1 on the two 32-bit halves, no LDS traffic.
+__device__ __forceinline__ double lane_below_wrap(double x, int lane, int n)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), 0x138, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), 0x138, 0xf, 0xf, true);
+    const double w = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), n - 1),
+                                      __builtin_amdgcn_readlane(__double2loint(x), n - 1));
+    return lane == 0 ? w : __hiloint2double(hi, lo);
+}
+
+// Value of the lane one above, lane n - 1 taking lane 0: DPP wave_shl:1.
+__device__ __forceinline__ double lane_above_wrap(double x, int lane, int n)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), 0x130, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), 0x130, 0xf, 0xf, true);
+    const double w = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), 0),
+                                      __builtin_amdgcn_readlane(__double2loint(x), 0));
+    return lane == n - 1 ? w : __hiloint2double(hi, lo);
+}
+
+// class index of (delta_y, delta_z) in {-1, 0, 1}^2, and the order in which
+// classes are taken (class 4 = (0, 0) first)
+__device__ __forceinline__ int fclass(int dy, int dz) { return (dy + 1) + 3 * (dz + 1); }
+__device__ __forceinline__ int fclass_at(int i) { return i == 0 ? 4 : (i <= 4 ? i - 1 : i); }
+
+// Stage times of a fused linear stage: the current one (gather, update) and
+// the next one (deposit).  MODE 5 deposits the current state.
+template <int MODE>
+__device__ __forceinline__ void fstage_times(int64_t n, double dt, double *t_cur, double *t_next)
+{
+    if (MODE == 1) {
+        *t_cur = stage_time(n, dt, 0.0);
+        *t_next = stage_time(n, dt, 0.5);
+    } else if (MODE == 2) {
+        *t_cur = stage_time(n, dt, 0.5);
+        *t_next = *t_cur;
+    } else if (MODE == 3) {
+        *t_cur = stage_time(n, dt, 0.5);
+        *t_next = stage_time(n, dt, 1.0);
+    } else if (MODE == 4) {
+        *t_cur = stage_time(n, dt, 1.0);
+        *t_next = stage_time(n + 1, dt, 0.0);
+    } else {
+        *t_cur = stage_time(n, dt, 0.0);
+        *t_next = *t_cur;
+    }
+}
+
+// scalar (constant address space) reads of the per-stage tables
+typedef const __attribute__((address_space(4))) FDir cFDir;
+typedef const __attribute__((address_space(4))) int32_t cint32;
+
+// The stored reals of a slope (no trace entries; see load_slope), and the
+// trace entries formed from them afterwards: split so that a kernel can issue
+// the loads well before it uses them.
+template <bool NT>
+__device__ __forceinline__ void load_slope_raw(const double *K, int64_t np, int64_t p, double k[18])
+{
+#pragma unroll
+    for (int c = 1; c < 18; c++)
+        if (c != 9)
+            k[c] = NT ? fpic::gld_nt(K + kslot(c) * np + p) : gld(K + kslot(c) * np + p);
+}
+
+__device__ __forceinline__ void slope_trace(double k[18])
+{
+    k[0] = -(k[1] + k[2]);
+    k[9] = -(k[10] + k[11]);
+}
+
+typedef const __attribute__((address_space(4))) Desc3 cDesc3;
+
+// Deposit of one round's sources (slots 0 .. nslot-1 of LDS buffer buf)
+// into this wave's accumulators: source component kown of every slot, in
+// slot order, pulling cell x's share from particles x and x - 1.
+__device__ __forceinline__ void fused_accumulate(const double (*Xb)[FW * W], const double (*Pb)[18],
+                                                 int nslot, int kown, int lane, int nx, double acc[16])
+{
+    for (int j = 0; j < nslot; ++j) {
+        const double *ps = Pb[j];
+        const double fx = ps[0];
+        const double xv = Xb[kown][j * W + lane];
+        const double xl = lane_below_wrap(xv, lane, nx);
+        const double xc = (1.0 - fx) * xv + fx * xl;
+#pragma unroll
+        for (int i = 0; i < 16; i++)
+            acc[i] += ps[1 + i] * xc;
+    }
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(FW * W)
+stage3f_kernel(const Desc3 *__restrict__ dp)
+{
+    __shared__ double Gt[MODE == 5 ? 1 : 4 * NGT * W];  // [row q = 2 qz + qy][comp][x]
+    __shared__ double Xs[2][NXT][FW * W];                // [buf][source comp][slot][x]
+    __shared__ double Ps[2][FW][18];                     // fxn, c[16] of a slot's direction
+    // The descriptor is read through the constant address space: its fields
+    // are scalar loads that no store of the kernel can alias, so the compiler
+    // may load them when used and keep or reload them freely.
+    const cDesc3 &S = *(const cDesc3 *)dp;
+    const cFDir *ft = (const cFDir *)S.ftab;
+    const cint32 *ford = (const cint32 *)S.forder;
+    const cint32 *fend = (const cint32 *)S.fcls_end;
+    const int lane = threadIdx.x & (W - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / W);
+    const int nx = S.n[0], ny = S.n[1], nz = S.n[2];
+    const int row = S.rowmap[blockIdx.x];
+    const int y0 = row % ny, z0 = row / ny;
+    const bool active = lane < nx;
+    const double dt = S.dt;
+    const double *Gin = S.G[(MODE - 1) & 1];
+    const double *Kp = (MODE == 2) ? S.K1 : (MODE == 3) ? S.K2 : S.K3;
+
+    // this wave's share of the deposit: source component k = wave, all four
+    // destination rows q and all four groups A, B_x, B_y, B_z
+    const int kown = wave;
+    double acc[16];
+#pragma unroll
+    for (int i = 0; i < 16; i++)
+        acc[i] = 0.0;
+
+    // A round's deposit is accumulated during the next round, once that
+    // round's particle loads are in flight (its own buffers stay untouched
+    // until the barrier after that round).
+    int round = 0, pend = 0;  // slots of the previous round still to deposit
+    for (int ci = 0; ci < 9; ++ci) {
+        const int cbeg = (ci == 0) ? 0 : fend[ci - 1], cend = fend[ci];
+        if (cbeg == cend)
+            continue;  // uniform
+        const int c = fclass_at(ci);
+        const int dys = c % 3 - 1, dzs = c / 3 - 1;
+        if (MODE != 5) {
+            if (round > 0)
+                __syncthreads();  // the previous class's gathers are done
+            // the class's gather rows (y0 + dys + qy, z0 + dzs + qz)
+            for (int idx = threadIdx.x; idx < 4 * NGT * nx; idx += blockDim.x) {
+                const int x = idx % nx, t = idx / nx;
+                const int comp = t % NGT, q = t / NGT;
+                int yy = y0 + dys + (q & 1), zz = z0 + dzs + (q >> 1);
+                yy = (yy < 0) ? yy + ny : (yy >= ny ? yy - ny : yy);
+                yy = (yy >= ny) ? yy - ny : yy;
+                zz = (zz < 0) ? zz + nz : (zz >= nz ? zz - nz : zz);
+                zz = (zz >= nz) ? zz - nz : zz;
+                Gt[(q * NGT + comp) * W + x] = gld(Gin + (int64_t)comp * S.ncell + ((int64_t)zz * ny + yy) * nx + x);
+            }
+            __syncthreads();
+        }
+        for (int i0 = cbeg; i0 < cend; i0 += FW, ++round) {
+            const int buf = round & 1;
+            const int idx = i0 + wave;
+            const bool has = idx < cend;  // wave-uniform
+            const int d = has ? ford[idx] : 0;
+            const cFDir &F = ft[d];
+            int64_t p = 0;
+            double Y[18], k1[18], k2[18], k3[18];
+            double pval = 0.0;
+            if (has) {
+                // the slot's deposit weights (17 reals, one per lane), loaded
+                // before the particle data, stored to LDS after the deposit of
+                // the previous round (the store waits for this load only)
+                if (lane < 17)
+                    pval = gld(reinterpret_cast<const double *>(S.ftab + d) + FDIR_DEP + lane);
+                // the particle whose next-stage lower cell is (lane, y0, z0):
+                // issue its loads first
+                int cx = lane - F.rxn, cy = y0 - F.ryn, cz = z0 - F.rzn;
+                cx = (cx < 0) ? cx + nx : cx;
+                cy = (cy < 0) ? cy + ny : cy;
+                cz = (cz < 0) ? cz + nz : cz;
+                const int64_t cc = ((int64_t)cz * ny + cy) * nx + (active ? cx : 0);
+                p = (int64_t)d * S.ncell + cc;
+                // (lanes past the row load a valid particle, cell 0's, and
+                // store nothing)
+#pragma unroll
+                for (int k = 0; k < 18; k++)
+                    Y[k] = gld(S.Y + k * S.np + p);
+                if (MODE == 4) {
+                    load_slope_raw<true>(S.K1, S.np, p, k1);
+                    load_slope_raw<true>(S.K2, S.np, p, k2);
+                    load_slope_raw<true>(S.K3, S.np, p, k3);
+                } else if (MODE == 2 || MODE == 3) {
+                    load_slope_raw<false>(Kp, S.np, p, k1);
+                }
+            }
+            if (pend)
+                fused_accumulate(Xs[buf ^ 1], Ps[buf ^ 1], pend, kown, lane, nx, acc);
+            if (has) {
+                if (lane < 17)
+                    Ps[buf][wave][lane] = pval;
+                double yn[18];
+                if (MODE == 5) {
+#pragma unroll
+                    for (int k = 0; k < 18; k++)
+                        yn[k] = Y[k];
+                } else {
+                    double yv[18], base[18];
+                    if (MODE == 1) {
+#pragma unroll
+                        for (int k = 0; k < 18; k++)
+                            yv[k] = base[k] = Y[k];
+                    } else if (MODE == 4) {
+                        const double h6 = dt / 6.0;
+                        slope_trace(k1);
+                        slope_trace(k2);
+                        slope_trace(k3);
+#pragma unroll
+                        for (int k = 0; k < 18; k++) {
+                            yv[k] = Y[k] + dt * k3[k];
+                            const double ks = (k1[k] + 2.0 * k2[k]) + 2.0 * k3[k];
+                            base[k] = Y[k] + h6 * ks;
+                        }
+                    } else {
+                        const double a = 0.5 * dt;
+                        slope_trace(k1);
+#pragma unroll
+                        for (int k = 0; k < 18; k++) {
+                            yv[k] = Y[k] + a * k1[k];
+                            base[k] = Y[k];
+                        }
+                    }
+                    // current lower cell = next lower cell + (dxs, dys, dzs):
+                    // the four staged rows, then x with the lane to the right
+                    int xa = lane + F.dxs;
+                    xa = (xa < 0) ? xa + nx : (xa >= nx ? xa - nx : xa);
+                    xa = active ? xa : 0;
+                    const double fx = F.fx;
+                    double Hnn[9];
+#pragma unroll
+                    for (int k = 0; k < 9; k++)
+                        Hnn[k] = 0.0;
+#pragma unroll 1
+                    for (int grp4 = 0; grp4 < 4; grp4++) {
+                        const double coef = (grp4 == 0) ? 1.0 : (grp4 == 1) ? -F.vx : (grp4 == 2) ? -F.vy : -F.vz;
+#pragma unroll
+                        for (int k = 0; k < NXT; k++) {
+                            const double *g = Gt + (NXT * grp4 + k) * W + xa;
+                            double ra = 0.0;
+#pragma unroll
+                            for (int q = 0; q < 4; q++)
+                                ra += F.wyz[q] * g[q * NGT * W];
+                            const double rb = lane_above_wrap(ra, lane, nx);
+                            Hnn[k + 1] += coef * ((1.0 - fx) * ra + fx * rb);
+                        }
+                    }
+                    double H[9], Hb[9], kk[18];
+#pragma unroll
+                    for (int k = 0; k < 9; k++) {
+                        H[k] = S.hvac[k] + Hnn[k];
+                        const double hb = S.hvacb[k] - Hnn[k];
+                        Hb[k] = (k == 4 || k == 6 || k == 8) ? -hb : hb;
+                    }
+                    commutator(H, yv, kk);
+                    commutator(Hb, yv + 9, kk + 9);
+                    if (MODE == 4) {
+                        const double h6 = dt / 6.0;
+#pragma unroll
+                        for (int k = 0; k < 18; k++) {
+                            yn[k] = base[k] + h6 * kk[k];
+                            if (active)
+                                fpic::gst_nt(S.Y + k * S.np + p, yn[k]);
+                        }
+                    } else {
+                        double *Ko = (MODE == 1) ? S.K1 : (MODE == 2) ? S.K2 : S.K3;
+                        const double an = (MODE == 3) ? dt : 0.5 * dt;
+#pragma unroll
+                        for (int k = 0; k < 18; k++) {
+                            if (active && k != 0 && k != 9) {
+                                if (MODE == 2)  // k2 streams; k1 and k3 stay cached (as in 1D)
+                                    fpic::gst_nt(Ko + kslot(k) * S.np + p, kk[k]);
+                                else
+                                    gst(Ko + kslot(k) * S.np + p, kk[k]);
+                            }
+                            yn[k] = base[k] + an * kk[k];
+                        }
+                    }
+                }
+                // the traceless source of the next stage state into this wave's slot
+                const double wN = F.wN, wNb = F.wNb;
+                double x[9];
+#pragma unroll
+                for (int k = 0; k < 9; k++)
+                    x[k] = (k == 4 || k == 6 || k == 8) ? wN * yn[k] + wNb * yn[9 + k] : wN * yn[k] - wNb * yn[9 + k];
+                double *xs = &Xs[buf][0][wave * W + lane];
+                xs[0 * FW * W] = active ? x[1] - x[0] : 0.0;
+                xs[1 * FW * W] = active ? x[2] - x[0] : 0.0;
+#pragma unroll
+                for (int k = 3; k < 9; k++)
+                    xs[(k - 1) * FW * W] = active ? x[k] : 0.0;
+            }
+            __syncthreads();
+            pend = min(FW, cend - i0);
+        }
+    }
+    if (pend)
+        fused_accumulate(Xs[(round - 1) & 1], Ps[(round - 1) & 1], pend, kown, lane, nx, acc);
+    if (active) {
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            int yy = y0 + (q & 1), zz = z0 + (q >> 1);
+            yy = (yy >= ny) ? yy - ny : yy;
+            zz = (zz >= nz) ? zz - nz : zz;
+            const int64_t cell = ((int64_t)zz * ny + yy) * nx + lane;
+            double *P = S.P4 + (int64_t)q * NGT * S.ncell;
+#pragma unroll
+            for (int g = 0; g < 4; g++)
+                gst(P + (int64_t)(NXT * g + kown) * S.ncell + cell, acc[4 * q + g]);
+        }
+    }
+}
+
+// Direction table of fused stage NEXT at step n (threads of one workgroup;
+// lcls: LDS scratch of FMAX_DIRS entries).
+template <int NEXT>
+__device__ void build_dirtab(const Desc3 &S, int64_t n, signed char *lcls)
+{
+    const int nx = S.n[0], ny = S.n[1], nz = S.n[2];
+    double t_cur, t_next;
+    fstage_times<NEXT>(n, S.dt, &t_cur, &t_next);
+    for (int d = threadIdx.x; d < S.ndir; d += blockDim.x) {
+        const double vx = tld(S.v[0], d), vy = tld(S.v[1], d), vz = tld(S.v[2], d);
+        int rxn, ryn, rzn, rx, ry, rz;
+        double fxn, fyn, fzn, fx, fy, fz;
+        axis_shift(vx, t_next, S.dx[0], nx, &rxn, &fxn);
+        axis_shift(vy, t_next, S.dx[1], ny, &ryn, &fyn);
+        axis_shift(vz, t_next, S.dx[2], nz, &rzn, &fzn);
+        axis_shift(vx, t_cur, S.dx[0], nx, &rx, &fx);
+        axis_shift(vy, t_cur, S.dx[1], ny, &ry, &fy);
+        axis_shift(vz, t_cur, S.dx[2], nz, &rz, &fz);
+        FDir F;
+        F.rxn = rxn;
+        F.ryn = ryn;
+        F.rzn = rzn;
+        F.dxs = near_delta(rx - rxn, nx);
+        F.cls = fclass(near_delta(ry - ryn, ny), near_delta(rz - rzn, nz));
+        F.pad_[0] = F.pad_[1] = F.pad_[2] = 0;
+        F.fx = fx;
+        F.fxn = fxn;
+        const double m[4] = {1.0, vx, vy, vz};
+#pragma unroll
+        for (int qz = 0; qz < 2; qz++)
+#pragma unroll
+            for (int qy = 0; qy < 2; qy++) {
+                const int q = 2 * qz + qy;
+                F.wyz[q] = (qy ? fy : 1.0 - fy) * (qz ? fz : 1.0 - fz);
+                const double wq = (qy ? fyn : 1.0 - fyn) * (qz ? fzn : 1.0 - fzn);
+#pragma unroll
+                for (int g = 0; g < 4; g++)
+                    F.c[4 * q + g] = wq * m[g];
+            }
+        F.vx = vx;
+        F.vy = vy;
+        F.vz = vz;
+        F.wN = tld(S.wN, d);
+        F.wNb = tld(S.wNb, d);
+        F.pad2_[0] = F.pad2_[1] = 0.0;
+        S.ftab[d] = F;
+        lcls[d] = (signed char)F.cls;
+    }
+    __syncthreads();
+    if (threadIdx.x < W) {
+        const int lane = threadIdx.x;
+        int at = 0;
+        for (int ci = 0; ci < 9; ++ci) {
+            const int c = fclass_at(ci);
+            for (int d0 = 0; d0 < S.ndir; d0 += W) {
+                const int d = d0 + lane;
+                const bool take = d < S.ndir && lcls[d] == c;
+                const uint64_t mask = __ballot(take);
+                if (take)
+                    S.forder[at + __popcll(mask & ((1ull << lane) - 1ull))] = d;
+                at += __popcll(mask);
+            }
+            if (lane == 0)
+                S.fcls_end[ci] = at;
+        }
+    }
+}
+
+// The direction table and class order of one fused stage (one workgroup).
+template <int MODE>
+__global__ void __launch_bounds__(1024) dirtab3f_kernel(const Desc3 *__restrict__ dp)
+{
+    __shared__ signed char lcls[FMAX_DIRS];
+    build_dirtab<MODE>(*dp, *dp->step, lcls);
+}
+
+// G[out_buf] = the sum of the four partial grids of a fused stage, in slot
+// order (traceless components).  Workgroup 0 also writes the direction table
+// of the next stage, NEXT, at step n + step_ahead, and then, if tick, moves
+// the step counter on by one (the next stage belongs to the next step).
+template <int NEXT>
+__global__ void __launch_bounds__(256) reduce3f_kernel(const Desc3 *__restrict__ dp, int out_buf,
+                                                      int step_ahead, int tick)
+{
+    __shared__ signed char lcls[FMAX_DIRS];
+    const Desc3 &S = *dp;
+    const int64_t len = (int64_t)NGT * S.ncell;
+    double *G = out_buf ? S.G[1] : S.G[0];
+    const double *P = S.P4;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += stride) {
+        const double a = fpic::gld_nt(P + i), b = fpic::gld_nt(P + len + i);
+        const double c = fpic::gld_nt(P + 2 * len + i), e = fpic::gld_nt(P + 3 * len + i);
+        gst(G + i, ((a + b) + c) + e);
+    }
+    if (blockIdx.x == 0) {
+        const int64_t n = *S.step;
+        build_dirtab<NEXT>(S, n + step_ahead, lcls);
+        __syncthreads();
+        if (tick && threadIdx.x == 0)
+            *S.step = n + 1;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -909,6 +1395,8 @@ struct Ctx3D {
     char *ws = nullptr;
     hipStream_t stream = nullptr, cap = nullptr;
     int waves = 8, dpw = 0, ngroup = 0, spg = 8, nitems = 0;
+    bool fused = false;  // linear shape: fused stage kernels
+    int nrows = 0;
     double *scratch = nullptr, *hbuf = nullptr;
     hipGraphExec_t g1 = nullptr, gK = nullptr;
     bool state_set = false;
@@ -917,8 +1405,9 @@ struct Ctx3D {
 static size_t al(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-    size_t tab, Y, K1, K2, K3, X, G0, G1, step, desc, scratch, total;
+    size_t tab, Y, K1, K2, K3, X, G0, G1, P4, rowmap, ftab, forder, fcls, step, desc, scratch, total;
     int waves, dpw, ngroup, spg;
+    bool fused;
 };
 
 static int validate(const fpic_config &c)
@@ -1000,6 +1489,10 @@ static int layout(const fpic_config &c, const fpic_tuning *t, Layout &L)
     L.spg = (t && t->steps_per_graph) ? t->steps_per_graph : 8;
     if (L.spg < 1 || L.spg > 256)
         return fail(FPIC_EINVAL, "steps_per_graph must be in 1..256");
+    const int fused = t ? t->fused : 0;
+    if (fused < 0 || fused > 2)
+        return fail(FPIC_EINVAL, "fused must be 0, 1 or 2");
+    L.fused = c.shape_order == 1 && fused != 2 && c.ndir <= FMAX_DIRS;
     size_t off = 0;
     auto take = [&](size_t b) {
         off = al(off);
@@ -1017,6 +1510,11 @@ static int layout(const fpic_config &c, const fpic_tuning *t, Layout &L)
     L.X = take(sizeof(double) * 9 * (size_t)np);
     L.G0 = take(sizeof(double) * NG * (size_t)nc);
     L.G1 = take(sizeof(double) * NG * (size_t)nc);
+    L.P4 = take(L.fused ? sizeof(double) * 4 * NGT * (size_t)nc : 0);
+    L.rowmap = take(sizeof(int32_t) * (size_t)nrows);
+    L.ftab = take(L.fused ? sizeof(FDir) * (size_t)c.ndir : 0);
+    L.forder = take(L.fused ? sizeof(int32_t) * (size_t)c.ndir : 0);
+    L.fcls = take(sizeof(int32_t) * 9);
     L.step = take(sizeof(int64_t));
     L.desc = take(sizeof(Desc3));
     L.scratch = take(sizeof(double) * (18 + 18 * kBlk + 3 * kBlk + 3));
@@ -1082,8 +1580,71 @@ static void launch_deposit(const Ctx3D *c, const Desc3 *dd, int half_steps, int 
     }
 }
 
+// fused linear stage `mode` (1..4; 5 = deposit of the current state) and
+// the reduction of its partials into G[out_buf]
+// The direction table of fused linear stage `mode` (1..4; 5 = deposit of
+// the current state), and the stage kernel itself.
+static void launch_dirtab(const Ctx3D *c, int mode, hipStream_t s)
+{
+    const dim3 tblk(1024);
+    switch (mode) {
+    case 1: dirtab3f_kernel<1><<<1, tblk, 0, s>>>(c->d); break;
+    case 2: dirtab3f_kernel<2><<<1, tblk, 0, s>>>(c->d); break;
+    case 3: dirtab3f_kernel<3><<<1, tblk, 0, s>>>(c->d); break;
+    case 4: dirtab3f_kernel<4><<<1, tblk, 0, s>>>(c->d); break;
+    default: dirtab3f_kernel<5><<<1, tblk, 0, s>>>(c->d); break;
+    }
+}
+
+static void launch_stage3f(const Ctx3D *c, int mode, hipStream_t s)
+{
+    const dim3 grid(c->nrows), blk(FW * W);
+    switch (mode) {
+    case 1: stage3f_kernel<1><<<grid, blk, 0, s>>>(c->d); break;
+    case 2: stage3f_kernel<2><<<grid, blk, 0, s>>>(c->d); break;
+    case 3: stage3f_kernel<3><<<grid, blk, 0, s>>>(c->d); break;
+    case 4: stage3f_kernel<4><<<grid, blk, 0, s>>>(c->d); break;
+    default: stage3f_kernel<5><<<grid, blk, 0, s>>>(c->d); break;
+    }
+}
+
+// The reduction after fused stage `done` (1..4; 5 = the deposit of the
+// current state) into G[out_buf], with the direction table of the stage
+// after it; after stage 4 it also moves the step counter on.
+static void launch_reduce3f(const Ctx3D *c, int done, hipStream_t s)
+{
+    const int64_t len = (int64_t)NGT * c->h.ncell;
+    const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(8192, (len + 255) / 256));
+    switch (done) {
+    case 1: reduce3f_kernel<2><<<blocks, 256, 0, s>>>(c->d, 1, 0, 0); break;
+    case 2: reduce3f_kernel<3><<<blocks, 256, 0, s>>>(c->d, 0, 0, 0); break;
+    case 3: reduce3f_kernel<4><<<blocks, 256, 0, s>>>(c->d, 1, 0, 0); break;
+    case 4: reduce3f_kernel<1><<<blocks, 256, 0, s>>>(c->d, 0, 1, 1); break;
+    default: reduce3f_kernel<1><<<blocks, 256, 0, s>>>(c->d, 0, 0, 0); break;
+    }
+}
+
+// Fused path: deposit the current state (its grid G[0]) and the table of
+// stage 1.
+static void deposit_current_fused(const Ctx3D *c, hipStream_t s)
+{
+    launch_dirtab(c, 5, s);
+    launch_stage3f(c, 5, s);
+    launch_reduce3f(c, 5, s);
+}
+
 static hipError_t launch_step(Ctx3D *c, hipStream_t s)
 {
+    if (c->fused) {
+        // stage k reads G[(k-1)&1]; its reduction writes G[k&1] and the
+        // table of the next stage (after stage 4: of the next step's first
+        // stage, and then moves the step counter on)
+        for (int k = 1; k <= 4; ++k) {
+            launch_stage3f(c, k, s);
+            launch_reduce3f(c, k, s);
+        }
+        return hipGetLastError();
+    }
     // stage s reads G[(s-1)&1]; its deposit writes G[s&1]
     launch_particle(c, 1, s);
     launch_deposit(c, c->d, 1, 1, s);
@@ -1134,6 +1695,8 @@ int create(const fpic_config &cfg, const fpic_tuning *tune, void *ws, size_t byt
     c->ngroup = L.ngroup;
     c->spg = L.spg;
     c->nitems = cfg.ncell[1] * cfg.ncell[2] * L.ngroup;
+    c->fused = L.fused;
+    c->nrows = cfg.ncell[1] * cfg.ncell[2];
     const int nd = cfg.ndir;
     const double dV = cfg.dx[0] * cfg.dx[1] * cfg.dx[2];
     std::vector<double> tab(7 * (size_t)nd);
@@ -1177,9 +1740,37 @@ int create(const fpic_config &cfg, const fpic_tuning *tune, void *ws, size_t byt
     D.G[0] = reinterpret_cast<double *>(c->ws + L.G0);
     D.G[1] = reinterpret_cast<double *>(c->ws + L.G1);
     D.step = reinterpret_cast<int64_t *>(c->ws + L.step);
+    D.P4 = L.fused ? reinterpret_cast<double *>(c->ws + L.P4) : nullptr;
+    D.rowmap = reinterpret_cast<const int32_t *>(c->ws + L.rowmap);
+    D.ftab = L.fused ? reinterpret_cast<FDir *>(c->ws + L.ftab) : nullptr;
+    D.forder = L.fused ? reinterpret_cast<int32_t *>(c->ws + L.forder) : nullptr;
+    D.fcls_end = reinterpret_cast<int32_t *>(c->ws + L.fcls);
     c->d = reinterpret_cast<Desc3 *>(c->ws + L.desc);
+    // The dispatcher hands workgroup b to XCD b % 8, each with its own L2:
+    // give every XCD one contiguous run of rows, so that the rows a fused
+    // workgroup stages and the partial rows it writes are shared in one L2.
+    std::vector<int32_t> rowmap(c->nrows);
+    {
+        constexpr int kXcds = 8;
+        const int n = c->nrows, per = n / kXcds, extra = n % kXcds;
+        int start[kXcds], count[kXcds], used[kXcds] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int x = 0, at = 0; x < kXcds; ++x) {
+            count[x] = per + (x < extra ? 1 : 0);
+            start[x] = at;
+            at += count[x];
+        }
+        for (int b = 0; b < n; ++b) {
+            int x = b % kXcds;
+            for (int tries = 0; tries < kXcds && used[x] >= count[x]; ++tries)
+                x = (x + 1) % kXcds;
+            rowmap[b] = start[x] + used[x]++;
+        }
+    }
     c->scratch = reinterpret_cast<double *>(c->ws + L.scratch);
     hipError_t e = hipMemcpy(c->ws + L.tab, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(c->ws + L.rowmap, rowmap.data(), sizeof(int32_t) * rowmap.size(),
+                      hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(c->d, &D, sizeof D, hipMemcpyHostToDevice);
     if (e == hipSuccess)
@@ -1208,8 +1799,12 @@ int set_state(Ctx3D *c, const double *state, int64_t step0)
     HIPCHECK(hipMemcpyAsync(c->h.Y, state, sizeof(double) * 18 * c->h.np, hipMemcpyDeviceToDevice, c->stream));
     set_step3d<<<1, 64, 0, c->stream>>>(c->d, step0);
     HIPCHECK(hipGetLastError());
-    launch_particle(c, 5, c->stream);
-    launch_deposit(c, c->d, 0, 0, c->stream);
+    if (c->fused) {
+        deposit_current_fused(c, c->stream);
+    } else {
+        launch_particle(c, 5, c->stream);
+        launch_deposit(c, c->d, 0, 0, c->stream);
+    }
     HIPCHECK(hipGetLastError());
     c->state_set = true;
     return FPIC_OK;
@@ -1315,7 +1910,30 @@ int profile(Ctx3D *c, int nsteps, double *ms)
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     hipStream_t s = c->stream;
     int rc = FPIC_OK;
-    for (int n = 0; n < nsteps && !rc; ++n) {
+    for (int n = 0; n < nsteps && !rc && c->fused; ++n) {
+        // per stage: the stage kernel, then its reduction (with the next
+        // stage's direction table)
+        hipError_t err = hipEventRecord(ev[0], s);
+        for (int k = 1; k <= 4 && err == hipSuccess; ++k) {
+            launch_stage3f(c, k, s);
+            err = hipEventRecord(ev[2 * k - 1], s);
+            launch_reduce3f(c, k, s);
+            if (err == hipSuccess)
+                err = hipEventRecord(ev[2 * k], s);
+        }
+        if (err == hipSuccess)
+            err = hipGetLastError();
+        if (err == hipSuccess)
+            err = hipEventSynchronize(ev[8]);
+        for (int k = 0; k < 8 && err == hipSuccess; ++k) {
+            float t = 0.f;
+            err = hipEventElapsedTime(&t, ev[k], ev[k + 1]);
+            acc[k] += t;
+        }
+        if (err != hipSuccess)
+            rc = fail(FPIC_EHIP, std::string("profile: ") + hipGetErrorString(err));
+    }
+    for (int n = 0; n < nsteps && !rc && !c->fused; ++n) {
         (void)hipEventRecord(ev[0], s);
         launch_particle(c, 1, s);
         (void)hipEventRecord(ev[1], s);
@@ -1376,21 +1994,31 @@ int autotune(const fpic_config &cfg, void *ws, size_t bytes, fpic_stream stream,
     double best_ms = 1e300;
     fpic_tuning bt{};
     int tried = 0;
-    std::vector<std::pair<int, int>> cands;  // (waves, dirs per wave)
+    std::vector<fpic_tuning> cands;
+    if (cfg.shape_order == 1)
+        cands.push_back(fpic_tuning{0, 0, 4, 0, 1});  // fused stages
     for (int waves : {2, 4, 8})
         for (int groups : {1, 2, 4}) {
             const int dpw = (cfg.ndir + waves * groups - 1) / (waves * groups);
             if (dpw >= 1 && (groups == 1 || dpw > 1))
-                cands.emplace_back(waves, dpw);
+                cands.push_back(fpic_tuning{waves, dpw, 4, 0, 2});
         }
-    for (auto [waves, dpw] : cands) {
-        fpic_tuning t{waves, dpw, 4, 0};
+    for (const fpic_tuning &t : cands) {
         Ctx3D *c = nullptr;
         int rc = create(cfg, &t, ws, bytes, stream, &c);
         if (rc)
             return rc;
-        // any finite state times the same: zeros
+        // any finite state times the same: zeros (deposited as by set_state,
+        // which also writes the fused path's first direction table)
         HIPCHECK(hipMemsetAsync(c->h.Y, 0, sizeof(double) * 18 * c->h.np, s));
+        set_step3d<<<1, 64, 0, s>>>(c->d, 0);
+        if (c->fused)
+            deposit_current_fused(c, s);
+        else {
+            launch_particle(c, 5, s);
+            launch_deposit(c, c->d, 0, 0, s);
+        }
+        HIPCHECK(hipGetLastError());
         c->state_set = true;
         rc = step(c, 2);
         hipEvent_t e0, e1;
