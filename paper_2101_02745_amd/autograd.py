@@ -73,6 +73,7 @@ class FlavorEvolve(torch.autograd.Function):
         Lnu = (Nt * (yT[1] + yT[2])).sum() / sN
         Lnb = (Nbt * (yT[10] + yT[11])).sum() / sNb
         ctx.sim = sim
+        ctx.pdev, ctx.pdtype = params.device, params.dtype
         ctx.save_for_backward(seeds.detach(), yT)
         ctx.aux = (N, Nb, dN_df, dNb_dnbar, dNb_dfbar, float(sN), float(sNb),
                    float(Lnu), float(Lnb))
@@ -99,7 +100,8 @@ class FlavorEvolve(torch.autograd.Function):
         gN = gN + gnu * (xs - Lnu * nc) / sN
         gNb = gNb + gnb * (xsb - Lnb * nc) / sNb
         gparams = torch.tensor([float(np.dot(gNb, dNb_dnbar)), float(np.dot(gN, dN_df)),
-                                float(np.dot(gNb, dNb_dfbar))], dtype=torch.float64)
+                                float(np.dot(gNb, dNb_dfbar))], dtype=ctx.pdtype,
+                               device=ctx.pdev)
         # chain through eq. initial_flavor_state
         gs = torch.empty_like(seeds)
         for base, o in ((0, 0), (9, 4)):
