@@ -96,23 +96,55 @@ def measured_traffic(kernel: str, workload: str, source_hash=None, launch=None):
     return ent.get("bytes_per_launch")
 
 
-def cpu_baseline(w, budget_s=20.0):
+def host_cpu():
+    """nproc, the CPUs this process may run on, and the CPU model name."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return os.cpu_count() or 1, avail, model
+
+
+def cpu_baseline(w, repeats=3):
+    """The CPU reference (the oracle, as it stands) on this host: the same
+    particle-steps/s of the same box, timed with one thread and with all the
+    host threads this process may use (capped by OMP_NUM_THREADS when that is
+    set), the median of `repeats` runs each; a bounded sample of steps."""
     import numpy as np
     from oracle import Problem, set_threads
-    threads = set_threads(min(16, os.cpu_count() or 1))
+    nproc, avail, model = host_cpu()
+    allt = avail
+    if os.environ.get("OMP_NUM_THREADS", "").isdigit():
+        allt = min(allt, int(os.environ["OMP_NUM_THREADS"]))
     P = Problem.from_workload(w)
-    s = w.state0()
-    t0 = time.perf_counter()
-    s = P.step(s, 1)
-    t1 = time.perf_counter() - t0
-    n = int(max(1, min(20, budget_s / max(t1, 1e-3))))
-    t0 = time.perf_counter()
-    P.step(s, n, n0=1)
-    dt = time.perf_counter() - t0
-    return {"value": w.nparticles * n / dt, "unit": "particle-steps/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{n} RK4 steps of the full {w.name} box ({w.nparticles} particles) "
-                      f"after one warm-up step, {threads} OpenMP threads"}
+    s = P.step(w.state0(), 1)          # warm-up (first touch of the buffers)
+    out = {}
+    for label, threads, steps in (("one_thread", 1, 1), ("all_threads", allt, 4)):
+        used = set_threads(threads)
+        rates = []
+        for r in range(repeats):
+            t0 = time.perf_counter()
+            P.step(s, steps, n0=1 + r * steps)
+            rates.append(w.nparticles * steps / (time.perf_counter() - t0))
+        out[label] = {"value": float(np.median(rates)), "threads": used, "steps": steps,
+                      "runs": rates}
+    return {"value": out["all_threads"]["value"], "unit": "particle-steps/s",
+            "cores": out["all_threads"]["threads"], "kind": "oracle",
+            "sample": f"{out['all_threads']['steps']} RK4 steps of the full {w.name} box "
+                      f"({w.nparticles} particles) per run, median of {repeats} runs, after a "
+                      f"warm-up step; {out['all_threads']['threads']} OpenMP threads "
+                      f"(one-thread figure: {out['one_thread']['steps']} step per run)",
+            "one_thread": out["one_thread"], "all_threads": out["all_threads"],
+            "nproc": nproc, "cpus_available": avail,
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS"), "cpu_model": model}
 
 
 def measure_adjoint(steps=2000, ckpt=50, tune=None):
@@ -251,10 +283,10 @@ def measure_quadratic(tuning, steps=200):
             "step_frac_of_hbm_peak": STEP_BYTES * P / (wall / steps) / 1e9 / HBM_PEAK_GBS}
 
 
-def measure_batch(steps=100, nsim=64):
-    """64 uneven 1D boxes: one batched launch per stage vs the same boxes
-    run one after another through the single-box path (each with its own
-    captured graph)."""
+def measure_batch(steps=1000, nsim=64):
+    """64 uneven 1D boxes for their 1000 steps: one batched launch per stage
+    vs the same boxes run one after another through the single-box path
+    (each with its own captured graph)."""
     import torch
     from paper_2101_02745_amd import inputs as I
     from paper_2101_02745_amd._lib import HostConfig
@@ -262,6 +294,7 @@ def measure_batch(steps=100, nsim=64):
     from paper_2101_02745_amd.sim import autotune
     ws = I.batch_workloads(nsim=nsim, steps=steps)
     P = sum(w.nparticles for w in ws)
+    ncell = sum(w.ncell_total for w in ws)
     cfgs = [HostConfig.from_workload(w) for w in ws]
     tune, _ = autotune(cfgs)
     b = Batch(cfgs, tuning=tune)
@@ -273,6 +306,8 @@ def measure_batch(steps=100, nsim=64):
     b.step(steps)
     torch.cuda.synchronize()
     tb = time.perf_counter() - t0
+    ms = b.profile(5)
+    b.close()
     del b
     sims = []
     for w in ws:
@@ -287,9 +322,25 @@ def measure_batch(steps=100, nsim=64):
     torch.cuda.synchronize()
     ts = time.perf_counter() - t0
     neg = sum(1 for w in ws if min(w.weights()[0].min(), w.weights()[1].min()) < 0)
-    return {"nsim": nsim, "particles": P, "steps": steps, "batch_launch": tune,
+    stage_ms = [ms[0], ms[2], ms[4], ms[6]]
+    stage_bytes = [STAGE_BYTES[k] * P + 2 * GRID_B * ncell for k in (1, 2, 3, 4)]
+    dom = max(range(4), key=lambda k: stage_ms[k])
+    ach = stage_bytes[dom] / (stage_ms[dom] * 1e-3) / 1e9
+    ms_step = 1e3 * tb / steps
+    return {"nsim": nsim, "particles": P, "cells": ncell, "steps": steps, "batch_launch": tune,
             "batched_psteps_per_s": P * steps / tb, "sequential_psteps_per_s": P * steps / ts,
-            "ratio": ts / tb, "sims_with_negative_weights": neg}
+            "ratio": ts / tb, "ms_per_step": ms_step,
+            "frac_of_1872B_roofline": CONTRACT_STEP_BYTES * P / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "ratio_note": "a 3x gain over the sequential runs would need "
+                          f"{3 * P * steps / ts:.3g} particle-steps/s, above the 1872 B "
+                          f"roofline of {HBM_PEAK_GBS * 1e9 / CONTRACT_STEP_BYTES:.3g}",
+            "stage_ms": stage_ms, "reduce_ms": [ms[1], ms[3], ms[5], ms[7]],
+            "roofline": {"bound": "hbm", "kernel": f"stage1d_kernel<{dom + 1}> (batched)",
+                         "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": ach / HBM_PEAK_GBS,
+                         "traffic": measured_traffic(f"stage{dom + 1}", "batch_64_uneven", launch=tune),
+                         "alg_bytes_per_launch": stage_bytes[dom], "ms_per_launch": stage_ms[dom]},
+            "sims_with_negative_weights": neg}
 
 
 def probe_batch(tuning=None, steps=40):

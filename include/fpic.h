@@ -183,6 +183,9 @@ int fpic_batch_step(fpic_batch *b, int64_t nsteps);
 int fpic_batch_flavor_totals(fpic_batch *b, double *out);
 int fpic_batch_sync(fpic_batch *b);
 void fpic_batch_destroy(fpic_batch *b);
+/* SYNC.  As fpic_profile, for the batch's segmented launches (host ms[8]:
+ * each stage kernel over all boxes, then its reduction). */
+int fpic_batch_profile(fpic_batch *b, int32_t nsteps, double *ms);
 
 /* ---------------------------------------------------------------------
  * Reverse mode (1D boxes, either shape order).  A hand-written discrete adjoint of the RK4

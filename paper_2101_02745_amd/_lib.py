@@ -87,6 +87,7 @@ EXPORTS = {
     "fpic_batch_flavor_totals": (C.c_int, [C.c_void_p, _dp]),
     "fpic_batch_sync": (C.c_int, [C.c_void_p]),
     "fpic_batch_destroy": (None, [C.c_void_p]),
+    "fpic_batch_profile": (C.c_int, [C.c_void_p, C.c_int32, _dp]),
     "fpic_autotune": (C.c_int, [C.c_int32, C.POINTER(Config), C.c_void_p, C.c_size_t, C.c_void_p,
                                 C.POINTER(Tuning), _dp]),
     "fpic_adjoint_workspace_bytes": (C.c_int, [C.c_void_p, C.POINTER(AdjointCfg),

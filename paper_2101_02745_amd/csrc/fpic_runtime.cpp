@@ -799,9 +799,16 @@ int fpic_profile(fpic_ctx *c, int32_t nsteps, double *ms)
         return fail(FPIC_EINVAL, "profile: bad argument");
     if (c->c3)
         return fpic3d::profile(c->c3, nsteps, ms);
-    fpic_batch *b = c->b;
-    if (!b->state_set[0])
-        return fail(FPIC_ESTATE, "profile before set_state");
+    return fpic_batch_profile(c->b, nsteps, ms);
+}
+
+int fpic_batch_profile(fpic_batch *b, int32_t nsteps, double *ms)
+{
+    if (!b || !ms || nsteps < 1)
+        return fail(FPIC_EINVAL, "profile: bad argument");
+    for (bool ok : b->state_set)
+        if (!ok)
+            return fail(FPIC_ESTATE, "profile before set_state");
     const Plan &P = b->plan;
     hipEvent_t ev[9];
     for (auto &e : ev)

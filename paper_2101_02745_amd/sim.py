@@ -4,6 +4,9 @@ the method runs in the HIP library."""
 from __future__ import annotations
 
 import ctypes as C
+import hashlib
+import json
+import os
 from typing import Optional, Sequence
 
 import numpy as np
@@ -202,6 +205,14 @@ class Batch:
     def sync(self):
         check(_lib.load().fpic_batch_sync(self.b))
 
+    def profile(self, nsteps: int = 10) -> np.ndarray:
+        """Mean ms per launch of [stage1, reduce1, ..., stage4, reduce4] over
+        all boxes, measured with HIP events on the batch's stream (advances
+        every box by nsteps)."""
+        out = np.empty(8)
+        check(_lib.load().fpic_batch_profile(self.b, int(nsteps), out.ctypes.data_as(_lib._dp)))
+        return out
+
     def close(self):
         if getattr(self, "b", None):
             _lib.load().fpic_batch_destroy(self.b)
@@ -231,9 +242,61 @@ def domain_averages(moments: torch.Tensor) -> dict:
     return out
 
 
-def autotune(cfgs: Sequence[HostConfig], device: str = "cuda:0", workspace_bytes=None):
-    """Time candidate launch shapes on the device; returns (tuning dict,
-    ms per step)."""
+TUNING_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_cache.json")
+
+
+def device_key(device="cuda:0") -> str:
+    """The device part of a tuning-cache key: the GPU architecture and its
+    compute-unit count."""
+    p = torch.cuda.get_device_properties(torch.device(device))
+    return f"{getattr(p, 'gcnArchName', p.name)}/{p.multi_processor_count}cu"
+
+
+def shape_key(cfgs: Sequence[HostConfig]) -> str:
+    """The box part of a tuning-cache key: cell counts, direction counts and
+    shape orders of the boxes (a batch lists every box)."""
+    desc = [[list(c.ncell), c.ndir, int(c.c.shape_order)] for c in cfgs]
+    if len(desc) == 1:
+        return json.dumps(desc[0], separators=(",", ""))
+    h = hashlib.sha256(json.dumps(desc).encode()).hexdigest()[:16]
+    return f"batch{len(desc)}:{h}"
+
+
+def _read_cache(path):
+    try:
+        return json.load(open(path))
+    except (OSError, ValueError):
+        return {}
+
+
+def autotune(cfgs: Sequence[HostConfig], device: str = "cuda:0", workspace_bytes=None,
+             cache: Optional[str] = TUNING_CACHE, retune: bool = False):
+    """Launch shape for these boxes on this device, and its ms per step.
+
+    The shape is taken from the JSON cache (keyed by device and box shapes)
+    when it holds one, else measured on the device with fpic_autotune and
+    stored in the cache (cache=None: neither read nor written; retune:
+    measure and overwrite)."""
+    cfgs = list(cfgs)
+    key = f"{device_key(device)}|{shape_key(cfgs)}"
+    if cache and not retune:
+        ent = _read_cache(cache).get(key)
+        if ent:
+            return dict(ent["launch"]), float(ent["ms_per_step"])
+    tune, ms = measure_launch(cfgs, device, workspace_bytes)
+    if cache:
+        rec = _read_cache(cache)
+        rec[key] = {"launch": tune, "ms_per_step": ms}
+        tmp = cache + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(rec, f, indent=1, sort_keys=True)
+        os.replace(tmp, cache)
+    return tune, ms
+
+
+def measure_launch(cfgs: Sequence[HostConfig], device: str = "cuda:0", workspace_bytes=None):
+    """Time candidate launch shapes on the device (fpic_autotune); returns
+    (tuning dict, ms per step)."""
     lib = _lib.load()
     dev = torch.device(device)
     cfgs = list(cfgs)
