@@ -350,8 +350,10 @@ def probe_batch(tuning=None, steps=40):
     from paper_2101_02745_amd import inputs as I
     from paper_2101_02745_amd._lib import HostConfig
     from paper_2101_02745_amd.sim import Batch
-    tuning = tuning or {"waves": 4, "dirs_per_wave": 8, "steps_per_graph": 8}
     ws = I.batch_workloads(nsim=64, steps=steps)
+    if not tuning:
+        from paper_2101_02745_amd.sim import autotune
+        tuning, _ = autotune([HostConfig.from_workload(w) for w in ws])
     P = sum(w.nparticles for w in ws)
     b = Batch([HostConfig.from_workload(w) for w in ws], tuning=tuning)
     for i, w in enumerate(ws):
@@ -440,6 +442,8 @@ def main():
     ap.add_argument("--workload", default="1d_2048x378")
     ap.add_argument("--shape", type=int, default=0, choices=[0, 1, 2],
                     help="shape-function order of the workload (0: its own; 1 linear, 2 quadratic)")
+    ap.add_argument("--step0", type=int, default=0,
+                    help="step number of the initial state (time step0*dt)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the adjoint and batch measurements")
@@ -450,7 +454,7 @@ def main():
                          "(the reference for HBM byte counters); 'kernels' runs 5 steps "
                          "with every kernel launched on its own, then exits; 'particles' "
                          "times the general-placement box; 'batch' steps the 64-box batch "
-                         "in one launch shape (--tuning, else 4 waves x 8 directions)")
+                         "in one launch shape (--tuning, else the cached autotuned one)")
     args = ap.parse_args()
     if args.probe == "copy":
         import torch
@@ -498,7 +502,7 @@ def main():
         print(f"[bench] autotuned launch shape {tuning} ({tune_ms:.4f} ms/step)",
               file=sys.stderr, flush=True)
     sim = Sim.from_workload(w, tuning=tuning)
-    sim.set_state(w.state0())
+    sim.set_state(w.state0(), args.step0)
     torch.cuda.synchronize()
     if args.probe == "kernels":
         ms = sim.profile(5)

@@ -36,6 +36,14 @@ def test_traffic_records_are_current():
         assert bench.measured_traffic(f"stage{s}", "1d_2048x378") == ent["bytes_per_launch"]
         # HBM bytes within a few percent above the algorithmic bytes
         assert 1.0 <= ent["bytes_per_launch"] / ent["alg_bytes"] < 1.2
+    for wl, hfun in (("3d_64x92", bench.source_hash_3d), ("batch_64_uneven", bench.kernel_source_hash)):
+        for k, ent in rec[wl].items():
+            assert ent["source_hash"] == hfun(), (wl, k)
+            # a record is used only in the launch shape it was taken at
+            assert bench.measured_traffic(k, wl, hfun(), launch=ent["launch"]) == ent["bytes_per_launch"]
+            other = dict(ent["launch"], steps_per_graph=ent["launch"]["steps_per_graph"] + 1)
+            assert bench.measured_traffic(k, wl, hfun(), launch=other) is None
+            assert 0.95 <= ent["bytes_per_launch"] / ent["alg_bytes"] < 1.2, (wl, k)
     h = bench.particles_source_hash()
     for k, ent in rec["1d_2048x378_random"].items():
         assert ent["source_hash"] == h, k
