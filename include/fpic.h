@@ -135,6 +135,13 @@ int fpic_moments(fpic_ctx *ctx, double *out);
  * (host out[18]). */
 int fpic_flavor_totals(fpic_ctx *ctx, double *out);
 
+/* SYNC.  Domain averages of the moment magnitudes (the quantities Sec. III.B
+ * follows in time): from moments (device [72][ncell], as fpic_moments writes
+ * them for this context), for each of n, f_x, nbar, fbar_x the mean over the
+ * cells of |X_ee|, |X_mumu|, |X_tautau|, |X_emu|, |X_etau|, |X_mutau| (host
+ * out[4][6]).  Fixed summation order. */
+int fpic_domain_averages(fpic_ctx *ctx, const double *moments, double *out);
+
 /* SYNC.  Largest |Tr rho - 1| and |Tr rhobar - 1| over all particles (host
  * *max_trace_err); returns FPIC_ENUMERIC if any state entry is NaN/Inf or
  * the trace error exceeds tol. */

@@ -71,6 +71,7 @@ EXPORTS = {
     "fpic_step": (C.c_int, [C.c_void_p, C.c_int64]),
     "fpic_moments": (C.c_int, [C.c_void_p, C.c_void_p]),
     "fpic_flavor_totals": (C.c_int, [C.c_void_p, _dp]),
+    "fpic_domain_averages": (C.c_int, [C.c_void_p, C.c_void_p, _dp]),
     "fpic_check": (C.c_int, [C.c_void_p, C.c_double, _dp]),
     "fpic_get_step": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
     "fpic_sync": (C.c_int, [C.c_void_p]),

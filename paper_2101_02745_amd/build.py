@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libflavorpic.so")
-SOURCES = ["fpic_1d.hip", "fpic_3d.hip", "fpic_particles.hip", "fpic_runtime.cpp"]
+SOURCES = ["fpic_1d.hip", "fpic_3d.hip", "fpic_particles.hip", "fpic_diag.hip", "fpic_runtime.cpp"]
 
 
 def hipcc() -> str:

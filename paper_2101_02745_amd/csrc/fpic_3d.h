@@ -24,5 +24,8 @@ int profile(Ctx3D *c, int nsteps, double *ms);
 void destroy(Ctx3D *c);
 int autotune(const fpic_config &cfg, void *ws, size_t bytes, fpic_stream stream,
              fpic_tuning *best, double *ms_per_step);
+// the context's stream, device scratch (>= 4000 doubles), pinned host
+// staging (>= 64 doubles) and cell count, for diagnostics
+void diag_buffers(Ctx3D *c, void **stream, double **scratch, double **hbuf, int64_t *ncell);
 
 }  // namespace fpic3d

@@ -1970,6 +1970,14 @@ int profile(Ctx3D *c, int nsteps, double *ms)
     return rc;
 }
 
+void diag_buffers(Ctx3D *c, void **stream, double **scratch, double **hbuf, int64_t *ncell)
+{
+    *stream = c->stream;
+    *scratch = c->scratch;
+    *hbuf = c->hbuf;
+    *ncell = c->h.ncell;
+}
+
 void destroy(Ctx3D *c)
 {
     if (!c)

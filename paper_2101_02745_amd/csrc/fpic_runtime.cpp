@@ -19,6 +19,7 @@
 #include "fpic.h"
 #include "fpic_internal.h"
 #include "fpic_3d.h"
+#include "fpic_diag.h"
 
 using namespace fpic;
 
@@ -756,6 +757,33 @@ int fpic_check(fpic_ctx *c, double tol, double *max_trace_err)
         return fail(FPIC_ENUMERIC, "state holds NaN or Inf entries");
     if (!(e <= tol))
         return fail(FPIC_ENUMERIC, "trace drift exceeds the tolerance");
+    return FPIC_OK;
+}
+
+int fpic_domain_averages(fpic_ctx *c, const double *moments, double *out)
+{
+    if (!c || !moments || !out)
+        return fail(FPIC_EINVAL, "domain_averages: null argument");
+    hipStream_t s;
+    double *scratch, *hbuf;
+    int64_t nc;
+    if (c->c3) {
+        void *sv;
+        fpic3d::diag_buffers(c->c3, &sv, &scratch, &hbuf, &nc);
+        s = static_cast<hipStream_t>(sv);
+    } else {
+        s = c->b->stream;
+        scratch = c->b->dscratch;
+        hbuf = c->b->hbuf;
+        nc = c->b->plan.sims[0].ncell;
+    }
+    // 24 sums, then nblk x 24 partials, in the context's diagnostic scratch
+    const int nblk = (int)std::max<int64_t>(1, std::min<int64_t>(128, (nc + 255) / 256));
+    HIPCHECK(launch_domain_sums(moments, nc, nblk, scratch + 24, scratch, s));
+    HIPCHECK(hipMemcpyAsync(hbuf, scratch, sizeof(double) * 24, hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    for (int q = 0; q < 24; ++q)
+        out[q] = hbuf[q] / (double)nc;
     return FPIC_OK;
 }
 

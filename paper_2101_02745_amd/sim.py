@@ -89,6 +89,18 @@ class Sim:
         check(_lib.load().fpic_flavor_totals(self.ctx, out.ctypes.data_as(_lib._dp)))
         return out.reshape(2, 9)
 
+    def domain_averages(self, moments: Optional[torch.Tensor] = None) -> dict:
+        """Domain averages of the moment magnitudes (Sec. III.B): <|n_ab|> and
+        <|f^(x)_ab|> for neutrinos and antineutrinos, reduced on the device
+        from `moments` ([72][ncell], default: this box's moments now)."""
+        if moments is None:
+            moments = self.moments()
+        out = np.empty(24)
+        check(_lib.load().fpic_domain_averages(
+            self.ctx, _dev_ptr(moments, 72 * self.cfg.ncell_total, self.device),
+            out.ctypes.data_as(_lib._dp)))
+        return unpack_domain_averages(out)
+
     def check(self, tol: float = 1e-10) -> float:
         e = C.c_double()
         check(_lib.load().fpic_check(self.ctx, float(tol), C.byref(e)))
@@ -225,19 +237,16 @@ class Batch:
             pass
 
 
-def domain_averages(moments: torch.Tensor) -> dict:
-    """Domain averages of the magnitudes of the moment entries (Sec. III.B):
-    <|n_ab|> and <|f^(x)_ab|> for neutrinos and antineutrinos, from the
-    [72][ncell] output of Sim.moments().  Keys: 'n', 'fx', 'nbar', 'fxbar',
-    each a 3x3 array of averages (diagonal and upper triangle filled)."""
-    m = moments.double()
+def unpack_domain_averages(out24) -> dict:
+    """The 4 x 6 averages of fpic_domain_averages as 3x3 arrays (diagonal
+    and upper triangle filled): keys 'n', 'fx', 'nbar', 'fxbar'."""
     out = {}
-    for name, base in (("n", 0), ("fx", 9), ("nbar", 36), ("fxbar", 45)):
+    v = np.asarray(out24).reshape(4, 6)
+    for f, name in enumerate(("n", "fx", "nbar", "fxbar")):
         a = np.zeros((3, 3))
         for i in range(3):
-            a[i, i] = m[base + i].abs().mean().item()
-        for (i, j), k in (((0, 1), 3), ((0, 2), 5), ((1, 2), 7)):
-            a[i, j] = torch.hypot(m[base + k], m[base + k + 1]).mean().item()
+            a[i, i] = v[f, i]
+        a[0, 1], a[0, 2], a[1, 2] = v[f, 3], v[f, 4], v[f, 5]
         out[name] = a
     return out
 
