@@ -61,7 +61,9 @@ typedef void *fpic_stream; /* hipStream_t */
 /* A periodic box with one particle per direction per cell. */
 typedef struct fpic_config {
     int32_t ncell[3];    /* cells along x, y, z; a 1D box is {1, 1, nz};
-                            any other shape is a 3D box and needs nx <= 64 */
+                            any other shape is a 3D box (at most 2^30
+                            cells); boxes with nx <= 64 and the linear
+                            shape take the fused stage kernels */
     double dx[3];        /* cell widths (cell volume dx*dy*dz) */
     int32_t ndir;        /* directions = particles per cell */
     const double *dirs;  /* host [ndir][3] unit vectors Omega_d */
@@ -101,7 +103,9 @@ typedef struct fpic_tuning {
                                 reduction; 2 a particle kernel and a deposit
                                 kernel per stage (waves and dirs_per_wave
                                 apply to these only).  Results differ by
-                                rounding only. */
+                                rounding only.  Boxes with nx > 64 or more
+                                than 1024 directions always take the
+                                separate kernels. */
 } fpic_tuning;
 
 typedef struct fpic_ctx fpic_ctx;

@@ -20,7 +20,8 @@
 // Positions are implicit as in 1D: particle (d, c) is at cell c shifted by
 // floor(Omega_a t / dx_a) along each axis with fraction Omega_a t / dx_a minus
 // that, t = n dt + c_s dt.  Along an axis with one cell the particle stays in
-// cell 0 with weight 1.  The x axis of a box must fit one wave (nx <= 64).
+// cell 0 with weight 1.  A row of at most 64 cells is one wave (lane = x);
+// a longer row is cut into segments with halo lanes (XRow below).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -131,6 +132,47 @@ __device__ __forceinline__ double lane_get(double v, int src)
     return __shfl(v, src, W);
 }
 
+// x-rows and waves.  In a box with nx <= 64 a wave holds a whole x-row:
+// lane x is cell x and the neighbours of lane x are the lanes x +- 1 mod nx.
+// A longer row is cut into segments of sw = 64 - HL - HR cells; lane j of
+// segment s holds cell (s sw - HL + j) mod nx, the lanes [HL, HL + width)
+// own the segment's cells, and the HL lanes below and HR lanes above them
+// only supply neighbour values: the cell to the right for the linear
+// interpolation in x (HR = 1), the particle to the left for the linear
+// deposit (HL = 1), both for the quadratic shape.  Every lane of a segment
+// holds a real cell, so its loads need no mask.
+__host__ __device__ constexpr int xsegs(int nx, int sw) { return nx <= W ? 1 : (nx + sw - 1) / sw; }
+
+struct XRow {
+    int x;            // the lane's cell (0 in lanes past a whole row)
+    bool own;         // the lane updates / writes its cell
+    bool valid;       // the lane holds a cell of the row (its values are used)
+    int left, right;  // lanes holding cells x - 1 and x + 1
+};
+
+template <int HL, int HR>
+__device__ __forceinline__ XRow xrow(int nx, int seg, int lane)
+{
+    XRow r;
+    if (nx <= W) {
+        r.valid = r.own = lane < nx;
+        r.x = r.own ? lane : 0;
+        r.left = (lane + nx - 1) % nx;
+        r.right = (lane + 1) % nx;
+    } else {
+        constexpr int sw = W - HL - HR;
+        const int x0 = seg * sw;
+        int x = x0 - HL + lane;  // in [-1, 2 nx)
+        x = (x < 0) ? x + nx : ((x >= nx) ? x - nx : x);
+        r.x = x;
+        r.valid = true;
+        r.own = lane >= HL && lane < HL + min(sw, nx - x0);
+        r.left = lane - 1;   // owners never take lane -1 or 64
+        r.right = lane + 1;
+    }
+    return r;
+}
+
 // Stage deposits carry the traceless part of each 3x3 source matrix: the
 // interpolated Hamiltonian is needed only up to a multiple of the identity,
 // which commutes with every state and leaves both commutators unchanged.
@@ -179,10 +221,13 @@ particle3d_kernel(const Desc3 *__restrict__ dp, int dpw, int nitems)
     if (item >= nitems)
         return;  // whole workgroup: uniform
     const int nx = S.n[0], ny = S.n[1], nz = S.n[2];
-    const int nrows = ny * nz;
-    const int row = item % nrows, grp = item / nrows;
+    const int nseg = xsegs(nx, W - 1);
+    const int nrs = ny * nz * nseg;
+    const int rs = item % nrs, grp = item / nrs;
+    const int row = rs / nseg, seg = rs % nseg;
     const int y0 = row % ny, z0 = row / ny;
-    const bool active = lane < nx;
+    const XRow xr = xrow<0, 1>(nx, seg, lane);
+    const bool active = xr.own;
     const int64_t n = *S.step;
     const double dt = S.dt;
     double t_cur = 0.0;
@@ -195,16 +240,20 @@ particle3d_kernel(const Desc3 *__restrict__ dp, int dpw, int nitems)
     const double *Gin = S.G[(MODE - 1) & 1];
     const double *Kp = (MODE == 2) ? S.K1 : (MODE == 3) ? S.K2 : S.K3;
     const int dbeg = (grp * nwaves + wave) * dpw, dend = min(dbeg + dpw, S.ndir);
-    const int right = (lane + 1) % (nx < 1 ? 1 : nx);
+    const int right = xr.right;
 
     if (MODE != 5) {
-        for (int idx = threadIdx.x; idx < 4 * NGT * nx; idx += blockDim.x) {
-            const int x = idx % nx, t = idx / nx;
+        // column j: the cell of lane j
+        const int ncol = min(nx, W), xbase = (nx <= W) ? 0 : seg * (W - 1);
+        for (int idx = threadIdx.x; idx < 4 * NGT * ncol; idx += blockDim.x) {
+            const int j = idx % ncol, t = idx / ncol;
             const int comp = t % NGT, q = t / NGT;
             int yy = y0 + (q & 1), zz = z0 + (q >> 1);
             yy = (yy >= ny) ? yy - ny : yy;
             zz = (zz >= nz) ? zz - nz : zz;
-            Gt[(q * NGT + comp) * W + x] = gld(Gin + (int64_t)comp * S.ncell + ((int64_t)zz * ny + yy) * nx + x);
+            int x = xbase + j;
+            x = (x >= nx) ? x - nx : x;
+            Gt[(q * NGT + comp) * W + j] = gld(Gin + (int64_t)comp * S.ncell + ((int64_t)zz * ny + yy) * nx + x);
         }
         __syncthreads();
     }
@@ -216,12 +265,12 @@ particle3d_kernel(const Desc3 *__restrict__ dp, int dpw, int nitems)
         double fx = 0.0, fy = 0.0, fz = 0.0;
         int64_t c;
         if (MODE == 5) {
-            c = (int64_t)row * nx + (active ? lane : 0);
+            c = (int64_t)row * nx + xr.x;
         } else {
             axis_shift(vx, t_cur, S.dx[0], nx, &rx, &fx);
             axis_shift(vy, t_cur, S.dx[1], ny, &ry, &fy);
             axis_shift(vz, t_cur, S.dx[2], nz, &rz, &fz);
-            int cx = lane - rx, cy = y0 - ry, cz = z0 - rz;
+            int cx = xr.x - rx, cy = y0 - ry, cz = z0 - rz;
             cx = (cx < 0) ? cx + nx : cx;
             cy = (cy < 0) ? cy + ny : cy;
             cz = (cz < 0) ? cz + nz : cz;
@@ -261,7 +310,7 @@ particle3d_kernel(const Desc3 *__restrict__ dp, int dpw, int nitems)
                     double r = 0.0;
 #pragma unroll
                     for (int q = 0; q < 4; q++)
-                        r += wyz[q] * (active ? g[q * NGT * W] : 0.0);
+                        r += wyz[q] * (xr.valid ? g[q * NGT * W] : 0.0);
                     const double nb = lane_get(r, right);
                     const double val = (1.0 - fx) * r + fx * nb;
                     Hnn[k + 1] += coef * val;
@@ -347,8 +396,8 @@ struct Pull {
 };
 
 // One direction's components and interpolation fractions, and its 4 NC raw
-// source values for the wave's row.  Lanes past the row (lane >= nx) load
-// cell 0 of the row (never used).
+// source values for the wave's row at the lane's cell xc (lanes past a whole
+// row load a cell of the row that is never used).
 template <int NC>
 struct DepDir {
     double vx, vy, vz, fx, fy, fz;
@@ -356,7 +405,7 @@ struct DepDir {
 };
 
 template <int NC>
-__device__ __forceinline__ void dep_load(const Desc3 &S, int d, double t, int y, int z, int lane,
+__device__ __forceinline__ void dep_load(const Desc3 &S, int d, double t, int y, int z, int xc,
                                          DepDir<NC> &o)
 {
     const int nx = S.n[0], ny = S.n[1], nz = S.n[2];
@@ -371,9 +420,8 @@ __device__ __forceinline__ void dep_load(const Desc3 &S, int d, double t, int y,
     rx = __builtin_amdgcn_readfirstlane(rx);
     ry = __builtin_amdgcn_readfirstlane(ry);
     rz = __builtin_amdgcn_readfirstlane(rz);
-    int xs = lane - rx;
+    int xs = xc - rx;
     xs = (xs < 0) ? xs + nx : xs;
-    xs = (lane < nx) ? xs : 0;
 #pragma unroll
     for (int cz = 0; cz < 2; cz++)
 #pragma unroll
@@ -442,12 +490,14 @@ deposit3d_kernel(const Desc3 *__restrict__ dp, int half_steps, int out_buf)
     const int lane = threadIdx.x & (W - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / W);
     const int nx = S.n[0], ny = S.n[1], nz = S.n[2];
+    const int nseg = xsegs(nx, W - 1);
+    const int patch = blockIdx.x / nseg, seg = blockIdx.x % nseg;
     const int npy = (ny + DEP_PY - 1) / DEP_PY;
-    const int y = (blockIdx.x % npy) * DEP_PY + wave % DEP_PY;
-    const int z = (blockIdx.x / npy) * DEP_PZ + wave / DEP_PY;
+    const int y = (patch % npy) * DEP_PY + wave % DEP_PY;
+    const int z = (patch / npy) * DEP_PZ + wave / DEP_PY;
     if (y >= ny || z >= nz)
         return;  // no workgroup barrier in this kernel
-    const bool active = lane < nx;
+    const XRow xr = xrow<1, 0>(nx, seg, lane);
     const int64_t n0 = *S.step;
     // half_steps: 0 -> t_n, 1 -> t_n + dt/2, 2 -> t_n + dt (stage 4 of step
     // n), 3 -> first stage of step n + 1
@@ -456,34 +506,38 @@ deposit3d_kernel(const Desc3 *__restrict__ dp, int half_steps, int out_buf)
         t = stage_time(n0 + 1, S.dt, 0.0);
     else
         t = stage_time(n0, S.dt, 0.5 * half_steps);
-    const int left = (lane + nx - 1) % (nx < 1 ? 1 : nx);
+    const int left = xr.left;
     double acc[4 * NC];
 #pragma unroll
     for (int q = 0; q < 4 * NC; q++)
         acc[q] = 0.0;
     DepDir<NC> nxt;
     if (S.ndir > 0)
-        dep_load<NC>(S, 0, t, y, z, lane, nxt);
+        dep_load<NC>(S, 0, t, y, z, xr.x, nxt);
     for (int d = 0; d < S.ndir; ++d) {
         const DepDir<NC> cur = nxt;
         if (d + 1 < S.ndir)
-            dep_load<NC>(S, d + 1, t, y, z, lane, nxt);
+            dep_load<NC>(S, d + 1, t, y, z, xr.x, nxt);
         Pull<NC> a;
-        pull_dir<NC>(cur, active, a);
+        pull_dir<NC>(cur, xr.valid, a);
         accumulate<NC>(a, left, acc);
     }
-    if (active) {
+    if (xr.own) {
         double *G = out_buf ? S.G[1] : S.G[0];  // (no dynamic index into the descriptor)
-        const int64_t cell = ((int64_t)z * ny + y) * nx + lane;
+        const int64_t cell = ((int64_t)z * ny + y) * nx + xr.x;
 #pragma unroll
         for (int q = 0; q < 4 * NC; q++)
             gst(G + (int64_t)q * S.ncell + cell, acc[q]);
     }
 }
 
+// workgroups of a deposit launch: patches of rows times x-segments (segments
+// of 63 cells for the linear shape, 62 for the quadratic one)
 static unsigned deposit_blocks(const Desc3 &h)
 {
-    return (unsigned)(((h.n[1] + DEP_PY - 1) / DEP_PY) * ((h.n[2] + DEP_PZ - 1) / DEP_PZ));
+    const int sw = (h.shape == 2) ? W - 2 : W - 1;
+    return (unsigned)(((h.n[1] + DEP_PY - 1) / DEP_PY) * ((h.n[2] + DEP_PZ - 1) / DEP_PZ) *
+                      xsegs(h.n[0], sw));
 }
 
 // ---------------------------------------------------------------------------
@@ -1013,10 +1067,13 @@ particle3q_kernel(const Desc3 *__restrict__ dp, int dpw, int nitems)
     if (item >= nitems)
         return;
     const int nx = S.n[0], ny = S.n[1], nz = S.n[2];
-    const int nrows = ny * nz;
-    const int row = item % nrows, grp = item / nrows;
+    const int nseg = xsegs(nx, W - 2);
+    const int nrs = ny * nz * nseg;
+    const int rs = item % nrs, grp = item / nrs;
+    const int row = rs / nseg, seg = rs % nseg;
     const int y0 = row % ny, z0 = row / ny;
-    const bool active = lane < nx;
+    const XRow xw = xrow<1, 1>(nx, seg, lane);
+    const bool active = xw.own;
     const int64_t n = *S.step;
     const double dt = S.dt;
     double t_cur = 0.0;
@@ -1029,20 +1086,23 @@ particle3q_kernel(const Desc3 *__restrict__ dp, int dpw, int nitems)
     const double *Gin = S.G[(MODE - 1) & 1];
     const double *Kp = (MODE == 2) ? S.K1 : (MODE == 3) ? S.K2 : S.K3;
     const int dbeg = (grp * nwaves + wave) * dpw, dend = min(dbeg + dpw, S.ndir);
-    const int xl = (lane + nx - 1) % (nx < 1 ? 1 : nx), xr = (lane + 1) % (nx < 1 ? 1 : nx);
+    const int xl = xw.left, xr = xw.right;
     // Stage the nine grid rows around the nearest row (y0, z0) in LDS, row
     // q = 3 c + b being (y0 + b - 1, z0 + c - 1): the 32 traceless moment
     // components of the stage grid (36 would not fit at 64 cells per row).
-    // Columns past the row (x >= nx) hold 0.
+    // Column j holds the cell of lane j; columns past a whole row (j >= nx)
+    // hold 0.
+    const int xbase = (nx <= W) ? 0 : seg * (W - 2) - 1 + nx;
     for (int idx = threadIdx.x; idx < 9 * 4 * W; idx += blockDim.x) {
-        const int x = idx % W, t = idx / W;
+        const int j = idx % W, t = idx / W;
         const int g4 = t % 4, q = t / 4;  // eight components of one matrix per task
         const int b = q % 3, cc = q / 3;
         double v[NXT];
 #pragma unroll
         for (int k = 0; k < NXT; k++)
             v[k] = 0.0;
-        if (x < nx) {
+        if (nx > W || j < nx) {
+            const int x = (nx <= W) ? j : (xbase + j) % nx;
             const int64_t cell = ((int64_t)wrap(z0 + cc - 1, nz) * ny + wrap(y0 + b - 1, ny)) * nx + x;
 #pragma unroll
             for (int k = 0; k < NXT; k++)
@@ -1050,7 +1110,7 @@ particle3q_kernel(const Desc3 *__restrict__ dp, int dpw, int nitems)
         }
 #pragma unroll
         for (int k = 0; k < NXT; k++)
-            Gq[(q * NGT + NXT * g4 + k) * W + x] = v[k];
+            Gq[(q * NGT + NXT * g4 + k) * W + j] = v[k];
     }
     __syncthreads();
 
@@ -1137,7 +1197,7 @@ particle3q_kernel(const Desc3 *__restrict__ dp, int dpw, int nitems)
                 for (int k = 1; k < 9; k++)
                     Hnn[k] = m ? Hb4[jj][k - 1] : Hnn[k];
             }
-            const int cx = wrap(lane - rx, nx), cy = wrap(y0 - ry, ny), cz = wrap(z0 - rz, nz);
+            const int cx = wrap(xw.x - rx, nx), cy = wrap(y0 - ry, ny), cz = wrap(z0 - rz, nz);
             const int64_t c = ((int64_t)cz * ny + cy) * nx + (active ? cx : 0);
             const int64_t p = (int64_t)d * S.ncell + c;
             double Y[18];
@@ -1223,19 +1283,22 @@ deposit3q_kernel(const Desc3 *__restrict__ dp, int half_steps, int out_buf)
     const int lane = threadIdx.x & (W - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / W);
     const int nx = S.n[0], ny = S.n[1], nz = S.n[2];
+    const int nseg = xsegs(nx, W - 2);
+    const int patch = blockIdx.x / nseg, seg = blockIdx.x % nseg;
     const int npy = (ny + DEP_PY - 1) / DEP_PY;
-    const int y = (blockIdx.x % npy) * DEP_PY + wave % DEP_PY;
-    const int z = (blockIdx.x / npy) * DEP_PZ + wave / DEP_PY;
+    const int y = (patch % npy) * DEP_PY + wave % DEP_PY;
+    const int z = (patch / npy) * DEP_PZ + wave / DEP_PY;
     if (y >= ny || z >= nz)
         return;  // no workgroup barrier in this kernel
-    const bool active = lane < nx;
+    const XRow xw = xrow<1, 1>(nx, seg, lane);
+    const bool active = xw.valid;
     const int64_t n0 = *S.step;
     double t;
     if (half_steps == 3)
         t = stage_time(n0 + 1, S.dt, 0.0);
     else
         t = stage_time(n0, S.dt, 0.5 * half_steps);
-    const int xl = (lane + nx - 1) % (nx < 1 ? 1 : nx), xr = (lane + 1) % (nx < 1 ? 1 : nx);
+    const int xl = xw.left, xr = xw.right;
     double acc[4 * NC];
 #pragma unroll
     for (int q = 0; q < 4 * NC; q++)
@@ -1247,7 +1310,7 @@ deposit3q_kernel(const Desc3 *__restrict__ dp, int half_steps, int out_buf)
         axis_quad(vx, t, S.dx[0], nx, &rx, wx);
         axis_quad(vy, t, S.dx[1], ny, &ry, wy);
         axis_quad(vz, t, S.dx[2], nz, &rz, wz);
-        const int xs = active ? wrap(lane - rx, nx) : 0;
+        const int xs = wrap(xw.x - rx, nx);
         double Xyz[NC];
 #pragma unroll
         for (int k = 0; k < NC; k++)
@@ -1273,9 +1336,9 @@ deposit3q_kernel(const Desc3 *__restrict__ dp, int half_steps, int out_buf)
             acc[3 * NC + k] += vz * xc;
         }
     }
-    if (active) {
+    if (xw.own) {
         double *G = out_buf ? S.G[1] : S.G[0];
-        const int64_t cell = ((int64_t)z * ny + y) * nx + lane;
+        const int64_t cell = ((int64_t)z * ny + y) * nx + xw.x;
 #pragma unroll
         for (int q = 0; q < 4 * NC; q++)
             gst(G + (int64_t)q * S.ncell + cell, acc[q]);
@@ -1414,8 +1477,6 @@ static int validate(const fpic_config &c)
 {
     if (c.ncell[0] < 1 || c.ncell[1] < 1 || c.ncell[2] < 1 || c.ndir < 1)
         return fail(FPIC_EINVAL, "cell and direction counts must be >= 1");
-    if (c.ncell[0] > W)
-        return fail(FPIC_EUNSUPPORTED, "3D boxes need nx <= 64 (the x axis of a box fits one wave)");
     if (!c.dirs || !c.N || !c.Nbar)
         return fail(FPIC_EINVAL, "dirs, N and Nbar must be non-null host arrays");
     if (c.shape_order != 1 && c.shape_order != 2)
@@ -1470,7 +1531,8 @@ static int layout(const fpic_config &c, const fpic_tuning *t, Layout &L)
         return rc;
     const int64_t nc = (int64_t)c.ncell[0] * c.ncell[1] * c.ncell[2];
     const int64_t np = nc * c.ndir;
-    const int64_t nrows = (int64_t)c.ncell[1] * c.ncell[2];
+    // x-rows, or x-segments of rows longer than a wave, of the particle kernels
+    const int64_t nrows = (int64_t)c.ncell[1] * c.ncell[2] * xsegs(c.ncell[0], c.shape_order == 2 ? W - 2 : W - 1);
     L.waves = (t && t->waves) ? t->waves : 8;
     if (L.waves != 1 && L.waves != 2 && L.waves != 4 && L.waves != MAX_WAVES3)
         return fail(FPIC_EINVAL, "waves must be 1, 2, 4 or 8 for 3D boxes");
@@ -1492,7 +1554,7 @@ static int layout(const fpic_config &c, const fpic_tuning *t, Layout &L)
     const int fused = t ? t->fused : 0;
     if (fused < 0 || fused > 2)
         return fail(FPIC_EINVAL, "fused must be 0, 1 or 2");
-    L.fused = c.shape_order == 1 && fused != 2 && c.ndir <= FMAX_DIRS;
+    L.fused = c.shape_order == 1 && fused != 2 && c.ndir <= FMAX_DIRS && c.ncell[0] <= W;
     size_t off = 0;
     auto take = [&](size_t b) {
         off = al(off);
@@ -1536,7 +1598,9 @@ int workspace_bytes(const fpic_config &cfg, const fpic_tuning *tune, size_t *byt
 // particle kernels, and the deposit of the sources, for the box's shape order
 static void launch_particle(const Ctx3D *c, int mode, hipStream_t s)
 {
-    const dim3 pgrid(c->nitems), pblk(c->waves * W);
+    // MODE 5 is the linear kernel in both shapes: its own x-segments
+    const int items5 = c->h.n[1] * c->h.n[2] * xsegs(c->h.n[0], W - 1) * c->ngroup;
+    const dim3 pgrid(mode == 5 ? items5 : c->nitems), pblk(c->waves * W);
     const bool q = c->h.shape == 2;
     switch (mode) {
     case 1:
@@ -1556,7 +1620,7 @@ static void launch_particle(const Ctx3D *c, int mode, hipStream_t s)
         else particle3d_kernel<4><<<pgrid, pblk, 0, s>>>(c->d, c->dpw, c->nitems);
         break;
     default:  // no interpolation: the same for both shapes
-        particle3d_kernel<5><<<pgrid, pblk, 0, s>>>(c->d, c->dpw, c->nitems);
+        particle3d_kernel<5><<<pgrid, pblk, 0, s>>>(c->d, c->dpw, items5);
         break;
     }
 }
@@ -1694,7 +1758,8 @@ int create(const fpic_config &cfg, const fpic_tuning *tune, void *ws, size_t byt
     c->dpw = L.dpw;
     c->ngroup = L.ngroup;
     c->spg = L.spg;
-    c->nitems = cfg.ncell[1] * cfg.ncell[2] * L.ngroup;
+    c->nitems = cfg.ncell[1] * cfg.ncell[2] * xsegs(cfg.ncell[0], cfg.shape_order == 2 ? W - 2 : W - 1) *
+                L.ngroup;
     c->fused = L.fused;
     c->nrows = cfg.ncell[1] * cfg.ncell[2];
     const int nd = cfg.ndir;
