@@ -47,6 +47,10 @@ CONTRACT_STEP_BYTES = 13 * STATE_B        # 1872 B per particle-step
 PSTATIC_B = (1 + 3 + 2) * 8
 PSTAGE_BYTES = {s: b + PSTATIC_B for s, b in STAGE_BYTES.items()}
 PSORT_BYTES = 16 + PSTATIC_B + 4
+# 3D general placement: three position components instead of one
+PSTATIC3_B = (3 + 3 + 2) * 8
+PSTAGE3_BYTES = {s: b + PSTATIC3_B for s, b in STAGE_BYTES.items()}
+PSORT3_BYTES = 48 + PSTATIC3_B + 4
 
 
 def kernel_source_hash():
@@ -368,15 +372,17 @@ def probe_batch(tuning=None, steps=40):
             "psteps_per_s": P * steps / wall}
 
 
-def measure_particles(steps=200, sort_every=4, with_3d=True):
+def measure_particles(steps=200, sort_every=4, with_3d=True, exact=True):
     """General placement: the 2048-cell, 64 pi box with 774,144 particles at
     uniform random positions (378 per cell on average), sorted by cell every
-    `sort_every` steps inside the timed region."""
+    `sort_every` steps inside the timed region.  exact: deposits summed
+    exactly (bitwise reproducible, the library's default); otherwise with
+    floating-point atomics (reported beside it)."""
     import torch
     from paper_2101_02745_amd import inputs as I
     from paper_2101_02745_amd.particles import ParticleSim
     w = I.particle_workload("1d_2048x378_random")
-    sim = ParticleSim.from_workload(w, sort_every=sort_every)
+    sim = ParticleSim.from_workload(w, sort_every=sort_every, exact=exact)
     sim.set_workload(w)
     sim.step(4 * sort_every)
     torch.cuda.synchronize()
@@ -392,11 +398,13 @@ def measure_particles(steps=200, sort_every=4, with_3d=True):
     # the per-kernel timings sort after every step: their stage 4 is the
     # sorting form (pstage_kernel<8>), which also moves the particles
     stage_bytes[3] += PSORT_BYTES * P
-    names = ["pstage_kernel<1>", "pstage_kernel<2>", "pstage_kernel<3>", "pstage_kernel<8>"]
+    mode = "exact" if exact else "float_atomics"
+    names = [f"pstage_kernel<{m}> {mode}" for m in (1, 2, 3, 8)]
     ms_step = 1e3 * wall / steps
     dom = max(range(4), key=lambda k: ms[k])
     sim.close()
-    return {"workload": w.name, "particles": P, "steps": steps, "sort_every": sort_every,
+    out = {"workload": w.name, "particles": P, "steps": steps, "sort_every": sort_every,
+            "deposit_sums": "exact" if exact else "float_atomics",
             "value": P * steps / wall, "unit": "particle-steps/s", "ms_per_step": ms_step,
             "stage_ms": list(ms[:4]), "sort_count_scan_ms": ms[4],
             "stage_GBs": [b / (t * 1e-3) / 1e9 for b, t in zip(stage_bytes, ms[:4])],
@@ -407,18 +415,26 @@ def measure_particles(steps=200, sort_every=4, with_3d=True):
                          "frac": stage_bytes[dom] / (ms[dom] * 1e-3) / 1e9 / HBM_PEAK_GBS,
                          "alg_bytes_per_launch": stage_bytes[dom], "ms_per_launch": ms[dom]},
             "alg_bytes_per_step": step_bytes,
-            "step_frac_of_hbm_peak": step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
-            "box3d": measure_particles_3d() if with_3d else None}
+            "step_frac_of_hbm_peak": step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    if with_3d:
+        out["box3d"] = measure_particles_3d(exact=exact)
+    if exact:
+        fast = measure_particles(steps, sort_every, with_3d, exact=False)
+        out["float_atomics"] = {"value": fast["value"], "ms_per_step": fast["ms_per_step"],
+                                "roofline_frac": fast["roofline"]["frac"],
+                                "box3d": {k: fast["box3d"][k] for k in ("value", "ms_per_step")}
+                                if with_3d else None}
+    return out
 
 
-def measure_particles_3d(steps=16, sort_every=4):
+def measure_particles_3d(steps=16, sort_every=4, exact=True):
     """General placement in 3D: 32^3 cells, 92 particles per cell on average
     at random positions (3,014,656 particles)."""
     import torch
     from paper_2101_02745_amd import inputs as I
     from paper_2101_02745_amd.particles import ParticleSim
     w = I.particle_workload("3d_32x92_random")
-    sim = ParticleSim.from_workload(w, sort_every=sort_every)
+    sim = ParticleSim.from_workload(w, sort_every=sort_every, exact=exact)
     sim.set_workload(w)
     sim.step(2 * sort_every)
     torch.cuda.synchronize()
@@ -428,10 +444,28 @@ def measure_particles_3d(steps=16, sort_every=4):
     wall = time.perf_counter() - t0
     ms = sim.profile(3)
     sim.close()
-    return {"workload": w.name, "particles": w.nparticles, "steps": steps,
-            "sort_every": sort_every, "value": w.nparticles * steps / wall,
-            "unit": "particle-steps/s", "ms_per_step": 1e3 * wall / steps,
-            "stage_ms": list(ms[:4]), "sort_count_scan_ms": ms[4]}
+    P = w.nparticles
+    grid = 2 * GRID3_B * w.ncell_total
+    stage_bytes = [PSTAGE3_BYTES[s] * P + grid for s in (1, 2, 3, 4)]
+    step_bytes = sum(stage_bytes) + PSORT3_BYTES * P / sort_every
+    stage_bytes[3] += PSORT3_BYTES * P  # the profiled stage 4 sorts
+    names = ["pstage_kernel<1>", "pstage_kernel<2>", "pstage_kernel<3>", "pstage_kernel<8>"]
+    ms_step = 1e3 * wall / steps
+    dom = max(range(4), key=lambda k: ms[k])
+    return {"workload": w.name, "particles": P, "steps": steps,
+            "sort_every": sort_every, "deposit_sums": "exact" if exact else "float_atomics",
+            "value": P * steps / wall,
+            "unit": "particle-steps/s", "ms_per_step": ms_step,
+            "stage_ms": list(ms[:4]), "sort_count_scan_ms": ms[4],
+            "stage_GBs": [b / (t * 1e-3) / 1e9 for b, t in zip(stage_bytes, ms[:4])],
+            "roofline": {"bound": "hbm", "kernel": names[dom],
+                         "traffic": measured_traffic(names[dom], w.name, particles_source_hash()),
+                         "achieved": stage_bytes[dom] / (ms[dom] * 1e-3) / 1e9,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": stage_bytes[dom] / (ms[dom] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                         "alg_bytes_per_launch": stage_bytes[dom], "ms_per_launch": ms[dom]},
+            "alg_bytes_per_step": step_bytes,
+            "step_frac_of_hbm_peak": step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
 
 def main():
@@ -449,7 +483,8 @@ def main():
                     help="skip the adjoint and batch measurements")
     ap.add_argument("--tuning", default="",
                     help="JSON launch shape; default: autotune on the device first")
-    ap.add_argument("--probe", default="", choices=["", "copy", "kernels", "adjoint", "particles", "batch"],
+    ap.add_argument("--probe", default="", choices=["", "copy", "kernels", "adjoint", "particles",
+                                                    "particles3d", "batch"],
                     help="counter-collection modes: 'copy' runs a plain 1 GiB device copy "
                          "(the reference for HBM byte counters); 'kernels' runs 5 steps "
                          "with every kernel launched on its own, then exits; 'particles' "
@@ -469,6 +504,11 @@ def main():
     if args.probe == "particles":
         r = measure_particles(steps=20, with_3d=False)
         print(json.dumps({"probe": "particles", **r}), flush=True)
+        return
+    if args.probe == "particles3d":
+        r = measure_particles_3d(steps=8)
+        f = measure_particles_3d(steps=8, exact=False)
+        print(json.dumps({"probe": "particles3d", **r, "float_atomics": f}), flush=True)
         return
     if args.probe == "batch":
         r = probe_batch(json.loads(args.tuning) if args.tuning else None)

@@ -20,9 +20,17 @@
  * call) the last Runge-Kutta stage writes each particle next to the other
  * particles of its new cell (a counting sort whose counts are taken before
  * that stage).  The order is internal: states go in and come out
- * in the caller's particle order.  Deposits add into the grid with
- * floating-point atomics, so results agree run to run only up to rounding
- * (sums in a different order).
+ * in the caller's particle order.
+ *
+ * Deposits (and the flavor totals) are summed exactly: every contribution
+ * is scaled by a power of two fixed at fpic_particles_set (from the
+ * particle count and the largest weight) and rounded to an integer, the
+ * integers are added as two 64-bit limbs with integer atomics, and the
+ * exact sum is rounded once to a double.  Results are therefore bitwise
+ * the same from run to run and whatever order the caller gives the
+ * particles in; a contribution's rounding error is at most 2^-91 of
+ * 16 npart max(|N| + |Nbar|)/dV.  The flag FPIC_PFLOAT_ATOMICS trades this
+ * for speed (floating-point atomics; flavor totals stay exact).
  *
  * Conventions are those of fpic.h: FPIC_* status codes, fpic_last_error(),
  * caller-owned device workspace, all device work on the stream given at
@@ -44,6 +52,11 @@
 extern "C" {
 #endif
 
+/* fpic_pconfig.flags: deposit with floating-point atomics instead of the
+ * exact limb sums.  Faster, but the sums then depend on the order in which
+ * the atomics land: results agree run to run only up to rounding. */
+#define FPIC_PFLOAT_ATOMICS 1
+
 typedef struct fpic_pconfig {
     int32_t ncell[3];     /* cells along x, y, z (1D: {1, 1, nz}); >= 1 each */
     double dx[3];         /* cell widths */
@@ -53,7 +66,7 @@ typedef struct fpic_pconfig {
     double dt;            /* time step, > 0 */
     int32_t shape_order;  /* 1 linear (cloud in cell), 2 quadratic */
     int32_t sort_every;   /* steps between sorts by cell, 1..1024; 0: 4 */
-    int32_t flags;        /* reserved, 0 */
+    int32_t flags;        /* 0, or FPIC_PFLOAT_ATOMICS */
     int32_t reserved;
 } fpic_pconfig;
 

@@ -197,8 +197,13 @@ def tuning(t) -> Tuning:
     return out
 
 
-def pconfig(ncell, dx, npart, hvac, dt, shape_order=1, vmat=None, sort_every=0) -> PConfig:
-    """PConfig for a general-placement box (hvac: 3x3 complex)."""
+FPIC_PFLOAT_ATOMICS = 1
+
+
+def pconfig(ncell, dx, npart, hvac, dt, shape_order=1, vmat=None, sort_every=0,
+            exact=True) -> PConfig:
+    """PConfig for a general-placement box (hvac: 3x3 complex); exact=False
+    deposits with floating-point atomics (FPIC_PFLOAT_ATOMICS)."""
     H = np.asarray(hvac, dtype=np.complex128).reshape(3, 3)
     h = np.empty(18)
     h[0::2] = H.real.ravel()
@@ -212,5 +217,5 @@ def pconfig(ncell, dx, npart, hvac, dt, shape_order=1, vmat=None, sort_every=0) 
     c.dt = float(dt)
     c.shape_order = int(shape_order)
     c.sort_every = int(sort_every)
-    c.flags = 0
+    c.flags = 0 if exact else FPIC_PFLOAT_ATOMICS
     return c

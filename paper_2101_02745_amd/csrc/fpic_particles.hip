@@ -19,12 +19,23 @@
 // (eq. eom) and the next stage state, and deposits that state with the
 // next-stage weights (eq. pic_deposition).  Because the particles are sorted
 // by cell, a workgroup's particles cover a small box of cells: it
-// accumulates their deposits in LDS (FP64 LDS atomics) over that box and
-// adds the box into the grid with global FP64 atomics.  A workgroup whose
-// box does not fit its LDS (particles spread out) adds straight to the
-// grid.  Three grid buffers rotate: stage s of step n reads G[(4n+s-1) % 3],
-// deposits into G[(4n+s) % 3] and clears G[(4n+s+1) % 3] for the next
-// stage.
+// accumulates their deposits in LDS over that box and adds the box into the
+// grid with global atomics.  A workgroup whose box does not fit its LDS
+// (particles spread out) adds straight to the grid.
+//
+// Deposits are summed exactly, in integers: each contribution v is scaled
+// by 2^S (S fixed per box from the particle count and the largest weight,
+// so that no cell's sum can pass 2^93) and split into two 64-bit limbs,
+// hi = floor(V / 2^32) and lo = V - 2^32 hi in [0, 2^32), V = rint(v 2^S).
+// Integer atomics add the
+// limbs; integer addition is associative, so the sums do not depend on the
+// order in which the atomics land or on the order of the particles within
+// a cell (the counting sort leaves that order to its atomics): every run
+// is bitwise reproducible.  A finalize pass turns each limb pair into a
+// double (one rounding of the exact sum of the scaled contributions, each
+// of which is off by at most 2^-(S+1), i.e. 2^-91 of 16 np max_p (|N_p| +
+// |Nbar_p|)/dV) and clears the limbs.  Stage s of step n reads G[(4n+s-1) % 3] and its
+// finalize writes G[(4n+s) % 3].
 //
 // Positions: x(t) = x0 + Omega t per axis, u = x / dx - 1/2, first cell
 // floor(u), fraction u - floor(u); every operation rounded once, the same
@@ -57,9 +68,16 @@ constexpr int NG = 36;
 constexpr int NXT = 8;   // traceless source components (stage grids: 4 NXT)
 constexpr int BLK = 256;            // particles (threads) per workgroup
 constexpr int NWAVE = BLK / 64;
-constexpr int ACC_DOUBLES = 6144;   // LDS of the deposit box accumulators (48 KB)
+// LDS of the deposit box accumulators: 48 KB with floating-point atomics
+// (three workgroups per CU when the stage kernel needs at most 168 VGPRs),
+// 64 KB for the exact sums, whose limbs take twice the room
+template <bool EXACT>
+constexpr int acc_words() { return EXACT ? 8192 : 6144; }
 constexpr int MAX_COPIES = 32;      // replicas of the box accumulator
 constexpr int kRedBlk = 256;        // blocks of the diagnostic reductions
+// scratch (8-byte words): [0, 32) results, then the totals partials
+// (36 limbs per block), the check partials (3 per block), the weight sums
+constexpr int kScratch1 = 32, kScratch2 = kScratch1 + 36 * kRedBlk, kScratch3 = kScratch2 + 3 * kRedBlk;
 
 enum : int { PM_DEPOSIT = 5, PM_MOM_NU = 6, PM_MOM_NUBAR = 7, PM_S4_SORT = 8 };
 
@@ -81,7 +99,59 @@ struct PDesc {
     double *G0, *G1, *G2;
     int64_t *step;
     int32_t *cnt, *cur;  // [ncell] sort counters
+    long long *GL;       // [2][NG][ncell] deposit limbs: hi plane, then lo plane
+    double qs, qi;       // 2^S and 2^-S: the fixed-point scale of the deposits
 };
+
+// ---- exact deposit sums -------------------------------------------------
+// v 2^S as the limb pair (hi, lo) with rint(v 2^S) = 2^32 hi + lo and
+// 0 <= lo < 2^32.  |v 2^S| < 2^93, so |hi| < 2^61.  Every step is exact.
+__device__ __forceinline__ void to_limbs(double v, double qs, long long &hi, long long &lo)
+{
+#pragma clang fp contract(off)
+    const double V = rint(v * qs);
+    const double h = floor(V * 0x1p-32);
+    const double r = V - h * 0x1p32;  // integer in [0, 2^32)
+    const double hh = floor(h * 0x1p-32);
+    const double hl = h - hh * 0x1p32;
+    hi = (long long)(((unsigned long long)(unsigned)(int)hh << 32) | (unsigned long long)(unsigned)hl);
+    lo = (long long)(unsigned)r;
+}
+
+// the double nearest to 2^-S (2^32 a1 + a0) for limb sums a1, a0 (a0 >= 0)
+__device__ __forceinline__ double from_limbs(long long a1, long long a0, double qi)
+{
+#pragma clang fp contract(off)
+    const long long t = a1 + (a0 >> 32);               // |t| < 2^62
+    const long long r0 = a0 & 0xffffffffLL;
+    const double th = (double)t;                       // rounded when |t| > 2^53
+    const long long e = t - (long long)th;             // exact, |e| <= 2^9
+    const double low = (double)(e * 4294967296LL + r0);  // exact, < 2^42
+    return fma(th, 0x1p32, low) * qi;                  // one rounding
+}
+
+typedef __attribute__((address_space(1))) long long glong;
+__device__ __forceinline__ void gatomic_add_ll(long long *p, long long v)
+{
+    __hip_atomic_fetch_add((glong *)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void lds_add_limbs(long long *hi_p, long long *lo_p, double v, double qs)
+{
+    long long hi, lo;
+    to_limbs(v, qs, hi, lo);
+    atomicAdd(reinterpret_cast<unsigned long long *>(hi_p), (unsigned long long)hi);
+    atomicAdd(reinterpret_cast<unsigned long long *>(lo_p), (unsigned long long)lo);
+}
+
+__device__ __forceinline__ void global_add_limbs(long long *GL, int64_t plane, int64_t q, double v,
+                                                 double qs)
+{
+    long long hi, lo;
+    to_limbs(v, qs, hi, lo);
+    gatomic_add_ll(GL + q, hi);
+    gatomic_add_ll(GL + plane + q, lo);
+}
 
 // n-periodic index of an integer-valued double (|i| < 2^52)
 __device__ __forceinline__ int wrap_cell(double i, int n)
@@ -270,7 +340,9 @@ __device__ __forceinline__ KeyRange key_range(int key, bool active, int nc, int 
 // sort needs no pass of its own; PM_DEPOSIT: deposit the current state at
 // the current time into the buffer stage 1 reads; PM_MOM_NU / PM_MOM_NUBAR:
 // deposit N rho or Nbar rhobar alone into outG (moment diagnostics).
-template <int MODE, int SH, bool D3>
+// EXACT: deposits summed exactly in the limbs (finalize_kernel then writes
+// the grid); otherwise with floating-point atomics straight into the grid.
+template <int MODE, int SH, bool D3, bool EXACT>
 __global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(SH == 1 ? 2 : 1)))
 pstage_kernel(const PDesc *__restrict__ dp, double *outG)
 {
@@ -284,6 +356,7 @@ pstage_kernel(const PDesc *__restrict__ dp, double *outG)
     constexpr bool FULL = MODE == PM_MOM_NU || MODE == PM_MOM_NUBAR;
     constexpr int NCS = FULL ? 9 : NXT, NGC = 4 * NCS;
     constexpr int STG = MODE == PM_S4_SORT ? 4 : MODE;  // Runge-Kutta stage
+    constexpr int ACC_DOUBLES = acc_words<EXACT>();
     __shared__ double acc[ACC_DOUBLES];
     __shared__ int sred[NWAVE][6];
     __shared__ int sref[3];
@@ -313,8 +386,10 @@ pstage_kernel(const PDesc *__restrict__ dp, double *outG)
         t_nxt = stage_time(n, dt, 0.0);
     }
 
-    // grid buffers (selects, no indexing into the descriptor copy)
-    double *Gin = nullptr, *Gout, *Gclr = nullptr;
+    // grid buffers (selects, no indexing into the descriptor copy): the one
+    // this stage interpolates from; exact sums deposit into the limbs S.GL,
+    // floating-point atomics into Gout, clearing Gclr for the next stage
+    double *Gin = nullptr, *Gout = nullptr, *Gclr = nullptr;
     if (RK) {
         const int r = (int)((4 * n + STG - 1) % 3);
         Gin = r == 0 ? S.G0 : (r == 1 ? S.G1 : S.G2);
@@ -326,13 +401,14 @@ pstage_kernel(const PDesc *__restrict__ dp, double *outG)
     } else {
         Gout = outG;
     }
-    if (RK) {
-        // clear the buffer the next stage deposits into (nothing reads or
-        // writes it during this launch)
+    if (RK && !EXACT) {
+        // nothing reads or writes Gclr during this launch
         const int64_t len = (int64_t)NGC * S.ncell;
         for (int64_t q = i; q < len; q += (int64_t)gridDim.x * BLK)
             gst(Gclr + q, 0.0);
     }
+    const int64_t plane = (int64_t)NG * S.ncell;  // hi plane -> lo plane
+    const double qs = S.qs;
 
     const double vx = gld(S.v + ip), vy = gld(S.v + np + ip), vz = gld(S.v + 2 * np + ip);
     const double px = D3 ? gld(S.pos + ip) : 0.0;
@@ -542,12 +618,123 @@ pstage_kernel(const PDesc *__restrict__ dp, double *outG)
     const Box db = block_box<SW, D3>(df, active, nn, sred, sref, o);
     const int sx = db.s[0], sy = db.s[1];
     const int64_t box = db.cells;
+    constexpr int NCORNER = D3 ? SW * SW * SW : SW;
+    // each lane walks its stencil corners starting at its own offset, so one
+    // instruction's lanes target different corners
+    const int rot = lane % NCORNER;
 
-    if (box * NGC <= ACC_DOUBLES) {
-        // R copies of the box accumulator, lane l adding into copy l % R:
-        // lanes of a dense workgroup target the same few cells, and the
-        // copies spread their atomics over distinct addresses.  A copy holds
-        // an odd number of doubles, so the copies start in different banks.
+    if (EXACT) {
+        // Limb accumulators of the box in LDS: some of the four groups
+        // (A, B_x, B_y, B_z) per pass, R copies of them (lane l adding into
+        // copy (l / NCORNER) % R: lanes of a dense workgroup target the same
+        // few cells, and the copies and the corner rotation spread their
+        // atomics over distinct addresses; a copy holds an odd number of
+        // 8-byte words, so the copies start in different banks).  Every
+        // contribution is the same whatever the passes, and its limbs add
+        // exactly.
+        // Fewer groups per pass buy more copies: passes are taken until a
+        // pass holds at least four copies (or one group).
+        // (workgroup-uniform integer arithmetic; box <= ACC_DOUBLES here)
+        const int cells = (int)min(box, (int64_t)ACC_DOUBLES);
+        int gpp = 4, R = 0;
+        for (;;) {
+            const int st = 2 * NCS * gpp * cells + 1;
+            R = ACC_DOUBLES / st;   // copies that fit, then a power of two
+            R = R >= MAX_COPIES ? MAX_COPIES : (R >= 16 ? 16 : (R >= 8 ? 8 : (R >= 4 ? 4 : (R >= 2 ? 2 : R))));
+            if (R >= 4 || gpp == 1)
+                break;
+            gpp >>= 1;
+        }
+        if (R > 0 && box <= ACC_DOUBLES) {
+            const int half = NCS * gpp * cells;
+            const int cstride = 2 * half + 1;
+            long long *lacc = reinterpret_cast<long long *>(acc);
+            for (int g0 = 0; g0 < 4; g0 += gpp) {
+                for (int q = threadIdx.x; q < R * cstride; q += BLK)
+                    lacc[q] = 0;
+                __syncthreads();
+                if (active) {
+                    // copy by lane / NCORNER, independent of the lane's
+                    // first corner (lane % NCORNER)
+                    long long *mine = lacc + ((lane / NCORNER) & (R - 1)) * cstride;
+#pragma unroll 1
+                    for (int g = 0; g < gpp; g++) {
+                        const int gg = g0 + g;
+                        const double m = gg == 0 ? 1.0 : (gg == 1 ? vx : (gg == 2 ? vy : vz));
+                        long long *mg = mine + g * NCS * cells;
+                        // (a rolled corner loop: unrolled, the limb
+                        // conversions of all corners would spill)
+#pragma unroll 1
+                        for (int j = 0; j < NCORNER; j++) {
+                            int c = j + rot;
+                            c = c >= NCORNER ? c - NCORNER : c;
+                            const int bx = D3 ? c % SW : 0;
+                            const int by = D3 ? (c / SW) % SW : 0;
+                            const int bz = D3 ? c / (SW * SW) : c;
+                            const double w = D3 ? (pick(dw[0], bx) * pick(dw[1], by)) * pick(dw[2], bz)
+                                                : pick(dw[2], bz);
+                            const int idx = ((o[2] - db.lo[2] + bz) * sy + (o[1] - db.lo[1] + by)) * sx +
+                                            (o[0] - db.lo[0] + bx);
+#pragma unroll
+                            for (int k = 0; k < NCS; k++) {
+                                // m * (w X_k): the product the floating-point
+                                // path forms (1 * x is x)
+                                const double xc = w * Xd[k];
+                                long long *a = mg + idx + k * cells;
+                                lds_add_limbs(a, a + half, m * xc, qs);
+                            }
+                        }
+                    }
+                }
+                __syncthreads();
+                for (int q = threadIdx.x; q < half; q += BLK) {
+                    long long hi = 0, lo = 0;
+#pragma unroll 4
+                    for (int r = 0; r < R; r++) {
+                        hi += lacc[r * cstride + q];
+                        lo += lacc[r * cstride + half + q];
+                    }
+                    if (hi != 0 || lo != 0) {
+                        const int comp = g0 * NCS + q / cells, l = q % cells;
+                        const int lx = l % sx, ly = (l / sx) % sy, lz = l / (sx * sy);
+                        const int cz = wrap_int(db.ref[2] + db.lo[2] + lz, nz);
+                        const int cy = D3 ? wrap_int(db.ref[1] + db.lo[1] + ly, ny) : 0;
+                        const int cx = D3 ? wrap_int(db.ref[0] + db.lo[0] + lx, nx) : 0;
+                        const int64_t g = (int64_t)comp * nc + ((int64_t)cz * ny + cy) * nx + cx;
+                        if (hi != 0)
+                            gatomic_add_ll(S.GL + g, hi);
+                        if (lo != 0)
+                            gatomic_add_ll(S.GL + plane + g, lo);
+                    }
+                }
+                __syncthreads();  // the next pass clears the accumulators
+            }
+        } else if (active) {
+            // spread-out workgroup: straight to the grid limbs (a rolled
+            // corner loop: unrolled, the conversions would spill)
+#pragma unroll 1
+            for (int c = 0; c < NCORNER; c++) {
+                const int bx = D3 ? c % SW : 0;
+                const int by = D3 ? (c / SW) % SW : 0;
+                const int bz = D3 ? c / (SW * SW) : c;
+                const double w = D3 ? (pick(dw[0], bx) * pick(dw[1], by)) * pick(dw[2], bz) : pick(dw[2], bz);
+                const int cz = wrap_int(df[2] + bz, nz);
+                const int cy = D3 ? wrap_int(df[1] + by, ny) : 0;
+                const int cx = D3 ? wrap_int(df[0] + bx, nx) : 0;
+                const int64_t g = ((int64_t)cz * ny + cy) * nx + cx;
+#pragma unroll 1
+                for (int k = 0; k < NCS; k++) {
+                    const double xc = w * Xd[k];
+                    global_add_limbs(S.GL, plane, g + (int64_t)k * nc, xc, qs);
+                    global_add_limbs(S.GL, plane, g + (int64_t)(NCS + k) * nc, vx * xc, qs);
+                    global_add_limbs(S.GL, plane, g + (int64_t)(2 * NCS + k) * nc, vy * xc, qs);
+                    global_add_limbs(S.GL, plane, g + (int64_t)(3 * NCS + k) * nc, vz * xc, qs);
+                }
+            }
+        }
+    } else if (box * NGC <= ACC_DOUBLES) {
+        // floating-point atomics (not reproducible bit for bit): R copies of
+        // the box accumulator as above, flushed with global FP64 atomics
         const int cells = (int)box;
         const int cstride = NGC * cells + 1;
         int R = MAX_COPIES;
@@ -557,11 +744,7 @@ pstage_kernel(const PDesc *__restrict__ dp, double *outG)
             acc[q] = 0.0;
         __syncthreads();
         if (active) {
-            // each lane walks its stencil corners starting at its own
-            // offset, so one instruction's lanes target different corners
-            double *mine = acc + (lane & (R - 1)) * cstride;
-            constexpr int NCORNER = D3 ? SW * SW * SW : SW;
-            const int rot = lane % NCORNER;
+            double *mine = acc + ((lane / NCORNER) & (R - 1)) * cstride;
 #pragma unroll
             for (int j = 0; j < NCORNER; j++) {
                 int c = j + rot;
@@ -596,7 +779,6 @@ pstage_kernel(const PDesc *__restrict__ dp, double *outG)
             }
         }
     } else if (active) {
-        // spread-out workgroup: straight to the grid
 #pragma unroll
         for (int bz = 0; bz < SW; bz++)
 #pragma unroll
@@ -664,6 +846,54 @@ pstage_kernel(const PDesc *__restrict__ dp, double *outG)
             S.pid2[j] = S.pid[i];
         }
     }
+}
+
+// After a deposit: the limb sums as doubles in the grid the next stage
+// reads (Runge-Kutta stage STG of step n: G[(4n + STG) % 3]; PM_DEPOSIT:
+// G[(4n) % 3], the grid stage 1 reads; moments: outG), and the limbs
+// cleared for the next deposit.  Runs before the step counter moves on.
+template <int MODE>
+__global__ void __launch_bounds__(256) finalize_kernel(const PDesc *__restrict__ dp, double *outG)
+{
+    constexpr bool FULL = MODE == PM_MOM_NU || MODE == PM_MOM_NUBAR;
+    constexpr int NGC = FULL ? NG : 4 * NXT;
+    constexpr int STG = MODE == PM_S4_SORT ? 4 : MODE;
+    const PDesc &S = *dp;
+    double *G = outG;
+    if (!FULL) {
+        const int64_t n = *S.step;
+        const int r = (int)((MODE == PM_DEPOSIT ? 4 * n : 4 * n + STG) % 3);
+        G = r == 0 ? S.G0 : (r == 1 ? S.G1 : S.G2);
+    }
+    const int64_t len = (int64_t)NGC * S.ncell, plane = (int64_t)NG * S.ncell;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < len;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const long long hi = S.GL[q], lo = S.GL[plane + q];
+        gst(G + q, from_limbs(hi, lo, S.qi));
+        S.GL[q] = 0;
+        S.GL[plane + q] = 0;
+    }
+}
+
+// the largest |N/dV| + |Nbar/dV| of a particle, for the scale of the exact
+// deposit sums (a maximum: the same whatever the particles' order)
+__global__ void __launch_bounds__(256) weight_max_kernel(const PDesc *__restrict__ dp, double *partial)
+{
+    const PDesc &S = *dp;
+    __shared__ double sh[256];
+    double a = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < S.np;
+         i += (int64_t)gridDim.x * blockDim.x)
+        a = fmax(a, fabs(S.wN[i]) + fabs(S.wNb[i]));
+    sh[threadIdx.x] = a;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h)
+            sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + h]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        partial[blockIdx.x] = sh[0];
 }
 
 __global__ void tick_kernel(const PDesc *dp)
@@ -841,32 +1071,54 @@ __global__ void unload_kernel(const PDesc *__restrict__ dp, double *out)
     }
 }
 
-__global__ void __launch_bounds__(256) totals_kernel(const PDesc *__restrict__ dp, double *partial)
+// Flavor totals, summed exactly in limbs like the deposits (the particle
+// order within a cell is not fixed): per block the 18 (hi, lo) limb sums.
+__global__ void __launch_bounds__(256) totals_kernel(const PDesc *__restrict__ dp, long long *partial)
 {
     const PDesc &S = *dp;
-    __shared__ double sh[18][256];
-    double s[18];
+    __shared__ long long sh[4][36];
+    long long hs[18], ls[18];
     for (int k = 0; k < 18; k++)
-        s[k] = 0.0;
+        hs[k] = ls[k] = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < S.np;
          i += (int64_t)gridDim.x * blockDim.x) {
         const double wN = S.wN[i], wNb = S.wNb[i];
-        for (int k = 0; k < 9; k++) {
-            s[k] += wN * S.Y[k * S.np + i];
-            s[9 + k] += wNb * S.Y[(9 + k) * S.np + i];
+        for (int k = 0; k < 18; k++) {
+            long long h, l;
+            to_limbs((k < 9 ? wN : wNb) * S.Y[k * S.np + i], S.qs, h, l);
+            hs[k] += h;
+            ls[k] += l;
         }
     }
-    for (int k = 0; k < 18; k++)
-        sh[k][threadIdx.x] = s[k];
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h)
-            for (int k = 0; k < 18; k++)
-                sh[k][threadIdx.x] += sh[k][threadIdx.x + h];
-        __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int k = 0; k < 18; k++) {
+        for (int m = 32; m >= 1; m >>= 1) {
+            hs[k] += __shfl_xor(hs[k], m, 64);
+            ls[k] += __shfl_xor(ls[k], m, 64);
+        }
+        if (lane == 0) {
+            sh[wave][2 * k] = hs[k];
+            sh[wave][2 * k + 1] = ls[k];
+        }
     }
-    if (threadIdx.x < 18)
-        partial[blockIdx.x * 18 + threadIdx.x] = sh[threadIdx.x][0];
+    __syncthreads();
+    if (threadIdx.x < 36)
+        partial[blockIdx.x * 36 + threadIdx.x] =
+            sh[0][threadIdx.x] + sh[1][threadIdx.x] + sh[2][threadIdx.x] + sh[3][threadIdx.x];
+}
+
+__global__ void totals_finish_kernel(const PDesc *__restrict__ dp, const long long *partial, int nblk,
+                                     double *out)
+{
+    const int k = threadIdx.x;
+    if (k >= 18)
+        return;
+    long long h = 0, l = 0;
+    for (int b = 0; b < nblk; b++) {
+        h += partial[(size_t)b * 36 + 2 * k];
+        l += partial[(size_t)b * 36 + 2 * k + 1];
+    }
+    out[k] = from_limbs(h, l, dp->qi);
 }
 
 __global__ void __launch_bounds__(256) check_kernel(const PDesc *__restrict__ dp, double *partial)
@@ -927,7 +1179,7 @@ static size_t al(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
     size_t set[2][6];  // Y, pos, v, wN, wNb, pid of sets A and B
-    size_t K1, K2, K3, G[3], cnt, cur, step, desc, scratch, flag, total;
+    size_t K1, K2, K3, G[3], GL, cnt, cur, step, desc, scratch, flag, total;
 };
 
 static int validate(const fpic_pconfig &c)
@@ -942,6 +1194,8 @@ static int validate(const fpic_pconfig &c)
         return fail(FPIC_EUNSUPPORTED, "shape_order must be 1 (linear) or 2 (quadratic)");
     if (c.sort_every < 0 || c.sort_every > 1024)
         return fail(FPIC_EINVAL, "sort_every must be in 0 .. 1024");
+    if (c.flags & ~FPIC_PFLOAT_ATOMICS)
+        return fail(FPIC_EINVAL, "unknown flags");
     if (!(c.dt > 0.0) || !std::isfinite(c.dt))
         return fail(FPIC_EINVAL, "dt must be positive and finite");
     for (int a = 0; a < 3; ++a)
@@ -994,11 +1248,12 @@ static int layout(const fpic_pconfig &c, Layout &L)
     L.K3 = take(d * fpic::NK * np);
     for (int g = 0; g < 3; ++g)
         L.G[g] = take(d * NG * nc);
+    L.GL = take(sizeof(long long) * 2 * NG * nc);
     L.cnt = take(sizeof(int32_t) * nc);
     L.cur = take(sizeof(int32_t) * nc);
     L.step = take(sizeof(int64_t));
     L.desc = take(2 * sizeof(PDesc));
-    L.scratch = take(d * (18 * kRedBlk + 3 * kRedBlk + 32));
+    L.scratch = take(d * (kScratch3 + kRedBlk));
     L.flag = take(sizeof(int32_t) * 4);
     L.total = al(off);
     return FPIC_OK;
@@ -1017,6 +1272,7 @@ struct fpic_pctx {
     int par = 0;         // set holding the particles after the enqueued work
     int sh = 1;
     bool d3 = false;
+    bool exact = true;   // exact (limb) deposit sums; false: floating-point atomics
     unsigned nblk = 1;   // stage workgroups
     double dV = 1.0;
     double *scratch = nullptr, *hbuf = nullptr;
@@ -1027,30 +1283,60 @@ struct fpic_pctx {
 
 namespace fpicp {
 
-template <int SH, bool D3>
+template <int SH, bool D3, bool EX>
 static void launch_mode_t(const fpic_pctx *c, int mode, const PDesc *dd, double *out, hipStream_t s)
 {
     const dim3 grid(c->nblk), blk(BLK);
     switch (mode) {
-    case 1: pstage_kernel<1, SH, D3><<<grid, blk, 0, s>>>(dd, out); break;
-    case 2: pstage_kernel<2, SH, D3><<<grid, blk, 0, s>>>(dd, out); break;
-    case 3: pstage_kernel<3, SH, D3><<<grid, blk, 0, s>>>(dd, out); break;
-    case 4: pstage_kernel<4, SH, D3><<<grid, blk, 0, s>>>(dd, out); break;
-    case PM_S4_SORT: pstage_kernel<PM_S4_SORT, SH, D3><<<grid, blk, 0, s>>>(dd, out); break;
-    case PM_DEPOSIT: pstage_kernel<PM_DEPOSIT, SH, D3><<<grid, blk, 0, s>>>(dd, out); break;
-    case PM_MOM_NU: pstage_kernel<PM_MOM_NU, SH, D3><<<grid, blk, 0, s>>>(dd, out); break;
-    default: pstage_kernel<PM_MOM_NUBAR, SH, D3><<<grid, blk, 0, s>>>(dd, out); break;
+    case 1: pstage_kernel<1, SH, D3, EX><<<grid, blk, 0, s>>>(dd, out); break;
+    case 2: pstage_kernel<2, SH, D3, EX><<<grid, blk, 0, s>>>(dd, out); break;
+    case 3: pstage_kernel<3, SH, D3, EX><<<grid, blk, 0, s>>>(dd, out); break;
+    case 4: pstage_kernel<4, SH, D3, EX><<<grid, blk, 0, s>>>(dd, out); break;
+    case PM_S4_SORT: pstage_kernel<PM_S4_SORT, SH, D3, EX><<<grid, blk, 0, s>>>(dd, out); break;
+    case PM_DEPOSIT: pstage_kernel<PM_DEPOSIT, SH, D3, EX><<<grid, blk, 0, s>>>(dd, out); break;
+    case PM_MOM_NU: pstage_kernel<PM_MOM_NU, SH, D3, EX><<<grid, blk, 0, s>>>(dd, out); break;
+    default: pstage_kernel<PM_MOM_NUBAR, SH, D3, EX><<<grid, blk, 0, s>>>(dd, out); break;
     }
 }
 
-static void launch_mode(const fpic_pctx *c, int mode, const PDesc *dd, double *out, hipStream_t s)
+// the limb sums of a deposit (mode as above) into their grid
+static void launch_finalize(const fpic_pctx *c, int mode, const PDesc *dd, double *out, hipStream_t s)
+{
+    const bool full = mode == PM_MOM_NU || mode == PM_MOM_NUBAR;
+    const int64_t len = (int64_t)(full ? NG : 4 * NXT) * c->h[0].ncell;
+    const dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, (len + 255) / 256))), blk(256);
+    switch (mode) {
+    case 1: finalize_kernel<1><<<grid, blk, 0, s>>>(dd, out); break;
+    case 2: finalize_kernel<2><<<grid, blk, 0, s>>>(dd, out); break;
+    case 3: finalize_kernel<3><<<grid, blk, 0, s>>>(dd, out); break;
+    case 4: finalize_kernel<4><<<grid, blk, 0, s>>>(dd, out); break;
+    case PM_S4_SORT: finalize_kernel<PM_S4_SORT><<<grid, blk, 0, s>>>(dd, out); break;
+    case PM_DEPOSIT: finalize_kernel<PM_DEPOSIT><<<grid, blk, 0, s>>>(dd, out); break;
+    case PM_MOM_NU: finalize_kernel<PM_MOM_NU><<<grid, blk, 0, s>>>(dd, out); break;
+    default: finalize_kernel<PM_MOM_NUBAR><<<grid, blk, 0, s>>>(dd, out); break;
+    }
+}
+
+template <bool EX>
+static void launch_mode_e(const fpic_pctx *c, int mode, const PDesc *dd, double *out, hipStream_t s)
 {
     if (c->sh == 2) {
-        if (c->d3) launch_mode_t<2, true>(c, mode, dd, out, s);
-        else launch_mode_t<2, false>(c, mode, dd, out, s);
+        if (c->d3) launch_mode_t<2, true, EX>(c, mode, dd, out, s);
+        else launch_mode_t<2, false, EX>(c, mode, dd, out, s);
     } else {
-        if (c->d3) launch_mode_t<1, true>(c, mode, dd, out, s);
-        else launch_mode_t<1, false>(c, mode, dd, out, s);
+        if (c->d3) launch_mode_t<1, true, EX>(c, mode, dd, out, s);
+        else launch_mode_t<1, false, EX>(c, mode, dd, out, s);
+    }
+}
+
+// a stage or deposit launch, and with exact sums the finalize of its limbs
+static void launch_mode(const fpic_pctx *c, int mode, const PDesc *dd, double *out, hipStream_t s)
+{
+    if (c->exact) {
+        launch_mode_e<true>(c, mode, dd, out, s);
+        launch_finalize(c, mode, dd, out, s);
+    } else {
+        launch_mode_e<false>(c, mode, dd, out, s);
     }
 }
 
@@ -1146,6 +1432,7 @@ int fpic_particles_create(const fpic_pconfig *cfg, void *workspace, size_t bytes
     c->spg = cfg->sort_every ? cfg->sort_every : 4;
     c->sh = cfg->shape_order;
     c->d3 = !(cfg->ncell[0] == 1 && cfg->ncell[1] == 1);
+    c->exact = !(cfg->flags & FPIC_PFLOAT_ATOMICS);
     c->nblk = (unsigned)((cfg->npart + BLK - 1) / BLK);
     c->dV = cfg->dx[0] * cfg->dx[1] * cfg->dx[2];
     auto P = [&](size_t o) { return reinterpret_cast<double *>(c->ws + o); };
@@ -1188,6 +1475,8 @@ int fpic_particles_create(const fpic_pconfig *cfg, void *workspace, size_t bytes
         D.G2 = P(L.G[2]);
         D.cnt = I(L.cnt);
         D.cur = I(L.cur);
+        D.GL = reinterpret_cast<long long *>(c->ws + L.GL);
+        D.qs = D.qi = 1.0;
         D.step = reinterpret_cast<int64_t *>(c->ws + L.step);
         c->d[p] = reinterpret_cast<PDesc *>(c->ws + L.desc) + p;
     }
@@ -1237,6 +1526,31 @@ int fpic_particles_set(fpic_pctx *c, const double *pos0, const double *dirs, con
         return fail(FPIC_EINVAL, "set: non-finite position or weight, or a direction that is "
                                  "not a unit vector");
     }
+    // the fixed-point scale of the exact deposit sums: 2^S with
+    // 16 np max_p (|N_p| + |Nbar_p|)/dV <= 2^91.  A cell's moment component
+    // is at most 2 sum_p (|N_p| + |Nbar_p|)/dV (density-matrix entries and
+    // differences of two diagonal entries are at most 1, velocity
+    // components and shape weights at most 1), so no limb sum can overflow.
+    // The bound uses a maximum, not a sum, so that S does not depend on the
+    // order of the particles.
+    double *wmax = c->scratch + kScratch3;
+    weight_max_kernel<<<kRedBlk, 256, 0, s>>>(c->d[0], wmax);
+    finish_kernel<<<1, 64, 0, s>>>(wmax, kRedBlk, 1, 1, c->scratch);
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipMemcpyAsync(c->hbuf, c->scratch, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    const double wtot = 16.0 * (double)H.np * c->hbuf[0];
+    int S2 = 0;
+    if (wtot > 0.0 && std::isfinite(wtot)) {
+        int e = 0;
+        (void)std::frexp(wtot, &e);  // wtot < 2^e
+        S2 = std::max(-1000, std::min(1000, 91 - e));
+    }
+    for (int p = 0; p < 2; ++p) {
+        c->h[p].qs = std::ldexp(1.0, S2);
+        c->h[p].qi = std::ldexp(1.0, -S2);
+    }
+    HIPCHECK(hipMemcpy(c->d[0], c->h, sizeof(PDesc) * 2, hipMemcpyHostToDevice));
     launch_sort(c, 0, s);
     c->par = 1;
     const int64_t glen = (int64_t)NG * H.ncell;
@@ -1244,6 +1558,7 @@ int fpic_particles_set(fpic_pctx *c, const double *pos0, const double *dirs, con
     fill_f64<<<gb, 256, 0, s>>>(H.G0, glen);
     fill_f64<<<gb, 256, 0, s>>>(H.G1, glen);
     fill_f64<<<gb, 256, 0, s>>>(H.G2, glen);
+    fill_f64<<<gb, 256, 0, s>>>(reinterpret_cast<double *>(H.GL), 2 * glen);
     launch_mode(c, PM_DEPOSIT, c->d[c->par], nullptr, s);
     HIPCHECK(hipGetLastError());
     c->state_set = true;
@@ -1289,9 +1604,11 @@ int fpic_particles_moments(fpic_pctx *c, double *out)
         return fail(FPIC_EINVAL, "moments: null argument");
     if (!c->state_set)
         return fail(FPIC_ESTATE, "moments before set");
-    const int64_t len = (int64_t)2 * NG * c->h[0].ncell;
-    const unsigned gb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, (len + 255) / 256));
-    fill_f64<<<gb, 256, 0, c->stream>>>(out, len);
+    if (!c->exact) {  // the atomics add into out
+        const int64_t len = (int64_t)2 * NG * c->h[0].ncell;
+        const unsigned gb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, (len + 255) / 256));
+        fill_f64<<<gb, 256, 0, c->stream>>>(out, len);
+    }
     launch_mode(c, PM_MOM_NU, c->d[c->par], out, c->stream);
     launch_mode(c, PM_MOM_NUBAR, c->d[c->par], out + (size_t)NG * c->h[0].ncell, c->stream);
     HIPCHECK(hipGetLastError());
@@ -1304,9 +1621,9 @@ int fpic_particles_flavor_totals(fpic_pctx *c, double *out)
         return fail(FPIC_EINVAL, "flavor_totals: null argument");
     if (!c->state_set)
         return fail(FPIC_ESTATE, "flavor_totals before set");
-    double *part = c->scratch + 32;
+    long long *part = reinterpret_cast<long long *>(c->scratch + kScratch1);
     totals_kernel<<<kRedBlk, 256, 0, c->stream>>>(c->d[c->par], part);
-    finish_kernel<<<1, 64, 0, c->stream>>>(part, kRedBlk, 18, 0, c->scratch);
+    totals_finish_kernel<<<1, 64, 0, c->stream>>>(c->d[c->par], part, kRedBlk, c->scratch);
     HIPCHECK(hipGetLastError());
     HIPCHECK(hipMemcpyAsync(c->hbuf, c->scratch, sizeof(double) * 18, hipMemcpyDeviceToHost, c->stream));
     HIPCHECK(hipStreamSynchronize(c->stream));
@@ -1321,7 +1638,7 @@ int fpic_particles_check(fpic_pctx *c, double tol, double *max_trace_err)
         return fail(FPIC_EINVAL, "null context");
     if (!c->state_set)
         return fail(FPIC_ESTATE, "check before set");
-    double *part = c->scratch + 32 + 18 * kRedBlk;
+    double *part = c->scratch + kScratch2;
     check_kernel<<<kRedBlk, 256, 0, c->stream>>>(c->d[c->par], part);
     finish_kernel<<<1, 64, 0, c->stream>>>(part, kRedBlk, 3, 1, c->scratch);
     HIPCHECK(hipGetLastError());

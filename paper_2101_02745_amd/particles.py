@@ -31,14 +31,14 @@ class ParticleSim:
     particles placed anywhere."""
 
     def __init__(self, ncell, dx, npart: int, hvac, dt: float, shape_order: int = 1,
-                 vmat=None, sort_every: int = 0, device: str = "cuda:0"):
+                 vmat=None, sort_every: int = 0, device: str = "cuda:0", exact: bool = True):
         lib = _lib.load()
         if not torch.cuda.is_available():
             raise RuntimeError("libflavorpic needs a HIP device")
         self.device = torch.device(device)
         self.ncell = tuple(int(x) for x in ncell)
         self.npart = int(npart)
-        self.cfg = _lib.pconfig(ncell, dx, npart, hvac, dt, shape_order, vmat, sort_every)
+        self.cfg = _lib.pconfig(ncell, dx, npart, hvac, dt, shape_order, vmat, sort_every, exact)
         nbytes = C.c_size_t()
         check(lib.fpic_particles_workspace_bytes(C.byref(self.cfg), C.byref(nbytes)))
         self.nbytes = nbytes.value
@@ -50,9 +50,9 @@ class ParticleSim:
         self.ctx = ctx
 
     @classmethod
-    def from_workload(cls, w, sort_every: int = 0, device: str = "cuda:0"):
+    def from_workload(cls, w, sort_every: int = 0, device: str = "cuda:0", exact: bool = True):
         return cls(w.ncell, w.dx, w.nparticles, w.hvac(), w.dt, w.shape_order, w.vmat,
-                   sort_every, device)
+                   sort_every, device, exact)
 
     @property
     def ncell_total(self) -> int:

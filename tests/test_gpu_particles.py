@@ -1,9 +1,10 @@
 """GPU parity of the general-placement path (include/fpic_particles.h)
 against the CPU reference with explicit particle positions: particles
 anywhere in the box, any number per cell, sorted by cell inside the
-library every `sort_every` steps.  Deposits use floating-point atomics, so
-the comparison is at the 1e-12 normwise tolerance of every other parity
-test, never bitwise."""
+library every `sort_every` steps.  The library sums deposits exactly (in
+integer limbs) and the reference in particle order, so the comparison is at
+the 1e-12 normwise tolerance of every other parity test, never bitwise
+(bitwise run-to-run reproducibility has its own tests)."""
 import numpy as np
 import pytest
 
