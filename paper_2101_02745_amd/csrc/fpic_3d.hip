@@ -550,21 +550,20 @@ static unsigned deposit_blocks(const Desc3 &h)
 // workgroup's particles deposit into the same four rows (y0 + cy, z0 + cz),
 // cy, cz in {0, 1}.  Their current lower cells differ from the next ones by
 // delta in {-1, 0, 1} per axis (no particle crosses a whole cell within a
-// stage); the gather rows (y0 + delta_y + cy, z0 + delta_z + cz) are the
-// four rows staged in LDS when delta_y = delta_z = 0 (stage 2 and 4 always,
-// stages 1 and 3 for the directions that cross no cell face in y or z) and
-// are read from the grid in memory otherwise (wave-uniform).
+// stage).  The directions are taken class by class (the pair delta_y,
+// delta_z; see fclass_at), and the four gather rows (y0 + delta_y + cy,
+// z0 + delta_z + cz) of a class are staged in LDS before its directions.
 //
 // The deposit goes through LDS in rounds of FW directions: every wave
 // forms the traceless source X = (N/dV) rho - (Nbar/dV) rhobar^* of its
 // direction's next stage state and writes it to its LDS slot; after a
-// barrier every wave accumulates one block of the 4 rows x 32 components
-// (row q = wave & 3, component groups 2 (wave >> 2) and 2 (wave >> 2) + 1
-// of A, B_x, B_y, B_z) from all slots in slot order, pulling cell x's share
-// from particles x (weight 1 - fx) and x - 1 (weight fx).  At the end each
-// wave writes its block as the partial (slot q) of its destination row, and
-// reduce3f_kernel adds the four partials of every cell in slot order:
-// no atomics, bitwise reproducible.
+// barrier wave w accumulates source component w of all slots in slot
+// order into 16 registers (the 4 destination rows times the groups A, B_x,
+// B_y, B_z), pulling cell x's share from particles x (weight 1 - fx) and
+// x - 1 (weight fx).  At the end each wave writes its accumulators as the
+// partials (slot q = destination row) of its rows, and reduce3f_kernel adds
+// the four partials of every cell in slot order: no atomics, bitwise
+// reproducible.
 // ---------------------------------------------------------------------------
 constexpr int FW = 8;
 
