@@ -86,8 +86,10 @@ int main()
         x.dirs[0] = 0.0;
         x.c.ncell[2] = 0;
         expect(fpic_workspace_bytes(&x.c, nullptr, &b), FPIC_EINVAL, "no cells");
-        Box wide(65, 2, 2, 6);
-        expect(fpic_workspace_bytes(&wide.c, nullptr, &b), FPIC_EUNSUPPORTED, "3D nx > 64");
+        Box wide(130, 2, 2, 6);  // rows longer than a wave: x-segments
+        expect(fpic_workspace_bytes(&wide.c, nullptr, &b), FPIC_OK, "3D nx > 64");
+        Box wide2(300, 1, 1, 6);
+        expect(fpic_workspace_bytes(&wide2.c, nullptr, &b), FPIC_OK, "3D rows of 300 cells");
         fpic_tuning t{3, 0, 0, 0, 0};
         Box y(1, 1, 64, 6);
         expect(fpic_workspace_bytes(&y.c, &t, &b), FPIC_EINVAL, "waves 3");

@@ -10,6 +10,8 @@ stays below it.
 """
 import math
 
+import os
+
 import numpy as np
 import pytest
 
@@ -257,38 +259,39 @@ def test_batch_matches_single_runs(torch_dev):
         assert np.abs(tots[i] - tref).max() <= TOL * np.abs(tref).max()
 
 
-def test_full_batch_sampled(torch_dev):
-    """The full batch workload (64 uneven 1D boxes, 25.5 M particles) in the
-    batched launch shape the benchmark uses: two steps of all 64 boxes in one
-    launch per stage; the smallest box, the largest box and a box with
-    negative weights are compared output by output with the reference, and
-    every box's traces stay 1."""
+def test_full_batch_every_box(torch_dev):
+    """The full batch workload (64 uneven 1D boxes, 25.5 M particles, 19 of
+    them with negative weights) in the benchmark's batched launch shape: two
+    steps of all 64 boxes in one launch per stage, and every box compared
+    output by output with the reference (state and flavor totals)."""
+    import time
+    from oracle import set_threads
     from paper_2101_02745_amd.sim import Batch
     from paper_2101_02745_amd._lib import HostConfig
     ws = I.batch_workloads()
     assert len(ws) == 64
+    neg = [i for i, w in enumerate(ws) if min(w.weights()[0].min(), w.weights()[1].min()) < 0]
+    assert neg, "the batch draws should include negative weights"
     b = Batch([HostConfig.from_workload(w) for w in ws],
-              tuning={"waves": 4, "dirs_per_wave": 8, "steps_per_graph": 8})
+              tuning={"waves": 4, "dirs_per_wave": 4, "steps_per_graph": 8, "cache_policy": 1})
     for i, w in enumerate(ws):
         b.set_state(i, w.state0())
     b.step(2)
     tots = b.flavor_totals()
-    sizes = [w.nparticles for w in ws]
-    neg = [i for i, w in enumerate(ws) if min(w.weights()[0].min(), w.weights()[1].min()) < 0]
-    assert neg, "the batch draws should include negative weights"
-    for i in sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), neg[0]}):
-        w = ws[i]
+    set_threads(int(os.environ.get("OMP_NUM_THREADS", "0") or 0))
+    t0 = time.perf_counter()
+    for i, w in enumerate(ws):
         P = Problem.from_workload(w)
         ref = P.step(w.state0(), 2)
         got = b.get_state(i).cpu().numpy()
         assert_parity(got, ref, what=f"batch box {i} ({w.ncell[2]} x {w.ndir})")
         tref = P.flavor_totals(ref)
-        assert np.abs(tots[i] - tref).max() <= TOL * np.abs(tref).max()
-    for i in range(64):
-        s = b.get_state(i)
-        tr = (s[0] + s[1] + s[2] - 1.0).abs().max().item()
-        trb = (s[9] + s[10] + s[11] - 1.0).abs().max().item()
-        assert max(tr, trb) < 1e-14, (i, tr, trb)
+        # the reference adds a total's terms one after another: its rounding
+        # error is bounded by n u sum|terms| (u = 2^-53), which passes 1e-12
+        # for boxes of more than about 9000 particles
+        ttol = max(TOL, w.nparticles * 2.0 ** -53)
+        assert np.abs(tots[i] - tref).max() <= ttol * np.abs(tref).max(), (i, ttol)
+    print(f"64 boxes against the reference in {time.perf_counter() - t0:.1f} s", flush=True)
 
 
 @pytest.mark.parametrize("ncell,ndir,tuning", [(70, 26, None), (150, 92, {"waves": 2, "dirs_per_wave": 3})])
