@@ -85,7 +85,9 @@ int fpic_particles_create(const fpic_pconfig *cfg, void *workspace, size_t works
  * (neutrinos and antineutrinos per particle) and the state at step step0
  * (time step0*dt); sort them by cell and deposit the first-stage moments.
  * FPIC_EINVAL if a position or weight is not finite or a direction is not a
- * unit vector (|Omega|^2 within 1e-9 of 1). */
+ * unit vector (|Omega|^2 within 1e-9 of 1); with exact sums,
+ * FPIC_EUNSUPPORTED if 16 npart max(|N| + |Nbar|)/dV lies outside about
+ * 2^-800 .. 2^990 (the range of the fixed-point scale). */
 int fpic_particles_set(fpic_pctx *ctx, const double *pos0, const double *dirs, const double *N,
                        const double *Nbar, const double *state, int64_t step0);
 

@@ -1544,8 +1544,16 @@ int fpic_particles_set(fpic_pctx *c, const double *pos0, const double *dirs, con
     if (wtot > 0.0 && std::isfinite(wtot)) {
         int e = 0;
         (void)std::frexp(wtot, &e);  // wtot < 2^e
-        S2 = std::max(-1000, std::min(1000, 91 - e));
+        S2 = 91 - e;
     }
+    if (c->exact && (S2 < -900 || S2 > 900)) {
+        // 2^S and 2^-S must stay normal doubles with room for the scaled
+        // contributions; weights this extreme take the floating-point path
+        c->state_set = false;
+        return fail(FPIC_EUNSUPPORTED, "set: weights outside the range of the exact deposit sums "
+                                       "(about 2^-800 .. 2^990 per particle); use FPIC_PFLOAT_ATOMICS");
+    }
+    S2 = std::max(-1000, std::min(1000, S2));  // (the totals' scale with floating-point atomics)
     for (int p = 0; p < 2; ++p) {
         c->h[p].qs = std::ldexp(1.0, S2);
         c->h[p].qi = std::ldexp(1.0, -S2);

@@ -93,3 +93,31 @@ def test_float_atomics_option(torch_dev):
     ref = P.step(w.state0(), 4)
     assert_parity(out[1], ref, what="float atomics")
     assert_parity(out[1], out[0], what="float atomics against exact sums")
+
+
+def test_exact_sums_reject_extreme_weights(torch_dev):
+    """Weights so small that the fixed-point scale of the exact sums would
+    leave the double range are refused (FPIC_EUNSUPPORTED) with exact sums
+    and accepted with floating-point atomics; ordinary weights scaled by
+    2^-600 still run exactly and match the reference (sums scale exactly)."""
+    from paper_2101_02745_amd.particles import ParticleSim
+    from paper_2101_02745_amd._lib import FpicError
+    w = I.particle_workload("1d_64x16_random")
+    N, Nb = w.weights()
+    for scale, exact, ok in ((2.0 ** -900, True, False), (2.0 ** -900, False, True),
+                             (2.0 ** -600, True, True)):
+        sim = ParticleSim(w.ncell, w.dx, w.nparticles, w.hvac(), w.dt, w.shape_order, w.vmat, 4,
+                          exact=exact)
+        try:
+            sim.set(w.positions(), w.dirs(), N * scale, Nb * scale, w.state0())
+        except FpicError as e:
+            assert not ok and "EUNSUPPORTED" in str(e), str(e)
+            sim.close()
+            continue
+        assert ok, (scale, exact)
+        sim.step(3)
+        got = sim.get_state().cpu().numpy()
+        sim.close()
+        P = ParticleProblem(w.ncell, w.dx, w.positions(), w.dirs(), N * scale, Nb * scale, w.hvac(),
+                            w.dt, vmat=w.vmat, shape_order=w.shape_order)
+        assert_parity(got, P.step(w.state0(), 3), what=f"weights x {scale}, exact {exact}")
