@@ -206,8 +206,7 @@ stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ si
             if (MODE == M_DEPOSIT) {
 #pragma unroll
                 for (int k = 0; k < 9; k++)
-                    X[k] = (k == 4 || k == 6 || k == 8) ? wN * Y[k] + wNb * Y[9 + k]
-                                                        : wN * Y[k] - wNb * Y[9 + k];
+                    X[k] = source_comp(k, wN, Y[k], wNb, Y[9 + k]);
             } else if (MODE == M_MOM_NU) {
 #pragma unroll
                 for (int k = 0; k < 9; k++)
@@ -308,8 +307,7 @@ stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ si
                 }
 #pragma unroll
                 for (int k = 0; k < 9; k++)
-                    X[k] = (k == 4 || k == 6 || k == 8) ? wN * yn[k] + wNb * yn[9 + k]
-                                                        : wN * yn[k] - wNb * yn[9 + k];
+                    X[k] = source_comp(k, wN, yn[k], wNb, yn[9 + k]);
             }
         } else {
 #pragma unroll
@@ -344,13 +342,13 @@ stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ si
                     b = x;
                     c = s1;
                 }
-                const double xc = (q.w0 * a + q.w1 * b) + q.w2 * c;
+                const double xc = wsum3(q.w0, a, q.w1, b, q.w2, c);
                 acc[k] += xc;
                 acc[9 + k] += vx * xc;
                 acc[18 + k] += vy * xc;
                 acc[27 + k] += vz * xc;
                 if (lane == nact - 1) {
-                    eb[((d - dbeg) * NE + 0) * 9 + k] = q.up ? q.w1 * x + q.w2 * s1 : q.w2 * x;
+                    eb[((d - dbeg) * NE + 0) * 9 + k] = q.up ? wsum2(q.w1, x, q.w2, s1) : q.w2 * x;
                     eb[((d - dbeg) * NE + 1) * 9 + k] = q.up ? q.w2 * x : 0.0;
                 }
                 if (lane == 0)
@@ -364,7 +362,7 @@ stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ si
             for (int k = 0; k < 9; k++) {
                 double xl = lane_below(X[k]);
                 xl = (lane == 0) ? 0.0 : xl;
-                const double xc = omph * X[k] + ph * xl;
+                const double xc = wsum2(omph, X[k], ph, xl);
                 acc[k] += xc;
                 acc[9 + k] += vx * xc;
                 acc[18 + k] += vy * xc;

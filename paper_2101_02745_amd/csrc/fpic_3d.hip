@@ -38,8 +38,11 @@ using fpic::commutator;
 using fpic::fail;
 using fpic::gld;
 using fpic::gst;
+using fpic::source_comp;
 using fpic::stage_time;
 using fpic::tld;
+using fpic::wsum2;
+using fpic::wsum3;
 
 constexpr int NG = 36;
 constexpr int W = 64;
@@ -188,7 +191,7 @@ __device__ __forceinline__ void store_source(const Desc3 &S, int64_t p, double w
     double x[9];
 #pragma unroll
     for (int k = 0; k < 9; k++)
-        x[k] = (k == 4 || k == 6 || k == 8) ? wN * yn[k] + wNb * yn[9 + k] : wN * yn[k] - wNb * yn[9 + k];
+        x[k] = source_comp(k, wN, yn[k], wNb, yn[9 + k]);
     gst(S.X + p, x[1] - x[0]);
     gst(S.X + S.np + p, x[2] - x[0]);
 #pragma unroll
@@ -467,7 +470,7 @@ __device__ __forceinline__ void accumulate(const Pull<NC> &o, int left, double a
 #pragma unroll
     for (int k = 0; k < NC; k++) {
         const double xl = lane_get(o.X[k], left);
-        const double xc = (1.0 - o.fx) * o.X[k] + o.fx * xl;
+        const double xc = wsum2(1.0 - o.fx, o.X[k], o.fx, xl);
         acc[k] += xc;
         acc[NC + k] += o.vx * xc;
         acc[2 * NC + k] += o.vy * xc;
@@ -666,7 +669,7 @@ __device__ __forceinline__ void fused_accumulate(const double (*Xb)[FW * W], con
         const double fx = ps[0];
         const double xv = Xb[kown][j * W + lane];
         const double xl = lane_below_wrap(xv, lane, nx);
-        const double xc = (1.0 - fx) * xv + fx * xl;
+        const double xc = wsum2(1.0 - fx, xv, fx, xl);
 #pragma unroll
         for (int i = 0; i < 16; i++)
             acc[i] += ps[1 + i] * xc;
@@ -864,7 +867,7 @@ stage3f_kernel(const Desc3 *__restrict__ dp)
                 double x[9];
 #pragma unroll
                 for (int k = 0; k < 9; k++)
-                    x[k] = (k == 4 || k == 6 || k == 8) ? wN * yn[k] + wNb * yn[9 + k] : wN * yn[k] - wNb * yn[9 + k];
+                    x[k] = source_comp(k, wN, yn[k], wNb, yn[9 + k]);
                 double *xs = &Xs[buf][0][wave * W + lane];
                 xs[0 * FW * W] = active ? x[1] - x[0] : 0.0;
                 xs[1 * FW * W] = active ? x[2] - x[0] : 0.0;
@@ -1328,7 +1331,7 @@ deposit3q_kernel(const Desc3 *__restrict__ dp, int half_steps, int out_buf)
 #pragma unroll
         for (int k = 0; k < NC; k++) {
             const double right = lane_get(Xyz[k], xr), left = lane_get(Xyz[k], xl);
-            const double xc = (wx[0] * right + wx[1] * Xyz[k]) + wx[2] * left;
+            const double xc = wsum3(wx[0], right, wx[1], Xyz[k], wx[2], left);
             acc[k] += xc;
             acc[NC + k] += vx * xc;
             acc[2 * NC + k] += vy * xc;

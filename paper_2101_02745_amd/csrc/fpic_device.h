@@ -40,6 +40,32 @@ __device__ __forceinline__ Quad quad_weights(double phi)
     return q;
 }
 
+// Component k of the source a particle deposits, N rho - Nbar conj(rhobar):
+// rhobar enters conjugated, so its imaginary parts (components 4, 6, 8)
+// add.  Written as one explicit fused multiply-add, so that every kernel
+// that forms a source (a stage forming the next stage's, the deposit of a
+// state handed over by the caller) rounds it the same way and a run resumed
+// from a saved state continues bitwise; left to the compiler, which of the
+// two products is fused can differ from one kernel to the next.
+__device__ __forceinline__ double source_comp(int k, double wN, double y, double wNb, double yb)
+{
+    const double b = wNb * yb;
+    return __builtin_fma(wN, y, (k == 4 || k == 6 || k == 8) ? b : -b);
+}
+
+// Shape-weighted sums of two and three values, w0 a + w1 b (+ w2 c), with
+// the rounding fixed by explicit fused multiply-adds in the order written,
+// for the same reason.
+__device__ __forceinline__ double wsum2(double w0, double a, double w1, double b)
+{
+    return __builtin_fma(w1, b, w0 * a);
+}
+
+__device__ __forceinline__ double wsum3(double w0, double a, double w1, double b, double w2, double c)
+{
+    return __builtin_fma(w2, c, __builtin_fma(w1, b, w0 * a));
+}
+
 // k = -i [H, rho] for Hermitian H, rho given as 9 packed reals (diagonal,
 // then Re/Im of the (0,1), (0,2), (1,2) entries).  With C = H rho:
 // k_aa = 2 Im C_aa and k_ab = -i (C_ab - conj(C_ba)) for a < b.  The trace

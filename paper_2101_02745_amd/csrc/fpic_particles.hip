@@ -61,6 +61,7 @@ using fpic::gst;
 using fpic::load_slope;
 using fpic::Quad;
 using fpic::quad_weights;
+using fpic::source_comp;
 using fpic::stage_time;
 using fpic::store_slope;
 
@@ -464,8 +465,7 @@ pstage_kernel(const PDesc *__restrict__ dp, double *outG)
         if (MODE == PM_DEPOSIT) {
 #pragma unroll
             for (int k = 0; k < 9; k++)
-                X[k] = (k == 4 || k == 6 || k == 8) ? wN * Y[k] + wNb * Y[9 + k]
-                                                    : wN * Y[k] - wNb * Y[9 + k];
+                X[k] = source_comp(k, wN, Y[k], wNb, Y[9 + k]);
         } else if (MODE == PM_MOM_NU) {
 #pragma unroll
             for (int k = 0; k < 9; k++)
@@ -589,8 +589,7 @@ pstage_kernel(const PDesc *__restrict__ dp, double *outG)
             }
 #pragma unroll
             for (int k = 0; k < 9; k++)
-                X[k] = (k == 4 || k == 6 || k == 8) ? wN * yn[k] + wNb * yn[9 + k]
-                                                    : wN * yn[k] - wNb * yn[9 + k];
+                X[k] = source_comp(k, wN, yn[k], wNb, yn[9 + k]);
         }
     }
 
