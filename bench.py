@@ -203,6 +203,32 @@ def measure_adjoint(steps=2000, ckpt=50, tune=None):
             "total_over_forward": (t2 - t0) / fwd}
 
 
+def stage_accounting(w, tune):
+    """Kernel names and algorithmic bytes per launch of the four stage
+    kernels and of the kernel that follows each (reduction or deposit), at
+    this implementation's slopes (own) and at the 13-pass contract, for a 1D
+    box, a 3D box on the fused linear stages, or a 3D box on the separate
+    kernels; and the source hash its counter records are keyed by."""
+    P, nc = w.nparticles, w.ncell_total
+    if w.ncell[0] == 1 and w.ncell[1] == 1:
+        own = [STAGE_BYTES[s] * P + 2 * GRID_B * nc for s in (1, 2, 3, 4)]
+        contract = [CONTRACT_STAGE_BYTES[s] * P + 2 * GRID_B * nc for s in (1, 2, 3, 4)]
+        return ("stage1d_kernel", "reduce1d_kernel"), own, contract, None, kernel_source_hash
+    fused = (tune or {}).get("fused", 0) != 2 and w.shape_order == 1 and w.ncell[0] <= 64
+    if fused:
+        # stage kernel: the state passes, four staged grid rows and four
+        # partial rows per workgroup (one x-row of cells); reduction: four
+        # partial grids read, the grid written
+        own = [STAGE_BYTES[s] * P + 2 * 4 * GRID3_B * nc for s in (1, 2, 3, 4)]
+        contract = [CONTRACT_STAGE_BYTES[s] * P + 2 * 4 * GRID3_B * nc for s in (1, 2, 3, 4)]
+        return ("stage3f_kernel", "reduce3f_kernel"), own, contract, 5 * GRID3_B * nc, source_hash_3d
+    own = [STAGE_BYTES[s] * P + SRC3_B * P for s in (1, 2, 3, 4)]
+    contract = [CONTRACT_STAGE_BYTES[s] * P + SRC3_B * P for s in (1, 2, 3, 4)]
+    names = ("particle3d_kernel", "deposit3d_kernel") if w.shape_order == 1 else \
+        ("particle3q_kernel", "deposit3q_kernel")
+    return names, own, contract, SRC3_B * P + GRID3_B * nc, source_hash_3d
+
+
 def measure_3d(steps=200, step0=0):
     """The 64^3 x 92 box (24,117,248 particles) for its 200 steps.  With the
     linear shape each stage is one fused kernel (particle update, and the
@@ -228,23 +254,9 @@ def measure_3d(steps=200, step0=0):
     trace = sim.check(1e-10)
     del sim
     P = w.nparticles
-    nc = w.ncell_total
-    fused = tune.get("fused", 0) != 2
     stage_ms = [ms[0], ms[2], ms[4], ms[6]]
     second_ms = [ms[1], ms[3], ms[5], ms[7]]
-    if fused:
-        # stage kernel: the state passes, four staged grid rows and four
-        # partial rows per workgroup (one x-row of cells); reduction: four
-        # partial grids read, the grid written
-        stage_bytes = [STAGE_BYTES[s] * P + 2 * 4 * GRID3_B * nc for s in (1, 2, 3, 4)]
-        contract_bytes = [CONTRACT_STAGE_BYTES[s] * P + 2 * 4 * GRID3_B * nc for s in (1, 2, 3, 4)]
-        second_bytes = 5 * GRID3_B * nc
-        names = ("stage3f_kernel", "reduce3f_kernel")
-    else:
-        stage_bytes = [STAGE_BYTES[s] * P + SRC3_B * P for s in (1, 2, 3, 4)]
-        contract_bytes = [CONTRACT_STAGE_BYTES[s] * P + SRC3_B * P for s in (1, 2, 3, 4)]
-        second_bytes = SRC3_B * P + GRID3_B * nc
-        names = ("particle3d_kernel", "deposit3d_kernel")
+    names, stage_bytes, contract_bytes, second_bytes, _ = stage_accounting(w, tune)
     step_bytes = sum(stage_bytes) + 4 * second_bytes
     ms_step = 1e3 * wall / steps
     dom = max(range(4), key=lambda k: stage_ms[k])
@@ -580,17 +592,17 @@ def main():
     stage_ms = {s: ms[2 * (s - 1)] for s in (1, 2, 3, 4)}
     red_ms = [ms[2 * s - 1] for s in (1, 2, 3, 4)]
     dom = max(stage_ms, key=lambda s: stage_ms[s])
-    ncell = w.ncell_total
-    alg_bytes = CONTRACT_STAGE_BYTES[dom] * w.nparticles + 2 * GRID_B * ncell
+    launch = sim.tune.as_dict() if sim.tune else None
+    names, own_b, contract_b, second_b, hashfn = stage_accounting(w, launch)
+    alg_bytes = contract_b[dom - 1]
     achieved = alg_bytes / (stage_ms[dom] * 1e-3) / 1e9
-    own_bytes = STAGE_BYTES[dom] * w.nparticles + 2 * GRID_B * ncell
+    own_bytes = own_b[dom - 1]
     own = own_bytes / (stage_ms[dom] * 1e-3) / 1e9
-    kname = f"stage{dom}"
     # the counter records are for the workloads' own (linear) shape
-    traffic = (measured_traffic(kname, w.name, launch=sim.tune.as_dict() if sim.tune else None)
+    traffic = (measured_traffic(f"stage{dom}", w.name, hashfn(), launch=launch)
                if w.shape_order == 1 else None)
-    step_bytes = CONTRACT_STEP_BYTES * w.nparticles + 4 * 2 * GRID_B * ncell
-    own_step_bytes = STEP_BYTES * w.nparticles + 4 * 2 * GRID_B * ncell
+    step_bytes = sum(contract_b) + 4 * (second_b or 0)
+    own_step_bytes = sum(own_b) + 4 * (second_b or 0)
     ok = sim.check(1e-10)
 
     rec = {
@@ -605,7 +617,7 @@ def main():
                    "launch_source": "explicit" if args.tuning else "autotuned"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": f"stage1d_kernel<{dom}>",
+                     "kernel": f"{names[0]}<{dom}>",
                      "alg_bytes_per_launch": alg_bytes, "ms_per_launch": stage_ms[dom],
                      "accounting": ACCOUNTING, "own_bytes_per_launch": own_bytes,
                      "own_achieved": own, "own_frac": own / HBM_PEAK_GBS},
