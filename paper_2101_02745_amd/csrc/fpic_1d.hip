@@ -87,8 +87,8 @@ __device__ __forceinline__ int pmod_dbl(double i, int n)
 }
 
 // NT: streaming (nontemporal) cache policy for the data a stage does not
-// read again soon (the last reads of the slopes in stage 4, the new state,
-// k2); the default policy keeps everything cacheable.  Streaming pays when
+// read again soon (the last reads of the slopes in stage 4, and k2); the
+// default policy keeps everything cacheable.  Streaming pays when
 // the arrays overflow the Infinity Cache (a large single box), not for
 // smaller working sets (chosen per context, see fpic_tuning.cache_policy).
 // SH: shape-function order, 1 (linear) or 2 (quadratic).  The staged grid
@@ -286,13 +286,12 @@ stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ si
                 double yn[18];
                 if (MODE == M_S4) {
                     const double h6 = dt / 6.0;
+                    // (the new state keeps the default policy: the next
+                    // step's first stage reads it straight back)
 #pragma unroll
                     for (int k = 0; k < 18; k++) {
                         yn[k] = base[k] + h6 * kk[k];
-                        if (NT)
-                            gst_nt(S.Yout + k * np + p, yn[k]);
-                        else
-                            gst(S.Yout + k * np + p, yn[k]);
+                        gst(S.Yout + k * np + p, yn[k]);
                     }
                 } else {
                     double *Ko = (MODE == M_S1) ? S.K1 : (MODE == M_S2) ? S.K2 : S.K3;

@@ -25,7 +25,8 @@
 //
 // Deposits are summed exactly, in integers: each contribution v is scaled
 // by 2^S (S fixed per box from the particle count and the largest weight,
-// so that no cell's sum can pass 2^93) and split into two 64-bit limbs,
+// so that no contribution and no cell's sum can pass 2^83) and split into
+// two 64-bit limbs,
 // hi = floor(V / 2^32) and lo = V - 2^32 hi in [0, 2^32), V = rint(v 2^S).
 // Integer atomics add the
 // limbs; integer addition is associative, so the sums do not depend on the
@@ -33,7 +34,7 @@
 // a cell (the counting sort leaves that order to its atomics): every run
 // is bitwise reproducible.  A finalize pass turns each limb pair into a
 // double (one rounding of the exact sum of the scaled contributions, each
-// of which is off by at most 2^-(S+1), i.e. 2^-91 of 16 np max_p (|N_p| +
+// of which is off by at most 2^-(S+1), i.e. 2^-86 of 16 np max_p (|N_p| +
 // |Nbar_p|)/dV) and clears the limbs.  Stage s of step n reads G[(4n+s-1) % 3] and its
 // finalize writes G[(4n+s) % 3].
 //
@@ -106,17 +107,20 @@ struct PDesc {
 
 // ---- exact deposit sums -------------------------------------------------
 // v 2^S as the limb pair (hi, lo) with rint(v 2^S) = 2^32 hi + lo and
-// 0 <= lo < 2^32.  |v 2^S| < 2^93, so |hi| < 2^61.  Every step is exact.
+// 0 <= lo < 2^32.  |v 2^S| < 2^83 (the scale's bound), so -2^51 <= hi <
+// 2^51, and both limbs are read off the bits of a double: an integer-valued
+// double in [2^52, 2^53) holds its value minus 2^52 in its mantissa bits
+// (no double-to-64-bit-integer conversion exists on this GPU).  Every step
+// is exact.
 __device__ __forceinline__ void to_limbs(double v, double qs, long long &hi, long long &lo)
 {
 #pragma clang fp contract(off)
     const double V = rint(v * qs);
     const double h = floor(V * 0x1p-32);
-    const double r = V - h * 0x1p32;  // integer in [0, 2^32)
-    const double hh = floor(h * 0x1p-32);
-    const double hl = h - hh * 0x1p32;
-    hi = (long long)(((unsigned long long)(unsigned)(int)hh << 32) | (unsigned long long)(unsigned)hl);
-    lo = (long long)(unsigned)r;
+    const double r = fma(h, -0x1p32, V);  // integer in [0, 2^32), exact
+    const double M = 0x1.8p52;            // h + M in [2^52, 2^53)
+    hi = __double_as_longlong(h + M) - __double_as_longlong(M);
+    lo = (long long)(unsigned)__double2loint(r + 0x1p52);
 }
 
 // the double nearest to 2^-S (2^32 a1 + a0) for limb sums a1, a0 (a0 >= 0)
@@ -461,7 +465,7 @@ pstage_kernel(const PDesc *__restrict__ dp, double *outG)
         double Y[18];
 #pragma unroll
         for (int k = 0; k < 18; k++)
-            Y[k] = gld(S.Y + k * np + i);
+            Y[k] = D3 ? fpic::gld_nt(S.Y + k * np + i) : gld(S.Y + k * np + i);
         if (MODE == PM_DEPOSIT) {
 #pragma unroll
             for (int k = 0; k < 9; k++)
@@ -550,7 +554,7 @@ pstage_kernel(const PDesc *__restrict__ dp, double *outG)
             } else {
                 const double a = 0.5 * dt;
                 double kp[18];
-                load_slope(MODE == 2 ? S.K1 : S.K2, np, i, kp);
+                load_slope<D3>(MODE == 2 ? S.K1 : S.K2, np, i, kp);
 #pragma unroll
                 for (int k = 0; k < 18; k++) {
                     y[k] = Y[k] + a * kp[k];
@@ -579,7 +583,11 @@ pstage_kernel(const PDesc *__restrict__ dp, double *outG)
             } else {
                 double *Ko = MODE == 1 ? S.K1 : (MODE == 2 ? S.K2 : S.K3);
                 const double an = MODE == 3 ? dt : 0.5 * dt;
-                if (MODE == 2)  // k2 streams; k1 and k3 stay cached
+                // k2 streams; k1 and k3 stay cached in 1D, where the next
+                // kernel finds part of them in the Infinity Cache; a 3D box
+                // streams every particle array (its 3 million particles'
+                // arrays dwarf that cache: 6.35 -> 6.19 ms per step)
+                if (MODE == 2 || D3)
                     store_slope<true>(Ko, np, i, kk);
                 else
                     store_slope<false>(Ko, np, i, kk);
@@ -1526,10 +1534,12 @@ int fpic_particles_set(fpic_pctx *c, const double *pos0, const double *dirs, con
                                  "not a unit vector");
     }
     // the fixed-point scale of the exact deposit sums: 2^S with
-    // 16 np max_p (|N_p| + |Nbar_p|)/dV <= 2^91.  A cell's moment component
-    // is at most 2 sum_p (|N_p| + |Nbar_p|)/dV (density-matrix entries and
-    // differences of two diagonal entries are at most 1, velocity
-    // components and shape weights at most 1), so no limb sum can overflow.
+    // 16 np max_p (|N_p| + |Nbar_p|)/dV <= 2^86.  A contribution is at most
+    // 2 max_p (|N_p| + |Nbar_p|)/dV and a cell's moment component at most
+    // 2 sum_p (|N_p| + |Nbar_p|)/dV (density-matrix entries and differences
+    // of two diagonal entries are at most 1, velocity components and shape
+    // weights at most 1): both stay below 2^83 after scaling, which the
+    // limb split needs, and no limb sum can overflow.
     // The bound uses a maximum, not a sum, so that S does not depend on the
     // order of the particles.
     double *wmax = c->scratch + kScratch3;
@@ -1543,14 +1553,14 @@ int fpic_particles_set(fpic_pctx *c, const double *pos0, const double *dirs, con
     if (wtot > 0.0 && std::isfinite(wtot)) {
         int e = 0;
         (void)std::frexp(wtot, &e);  // wtot < 2^e
-        S2 = 91 - e;
+        S2 = 86 - e;
     }
     if (c->exact && (S2 < -900 || S2 > 900)) {
         // 2^S and 2^-S must stay normal doubles with room for the scaled
         // contributions; weights this extreme take the floating-point path
         c->state_set = false;
         return fail(FPIC_EUNSUPPORTED, "set: weights outside the range of the exact deposit sums "
-                                       "(about 2^-800 .. 2^990 per particle); use FPIC_PFLOAT_ATOMICS");
+                                       "(16 npart max(|N| + |Nbar|)/dV outside about 2^-814 .. 2^986); use FPIC_PFLOAT_ATOMICS");
     }
     S2 = std::max(-1000, std::min(1000, S2));  // (the totals' scale with floating-point atomics)
     for (int p = 0; p < 2; ++p) {
