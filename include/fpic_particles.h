@@ -28,7 +28,7 @@
  * integers are added as two 64-bit limbs with integer atomics, and the
  * exact sum is rounded once to a double.  Results are therefore bitwise
  * the same from run to run and whatever order the caller gives the
- * particles in; a contribution's rounding error is at most 2^-86 of
+ * particles in; a contribution's rounding error is at most 2^-84 of
  * 16 npart max(|N| + |Nbar|)/dV.  The flag FPIC_PFLOAT_ATOMICS trades this
  * for speed (floating-point atomics; flavor totals stay exact).
  *
@@ -87,7 +87,7 @@ int fpic_particles_create(const fpic_pconfig *cfg, void *workspace, size_t works
  * FPIC_EINVAL if a position or weight is not finite or a direction is not a
  * unit vector (|Omega|^2 within 1e-9 of 1); with exact sums,
  * FPIC_EUNSUPPORTED if 16 npart max(|N| + |Nbar|)/dV lies outside about
- * 2^-814 .. 2^986 (the range of the fixed-point scale). */
+ * 2^-816 .. 2^984 (the range of the fixed-point scale). */
 int fpic_particles_set(fpic_pctx *ctx, const double *pos0, const double *dirs, const double *N,
                        const double *Nbar, const double *state, int64_t step0);
 

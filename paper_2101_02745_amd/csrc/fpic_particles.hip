@@ -25,7 +25,7 @@
 //
 // Deposits are summed exactly, in integers: each contribution v is scaled
 // by 2^S (S fixed per box from the particle count and the largest weight,
-// so that no contribution and no cell's sum can pass 2^83) and split into
+// so that no contribution and no cell's sum can pass 2^81) and split into
 // two 64-bit limbs,
 // hi = floor(V / 2^32) and lo = V - 2^32 hi in [0, 2^32), V = rint(v 2^S).
 // Integer atomics add the
@@ -34,7 +34,7 @@
 // a cell (the counting sort leaves that order to its atomics): every run
 // is bitwise reproducible.  A finalize pass turns each limb pair into a
 // double (one rounding of the exact sum of the scaled contributions, each
-// of which is off by at most 2^-(S+1), i.e. 2^-86 of 16 np max_p (|N_p| +
+// of which is off by at most 2^-(S+1), i.e. 2^-84 of 16 np max_p (|N_p| +
 // |Nbar_p|)/dV) and clears the limbs.  Stage s of step n reads G[(4n+s-1) % 3] and its
 // finalize writes G[(4n+s) % 3].
 //
@@ -107,8 +107,8 @@ struct PDesc {
 
 // ---- exact deposit sums -------------------------------------------------
 // v 2^S as the limb pair (hi, lo) with rint(v 2^S) = 2^32 hi + lo and
-// 0 <= lo < 2^32.  |v 2^S| < 2^83 (the scale's bound), so -2^51 <= hi <
-// 2^51, and both limbs are read off the bits of a double: an integer-valued
+// 0 <= lo < 2^32.  Valid for |v 2^S| < 2^83 (the scale keeps contributions
+// below 2^81), so that -2^51 <= hi < 2^51; both limbs are read off the bits of a double: an integer-valued
 // double in [2^52, 2^53) holds its value minus 2^52 in its mantissa bits
 // (no double-to-64-bit-integer conversion exists on this GPU).  Every step
 // is exact.
@@ -1534,12 +1534,13 @@ int fpic_particles_set(fpic_pctx *c, const double *pos0, const double *dirs, con
                                  "not a unit vector");
     }
     // the fixed-point scale of the exact deposit sums: 2^S with
-    // 16 np max_p (|N_p| + |Nbar_p|)/dV <= 2^86.  A contribution is at most
+    // 16 np max_p (|N_p| + |Nbar_p|)/dV <= 2^84.  A contribution is at most
     // 2 max_p (|N_p| + |Nbar_p|)/dV and a cell's moment component at most
     // 2 sum_p (|N_p| + |Nbar_p|)/dV (density-matrix entries and differences
     // of two diagonal entries are at most 1, velocity components and shape
-    // weights at most 1): both stay below 2^83 after scaling, which the
-    // limb split needs, and no limb sum can overflow.
+    // weights at most 1): both stay below 2^81 after scaling, a factor 4
+    // inside the 2^83 that the limb split needs (room for states whose
+    // entries drift past 1), and no limb sum can overflow.
     // The bound uses a maximum, not a sum, so that S does not depend on the
     // order of the particles.
     double *wmax = c->scratch + kScratch3;
@@ -1553,14 +1554,14 @@ int fpic_particles_set(fpic_pctx *c, const double *pos0, const double *dirs, con
     if (wtot > 0.0 && std::isfinite(wtot)) {
         int e = 0;
         (void)std::frexp(wtot, &e);  // wtot < 2^e
-        S2 = 86 - e;
+        S2 = 84 - e;
     }
     if (c->exact && (S2 < -900 || S2 > 900)) {
         // 2^S and 2^-S must stay normal doubles with room for the scaled
         // contributions; weights this extreme take the floating-point path
         c->state_set = false;
         return fail(FPIC_EUNSUPPORTED, "set: weights outside the range of the exact deposit sums "
-                                       "(16 npart max(|N| + |Nbar|)/dV outside about 2^-814 .. 2^986); use FPIC_PFLOAT_ATOMICS");
+                                       "(16 npart max(|N| + |Nbar|)/dV outside about 2^-816 .. 2^984); use FPIC_PFLOAT_ATOMICS");
     }
     S2 = std::max(-1000, std::min(1000, S2));  // (the totals' scale with floating-point atomics)
     for (int p = 0; p < 2; ++p) {
