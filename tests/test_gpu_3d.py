@@ -37,6 +37,10 @@ def box(ncell, ndir, dx=0.5, dt=0.1, **kw):
     ((8, 6, 5), 26, {"waves": 1, "dirs_per_wave": 3}, 57),
     ((13, 7, 3), 26, {"waves": 2, "dirs_per_wave": 2}, 1000),
     ((64, 3, 4), 92, {"waves": 4, "dirs_per_wave": 7}, 333),
+    # the largest direction table of the fused linear stages, and one past it
+    # (the separate kernels take over)
+    ((6, 5, 4), 1024, None, 2),
+    ((6, 5, 4), 1030, None, 2),
 ])
 def test_3d_parity(torch_dev, ncell, ndir, tuning, step0):
     from paper_2101_02745_amd.sim import Sim
