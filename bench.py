@@ -203,6 +203,30 @@ def measure_adjoint(steps=2000, ckpt=50, tune=None):
             "total_over_forward": (t2 - t0) / fwd}
 
 
+def event_timing(reset, step, steps, runs=5):
+    """Per-step time of `steps` steps from HIP events, median of `runs` runs,
+    each from the same initial state (reset()) after one warm-up step.  The
+    events are recorded on torch's current stream, the stream the library's
+    context was created on, so they bracket its kernels."""
+    import numpy as np
+    import torch
+    per = []
+    for _ in range(runs):
+        reset()
+        step(1)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        step(steps)
+        e1.record()
+        e1.synchronize()
+        per.append(e0.elapsed_time(e1) / steps)
+    return {"ms_per_step_median": float(np.median(per)), "ms_per_step_runs": per,
+            "steps_per_run": steps, "runs": runs,
+            "timer": "HIP events on the context's stream around the steps, median of the runs, "
+                     "each from the initial state after one warm-up step"}
+
+
 def stage_accounting(w, tune):
     """Kernel names and algorithmic bytes per launch of the four stage
     kernels and of the kernel that follows each (reduction or deposit), at
@@ -243,13 +267,15 @@ def measure_3d(steps=200, step0=0):
     w = I.workload("3d_64x92")
     tune, _ = autotune([HostConfig.from_workload(w)])
     sim = Sim.from_workload(w, tuning=tune)
-    sim.set_state(w.state0(), step0)
+    s0 = w.state0()
+    sim.set_state(s0, step0)
     sim.step(2)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sim.step(steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    ev = event_timing(lambda: sim.set_state(s0, step0), sim.step, steps)
     ms = sim.profile(3)
     trace = sim.check(1e-10)
     del sim
@@ -280,6 +306,7 @@ def measure_3d(steps=200, step0=0):
                         "alg_bytes_per_launch": contract_bytes[dom], "ms_per_launch": stage_ms[dom],
                         "accounting": ACCOUNTING, "own_bytes_per_launch": stage_bytes[dom],
                         "own_achieved": own, "own_frac": own / HBM_PEAK_GBS},
+           "event_timing": ev,
            "trace_error": trace}
     return rec
 
@@ -332,6 +359,13 @@ def measure_batch(steps=1000, nsim=64):
     b.step(steps)
     torch.cuda.synchronize()
     tb = time.perf_counter() - t0
+    s0s = [w.state0() for w in ws]
+
+    def reset():
+        for i, st in enumerate(s0s):
+            b.set_state(i, st)
+
+    ev = event_timing(reset, b.step, min(steps, 200))
     ms = b.profile(5)
     b.close()
     del b
@@ -362,6 +396,7 @@ def measure_batch(steps=1000, nsim=64):
             "ratio_note": "a 3x gain over the sequential runs would need "
                           f"{3 * P * steps / ts:.3g} particle-steps/s, above the 1872 B "
                           f"roofline of {HBM_PEAK_GBS * 1e9 / CONTRACT_STEP_BYTES:.3g}",
+            "event_timing": ev,
             "stage_ms": stage_ms, "reduce_ms": [ms[1], ms[3], ms[5], ms[7]],
             "roofline": {"bound": "hbm", "kernel": f"stage1d_kernel<{dom + 1}> (batched)",
                          "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -586,6 +621,10 @@ def main():
     ms_step = 1e3 * wall / args.steps
     value = w.nparticles * args.steps / wall
     print(f"[bench] timed {args.steps} steps: {ms_step:.4f} ms/step", file=sys.stderr, flush=True)
+    s0 = w.state0()
+    ev = event_timing(lambda: sim.set_state(s0, args.step0), sim.step, args.steps)
+    print(f"[bench] HIP events: {ev['ms_per_step_median']:.4f} ms/step (median of {ev['runs']})",
+          file=sys.stderr, flush=True)
 
     # per-kernel launch times (HIP events on the library's stream)
     ms = sim.profile(20)
@@ -628,6 +667,7 @@ def main():
                           "own_frac": own_step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
                           "stage_ms": [stage_ms[s] for s in (1, 2, 3, 4)],
                           "reduce_ms": red_ms},
+        "event_timing": ev,
         "trace_error": ok,
     }
     if not args.no_extra:
