@@ -86,8 +86,7 @@ typedef struct fpic_config {
 /* Launch shape.  Zero fields take the built-in choice; fpic_autotune
  * measures candidates on the device and returns the fastest. */
 typedef struct fpic_tuning {
-    int32_t waves;           /* 64-lane waves per workgroup: 1, 2 or 4
-                                (1D boxes and batches); 1, 2, 4 or 8 (3D) */
+    int32_t waves;           /* 64-lane waves per workgroup: 1, 2, 4 or 8 */
     int32_t dirs_per_wave;   /* directions each wave sweeps, >= 1 */
     int32_t steps_per_graph; /* steps captured in one hipGraph, >= 1 */
     int32_t cache_policy;    /* 1D boxes and batches: 1 default caching; 2

@@ -27,7 +27,7 @@ constexpr int gt_stride(int sh) { return gt_cells(sh) + 1; }
 // tile only to the right (one cell); the quadratic one two cells to the
 // right and one to the left (slots 0, 1: right; 2: left).
 constexpr int n_edges(int sh) { return sh == 2 ? 3 : 1; }
-constexpr int MAX_WAVES = 4;
+constexpr int MAX_WAVES = 8;
 // Reals stored per Runge-Kutta slope.  A slope k = -i[H, rho] is traceless
 // (the trace of a commutator vanishes), so its first diagonal entry is kept
 // as -(k_11 + k_22) and only the other 8 + 8 reals of k and kbar are stored:

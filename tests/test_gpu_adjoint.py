@@ -25,6 +25,7 @@ def normwise(a, b):
     (70, 26, 11, 4, None),
     (33, 6, 5, 5, {"waves": 1, "dirs_per_wave": 1}),
     (130, 92, 6, 4, {"waves": 4, "dirs_per_wave": 5}),
+    (200, 92, 5, 3, {"waves": 8, "dirs_per_wave": 3}),
     (1, 26, 7, 3, None),
 ])
 def test_adjoint_matches_reference(torch_dev, ncell, ndir, nsteps, ckpt, tuning):

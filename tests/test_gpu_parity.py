@@ -104,7 +104,8 @@ def test_ragged_shapes(torch_dev, ncell, ndir):
 
 @pytest.mark.parametrize("tuning", [{"waves": 1, "dirs_per_wave": 1},
                                     {"waves": 2, "dirs_per_wave": 3},
-                                    {"waves": 4, "dirs_per_wave": 5, "steps_per_graph": 3}])
+                                    {"waves": 4, "dirs_per_wave": 5, "steps_per_graph": 3},
+                                    {"waves": 8, "dirs_per_wave": 2, "steps_per_graph": 5}])
 def test_launch_shapes(torch_dev, tuning):
     w = I.scaled(I.workload("1d_2048x378"), ncell=(1, 1, 150), ndir=92)
     _, _, got, ref = run_pair(w, 7, tuning=tuning)
@@ -273,7 +274,7 @@ def test_full_batch_every_box(torch_dev):
     neg = [i for i, w in enumerate(ws) if min(w.weights()[0].min(), w.weights()[1].min()) < 0]
     assert neg, "the batch draws should include negative weights"
     b = Batch([HostConfig.from_workload(w) for w in ws],
-              tuning={"waves": 4, "dirs_per_wave": 4, "steps_per_graph": 8, "cache_policy": 1})
+              tuning={"waves": 8, "dirs_per_wave": 8, "steps_per_graph": 8, "cache_policy": 0})
     for i, w in enumerate(ws):
         b.set_state(i, w.state0())
     b.step(2)

@@ -55,7 +55,8 @@ def test_quadratic_ragged_shapes(torch_dev, ncell, ndir):
 
 @pytest.mark.parametrize("tuning", [{"waves": 1, "dirs_per_wave": 1},
                                     {"waves": 2, "dirs_per_wave": 3},
-                                    {"waves": 4, "dirs_per_wave": 5, "steps_per_graph": 3}])
+                                    {"waves": 4, "dirs_per_wave": 5, "steps_per_graph": 3},
+                                    {"waves": 8, "dirs_per_wave": 2, "steps_per_graph": 5}])
 def test_quadratic_launch_shapes(torch_dev, tuning):
     w = quad(I.scaled(I.workload("1d_2048x378"), ncell=(1, 1, 150), ndir=92))
     _, _, got, ref = run_pair(w, 7, tuning=tuning)
