@@ -158,6 +158,23 @@ __device__ __forceinline__ void global_add_limbs(long long *GL, int64_t plane, i
     gatomic_add_ll(GL + plane + q, lo);
 }
 
+// Limb sums of one box entry (LDS offset q of each of the R copies, hi
+// limbs, then lo limbs half further on) added to grid entry g.
+__device__ __forceinline__ void flush_limbs(const long long *lacc, int R, int cstride, int half, int q,
+                                            long long *GL, int64_t g, int64_t plane)
+{
+    long long hi = 0, lo = 0;
+#pragma unroll 4
+    for (int r = 0; r < R; r++) {
+        hi += lacc[r * cstride + q];
+        lo += lacc[r * cstride + half + q];
+    }
+    if (hi != 0)
+        gatomic_add_ll(GL + g, hi);
+    if (lo != 0)
+        gatomic_add_ll(GL + plane + g, lo);
+}
+
 // n-periodic index of an integer-valued double (|i| < 2^52)
 __device__ __forceinline__ int wrap_cell(double i, int n)
 {
@@ -425,10 +442,13 @@ pstage_kernel(const PDesc *__restrict__ dp, double *outG)
 
     const int nn[3] = {nx, ny, nz};
 
-    // stencil at the current position.  Stages 1-3 stage the grid cells
-    // their particles interpolate from in LDS when they fit; stage 4, which
-    // streams the most particle data, reads them through the caches (the
-    // staging barrier would hold its streams back).
+    // stencil at the current position.  The grid cells a workgroup's
+    // particles interpolate from are staged in LDS when they fit, except in
+    // stage 4 of a 1D box, which streams the most particle data and reads
+    // its two cells per particle through the caches (there the staging
+    // barrier held its streams back).  In 3D the 256 reads per particle
+    // from memory keep only a few loads in flight: staging them took the
+    // random 32^3 box from 6.20 to 5.93 ms per step.
     int gf[3] = {0, 0, 0}, go[3] = {0, 0, 0};
     double gw[3][3] = {{1.0, 0.0, 0.0}, {1.0, 0.0, 0.0}, {1.0, 0.0, 0.0}};
     Box gb = {};
@@ -440,18 +460,38 @@ pstage_kernel(const PDesc *__restrict__ dp, double *outG)
             axis_stencil<SH>(py, vy, t_cur, S.dx[1], ny, &gf[1], gw[1]);
         }
     }
-    if (MODE <= 3) {
+    if (MODE <= 3 || (D3 && RK)) {
         gb = block_box<SW, D3>(gf, active, nn, sred, sref, go);
-        g_lds = gb.cells * NGC <= ACC_DOUBLES;
+        g_lds = gb.cells * NGC <= ACC_DOUBLES && gb.cells <= BLK;
         if (g_lds) {
             const int cells = (int)gb.cells;
-            for (int q = threadIdx.x; q < NGC * cells; q += BLK) {
-                const int comp = q / cells, l = q - comp * cells;
-                const int lx = l % gb.s[0], ly = (l / gb.s[0]) % gb.s[1], lz = l / (gb.s[0] * gb.s[1]);
-                const int cz = wrap_int(gb.ref[2] + gb.lo[2] + lz, nz);
-                const int cy = D3 ? wrap_int(gb.ref[1] + gb.lo[1] + ly, ny) : 0;
-                const int cx = D3 ? wrap_int(gb.ref[0] + gb.lo[0] + lx, nx) : 0;
-                acc[q] = gld(Gin + (int64_t)comp * nc + ((int64_t)cz * ny + cy) * nx + cx);
+            if (D3) {
+                // thread l stages cell l of the box: one cell index
+                // decomposition, all its components' loads in flight at once
+                // (a 3D box has tens of cells; element by element, each
+                // thread's loads waited one after another)
+                const int l = threadIdx.x;
+                if (l < cells) {
+                    const int lx = l % gb.s[0], ly = (l / gb.s[0]) % gb.s[1], lz = l / (gb.s[0] * gb.s[1]);
+                    const int cz = wrap_int(gb.ref[2] + gb.lo[2] + lz, nz);
+                    const int cy = wrap_int(gb.ref[1] + gb.lo[1] + ly, ny);
+                    const int cx = wrap_int(gb.ref[0] + gb.lo[0] + lx, nx);
+                    const double *src = Gin + ((int64_t)cz * ny + cy) * nx + cx;
+                    double v[NGC];
+#pragma unroll
+                    for (int comp = 0; comp < NGC; comp++)
+                        v[comp] = gld(src + (int64_t)comp * nc);
+#pragma unroll
+                    for (int comp = 0; comp < NGC; comp++)
+                        acc[comp * cells + l] = v[comp];
+                }
+            } else {
+                // a 1D box has a few cells: one element per thread
+                for (int q = threadIdx.x; q < NGC * cells; q += BLK) {
+                    const int comp = q / cells, l = q - comp * cells;
+                    const int cz = wrap_int(gb.ref[2] + gb.lo[2] + l, nz);
+                    acc[q] = gld(Gin + (int64_t)comp * nc + cz);
+                }
             }
             __syncthreads();
         }
@@ -694,24 +734,29 @@ pstage_kernel(const PDesc *__restrict__ dp, double *outG)
                     }
                 }
                 __syncthreads();
-                for (int q = threadIdx.x; q < half; q += BLK) {
-                    long long hi = 0, lo = 0;
-#pragma unroll 4
-                    for (int r = 0; r < R; r++) {
-                        hi += lacc[r * cstride + q];
-                        lo += lacc[r * cstride + half + q];
-                    }
-                    if (hi != 0 || lo != 0) {
-                        const int comp = g0 * NCS + q / cells, l = q % cells;
+                // flush; integer sums, so the order in which the atomics land
+                // does not matter
+                if (D3) {
+                    // BLK / cells threads per box cell (each forms the cell's
+                    // grid index once) share the pass's components
+                    const int per = cells < BLK ? BLK / cells : 1;
+                    for (int t = threadIdx.x; t < per * cells; t += BLK) {
+                        const int l = t % cells, c0 = t / cells;
                         const int lx = l % sx, ly = (l / sx) % sy, lz = l / (sx * sy);
                         const int cz = wrap_int(db.ref[2] + db.lo[2] + lz, nz);
-                        const int cy = D3 ? wrap_int(db.ref[1] + db.lo[1] + ly, ny) : 0;
-                        const int cx = D3 ? wrap_int(db.ref[0] + db.lo[0] + lx, nx) : 0;
-                        const int64_t g = (int64_t)comp * nc + ((int64_t)cz * ny + cy) * nx + cx;
-                        if (hi != 0)
-                            gatomic_add_ll(S.GL + g, hi);
-                        if (lo != 0)
-                            gatomic_add_ll(S.GL + plane + g, lo);
+                        const int cy = wrap_int(db.ref[1] + db.lo[1] + ly, ny);
+                        const int cx = wrap_int(db.ref[0] + db.lo[0] + lx, nx);
+                        const int64_t cell = ((int64_t)cz * ny + cy) * nx + cx;
+                        for (int c = c0; c < NCS * gpp; c += per)
+                            flush_limbs(lacc, R, cstride, half, c * cells + l, S.GL,
+                                        (int64_t)(g0 * NCS + c) * nc + cell, plane);
+                    }
+                } else {
+                    // a 1D box has a few cells: one entry per thread
+                    for (int q = threadIdx.x; q < half; q += BLK) {
+                        const int c = q / cells, l = q - c * cells;
+                        const int cz = wrap_int(db.ref[2] + db.lo[2] + l, nz);
+                        flush_limbs(lacc, R, cstride, half, q, S.GL, (int64_t)(g0 * NCS + c) * nc + cz, plane);
                     }
                 }
                 __syncthreads();  // the next pass clears the accumulators
@@ -772,17 +817,32 @@ pstage_kernel(const PDesc *__restrict__ dp, double *outG)
             }
         }
         __syncthreads();
-        for (int q = threadIdx.x; q < NGC * cells; q += BLK) {
-            double val = 0.0;
-            for (int r = 0; r < R; r++)
-                val += acc[r * cstride + q];
-            if (val != 0.0) {
-                const int comp = q / cells, l = q - comp * cells;
+        if (D3) {
+            const int per = cells < BLK ? BLK / cells : 1;  // threads per box cell
+            for (int t = threadIdx.x; t < per * cells; t += BLK) {
+                const int l = t % cells, c0 = t / cells;
                 const int lx = l % sx, ly = (l / sx) % sy, lz = l / (sx * sy);
                 const int cz = wrap_int(db.ref[2] + db.lo[2] + lz, nz);
-                const int cy = D3 ? wrap_int(db.ref[1] + db.lo[1] + ly, ny) : 0;
-                const int cx = D3 ? wrap_int(db.ref[0] + db.lo[0] + lx, nx) : 0;
-                gatomic_add(Gout + (int64_t)comp * nc + ((int64_t)cz * ny + cy) * nx + cx, val);
+                const int cy = wrap_int(db.ref[1] + db.lo[1] + ly, ny);
+                const int cx = wrap_int(db.ref[0] + db.lo[0] + lx, nx);
+                double *gcell = Gout + ((int64_t)cz * ny + cy) * nx + cx;
+                for (int comp = c0; comp < NGC; comp += per) {
+                    const int q = comp * cells + l;
+                    double val = 0.0;
+                    for (int r = 0; r < R; r++)
+                        val += acc[r * cstride + q];
+                    if (val != 0.0)
+                        gatomic_add(gcell + (int64_t)comp * nc, val);
+                }
+            }
+        } else {
+            for (int q = threadIdx.x; q < NGC * cells; q += BLK) {
+                const int comp = q / cells, l = q - comp * cells;
+                double val = 0.0;
+                for (int r = 0; r < R; r++)
+                    val += acc[r * cstride + q];
+                if (val != 0.0)
+                    gatomic_add(Gout + (int64_t)comp * nc + wrap_int(db.ref[2] + db.lo[2] + l, nz), val);
             }
         }
     } else if (active) {
