@@ -510,7 +510,8 @@ def measure_particles_3d(steps=16, sort_every=4, exact=True):
     stage_bytes = [PSTAGE3_BYTES[s] * P + grid for s in (1, 2, 3, 4)]
     step_bytes = sum(stage_bytes) + PSORT3_BYTES * P / sort_every
     stage_bytes[3] += PSORT3_BYTES * P  # the profiled stage 4 sorts
-    names = ["pstage_kernel<1>", "pstage_kernel<2>", "pstage_kernel<3>", "pstage_kernel<8>"]
+    sums = "exact" if exact else "float_atomics"
+    names = [f"pstage_kernel<{m}> {sums}" for m in (1, 2, 3, 8)]
     ms_step = 1e3 * wall / steps
     dom = max(range(4), key=lambda k: ms[k])
     return {"workload": w.name, "particles": P, "steps": steps,
