@@ -121,3 +121,29 @@ def test_exact_sums_reject_extreme_weights(torch_dev):
         P = ParticleProblem(w.ncell, w.dx, w.positions(), w.dirs(), N * scale, Nb * scale, w.hvac(),
                             w.dt, vmat=w.vmat, shape_order=w.shape_order)
         assert_parity(got, P.step(w.state0(), 3), what=f"weights x {scale}, exact {exact}")
+
+
+def test_exact_sums_near_the_scale_bound(torch_dev):
+    """Two particles, one carrying 2^-20 of the other's weights: the scale is
+    set by the pair alone, so the heavy particle's contributions come within
+    a few bits of the largest the limb split takes (2^81 after scaling), the
+    light one's lie 20 bits lower; the exact sums match the reference at
+    1e-12 and repeat bit for bit."""
+    from paper_2101_02745_amd.particles import ParticleSim
+    w = I.particle_workload("1d_64x16_random")
+    pos, dirs, st = w.positions()[:2].copy(), w.dirs()[:2].copy(), w.state0()[:, :2].copy()
+    N, Nb = w.weights()
+    N, Nb = N[:2].copy(), Nb[:2].copy()
+    N[1] *= 2.0 ** -20
+    Nb[1] *= 2.0 ** -20
+    out = []
+    for _ in range(2):
+        sim = ParticleSim(w.ncell, w.dx, 2, w.hvac(), w.dt, w.shape_order, w.vmat, 4)
+        sim.set(pos, dirs, N, Nb, st)
+        sim.step(5)
+        out.append(sim.get_state().cpu().numpy())
+        sim.close()
+    assert np.array_equal(out[0], out[1])
+    P = ParticleProblem(w.ncell, w.dx, pos, dirs, N, Nb, w.hvac(), w.dt, vmat=w.vmat,
+                        shape_order=w.shape_order)
+    assert_parity(out[0], P.step(st, 5), what="two particles, weights 2^20 apart")
