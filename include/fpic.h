@@ -119,7 +119,10 @@ int fpic_create(const fpic_config *cfg, const fpic_tuning *tune, void *workspace
                 size_t workspace_bytes, fpic_stream stream, fpic_ctx **out);
 
 /* Copy a state (device, [18][ndir][ncell]) in, set the step counter to
- * step0 (time step0*dt) and deposit the first-stage moments. */
+ * step0 (time step0*dt) and deposit the first-stage moments.  A state read
+ * with fpic_get_state after step n and handed to a context of the same
+ * configuration and launch shape with step0 = n continues bit for bit as
+ * the uninterrupted run does (restart from a checkpoint). */
 int fpic_set_state(fpic_ctx *ctx, const double *state, int64_t step0);
 
 /* Copy the current state out (device, [18][ndir][ncell]). */

@@ -87,7 +87,10 @@ int fpic_particles_create(const fpic_pconfig *cfg, void *workspace, size_t works
  * FPIC_EINVAL if a position or weight is not finite or a direction is not a
  * unit vector (|Omega|^2 within 1e-9 of 1); with exact sums,
  * FPIC_EUNSUPPORTED if 16 npart max(|N| + |Nbar|)/dV lies outside about
- * 2^-816 .. 2^984 (the range of the fixed-point scale). */
+ * 2^-816 .. 2^984 (the range of the fixed-point scale).  With exact sums, a
+ * state read with fpic_particles_get_state after step n and handed back with
+ * the same particles and step0 = n continues bit for bit as the
+ * uninterrupted run does. */
 int fpic_particles_set(fpic_pctx *ctx, const double *pos0, const double *dirs, const double *N,
                        const double *Nbar, const double *state, int64_t step0);
 
