@@ -42,8 +42,19 @@ STEP_BYTES = sum(STAGE_BYTES.values())   # 1744 B per particle-step
 CONTRACT_STAGE_BYTES = {1: 2 * STATE_B, 2: 3 * STATE_B, 3: 3 * STATE_B, 4: 5 * STATE_B}
 CONTRACT_STEP_BYTES = 13 * STATE_B        # 1872 B per particle-step
 ACCOUNTING = ("13-pass stage-synchronous contract: 2, 3, 3, 5 passes of 144 B per particle "
-              "for stages 1-4, plus the grid; own_* fields: the 16-real slopes this "
-              "implementation stores (272, 400, 400, 672 B)")
+              "for stages 1-4, plus the grid; own_* fields: the bytes this implementation "
+              "moves, with 16-real slopes: 1D boxes and batches 144, 272, 400, 544 B (the "
+              "stage-1 slope formed again in stages 2 and 4 instead of stored; 272, 400, "
+              "400, 672 B when it is stored), 3D boxes 272, 400, 400, 672 B")
+# 1D boxes and batches (fpic_tuning.fused != 2): stage 1 stores no slope, and
+# stages 2 and 4 form it again from the state and the stage-1 grid
+RK1_STAGE_BYTES = {1: STATE_B, 2: STATE_B + SLOPE_B, 3: STATE_B + 2 * SLOPE_B,
+                   4: 2 * STATE_B + 2 * SLOPE_B}   # 1360 B per particle-step
+
+
+def own_stage_bytes_1d(tune):
+    """Per-particle bytes of the four 1D stage kernels in this launch form."""
+    return STAGE_BYTES if (tune or {}).get("fused", 0) == 2 else RK1_STAGE_BYTES
 # general placement (1D): every stage also reads the particle's own z
 # position at t = 0, direction and two weights; a sort reads the key inputs
 # (z, Omega_z) once more, and its stage 4 also writes the particle's z,
@@ -235,7 +246,8 @@ def stage_accounting(w, tune):
     kernels; and the source hash its counter records are keyed by."""
     P, nc = w.nparticles, w.ncell_total
     if w.ncell[0] == 1 and w.ncell[1] == 1:
-        own = [STAGE_BYTES[s] * P + 2 * GRID_B * nc for s in (1, 2, 3, 4)]
+        sb = own_stage_bytes_1d(tune)
+        own = [sb[s] * P + 2 * GRID_B * nc for s in (1, 2, 3, 4)]
         contract = [CONTRACT_STAGE_BYTES[s] * P + 2 * GRID_B * nc for s in (1, 2, 3, 4)]
         return ("stage1d_kernel", "reduce1d_kernel"), own, contract, None, kernel_source_hash
     fused = (tune or {}).get("fused", 0) != 2 and w.shape_order == 1 and w.ncell[0] <= 64
@@ -335,7 +347,8 @@ def measure_quadratic(steps=200):
             "launch": tuning, "value": P * steps / wall, "unit": "particle-steps/s",
             "ms_per_step": 1e3 * wall / steps,
             "stage_ms": [ms[0], ms[2], ms[4], ms[6]], "reduce_ms": [ms[1], ms[3], ms[5], ms[7]],
-            "step_frac_of_hbm_peak": STEP_BYTES * P / (wall / steps) / 1e9 / HBM_PEAK_GBS}
+            "step_frac_of_hbm_peak": sum(own_stage_bytes_1d(tuning).values()) * P / (wall / steps) / 1e9
+                                     / HBM_PEAK_GBS}
 
 
 def measure_batch(steps=1000, nsim=64):
@@ -385,7 +398,8 @@ def measure_batch(steps=1000, nsim=64):
     ts = time.perf_counter() - t0
     neg = sum(1 for w in ws if min(w.weights()[0].min(), w.weights()[1].min()) < 0)
     stage_ms = [ms[0], ms[2], ms[4], ms[6]]
-    stage_bytes = [STAGE_BYTES[k] * P + 2 * GRID_B * ncell for k in (1, 2, 3, 4)]
+    sb = own_stage_bytes_1d(tune)
+    stage_bytes = [sb[k] * P + 2 * GRID_B * ncell for k in (1, 2, 3, 4)]
     contract_bytes = [CONTRACT_STAGE_BYTES[k] * P + 2 * GRID_B * ncell for k in (1, 2, 3, 4)]
     dom = max(range(4), key=lambda k: stage_ms[k])
     ach = contract_bytes[dom] / (stage_ms[dom] * 1e-3) / 1e9
@@ -396,8 +410,10 @@ def measure_batch(steps=1000, nsim=64):
             "ratio": ts / tb, "ms_per_step": ms_step,
             "frac_of_1872B_roofline": CONTRACT_STEP_BYTES * P / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "ratio_note": "a 3x gain over the sequential runs would need "
-                          f"{3 * P * steps / ts:.3g} particle-steps/s, above the 1872 B "
-                          f"roofline of {HBM_PEAK_GBS * 1e9 / CONTRACT_STEP_BYTES:.3g}",
+                          f"{3 * P * steps / ts:.3g} particle-steps/s; the 1872 B "
+                          f"roofline is {HBM_PEAK_GBS * 1e9 / CONTRACT_STEP_BYTES:.3g}, and at the "
+                          f"{sum(sb.values())} B per particle-step this launch form moves "
+                          f"{HBM_PEAK_GBS * 1e9 / sum(sb.values()):.3g}",
             "event_timing": ev,
             "stage_ms": stage_ms, "reduce_ms": [ms[1], ms[3], ms[5], ms[7]],
             "roofline": {"bound": "hbm", "kernel": f"stage1d_kernel<{dom + 1}> (batched)",

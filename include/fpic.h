@@ -104,7 +104,13 @@ typedef struct fpic_tuning {
                                 apply to these only).  Results differ by
                                 rounding only.  Boxes with nx > 64 or more
                                 than 1024 directions always take the
-                                separate kernels. */
+                                separate kernels.
+                                1D boxes and batches: 0 or 1 stage 1 stores
+                                no slope, and stages 2 and 4 form the
+                                stage-1 slope again from the state and the
+                                stage-1 grid (128 B per particle less in each
+                                of the three stages); 2 it is stored and read
+                                back.  Bitwise the same results. */
 } fpic_tuning;
 
 typedef struct fpic_ctx fpic_ctx;

@@ -12,7 +12,8 @@
 //   3. builds H and Hbar (eq. potentials, antineutrino conventions of
 //      Sec. II.A) and the slopes -i[H, rho], -i[Hbar, rhobar] (eq. eom),
 //   4. writes the slope (or the finished step) and forms the next-stage
-//      state,
+//      state; with RK1 stage 1 writes no slope, and stages 2 and 4 form k1
+//      again from the state and the stage-1 grid,
 //   5. deposits that state with the next-stage weights (eq. pic_deposition):
 //      its left weight goes to cell m, its right weight to cell m+1, which
 //      lane l+1 picks up with a one-lane shuffle; the last lane's right part
@@ -86,6 +87,56 @@ __device__ __forceinline__ int pmod_dbl(double i, int n)
     return (int)r;
 }
 
+// Neutrino self-interaction part of H at a particle (eq. potentials,
+// interpolated with eq. pic_interpolation): the four staged moment groups
+// n - nbar^*, f_x, f_y, f_z - fbar^* of the tile Gt (stride gts per
+// component) at column kl and fraction phi, combined as n - v.f.
+template <int SH>
+__device__ __forceinline__ void gather_hnn(const double *Gt, int gts, int kl, double phi, double vx,
+                                           double vy, double vz, double Hnn[9])
+{
+    if (SH == 2) {
+        const Quad q = quad_weights(phi);
+#pragma unroll
+        for (int k = 0; k < 9; k++) {
+            const double *g = Gt + k * gts + kl - 1 + q.up;
+            const double A = (q.w0 * g[0] + q.w1 * g[1]) + q.w2 * g[2];
+            const double Bx = (q.w0 * g[9 * gts] + q.w1 * g[9 * gts + 1]) + q.w2 * g[9 * gts + 2];
+            const double By = (q.w0 * g[18 * gts] + q.w1 * g[18 * gts + 1]) + q.w2 * g[18 * gts + 2];
+            const double Bz = (q.w0 * g[27 * gts] + q.w1 * g[27 * gts + 1]) + q.w2 * g[27 * gts + 2];
+            Hnn[k] = A - (vx * Bx + vy * By + vz * Bz);
+        }
+    } else {
+        const double omp = 1.0 - phi;
+#pragma unroll
+        for (int k = 0; k < 9; k++) {
+            const double *g = Gt + k * gts + kl;
+            const double A = omp * g[0] + phi * g[1];
+            const double Bx = omp * g[9 * gts] + phi * g[9 * gts + 1];
+            const double By = omp * g[18 * gts] + phi * g[18 * gts + 1];
+            const double Bz = omp * g[27 * gts] + phi * g[27 * gts + 1];
+            Hnn[k] = A - (vx * Bx + vy * By + vz * Bz);
+        }
+    }
+}
+
+// Slopes of rho and rhobar (eq. eom): H = Hvac + Hmat + Hnn and
+// Hbar = (Hvac - Hmat - Hnn)^*, hv and hvb holding Hvac + Hmat and
+// Hvac - Hmat packed.
+__device__ __forceinline__ void slope_of(const double hv[9], const double hvb[9], const double Hnn[9],
+                                         const double y[18], double kk[18])
+{
+    double H[9], Hb[9];
+#pragma unroll
+    for (int k = 0; k < 9; k++) {
+        H[k] = hv[k] + Hnn[k];
+        const double hb = hvb[k] - Hnn[k];
+        Hb[k] = (k == 4 || k == 6 || k == 8) ? -hb : hb;
+    }
+    commutator(H, y, kk);
+    commutator(Hb, y + 9, kk + 9);
+}
+
 // NT: streaming (nontemporal) cache policy for the data a stage does not
 // read again soon (the last reads of the slopes in stage 4, and k2); the
 // default policy keeps everything cacheable.  Streaming pays when
@@ -94,11 +145,21 @@ __device__ __forceinline__ int pmod_dbl(double i, int n)
 // SH: shape-function order, 1 (linear) or 2 (quadratic).  The staged grid
 // tile holds cells tile*64 - SH .. tile*64 + 64 + SH; the quadratic deposit
 // reaches one cell left of the tile and two right of it (edge partials).
-template <int MODE, int SH, bool NT>
+// RK1: the stage-1 slope k1 is not stored; stages 2 and 4 form it again from
+// the state and the stage-1 grid, which stays in HBM until stage 4 ends (the
+// grid is tiny in 1D, so 128 B per particle are neither written in stage 1
+// nor read in stages 2 and 4).  The same operations on the same operands
+// give the same k1, bit for bit.
+template <int MODE, int SH, bool NT, bool RK1>
 __global__ void __launch_bounds__(MAX_WAVES * TILE)
 stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ sims, int max_dpw)
 {
     constexpr int GTC = gt_cells(SH), GTS = gt_stride(SH), NE = n_edges(SH);
+    // stage-1 grid tile of the recomputing stages: one more cell on each
+    // side, since a particle moves up to two cells between the stage-1
+    // position and the next step's (dt/2 max|v| < dz)
+    constexpr bool G1 = RK1 && (MODE == M_S2 || MODE == M_S4);
+    constexpr int GTC1 = gt_cells(SH + 1), GTS1 = gt_stride(SH + 1);
     extern __shared__ double smem[];
     const WorkItem wi = work[blockIdx.x];
     // private copy: the kernel's stores cannot alias the descriptor
@@ -139,6 +200,8 @@ stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ si
     double *eb = smem + gslot + wave * max_dpw * 9 * NE;      // [dpw][NE][9] of this wave
     double *tphi = smem + gslot + nwaves * max_dpw * 9 * NE;  // [dpg][2]: phi_cur, phi_nxt
     int *tint = (int *)(tphi + 2 * nwaves * max_dpw);         // [dpg][2]: r, delta
+    double *G1t = (double *)(tint + 2 * nwaves * max_dpw);    // [NG][GTS1], G1 only
+    const double t1 = stage_time(n, dt, 0.0);                 // stage-1 time
 
     const int dgrp0 = wi.group * S.dpg;
     // shifts of the workgroup's directions, one thread per direction
@@ -167,6 +230,21 @@ stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ si
                 cell = (cell < 0) ? cell + nc : (cell >= nc ? cell - nc : cell);
             }
             Gt[comp * GTS + k] = gld(Gin + (size_t)comp * nc + cell);
+        }
+    }
+    if (G1) {
+        const double *Gin1 = S.G[0];
+        for (int idx = threadIdx.x; idx < NG * GTC1; idx += blockDim.x) {
+            const int comp = idx / GTC1;
+            const int k = idx - comp * GTC1;
+            int cell = tile0 - SH - 1 + k;
+            if (nc < GTC1) {
+                cell %= nc;
+                cell = (cell < 0) ? cell + nc : cell;
+            } else {
+                cell = (cell < 0) ? cell + nc : (cell >= nc ? cell - nc : cell);
+            }
+            G1t[comp * GTS1 + k] = gld(Gin1 + (size_t)comp * nc + cell);
         }
     }
     __syncthreads();
@@ -218,29 +296,19 @@ stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ si
             } else {
                 // interpolate the staged grid at the current position
                 const int kl = lane - tint[2 * j + 1] + SH;  // LDS column of cell m - delta
-                const double phi = tphi[2 * j + 0], omp = 1.0 - phi;
+                const double phi = tphi[2 * j + 0];
                 double Hnn[9];
-                if (SH == 2) {
-                    const Quad q = quad_weights(phi);
-#pragma unroll
-                    for (int k = 0; k < 9; k++) {
-                        const double *g = Gt + k * GTS + kl - 1 + q.up;
-                        const double A = (q.w0 * g[0] + q.w1 * g[1]) + q.w2 * g[2];
-                        const double Bx = (q.w0 * g[9 * GTS] + q.w1 * g[9 * GTS + 1]) + q.w2 * g[9 * GTS + 2];
-                        const double By = (q.w0 * g[18 * GTS] + q.w1 * g[18 * GTS + 1]) + q.w2 * g[18 * GTS + 2];
-                        const double Bz = (q.w0 * g[27 * GTS] + q.w1 * g[27 * GTS + 1]) + q.w2 * g[27 * GTS + 2];
-                        Hnn[k] = A - (vx * Bx + vy * By + vz * Bz);
-                    }
-                } else
-#pragma unroll
-                for (int k = 0; k < 9; k++) {
-                    const double *g = Gt + k * GTS + kl;
-                    const double A = omp * g[0] + phi * g[1];
-                    const double Bx = omp * g[9 * GTS] + phi * g[9 * GTS + 1];
-                    const double By = omp * g[18 * GTS] + phi * g[18 * GTS + 1];
-                    const double Bz = omp * g[27 * GTS] + phi * g[27 * GTS + 1];
-                    Hnn[k] = A - (vx * Bx + vy * By + vz * Bz);
-                }
+                gather_hnn<SH>(Gt, GTS, kl, phi, vx, vy, vz, Hnn);
+                // k1 of the RK1 stages, from the stage-1 grid at the stage-1
+                // position (the same gather and commutators as stage 1)
+                auto stage1_slope = [&](double k1[18]) {
+                    const Shift s1 = shift_of(vz, t1, dz);
+                    const Shift sn = shift_of(vz, t_nxt, dz);
+                    const int dl = max(-2, min(2, (int)(sn.i - s1.i)));
+                    double H1[9];
+                    gather_hnn<SH>(G1t, GTS1, lane - dl + SH + 1, s1.phi, vx, vy, vz, H1);
+                    slope_of(hv, hvb, H1, Y, k1);
+                };
                 // stage state y, and the base the next state is built on:
                 // Y for stages 1-3, Y + dt/6 (k1 + 2 k2 + 2 k3) for stage 4
                 // (the slopes are consumed before the commutators)
@@ -253,7 +321,10 @@ stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ si
                     // last reads of the three slopes
                     const double h6 = dt / 6.0;
                     double k1[18], k2[18], k3[18];
-                    load_slope<NT>(S.K1, np, p, k1);
+                    if (G1)
+                        stage1_slope(k1);
+                    else
+                        load_slope<NT>(S.K1, np, p, k1);
                     load_slope<NT>(S.K2, np, p, k2);
                     load_slope<NT>(S.K3, np, p, k3);
 #pragma unroll
@@ -265,24 +336,20 @@ stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ si
                 } else {
                     const double a = 0.5 * dt;
                     double kp[18];
-                    load_slope((MODE == M_S2) ? S.K1 : S.K2, np, p, kp);
+                    if (G1)
+                        stage1_slope(kp);
+                    else
+                        load_slope((MODE == M_S2) ? S.K1 : S.K2, np, p, kp);
 #pragma unroll
                     for (int k = 0; k < 18; k++) {
                         y[k] = Y[k] + a * kp[k];
                         base[k] = Y[k];
                     }
                 }
-                // Hamiltonians: H = Hvac + Hmat + Hnn,
-                // Hbar = (Hvac - Hmat - Hnn)^*
-                double H[9], Hb[9], kk[18];
-#pragma unroll
-                for (int k = 0; k < 9; k++) {
-                    H[k] = hv[k] + Hnn[k];
-                    const double hb = hvb[k] - Hnn[k];
-                    Hb[k] = (k == 4 || k == 6 || k == 8) ? -hb : hb;
-                }
-                commutator(H, y, kk);
-                commutator(Hb, y + 9, kk + 9);
+                // Hamiltonians and slopes, through the same helper as the
+                // k1 of the RK1 stages (one code path, one rounding)
+                double kk[18];
+                slope_of(hv, hvb, Hnn, y, kk);
                 double yn[18];
                 if (MODE == M_S4) {
                     const double h6 = dt / 6.0;
@@ -299,7 +366,8 @@ stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ si
                     // with streaming, k2 streams; k1 and k3, read again by
                     // the very next kernel, stay cached (measured on the
                     // 2048-cell, 378-direction box)
-                    store_slope<NT && MODE == M_S2>(Ko, np, p, kk);
+                    if (!(RK1 && MODE == M_S1))
+                        store_slope<NT && MODE == M_S2>(Ko, np, p, kk);
 #pragma unroll
                     for (int k = 0; k < 18; k++)
                         yn[k] = base[k] + an * kk[k];
@@ -1035,34 +1103,46 @@ size_t stage1d_smem_bytes(int waves, int max_dpw, int shape)
     return (gslot + dpg * 9 * ne + dpg * 2) * sizeof(double) + dpg * 2 * sizeof(int);
 }
 
-template <int SH, bool NT>
+template <int SH, bool NT, bool RK1>
 static hipError_t launch_stage1d_sh(int mode, const WorkItem *work, int nwork, const SimDesc *sims,
                                     int waves, int max_dpw, hipStream_t s)
 {
     const dim3 grid(nwork), block(waves * TILE);
-    const size_t smem = stage1d_smem_bytes(waves, max_dpw, SH);
+    size_t smem = stage1d_smem_bytes(waves, max_dpw, SH);
+    if (RK1 && (mode == M_S2 || mode == M_S4))
+        smem += sizeof(double) * NG * gt_stride(SH + 1);
     switch (mode) {
-    case M_S1: stage1d_kernel<M_S1, SH, NT><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
-    case M_S2: stage1d_kernel<M_S2, SH, NT><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
-    case M_S3: stage1d_kernel<M_S3, SH, NT><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
-    case M_S4: stage1d_kernel<M_S4, SH, NT><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
-    case M_DEPOSIT: stage1d_kernel<M_DEPOSIT, SH, false><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
-    case M_MOM_NU: stage1d_kernel<M_MOM_NU, SH, false><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
-    case M_MOM_NUBAR: stage1d_kernel<M_MOM_NUBAR, SH, false><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
+    case M_S1: stage1d_kernel<M_S1, SH, NT, RK1><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
+    case M_S2: stage1d_kernel<M_S2, SH, NT, RK1><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
+    case M_S3: stage1d_kernel<M_S3, SH, NT, false><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
+    case M_S4: stage1d_kernel<M_S4, SH, NT, RK1><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
+    case M_DEPOSIT: stage1d_kernel<M_DEPOSIT, SH, false, false><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
+    case M_MOM_NU: stage1d_kernel<M_MOM_NU, SH, false, false><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
+    case M_MOM_NUBAR: stage1d_kernel<M_MOM_NUBAR, SH, false, false><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
+template <int SH>
+static hipError_t launch_stage1d_shape(int mode, const WorkItem *work, int nwork, const SimDesc *sims,
+                                       int waves, int max_dpw, bool nt, bool rk1, hipStream_t s)
+{
+    if (nt)
+        return rk1 ? launch_stage1d_sh<SH, true, true>(mode, work, nwork, sims, waves, max_dpw, s)
+                   : launch_stage1d_sh<SH, true, false>(mode, work, nwork, sims, waves, max_dpw, s);
+    return rk1 ? launch_stage1d_sh<SH, false, true>(mode, work, nwork, sims, waves, max_dpw, s)
+               : launch_stage1d_sh<SH, false, false>(mode, work, nwork, sims, waves, max_dpw, s);
+}
+
 hipError_t launch_stage1d(int mode, const WorkItem *work, int nwork, const SimDesc *sims,
-                          int waves, int max_dpw, int shape, bool stream_policy, hipStream_t s)
+                          int waves, int max_dpw, int shape, bool stream_policy, bool recompute_k1,
+                          hipStream_t s)
 {
     if (shape == 2)
-        return stream_policy ? launch_stage1d_sh<2, true>(mode, work, nwork, sims, waves, max_dpw, s)
-                             : launch_stage1d_sh<2, false>(mode, work, nwork, sims, waves, max_dpw, s);
+        return launch_stage1d_shape<2>(mode, work, nwork, sims, waves, max_dpw, stream_policy, recompute_k1, s);
     if (shape == 1)
-        return stream_policy ? launch_stage1d_sh<1, true>(mode, work, nwork, sims, waves, max_dpw, s)
-                             : launch_stage1d_sh<1, false>(mode, work, nwork, sims, waves, max_dpw, s);
+        return launch_stage1d_shape<1>(mode, work, nwork, sims, waves, max_dpw, stream_policy, recompute_k1, s);
     return hipErrorInvalidValue;
 }
 

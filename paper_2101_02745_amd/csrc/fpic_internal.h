@@ -73,7 +73,8 @@ struct SimDesc {
     double *K1, *K2, *K3;        // [18][ndir][ncell] stage slopes
     // [36][ncell] deposited moments: stage s reads G[s-1]; the reduction
     // after stage s writes G[s] (G[4] is the next step's G[0]).  A single
-    // box ping-pongs two buffers: {g0, g1, g0, g1, g0}.
+    // box cycles three buffers, {g0, g1, g2, g1, g0}, so that the stage-1
+    // grid is still there when stage 4 forms k1 again.
     double *G[5];
     double *part;                // [ngroup][36][ntile*TILE] per-group partials
     double *edge;                // [ngroup][36][n_edges][ntile] edge partials
@@ -97,9 +98,12 @@ struct RedItem {
 
 // Launchers (fpic_1d.hip).
 // stream_policy: streaming cache policy for the data a stage does not read
-// again soon (large boxes), else the default policy
+// again soon (large boxes), else the default policy.  recompute_k1: stage 1
+// stores no slope and stages 2 and 4 form k1 again from the state and G[0]
+// (needs G[0] intact until stage 4); otherwise k1 is stored and read back
 hipError_t launch_stage1d(int mode, const WorkItem *work, int nwork, const SimDesc *sims,
-                          int waves, int max_dpw, int shape, bool stream_policy, hipStream_t s);
+                          int waves, int max_dpw, int shape, bool stream_policy, bool recompute_k1,
+                          hipStream_t s);
 hipError_t launch_reduce1d(const RedItem *items, int nitems, const SimDesc *sims, int which,
                            double *override_out, int tick, hipStream_t s);
 // adjoint kernels: kind 4 = sources of stage 4 and their deposit; kind 3, 2,
