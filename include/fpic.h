@@ -105,12 +105,16 @@ typedef struct fpic_tuning {
                                 rounding only.  Boxes with nx > 64 or more
                                 than 1024 directions always take the
                                 separate kernels.
-                                1D boxes and batches: 0 or 1 stage 1 stores
-                                no slope, and stages 2 and 4 form the
-                                stage-1 slope again from the state and the
-                                stage-1 grid (128 B per particle less in each
-                                of the three stages); 2 it is stored and read
-                                back.  Bitwise the same results. */
+                                1D boxes and batches: slopes formed again
+                                from the state and the kept stage grids
+                                instead of stored and read back.  1: stage 1
+                                stores no slope, stages 2 and 4 form k1
+                                (bitwise the same results as 2); 0: stage 2
+                                stores none either, stages 3 and 4 form k1
+                                and k2 (the same up to the last bits: some
+                                products are fused differently); 2: every
+                                slope stored.  Per particle-step 1360, 976
+                                and 1744 B. */
 } fpic_tuning;
 
 typedef struct fpic_ctx fpic_ctx;

@@ -145,12 +145,14 @@ __device__ __forceinline__ void slope_of(const double hv[9], const double hvb[9]
 // SH: shape-function order, 1 (linear) or 2 (quadratic).  The staged grid
 // tile holds cells tile*64 - SH .. tile*64 + 64 + SH; the quadratic deposit
 // reaches one cell left of the tile and two right of it (edge partials).
-// RK1: the stage-1 slope k1 is not stored; stages 2 and 4 form it again from
-// the state and the stage-1 grid, which stays in HBM until stage 4 ends (the
-// grid is tiny in 1D, so 128 B per particle are neither written in stage 1
-// nor read in stages 2 and 4).  The same operations on the same operands
-// give the same k1, bit for bit.
-template <int MODE, int SH, bool NT, bool RK1>
+// RK: slopes formed again instead of stored.  RK >= 1: stage 1 stores no k1;
+// stages 2 and 4 form it again from the state and the stage-1 grid, which
+// stays in HBM until stage 4 ends (the grid is tiny in 1D, so 128 B per
+// particle are neither written in stage 1 nor read in stages 2 and 4).
+// RK = 2: stage 2 stores no k2 either; stages 3 and 4 form k1 and then k2
+// from the stage-2 grid.  The same operations on the same operands give the
+// same slopes, bit for bit.
+template <int MODE, int SH, bool NT, int RK>
 __global__ void __launch_bounds__(MAX_WAVES * TILE)
 stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ sims, int max_dpw)
 {
@@ -158,7 +160,8 @@ stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ si
     // stage-1 grid tile of the recomputing stages: one more cell on each
     // side, since a particle moves up to two cells between the stage-1
     // position and the next step's (dt/2 max|v| < dz)
-    constexpr bool G1 = RK1 && (MODE == M_S2 || MODE == M_S4);
+    constexpr bool G1 = (RK >= 1 && (MODE == M_S2 || MODE == M_S4)) || (RK >= 2 && MODE == M_S3);
+    constexpr bool G2 = RK >= 2 && (MODE == M_S3 || MODE == M_S4);
     constexpr int GTC1 = gt_cells(SH + 1), GTS1 = gt_stride(SH + 1);
     extern __shared__ double smem[];
     const WorkItem wi = work[blockIdx.x];
@@ -201,7 +204,9 @@ stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ si
     double *tphi = smem + gslot + nwaves * max_dpw * 9 * NE;  // [dpg][2]: phi_cur, phi_nxt
     int *tint = (int *)(tphi + 2 * nwaves * max_dpw);         // [dpg][2]: r, delta
     double *G1t = (double *)(tint + 2 * nwaves * max_dpw);    // [NG][GTS1], G1 only
+    double *G2t = G1t + (G1 ? NG * GTS1 : 0);                 // [NG][GTS1], G2 only
     const double t1 = stage_time(n, dt, 0.0);                 // stage-1 time
+    const double t2 = stage_time(n, dt, 0.5);                 // stage-2 time
 
     const int dgrp0 = wi.group * S.dpg;
     // shifts of the workgroup's directions, one thread per direction
@@ -232,8 +237,8 @@ stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ si
             Gt[comp * GTS + k] = gld(Gin + (size_t)comp * nc + cell);
         }
     }
-    if (G1) {
-        const double *Gin1 = S.G[0];
+    // earlier stages' grid tiles, one more cell on each side
+    auto stage_tile = [&](const double *Gin, double *Gdst) {
         for (int idx = threadIdx.x; idx < NG * GTC1; idx += blockDim.x) {
             const int comp = idx / GTC1;
             const int k = idx - comp * GTC1;
@@ -244,9 +249,13 @@ stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ si
             } else {
                 cell = (cell < 0) ? cell + nc : (cell >= nc ? cell - nc : cell);
             }
-            G1t[comp * GTS1 + k] = gld(Gin1 + (size_t)comp * nc + cell);
+            Gdst[comp * GTS1 + k] = gld(Gin + (size_t)comp * nc + cell);
         }
-    }
+    };
+    if (G1)
+        stage_tile(S.G[0], G1t);
+    if (G2)
+        stage_tile(S.G[1], G2t);
     __syncthreads();
 
     double hv[9], hvb[9];
@@ -297,9 +306,11 @@ stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ si
                 // interpolate the staged grid at the current position
                 const int kl = lane - tint[2 * j + 1] + SH;  // LDS column of cell m - delta
                 const double phi = tphi[2 * j + 0];
+                // (where k2 is formed again, after it: fewer live registers)
                 double Hnn[9];
-                gather_hnn<SH>(Gt, GTS, kl, phi, vx, vy, vz, Hnn);
-                // k1 of the RK1 stages, from the stage-1 grid at the stage-1
+                if (!G2)
+                    gather_hnn<SH>(Gt, GTS, kl, phi, vx, vy, vz, Hnn);
+                // k1 of the RK stages, from the stage-1 grid at the stage-1
                 // position (the same gather and commutators as stage 1)
                 auto stage1_slope = [&](double k1[18]) {
                     const Shift s1 = shift_of(vz, t1, dz);
@@ -308,6 +319,21 @@ stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ si
                     double H1[9];
                     gather_hnn<SH>(G1t, GTS1, lane - dl + SH + 1, s1.phi, vx, vy, vz, H1);
                     slope_of(hv, hvb, H1, Y, k1);
+                };
+                // k2 of the RK = 2 stages, from k1, the stage-2 grid and the
+                // stage-2 position (the same stage state and gather as stage 2)
+                auto stage2_slope = [&](const double k1[18], double k2[18]) {
+                    const Shift s2 = shift_of(vz, t2, dz);
+                    const Shift sn = shift_of(vz, t_nxt, dz);
+                    const int dl = max(-2, min(2, (int)(sn.i - s2.i)));
+                    const double a = 0.5 * dt;
+                    double y2[18];
+#pragma unroll
+                    for (int k = 0; k < 18; k++)
+                        y2[k] = __builtin_fma(a, k1[k], Y[k]);
+                    double H2[9];
+                    gather_hnn<SH>(G2t, GTS1, lane - dl + SH + 1, s2.phi, vx, vy, vz, H2);
+                    slope_of(hv, hvb, H2, y2, k2);
                 };
                 // stage state y, and the base the next state is built on:
                 // Y for stages 1-3, Y + dt/6 (k1 + 2 k2 + 2 k3) for stage 4
@@ -320,34 +346,62 @@ stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ si
                 } else if (MODE == M_S4) {
                     // last reads of the three slopes
                     const double h6 = dt / 6.0;
-                    double k1[18], k2[18], k3[18];
-                    if (G1)
-                        stage1_slope(k1);
-                    else
-                        load_slope<NT>(S.K1, np, p, k1);
-                    load_slope<NT>(S.K2, np, p, k2);
-                    load_slope<NT>(S.K3, np, p, k3);
+                    if (G2) {
+                        // k1 + 2 k2 as soon as k2 exists (the same sums)
+                        double k12[18], k3[18];
+                        {
+                            double k1[18], k2[18];
+                            stage1_slope(k1);
+                            stage2_slope(k1, k2);
 #pragma unroll
-                    for (int k = 0; k < 18; k++) {
-                        y[k] = Y[k] + dt * k3[k];
-                        const double ks = (k1[k] + 2.0 * k2[k]) + 2.0 * k3[k];
-                        base[k] = Y[k] + h6 * ks;
+                            for (int k = 0; k < 18; k++)
+                                k12[k] = k1[k] + 2.0 * k2[k];
+                        }
+                        load_slope<NT>(S.K3, np, p, k3);
+#pragma unroll
+                        for (int k = 0; k < 18; k++) {
+                            y[k] = Y[k] + dt * k3[k];
+                            const double ks = k12[k] + 2.0 * k3[k];
+                            base[k] = Y[k] + h6 * ks;
+                        }
+                    } else {
+                        double k1[18], k2[18], k3[18];
+                        if (G1)
+                            stage1_slope(k1);
+                        else
+                            load_slope<NT>(S.K1, np, p, k1);
+                        load_slope<NT>(S.K2, np, p, k2);
+                        load_slope<NT>(S.K3, np, p, k3);
+#pragma unroll
+                        for (int k = 0; k < 18; k++) {
+                            y[k] = Y[k] + dt * k3[k];
+                            const double ks = (k1[k] + 2.0 * k2[k]) + 2.0 * k3[k];
+                            base[k] = Y[k] + h6 * ks;
+                        }
                     }
                 } else {
                     const double a = 0.5 * dt;
                     double kp[18];
-                    if (G1)
+                    if (MODE == M_S2 && G1) {
                         stage1_slope(kp);
-                    else
+                    } else if (MODE == M_S3 && G2) {
+                        double k1[18];
+                        stage1_slope(k1);
+                        stage2_slope(k1, kp);
+                    } else {
                         load_slope((MODE == M_S2) ? S.K1 : S.K2, np, p, kp);
+                    }
+                    // one fused multiply-add, as where k2 is formed again
 #pragma unroll
                     for (int k = 0; k < 18; k++) {
-                        y[k] = Y[k] + a * kp[k];
+                        y[k] = __builtin_fma(a, kp[k], Y[k]);
                         base[k] = Y[k];
                     }
                 }
+                if (G2)
+                    gather_hnn<SH>(Gt, GTS, kl, phi, vx, vy, vz, Hnn);
                 // Hamiltonians and slopes, through the same helper as the
-                // k1 of the RK1 stages (one code path, one rounding)
+                // k1 and k2 of the RK stages (one code path, one rounding)
                 double kk[18];
                 slope_of(hv, hvb, Hnn, y, kk);
                 double yn[18];
@@ -366,7 +420,7 @@ stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ si
                     // with streaming, k2 streams; k1 and k3, read again by
                     // the very next kernel, stay cached (measured on the
                     // 2048-cell, 378-direction box)
-                    if (!(RK1 && MODE == M_S1))
+                    if (!(RK >= 1 && MODE == M_S1) && !(RK >= 2 && MODE == M_S2))
                         store_slope<NT && MODE == M_S2>(Ko, np, p, kk);
 #pragma unroll
                     for (int k = 0; k < 18; k++)
@@ -1103,46 +1157,53 @@ size_t stage1d_smem_bytes(int waves, int max_dpw, int shape)
     return (gslot + dpg * 9 * ne + dpg * 2) * sizeof(double) + dpg * 2 * sizeof(int);
 }
 
-template <int SH, bool NT, bool RK1>
+template <int SH, bool NT, int RK>
 static hipError_t launch_stage1d_sh(int mode, const WorkItem *work, int nwork, const SimDesc *sims,
                                     int waves, int max_dpw, hipStream_t s)
 {
     const dim3 grid(nwork), block(waves * TILE);
     size_t smem = stage1d_smem_bytes(waves, max_dpw, SH);
-    if (RK1 && (mode == M_S2 || mode == M_S4))
-        smem += sizeof(double) * NG * gt_stride(SH + 1);
+    // staged tiles of earlier stages' grids (k1: stages 2 and 4, and 3 when
+    // k2 is formed too; k2: stages 3 and 4)
+    const int ntiles = ((RK >= 1 && (mode == M_S2 || mode == M_S4)) || (RK >= 2 && mode == M_S3) ? 1 : 0) +
+                       (RK >= 2 && (mode == M_S3 || mode == M_S4) ? 1 : 0);
+    smem += sizeof(double) * NG * gt_stride(SH + 1) * ntiles;
     switch (mode) {
-    case M_S1: stage1d_kernel<M_S1, SH, NT, RK1><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
-    case M_S2: stage1d_kernel<M_S2, SH, NT, RK1><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
-    case M_S3: stage1d_kernel<M_S3, SH, NT, false><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
-    case M_S4: stage1d_kernel<M_S4, SH, NT, RK1><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
-    case M_DEPOSIT: stage1d_kernel<M_DEPOSIT, SH, false, false><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
-    case M_MOM_NU: stage1d_kernel<M_MOM_NU, SH, false, false><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
-    case M_MOM_NUBAR: stage1d_kernel<M_MOM_NUBAR, SH, false, false><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
+    case M_S1: stage1d_kernel<M_S1, SH, NT, RK><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
+    case M_S2: stage1d_kernel<M_S2, SH, NT, RK><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
+    case M_S3: stage1d_kernel<M_S3, SH, NT, RK><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
+    case M_S4: stage1d_kernel<M_S4, SH, NT, RK><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
+    case M_DEPOSIT: stage1d_kernel<M_DEPOSIT, SH, false, 0><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
+    case M_MOM_NU: stage1d_kernel<M_MOM_NU, SH, false, 0><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
+    case M_MOM_NUBAR: stage1d_kernel<M_MOM_NUBAR, SH, false, 0><<<grid, block, smem, s>>>(work, sims, max_dpw); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-template <int SH>
-static hipError_t launch_stage1d_shape(int mode, const WorkItem *work, int nwork, const SimDesc *sims,
-                                       int waves, int max_dpw, bool nt, bool rk1, hipStream_t s)
+template <int SH, bool NT>
+static hipError_t launch_stage1d_nt(int mode, const WorkItem *work, int nwork, const SimDesc *sims,
+                                    int waves, int max_dpw, int rk, hipStream_t s)
 {
-    if (nt)
-        return rk1 ? launch_stage1d_sh<SH, true, true>(mode, work, nwork, sims, waves, max_dpw, s)
-                   : launch_stage1d_sh<SH, true, false>(mode, work, nwork, sims, waves, max_dpw, s);
-    return rk1 ? launch_stage1d_sh<SH, false, true>(mode, work, nwork, sims, waves, max_dpw, s)
-               : launch_stage1d_sh<SH, false, false>(mode, work, nwork, sims, waves, max_dpw, s);
+    if (rk == 2)
+        return launch_stage1d_sh<SH, NT, 2>(mode, work, nwork, sims, waves, max_dpw, s);
+    if (rk == 1)
+        return launch_stage1d_sh<SH, NT, 1>(mode, work, nwork, sims, waves, max_dpw, s);
+    return launch_stage1d_sh<SH, NT, 0>(mode, work, nwork, sims, waves, max_dpw, s);
 }
 
 hipError_t launch_stage1d(int mode, const WorkItem *work, int nwork, const SimDesc *sims,
-                          int waves, int max_dpw, int shape, bool stream_policy, bool recompute_k1,
+                          int waves, int max_dpw, int shape, bool stream_policy, int reform,
                           hipStream_t s)
 {
+    if (reform < 0 || reform > 2)
+        return hipErrorInvalidValue;
     if (shape == 2)
-        return launch_stage1d_shape<2>(mode, work, nwork, sims, waves, max_dpw, stream_policy, recompute_k1, s);
+        return stream_policy ? launch_stage1d_nt<2, true>(mode, work, nwork, sims, waves, max_dpw, reform, s)
+                             : launch_stage1d_nt<2, false>(mode, work, nwork, sims, waves, max_dpw, reform, s);
     if (shape == 1)
-        return launch_stage1d_shape<1>(mode, work, nwork, sims, waves, max_dpw, stream_policy, recompute_k1, s);
+        return stream_policy ? launch_stage1d_nt<1, true>(mode, work, nwork, sims, waves, max_dpw, reform, s)
+                             : launch_stage1d_nt<1, false>(mode, work, nwork, sims, waves, max_dpw, reform, s);
     return hipErrorInvalidValue;
 }
 

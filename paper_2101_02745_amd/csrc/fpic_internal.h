@@ -73,8 +73,8 @@ struct SimDesc {
     double *K1, *K2, *K3;        // [18][ndir][ncell] stage slopes
     // [36][ncell] deposited moments: stage s reads G[s-1]; the reduction
     // after stage s writes G[s] (G[4] is the next step's G[0]).  A single
-    // box cycles three buffers, {g0, g1, g2, g1, g0}, so that the stage-1
-    // grid is still there when stage 4 forms k1 again.
+    // box cycles four buffers, {g0, g1, g2, g3, g0}, so that the stage-1 and
+    // stage-2 grids are still there when stage 4 forms k1 and k2 again.
     double *G[5];
     double *part;                // [ngroup][36][ntile*TILE] per-group partials
     double *edge;                // [ngroup][36][n_edges][ntile] edge partials
@@ -98,11 +98,13 @@ struct RedItem {
 
 // Launchers (fpic_1d.hip).
 // stream_policy: streaming cache policy for the data a stage does not read
-// again soon (large boxes), else the default policy.  recompute_k1: stage 1
-// stores no slope and stages 2 and 4 form k1 again from the state and G[0]
-// (needs G[0] intact until stage 4); otherwise k1 is stored and read back
+// again soon (large boxes), else the default policy.  reform: 0 every slope
+// stored and read back; 1 stage 1 stores no slope and stages 2 and 4 form k1
+// again from the state and G[0]; 2 stage 2 stores none either and stages 3
+// and 4 form k1 and k2 again (G[1] as well); G[0] and G[1] must stay intact
+// until stage 4
 hipError_t launch_stage1d(int mode, const WorkItem *work, int nwork, const SimDesc *sims,
-                          int waves, int max_dpw, int shape, bool stream_policy, bool recompute_k1,
+                          int waves, int max_dpw, int shape, bool stream_policy, int reform,
                           hipStream_t s);
 hipError_t launch_reduce1d(const RedItem *items, int nitems, const SimDesc *sims, int which,
                            double *override_out, int tick, hipStream_t s);

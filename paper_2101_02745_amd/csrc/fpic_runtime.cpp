@@ -61,14 +61,14 @@ constexpr int kRedBlocks = 256;  // blocks of the diagnostic reductions
 struct SimPlan {
     int ncell = 0, ndir = 0, ntile = 0, ngroup = 0, dpw = 0;
     int64_t np = 0;
-    size_t o_tab = 0, o_Y = 0, o_K1 = 0, o_K2 = 0, o_K3 = 0, o_G0 = 0, o_G1 = 0, o_G2 = 0;
+    size_t o_tab = 0, o_Y = 0, o_K1 = 0, o_K2 = 0, o_K3 = 0, o_G0 = 0, o_G1 = 0, o_G2 = 0, o_G3 = 0;
     size_t o_part = 0, o_edge = 0, o_step = 0;
 };
 
 struct Plan {
     int nsim = 0, waves = 0, max_dpw = 0, spg = 0, shape = 1;
     bool nt = false;  // streaming cache policy in the stage kernels
-    bool rk1 = true;  // stages 2 and 4 form k1 again instead of reading it
+    int rk = 2;       // slopes formed again: 2 k1 and k2, 1 k1, 0 none
     std::vector<SimPlan> sims;
     size_t o_desc = 0, o_work = 0, o_red = 0, o_scratch = 0, total = 0;
     int nwork = 0, nred = 0;
@@ -174,7 +174,7 @@ int make_plan(int nsim, const fpic_config *cfgs, const fpic_tuning *tune, Plan &
     const int fused = tune ? tune->fused : 0;
     if (fused < 0 || fused > 2)
         return fail(FPIC_EINVAL, "fused must be 0, 1 or 2");
-    P.rk1 = fused != 2;
+    P.rk = 2 - fused;
     int64_t wavedirs = 0;
     for (int i = 0; i < nsim; ++i)
         wavedirs += (int64_t)((cfgs[i].ncell[2] + TILE - 1) / TILE) * cfgs[i].ndir;
@@ -208,6 +208,7 @@ int make_plan(int nsim, const fpic_config *cfgs, const fpic_tuning *tune, Plan &
         s.o_G0 = cv.take(sizeof(double) * NG * s.ncell);
         s.o_G1 = cv.take(sizeof(double) * NG * s.ncell);
         s.o_G2 = cv.take(sizeof(double) * NG * s.ncell);
+        s.o_G3 = cv.take(sizeof(double) * NG * s.ncell);
         s.o_part = cv.take(sizeof(double) * (size_t)s.ngroup * NG * s.ntile * TILE);
         s.o_edge = cv.take(sizeof(double) * (size_t)s.ngroup * NG * n_edges(P.shape) * s.ntile);
         s.o_step = cv.take(sizeof(int64_t));
@@ -266,7 +267,7 @@ int capture_steps(fpic_batch *b, int nsteps, hipGraphExec_t *exec)
     hipError_t err = hipSuccess;
     for (int s = 0; s < nsteps && err == hipSuccess; ++s)
         for (int st = M_S1; st <= M_S4 && err == hipSuccess; ++st) {
-            err = launch_stage1d(st, b->dwork, P.nwork, b->ddesc, P.waves, P.max_dpw, P.shape, P.nt, P.rk1, b->cap);
+            err = launch_stage1d(st, b->dwork, P.nwork, b->ddesc, P.waves, P.max_dpw, P.shape, P.nt, P.rk, b->cap);
             if (err == hipSuccess)
                 err = launch_reduce1d(b->dred, P.nred, b->ddesc, st, nullptr,
                                       st == M_S4 ? 1 : 0, b->cap);
@@ -386,11 +387,12 @@ void build_tables(const Plan &P, const fpic_config *cfgs, char *ws, HostTables &
         double *g0 = reinterpret_cast<double *>(ws + s.o_G0);
         double *g1 = reinterpret_cast<double *>(ws + s.o_G1);
         double *g2 = reinterpret_cast<double *>(ws + s.o_G2);
-        // the stage-1 grid g0 stays until stage 4 has read it
+        double *g3 = reinterpret_cast<double *>(ws + s.o_G3);
+        // the stage-1 and stage-2 grids g0, g1 stay until stage 4 has read them
         D.G[0] = g0;
         D.G[1] = g1;
         D.G[2] = g2;
-        D.G[3] = g1;
+        D.G[3] = g3;
         D.G[4] = g0;
         D.part = reinterpret_cast<double *>(ws + s.o_part);
         D.edge = reinterpret_cast<double *>(ws + s.o_edge);
@@ -531,7 +533,7 @@ int batch_set_state(fpic_batch *b, int sim, const double *state, int64_t step0)
     int off, n, roff, rn;
     sim_work(b, sim, &off, &n, &roff, &rn);
     HIPCHECK(launch_stage1d(M_DEPOSIT, b->dwork + off, n, b->ddesc, b->plan.waves, b->plan.max_dpw, b->plan.shape,
-                            b->plan.nt, false, b->stream));
+                            b->plan.nt, 0, b->stream));
     HIPCHECK(launch_reduce1d(b->dred + roff, rn, b->ddesc, 0, nullptr, 0, b->stream));
     b->state_set[sim] = true;
     return FPIC_OK;
@@ -720,9 +722,9 @@ int fpic_moments(fpic_ctx *c, double *out)
     int off, n, roff, rn;
     sim_work(b, 0, &off, &n, &roff, &rn);
     const int nc = b->plan.sims[0].ncell;
-    HIPCHECK(launch_stage1d(M_MOM_NU, b->dwork + off, n, b->ddesc, b->plan.waves, b->plan.max_dpw, b->plan.shape, b->plan.nt, false, b->stream));
+    HIPCHECK(launch_stage1d(M_MOM_NU, b->dwork + off, n, b->ddesc, b->plan.waves, b->plan.max_dpw, b->plan.shape, b->plan.nt, 0, b->stream));
     HIPCHECK(launch_reduce1d(b->dred + roff, rn, b->ddesc, RED_OUT, out, 0, b->stream));
-    HIPCHECK(launch_stage1d(M_MOM_NUBAR, b->dwork + off, n, b->ddesc, b->plan.waves, b->plan.max_dpw, b->plan.shape, b->plan.nt, false, b->stream));
+    HIPCHECK(launch_stage1d(M_MOM_NUBAR, b->dwork + off, n, b->ddesc, b->plan.waves, b->plan.max_dpw, b->plan.shape, b->plan.nt, 0, b->stream));
     HIPCHECK(launch_reduce1d(b->dred + roff, rn, b->ddesc, RED_OUT, out + (size_t)NG * nc, 0, b->stream));
     return FPIC_OK;
 }
@@ -854,7 +856,7 @@ int fpic_batch_profile(fpic_batch *b, int32_t nsteps, double *ms)
     for (int n = 0; n < nsteps && !rc; ++n) {
         hipError_t err = hipEventRecord(ev[0], b->stream);
         for (int st = M_S1; st <= M_S4 && err == hipSuccess; ++st) {
-            err = launch_stage1d(st, b->dwork, P.nwork, b->ddesc, P.waves, P.max_dpw, P.shape, P.nt, P.rk1, b->stream);
+            err = launch_stage1d(st, b->dwork, P.nwork, b->ddesc, P.waves, P.max_dpw, P.shape, P.nt, P.rk, b->stream);
             if (err == hipSuccess)
                 err = hipEventRecord(ev[2 * st - 1], b->stream);
             if (err == hipSuccess)
@@ -959,7 +961,7 @@ int adj_graph(fpic_batch *b, bool reverse, int len, hipGraphExec_t *out)
                 for (int st = M_S1; st <= M_S4; ++st) {
                     // the reverse sweep reads every stored slope, k1 included
                     hipError_t e = launch_stage1d(st, b->dwork, P.nwork, F + j, P.waves, P.max_dpw, P.shape, P.nt,
-                                                  false, b->cap);
+                                                  0, b->cap);
                     if (e == hipSuccess)
                         e = launch_reduce1d(b->dred, P.nred, F + j, st, nullptr, st == M_S4 ? 1 : 0, b->cap);
                     if (e != hipSuccess)
@@ -1128,7 +1130,7 @@ int fpic_adjoint_backward(fpic_ctx *c, const double *dLdy_end, double *dLdy0, do
         // states, slopes and moment grids
         HIPCHECK(hipMemcpyAsync(segY, ckpt + st * seg, sizeof(double) * st, hipMemcpyDeviceToDevice, s));
         HIPCHECK(launch_set_step(F, 0, 1, n0, s));
-        HIPCHECK(launch_stage1d(M_DEPOSIT, b->dwork + off, n, F, P.waves, P.max_dpw, P.shape, P.nt, false, s));
+        HIPCHECK(launch_stage1d(M_DEPOSIT, b->dwork + off, n, F, P.waves, P.max_dpw, P.shape, P.nt, 0, s));
         HIPCHECK(launch_reduce1d(b->dred + roff, rn, F, 0, nullptr, 0, s));
         hipGraphExec_t g = nullptr;
         int rc = adj_graph(b, false, len, &g);
@@ -1198,7 +1200,7 @@ static int time_candidate(int nsim, const fpic_config *cfgs, const fpic_tuning &
         }
         int off, n, roff, rn;
         sim_work(b, i, &off, &n, &roff, &rn);
-        (void)launch_stage1d(M_DEPOSIT, b->dwork + off, n, b->ddesc, P.waves, P.max_dpw, P.shape, P.nt, false, s);
+        (void)launch_stage1d(M_DEPOSIT, b->dwork + off, n, b->ddesc, P.waves, P.max_dpw, P.shape, P.nt, 0, s);
         (void)launch_reduce1d(b->dred + roff, rn, b->ddesc, 0, nullptr, 0, s);
         b->state_set[i] = true;
     }
@@ -1288,10 +1290,10 @@ int fpic_autotune(int32_t nsim, const fpic_config *cfgs, void *workspace, size_t
             bt = t;
         }
     }
-    // and k1 stored and read back instead of formed again
-    {
+    // and fewer slopes formed again (1: k1 only; 2: none, all stored)
+    for (int fused : {1, 2}) {
         fpic_tuning t = bt;
-        t.fused = 2;
+        t.fused = fused;
         double per;
         int rc = precise(t, &per);
         if (rc)
@@ -1396,12 +1398,12 @@ int fpic_step_noalloc(const fpic_config *cfg, const fpic_tuning *tune, double *s
                             hipMemcpyHostToDevice, s));
     // as fpic_set_state: step counter, then the first-stage moments
     HIPCHECK(launch_set_step(ddesc, 0, 1, step0, s));
-    HIPCHECK(launch_stage1d(M_DEPOSIT, dwork, P.nwork, ddesc, P.waves, P.max_dpw, P.shape, P.nt, false, s));
+    HIPCHECK(launch_stage1d(M_DEPOSIT, dwork, P.nwork, ddesc, P.waves, P.max_dpw, P.shape, P.nt, 0, s));
     HIPCHECK(launch_reduce1d(dred, P.nred, ddesc, 0, nullptr, 0, s));
     // as fpic_step, one launch per kernel instead of a graph
     for (int64_t n = 0; n < nsteps; ++n)
         for (int st = M_S1; st <= M_S4; ++st) {
-            HIPCHECK(launch_stage1d(st, dwork, P.nwork, ddesc, P.waves, P.max_dpw, P.shape, P.nt, P.rk1, s));
+            HIPCHECK(launch_stage1d(st, dwork, P.nwork, ddesc, P.waves, P.max_dpw, P.shape, P.nt, P.rk, s));
             HIPCHECK(launch_reduce1d(dred, P.nred, ddesc, st, nullptr, st == M_S4 ? 1 : 0, s));
         }
     // the host tables above must outlive their copies

@@ -1,11 +1,15 @@
-"""The stage-1 slope formed again in stages 2 and 4 (fpic_tuning.fused 0,
-the default for 1D boxes and batches) against the same slope stored in stage
-1 and read back (fused 2): the same operations on the same operands, so the
-two runs must agree bit for bit (classical RK4, Sec. II.C).  Cases: boxes
-smaller than the staged tile (wrapped cells), ragged last tiles with stage-4
-shifts of up to two cells, both shape orders at the full 2048 x 378 size,
-and an uneven batch.  Agreement with the CPU reference in the default form
-is what the parity tests check."""
+"""Slopes formed again instead of stored, against the stored form
+(fpic_tuning.fused 2), classical RK4 (Sec. II.C).  fused 1 forms the stage-1
+slope again in stages 2 and 4 with the same operations on the same operands
+as stage 1: it must agree with the stored form bit for bit.  fused 0 (the
+default for 1D boxes and batches) also forms the stage-2 slope again in
+stages 3 and 4; the compiler contracts some products of that second
+evaluation into fused multiply-adds differently, so it agrees with the
+stored form to the last bits (checked here at 1e-13 of the state's scale
+over six steps) and with the CPU reference as closely as the stored form
+does (the parity tests run it).  Cases: boxes smaller than the staged tile
+(wrapped cells), ragged last tiles with stage-4 shifts of up to two cells,
+both shape orders at the full 2048 x 378 size, and an uneven batch."""
 import dataclasses
 
 import numpy as np
@@ -42,6 +46,17 @@ def assert_bitwise(a, b, what):
     assert same.all(), f"{what}: {np.count_nonzero(~same)} of {a.size} entries differ"
 
 
+def assert_form(a, b, fused, what):
+    """fused 1 bitwise; fused 0 to the rounding of the state's scale."""
+    if fused == 1:
+        assert_bitwise(a, b, what)
+        return
+    assert a.shape == b.shape
+    assert np.isfinite(a).all(), what
+    err = np.abs(a - b).max() / np.abs(b).max()
+    assert err <= 1e-13, f"{what}: {err:.3g} of the state's scale"
+
+
 BOXES = [
     # (name, ncell, ndir, dt in units of the cell width, shape order)
     ("32 cells, smaller than a staged tile", 32, 26, None, 1),
@@ -60,17 +75,19 @@ def test_recompute_matches_stored_small(torch_dev, name, ncell, ndir, dtc, shape
         w = dataclasses.replace(w, dt=dtc * w.dx[2])
     w = dataclasses.replace(w, shape_order=shape)
     for waves, dpw in ((4, 3), (8, 1), (1, 8)):
-        a = run_box(w, 0, 6, step0=5, waves=waves, dpw=dpw)
         b = run_box(w, 2, 6, step0=5, waves=waves, dpw=dpw)
-        assert_bitwise(a, b, f"{name} in {waves} x {dpw}")
+        for fused in (0, 1):
+            a = run_box(w, fused, 6, step0=5, waves=waves, dpw=dpw)
+            assert_form(a, b, fused, f"{name} in {waves} x {dpw}, fused {fused}")
 
 
 @pytest.mark.parametrize("shape", [1, 2])
 def test_recompute_matches_stored_full_size(torch_dev, shape):
     w = dataclasses.replace(I.workload("1d_2048x378"), shape_order=shape)
-    a = run_box(w, 0, 3, waves=4, dpw=12)
-    b = run_box(w, 2, 3, waves=4, dpw=12)
-    assert_bitwise(a, b, f"2048 x 378, shape {shape}")
+    b = run_box(w, 2, 3, waves=8, dpw=6)
+    for fused in (0, 1):
+        a = run_box(w, fused, 3, waves=8, dpw=6)
+        assert_form(a, b, fused, f"2048 x 378, shape {shape}, fused {fused}")
 
 
 def test_recompute_matches_stored_batch(torch_dev):
@@ -80,7 +97,7 @@ def test_recompute_matches_stored_batch(torch_dev):
     ws = [I.scaled(w, ncell=(1, 1, 70 + 61 * i)) for i, w in enumerate(ws)]
     cfgs = [HostConfig.from_workload(w) for w in ws]
     outs = []
-    for fused in (0, 2):
+    for fused in (0, 1, 2):
         t = {"waves": 8, "dirs_per_wave": 8, "steps_per_graph": 4, "cache_policy": 0, "fused": fused}
         b = Batch(cfgs, tuning=t)
         for i, w in enumerate(ws):
@@ -89,4 +106,5 @@ def test_recompute_matches_stored_batch(torch_dev):
         outs.append([b.get_state(i).cpu().numpy() for i in range(len(ws))])
         b.close()
     for i in range(len(ws)):
-        assert_bitwise(outs[0][i], outs[1][i], f"batch box {i}")
+        for f in (0, 1):
+            assert_form(outs[f][i], outs[2][i], f, f"batch box {i}, fused {f}")
