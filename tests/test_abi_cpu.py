@@ -113,6 +113,18 @@ def test_bad_tuning_rejected(lib):
     for policy in (0, 1, 2):
         rc, _ = ws_bytes(lib, hc, {"cache_policy": policy})
         assert rc == _lib.FPIC_OK
+    # 1D slope forms: 0 k1 and k2 formed again, 1 k1 only, 2 every slope
+    # stored; the workspace holds every form's buffers, so its size is one
+    sizes = set()
+    for fused in (0, 1, 2):
+        rc, n = ws_bytes(lib, hc, {"fused": fused})
+        assert rc == _lib.FPIC_OK
+        sizes.add(n)
+    assert len(sizes) == 1
+    for fused in (-1, 3):
+        rc, _ = ws_bytes(lib, hc, {"fused": fused})
+        assert rc == _lib.FPIC_EINVAL
+        assert b"fused" in lib.fpic_last_error()
 
 
 def test_batch_rejects_3d(lib):
