@@ -108,13 +108,11 @@ typedef struct fpic_tuning {
                                 1D boxes and batches: slopes formed again
                                 from the state and the kept stage grids
                                 instead of stored and read back.  1: stage 1
-                                stores no slope, stages 2 and 4 form k1
-                                (bitwise the same results as 2); 0: stage 2
-                                stores none either, stages 3 and 4 form k1
-                                and k2 (the same up to the last bits: some
-                                products are fused differently); 2: every
-                                slope stored.  Per particle-step 1360, 976
-                                and 1744 B. */
+                                stores no slope, stages 2 and 4 form k1;
+                                0: stage 2 stores none either, stages 3 and
+                                4 form k1 and k2; 2: every slope stored.
+                                Bitwise the same results.  Per particle-step
+                                1360, 976 and 1744 B. */
 } fpic_tuning;
 
 typedef struct fpic_ctx fpic_ctx;

@@ -87,6 +87,11 @@ __device__ __forceinline__ int pmod_dbl(double i, int n)
     return (int)r;
 }
 
+// The slope path of the 1D stages (gather, Hamiltonians, commutators) is
+// written with explicit fused multiply-adds and no other contraction, so a
+// slope formed again in a later stage rounds exactly as where it was first
+// formed, whatever the surrounding code lets the compiler fuse.
+
 // Neutrino self-interaction part of H at a particle (eq. potentials,
 // interpolated with eq. pic_interpolation): the four staged moment groups
 // n - nbar^*, f_x, f_y, f_z - fbar^* of the tile Gt (stride gts per
@@ -95,29 +100,73 @@ template <int SH>
 __device__ __forceinline__ void gather_hnn(const double *Gt, int gts, int kl, double phi, double vx,
                                            double vy, double vz, double Hnn[9])
 {
+#pragma clang fp contract(off)
     if (SH == 2) {
         const Quad q = quad_weights(phi);
 #pragma unroll
         for (int k = 0; k < 9; k++) {
             const double *g = Gt + k * gts + kl - 1 + q.up;
-            const double A = (q.w0 * g[0] + q.w1 * g[1]) + q.w2 * g[2];
-            const double Bx = (q.w0 * g[9 * gts] + q.w1 * g[9 * gts + 1]) + q.w2 * g[9 * gts + 2];
-            const double By = (q.w0 * g[18 * gts] + q.w1 * g[18 * gts + 1]) + q.w2 * g[18 * gts + 2];
-            const double Bz = (q.w0 * g[27 * gts] + q.w1 * g[27 * gts + 1]) + q.w2 * g[27 * gts + 2];
-            Hnn[k] = A - (vx * Bx + vy * By + vz * Bz);
+            double B[4];
+#pragma unroll
+            for (int c = 0; c < 4; c++) {
+                const double *h = g + 9 * c * gts;
+                B[c] = __builtin_fma(q.w2, h[2], __builtin_fma(q.w1, h[1], q.w0 * h[0]));
+            }
+            Hnn[k] = __builtin_fma(-vz, B[3], __builtin_fma(-vy, B[2], __builtin_fma(-vx, B[1], B[0])));
         }
     } else {
         const double omp = 1.0 - phi;
 #pragma unroll
         for (int k = 0; k < 9; k++) {
             const double *g = Gt + k * gts + kl;
-            const double A = omp * g[0] + phi * g[1];
-            const double Bx = omp * g[9 * gts] + phi * g[9 * gts + 1];
-            const double By = omp * g[18 * gts] + phi * g[18 * gts + 1];
-            const double Bz = omp * g[27 * gts] + phi * g[27 * gts + 1];
-            Hnn[k] = A - (vx * Bx + vy * By + vz * Bz);
+            double B[4];
+#pragma unroll
+            for (int c = 0; c < 4; c++) {
+                const double *h = g + 9 * c * gts;
+                B[c] = __builtin_fma(phi, h[1], omp * h[0]);
+            }
+            Hnn[k] = __builtin_fma(-vz, B[3], __builtin_fma(-vy, B[2], __builtin_fma(-vx, B[1], B[0])));
         }
     }
+}
+
+// -i [H, rho] for Hermitian H and rho packed as 9 reals (diagonal, then
+// Re/Im of the (0,1), (0,2), (1,2) entries), the same packing and slope as
+// commutator() of the shared helpers, each sum of products written as one
+// chain of fused multiply-adds.
+__device__ __forceinline__ void commutator_fma(const double h[9], const double r[9], double k[9])
+{
+#pragma clang fp contract(off)
+    const double h0 = h[0], h1 = h[1], h2 = h[2];
+    const double ar = h[3], ai = h[4], br = h[5], bi = h[6], cr = h[7], ci = h[8];
+    const double p0 = r[0], p1 = r[1], p2 = r[2];
+    const double xr = r[3], xi = r[4], yr = r[5], yi = r[6], zr = r[7], zi = r[8];
+    const double k1 = 2.0 * (__builtin_fma(ar, xi, -(ai * xr)) + __builtin_fma(ci, zr, -(cr * zi)));
+    const double k2 = 2.0 * (__builtin_fma(br, yi, -(bi * yr)) + __builtin_fma(cr, zi, -(ci * zr)));
+    k[1] = k1;
+    k[2] = k2;
+    k[0] = -(k1 + k2);
+    // C01 = h0 x + a p1 + b z^*,  C10 = a^* p0 + h1 x^* + c y^*
+    const double c01r = __builtin_fma(h0, xr, __builtin_fma(ar, p1, __builtin_fma(br, zr, bi * zi)));
+    const double c01i = __builtin_fma(h0, xi, __builtin_fma(ai, p1, __builtin_fma(bi, zr, -(br * zi))));
+    const double c10r = __builtin_fma(ar, p0, __builtin_fma(h1, xr, __builtin_fma(cr, yr, ci * yi)));
+    const double c10i = __builtin_fma(-ai, p0, __builtin_fma(-h1, xi, __builtin_fma(ci, yr, -(cr * yi))));
+    k[3] = c01i + c10i;
+    k[4] = c10r - c01r;
+    // C02 = h0 y + a z + b p2,  C20 = b^* p0 + c^* x^* + h2 y^*
+    const double c02r = __builtin_fma(h0, yr, __builtin_fma(ar, zr, __builtin_fma(-ai, zi, br * p2)));
+    const double c02i = __builtin_fma(h0, yi, __builtin_fma(ar, zi, __builtin_fma(ai, zr, bi * p2)));
+    const double c20r = __builtin_fma(br, p0, __builtin_fma(cr, xr, __builtin_fma(-ci, xi, h2 * yr)));
+    const double c20i = __builtin_fma(-bi, p0, __builtin_fma(-cr, xi, __builtin_fma(-ci, xr, -(h2 * yi))));
+    k[5] = c02i + c20i;
+    k[6] = c20r - c02r;
+    // C12 = a^* y + h1 z + c p2,  C21 = b^* x + c^* p1 + h2 z^*
+    const double c12r = __builtin_fma(ar, yr, __builtin_fma(ai, yi, __builtin_fma(h1, zr, cr * p2)));
+    const double c12i = __builtin_fma(ar, yi, __builtin_fma(-ai, yr, __builtin_fma(h1, zi, ci * p2)));
+    const double c21r = __builtin_fma(br, xr, __builtin_fma(bi, xi, __builtin_fma(cr, p1, h2 * zr)));
+    const double c21i = __builtin_fma(br, xi, __builtin_fma(-bi, xr, __builtin_fma(-ci, p1, -(h2 * zi))));
+    k[7] = c12i + c21i;
+    k[8] = c21r - c12r;
 }
 
 // Slopes of rho and rhobar (eq. eom): H = Hvac + Hmat + Hnn and
@@ -126,6 +175,7 @@ __device__ __forceinline__ void gather_hnn(const double *Gt, int gts, int kl, do
 __device__ __forceinline__ void slope_of(const double hv[9], const double hvb[9], const double Hnn[9],
                                          const double y[18], double kk[18])
 {
+#pragma clang fp contract(off)
     double H[9], Hb[9];
 #pragma unroll
     for (int k = 0; k < 9; k++) {
@@ -133,8 +183,8 @@ __device__ __forceinline__ void slope_of(const double hv[9], const double hvb[9]
         const double hb = hvb[k] - Hnn[k];
         Hb[k] = (k == 4 || k == 6 || k == 8) ? -hb : hb;
     }
-    commutator(H, y, kk);
-    commutator(Hb, y + 9, kk + 9);
+    commutator_fma(H, y, kk);
+    commutator_fma(Hb, y + 9, kk + 9);
 }
 
 // NT: streaming (nontemporal) cache policy for the data a stage does not
@@ -360,9 +410,9 @@ stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ si
                         load_slope<NT>(S.K3, np, p, k3);
 #pragma unroll
                         for (int k = 0; k < 18; k++) {
-                            y[k] = Y[k] + dt * k3[k];
+                            y[k] = __builtin_fma(dt, k3[k], Y[k]);
                             const double ks = k12[k] + 2.0 * k3[k];
-                            base[k] = Y[k] + h6 * ks;
+                            base[k] = __builtin_fma(h6, ks, Y[k]);
                         }
                     } else {
                         double k1[18], k2[18], k3[18];
@@ -374,9 +424,9 @@ stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ si
                         load_slope<NT>(S.K3, np, p, k3);
 #pragma unroll
                         for (int k = 0; k < 18; k++) {
-                            y[k] = Y[k] + dt * k3[k];
+                            y[k] = __builtin_fma(dt, k3[k], Y[k]);
                             const double ks = (k1[k] + 2.0 * k2[k]) + 2.0 * k3[k];
-                            base[k] = Y[k] + h6 * ks;
+                            base[k] = __builtin_fma(h6, ks, Y[k]);
                         }
                     }
                 } else {
@@ -411,7 +461,7 @@ stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ si
                     // step's first stage reads it straight back)
 #pragma unroll
                     for (int k = 0; k < 18; k++) {
-                        yn[k] = base[k] + h6 * kk[k];
+                        yn[k] = __builtin_fma(h6, kk[k], base[k]);
                         gst(S.Yout + k * np + p, yn[k]);
                     }
                 } else {
@@ -424,7 +474,7 @@ stage1d_kernel(const WorkItem *__restrict__ work, const SimDesc *__restrict__ si
                         store_slope<NT && MODE == M_S2>(Ko, np, p, kk);
 #pragma unroll
                     for (int k = 0; k < 18; k++)
-                        yn[k] = base[k] + an * kk[k];
+                        yn[k] = __builtin_fma(an, kk[k], base[k]);
                 }
 #pragma unroll
                 for (int k = 0; k < 9; k++)
